@@ -1,0 +1,319 @@
+"""CPU oracle for the CTU + PPMC + exact-Riemann step (TEST INFRASTRUCTURE ONLY).
+
+Thin ctypes wrapper over ``libctu_oracle.so`` (plain serial FP64 C, see ctu_oracle.c).
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import this package;
+the GPU library never does.  Arrays are numpy float64; a conserved state is a (5, NZ, NY, NX)
+array over the allocated box (three ghost layers per side), fields (rho, mx, my, mz, E).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+NG = 3
+BC_PERIODIC = 0
+BC_OUTFLOW = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.environ.get("CTU_ORACLE_LIB") or os.path.join(_HERE, "libctu_oracle.so")
+_lib = None
+
+
+class _Config(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("gamma", C.c_double), ("bc", C.c_int * 6), ("cfl", C.c_double),
+                ("newton_tol", C.c_double), ("newton_max_iter", C.c_int),
+                ("p_floor", C.c_double)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("solves", C.c_long), ("newton_iters", C.c_long),
+                ("newton_capped", C.c_long), ("p_floored", C.c_long)]
+
+
+_dp = C.POINTER(C.c_double)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        from . import build as _b  # noqa: F401  (build on first use)
+        _b.build()
+    lib = C.CDLL(_LIBPATH)
+    lib.ref_cons_to_prim.argtypes = [_dp, C.c_double, C.c_double, _dp]
+    lib.ref_cons_to_prim.restype = C.c_int
+    lib.ref_prim_to_cons.argtypes = [_dp, C.c_double, _dp]
+    lib.ref_char_project.argtypes = [_dp, C.c_double, C.c_double, _dp]
+    lib.ref_char_unproject.argtypes = [_dp, C.c_double, C.c_double, _dp]
+    lib.ref_plmc_slope.argtypes = [_dp, _dp, _dp, C.c_double, _dp]
+    lib.ref_ppmc.argtypes = [_dp, C.c_double, C.c_double, _dp, _dp, _dp]
+    lib.ref_riemann_star.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_int, C.c_double,
+                                     _dp, _dp, C.POINTER(C.c_int)]
+    lib.ref_riemann_star.restype = C.c_int
+    lib.ref_riemann_sample.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, _dp]
+    lib.ref_riemann_sample.restype = C.c_int
+    lib.ref_riemann_wave_speeds.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
+    lib.ref_riemann_flux.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_int, C.c_double,
+                                     _dp, C.POINTER(_Stats)]
+    lib.ref_bc_fill.argtypes = [C.POINTER(_Config), C.POINTER(_dp)]
+    lib.ref_compute_dt.argtypes = [C.POINTER(_Config), C.POINTER(_dp)]
+    lib.ref_compute_dt.restype = C.c_double
+    lib.ref_ctu_update_box.argtypes = [C.POINTER(_Config), C.POINTER(_dp), C.c_double,
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(_dp),
+                                       C.POINTER(_dp), C.POINTER(_dp), C.POINTER(_Stats)]
+    lib.ref_ctu_update_box.restype = C.c_int
+    lib.ref_ctu_step.argtypes = [C.POINTER(_Config), C.POINTER(_dp), C.c_double,
+                                 C.POINTER(_Stats)]
+    lib.ref_ctu_step.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _vec(x, n) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(n))
+    return a
+
+
+@dataclass
+class Config:
+    """Grid and solver parameters (mirrors the oracle's C struct)."""
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    gamma: float
+    bc: Sequence[int] = (BC_PERIODIC,) * 6
+    cfl: float = 0.3
+    newton_tol: float = 1e-6
+    newton_max_iter: int = 50
+    p_floor: float = 1e-20
+
+    def _c(self) -> _Config:
+        c = _Config()
+        c.nx, c.ny, c.nz = self.nx, self.ny, self.nz
+        c.dx, c.dy, c.dz = self.dx, self.dy, self.dz
+        c.gamma = self.gamma
+        for i in range(6):
+            c.bc[i] = int(self.bc[i])
+        c.cfl = self.cfl
+        c.newton_tol = self.newton_tol
+        c.newton_max_iter = self.newton_max_iter
+        c.p_floor = self.p_floor
+        return c
+
+    @property
+    def alloc_shape(self) -> Tuple[int, int, int]:
+        return (self.nz + 2 * NG, self.ny + 2 * NG, self.nx + 2 * NG)
+
+
+@dataclass
+class Stats:
+    solves: int = 0
+    newton_iters: int = 0
+    newton_capped: int = 0
+    p_floored: int = 0
+
+
+def _stats_out(s: _Stats) -> Stats:
+    return Stats(s.solves, s.newton_iters, s.newton_capped, s.p_floored)
+
+
+# --- pointwise pieces ----------------------------------------------------------------------
+
+def cons_to_prim(U, gamma: float, p_floor: float = 1e-20) -> np.ndarray:
+    lib = _load()
+    U = _vec(U, 5)
+    W = np.zeros(5)
+    lib.ref_cons_to_prim(_ptr(U), gamma, p_floor, _ptr(W))
+    return W
+
+
+def prim_to_cons(W, gamma: float) -> np.ndarray:
+    lib = _load()
+    W = _vec(W, 5)
+    U = np.zeros(5)
+    lib.ref_prim_to_cons(_ptr(W), gamma, _ptr(U))
+    return U
+
+
+def char_project(d, rho: float, a: float) -> np.ndarray:
+    lib = _load()
+    d = _vec(d, 5)
+    xi = np.zeros(5)
+    lib.ref_char_project(_ptr(d), rho, a, _ptr(xi))
+    return xi
+
+
+def char_unproject(xi, rho: float, a: float) -> np.ndarray:
+    lib = _load()
+    xi = _vec(xi, 5)
+    d = np.zeros(5)
+    lib.ref_char_unproject(_ptr(xi), rho, a, _ptr(d))
+    return d
+
+
+def plmc_slope(wm, w0, wp, gamma: float) -> np.ndarray:
+    lib = _load()
+    wm, w0, wp = _vec(wm, 5), _vec(w0, 5), _vec(wp, 5)
+    dw = np.zeros(5)
+    lib.ref_plmc_slope(_ptr(wm), _ptr(w0), _ptr(wp), gamma, _ptr(dw))
+    return dw
+
+
+def ppmc(w5x5, dtodx: float, gamma: float):
+    """PPMC of the centre cell of a 5-cell stencil of rotated primitives.
+
+    Returns (W*_L, W*_R, W_L, W_R): traced states and the monotonized face values."""
+    lib = _load()
+    w = np.ascontiguousarray(np.asarray(w5x5, dtype=np.float64).reshape(5, 5))
+    wl, wr, wlr = np.zeros(5), np.zeros(5), np.zeros(10)
+    lib.ref_ppmc(_ptr(w), dtodx, gamma, _ptr(wl), _ptr(wr), _ptr(wlr))
+    return wl, wr, wlr[:5].copy(), wlr[5:].copy()
+
+
+def riemann_star(WL, WR, gamma: float, tol: float = 1e-6, max_iter: int = 50,
+                 p_floor: float = 1e-20):
+    """Star pressure and velocity of the exact Riemann problem; WL, WR = (rho, u, p)."""
+    lib = _load()
+    wl, wr = _vec(WL, 3), _vec(WR, 3)
+    ps, us = C.c_double(), C.c_double()
+    capped = C.c_int()
+    it = lib.ref_riemann_star(_ptr(wl), _ptr(wr), gamma, tol, max_iter, p_floor,
+                              C.byref(ps), C.byref(us), C.byref(capped))
+    return ps.value, us.value, it, bool(capped.value)
+
+
+def riemann_sample(WL, WR, pstar: float, ustar: float, gamma: float, S: float):
+    lib = _load()
+    wl, wr = _vec(WL, 3), _vec(WR, 3)
+    out = np.zeros(3)
+    side = lib.ref_riemann_sample(_ptr(wl), _ptr(wr), pstar, ustar, gamma, S, _ptr(out))
+    return out, side
+
+
+def riemann_wave_speeds(WL, WR, pstar: float, ustar: float, gamma: float) -> np.ndarray:
+    lib = _load()
+    wl, wr = _vec(WL, 3), _vec(WR, 3)
+    out = np.zeros(5)
+    lib.ref_riemann_wave_speeds(_ptr(wl), _ptr(wr), pstar, ustar, gamma, _ptr(out))
+    return out
+
+
+def exact_solution(WL, WR, gamma: float, xi: np.ndarray, tol: float = 1e-14,
+                   max_iter: int = 200) -> np.ndarray:
+    """Exact Riemann solution (rho, u, p) at similarity coordinates xi = (x - x0)/t."""
+    ps, us, _, _ = riemann_star(WL, WR, gamma, tol, max_iter)
+    out = np.zeros((3, len(xi)))
+    for n, s in enumerate(np.asarray(xi, dtype=np.float64)):
+        out[:, n], _ = riemann_sample(WL, WR, ps, us, gamma, float(s))
+    return out
+
+
+def riemann_flux(UL, UR, gamma: float, tol: float = 1e-6, max_iter: int = 50,
+                 p_floor: float = 1e-20):
+    lib = _load()
+    ul, ur = _vec(UL, 5), _vec(UR, 5)
+    F = np.zeros(5)
+    st = _Stats()
+    lib.ref_riemann_flux(_ptr(ul), _ptr(ur), gamma, tol, max_iter, p_floor, _ptr(F),
+                         C.byref(st))
+    return F, _stats_out(st)
+
+
+# --- whole-grid operations ------------------------------------------------------------------
+
+def _field_ptrs(u: np.ndarray):
+    assert u.dtype == np.float64 and u.flags.c_contiguous and u.shape[0] == 5
+    arr = (_dp * 5)()
+    for f in range(5):
+        arr[f] = u[f].ctypes.data_as(_dp)
+    return arr
+
+
+def alloc_state(cfg: Config) -> np.ndarray:
+    return np.zeros((5,) + cfg.alloc_shape, dtype=np.float64)
+
+
+def bc_fill(cfg: Config, u: np.ndarray) -> None:
+    _load().ref_bc_fill(C.byref(cfg._c()), _field_ptrs(u))
+
+
+def compute_dt(cfg: Config, u: np.ndarray) -> float:
+    return float(_load().ref_compute_dt(C.byref(cfg._c()), _field_ptrs(u)))
+
+
+def step(cfg: Config, u: np.ndarray, dt: float) -> Stats:
+    """One CTU step in place (ghost fill included)."""
+    st = _Stats()
+    rc = _load().ref_ctu_step(C.byref(cfg._c()), _field_ptrs(u), dt, C.byref(st))
+    if rc != 0:
+        raise ValueError("oracle step failed")
+    return _stats_out(st)
+
+
+def update_box(cfg: Config, u: np.ndarray, dt: float, lo, hi, want_fluxes: bool = False):
+    """u^{n+1} on the real-cell box [lo, hi) (x, y, z order) of a ghost-filled state.
+
+    Returns (out, stats) with out of shape (5, nz_box, ny_box, nx_box); with want_fluxes
+    also the first-stage and CTU flux arrays, each (3, 5) + alloc_shape (face i+1/2 at i)."""
+    lib = _load()
+    lo3 = (C.c_int * 3)(*[int(v) for v in lo])
+    hi3 = (C.c_int * 3)(*[int(v) for v in hi])
+    shape = tuple(int(hi[a] - lo[a]) for a in (2, 1, 0))
+    out = np.zeros((5,) + shape)
+    st = _Stats()
+    fs_arr = fh_arr = None
+    fstar = fhalf = None
+    if want_fluxes:
+        fstar = np.full((3, 5) + cfg.alloc_shape, np.nan)
+        fhalf = np.full((3, 5) + cfg.alloc_shape, np.nan)
+        fs_arr = (_dp * 15)()
+        fh_arr = (_dp * 15)()
+        for d in range(3):
+            for f in range(5):
+                fs_arr[d * 5 + f] = fstar[d, f].ctypes.data_as(_dp)
+                fh_arr[d * 5 + f] = fhalf[d, f].ctypes.data_as(_dp)
+    rc = lib.ref_ctu_update_box(C.byref(cfg._c()), _field_ptrs(u), dt, lo3, hi3,
+                                _field_ptrs(out), fs_arr, fh_arr, C.byref(st))
+    if rc != 0:
+        raise ValueError("invalid box")
+    if want_fluxes:
+        return out, _stats_out(st), fstar, fhalf
+    return out, _stats_out(st)
+
+
+def real(cfg: Config, u: np.ndarray) -> np.ndarray:
+    """View of the real cells of an allocated state."""
+    return u[:, NG:NG + cfg.nz, NG:NG + cfg.ny, NG:NG + cfg.nx]
+
+
+def state_from_primitive(cfg: Config, W: np.ndarray) -> np.ndarray:
+    """Allocated conserved state from real-cell primitives W of shape (5, nz, ny, nx).
+
+    Uses the oracle's own EOS conversion, cell by cell in a numpy-vectorized restatement of
+    ref_prim_to_cons (same operation order)."""
+    g = cfg.gamma
+    u = alloc_state(cfg)
+    rho, vx, vy, vz, p = (np.asarray(W[q], dtype=np.float64) for q in range(5))
+    r = real(cfg, u)
+    r[0] = rho
+    r[1] = rho * vx
+    r[2] = rho * vy
+    r[3] = rho * vz
+    r[4] = p / (g - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+    return u

@@ -1,0 +1,713 @@
+/*
+ * ctu_oracle.c -- plain serial FP64 oracle for one CTU + PPMC + exact-Riemann step.
+ *
+ * TEST INFRASTRUCTURE ONLY (see ctu_oracle.h).  Written from the paper
+ * (Schneider & Robertson 2015, arXiv:1410.4194):
+ *   - CTU six-solve algorithm: Sec. 2.1, eqs. (simple_conserved_update),
+ *     (transverse_evolution), (conserved_update); time step eqs. (calc_dt_1D/3D).
+ *   - PPMC reconstruction: App. A.3, which reuses the PLMC slope step of App. A.2.
+ *   - Exact Riemann solver: App. B.1 (Toro's solver, sampled at x/t = 0).
+ *   - Boundary conditions: Sec. 3.1 (periodic and transmissive ghost copies).
+ * Readings of garbled or silent passages are marked [Qn] and listed in the design notes.
+ */
+#include "ctu_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NG REF_NG
+
+/* ------------------------------------------------------------------------------------ */
+/* Equation of state and variable sets (Sec. 2, eqs. conserved_variables,                */
+/* primitive_variables; ideal gas p = (gamma-1) rho e, E = rho(V^2/2 + e)).               */
+/* ------------------------------------------------------------------------------------ */
+
+int ref_cons_to_prim(const double U[5], double gamma, double p_floor, double W[5]) {
+  double rho = U[0];
+  double u = U[1] / rho;
+  double v = U[2] / rho;
+  double w = U[3] / rho;
+  double p = (gamma - 1.0) * (U[4] - 0.5 * rho * (u * u + v * v + w * w));
+  int floored = 0;
+  /* [Q11] the pressure floor of Sec. 2.3.1 is applied on every primitive conversion. */
+  if (!(p >= p_floor)) {
+    p = p_floor;
+    floored = 1;
+  }
+  W[0] = rho;
+  W[1] = u;
+  W[2] = v;
+  W[3] = w;
+  W[4] = p;
+  return floored;
+}
+
+void ref_prim_to_cons(const double W[5], double gamma, double U[5]) {
+  double rho = W[0];
+  U[0] = rho;
+  U[1] = rho * W[1];
+  U[2] = rho * W[2];
+  U[3] = rho * W[3];
+  U[4] = W[4] / (gamma - 1.0) + 0.5 * rho * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Characteristic projection (App. A.2, PLMC).                                            */
+/* [Q1] The first component is printed as -1/2(rho du/a + dp/a^2); with the printed       */
+/* back-projection that would make the pressure slope vanish identically.  The left       */
+/* eigenvector of the u-a wave gives +1/2(dp/a^2 - rho du/a), which is used here; the      */
+/* round-trip pin (unproject(project(d)) == d) fixes this choice.                         */
+/* ------------------------------------------------------------------------------------ */
+
+void ref_char_project(const double d[5], double rho, double a, double xi[5]) {
+  double a2 = a * a;
+  xi[0] = 0.5 * (d[4] / a2 - rho * d[1] / a);
+  xi[1] = d[0] - d[4] / a2;
+  xi[2] = d[2];
+  xi[3] = d[3];
+  xi[4] = 0.5 * (d[4] / a2 + rho * d[1] / a);
+}
+
+void ref_char_unproject(const double xi[5], double rho, double a, double d[5]) {
+  d[0] = xi[0] + xi[1] + xi[4];
+  d[1] = (a / rho) * (xi[4] - xi[0]);
+  d[2] = xi[2];
+  d[3] = xi[3];
+  d[4] = a * a * (xi[0] + xi[4]);
+}
+
+/* Monotonized central-difference limiter (App. A.1/A.2), sgn(0) = +1. */
+static double mc_limit(double dl, double dr, double dc) {
+  if (dl * dr > 0.0) {
+    double s = (dc < 0.0) ? -1.0 : 1.0;
+    double m = fabs(dc);
+    if (2.0 * fabs(dl) < m) m = 2.0 * fabs(dl);
+    if (2.0 * fabs(dr) < m) m = 2.0 * fabs(dr);
+    return s * m;
+  }
+  return 0.0;
+}
+
+static double sound_speed(const double w[5], double gamma) { return sqrt(gamma * w[4] / w[0]); }
+
+/* PLMC slope step for one cell (App. A.2): left, right and centred differences of the
+ * primitives, projected onto the characteristics of that cell [Q8: each of the cells
+ * c-1, c, c+1 uses its own rho and a], limited per component, projected back. */
+void ref_plmc_slope(const double wm[5], const double w0[5], const double wp[5], double gamma,
+                    double dw[5]) {
+  double rho = w0[0];
+  double a = sound_speed(w0, gamma);
+  double dL[5], dR[5], dC[5];
+  for (int q = 0; q < 5; ++q) {
+    dL[q] = w0[q] - wm[q];
+    dR[q] = wp[q] - w0[q];
+    dC[q] = 0.5 * (wp[q] - wm[q]);
+  }
+  double xL[5], xR[5], xC[5], xi[5];
+  ref_char_project(dL, rho, a, xL);
+  ref_char_project(dR, rho, a, xR);
+  ref_char_project(dC, rho, a, xC);
+  for (int q = 0; q < 5; ++q) xi[q] = mc_limit(xL[q], xR[q], xC[q]);
+  ref_char_unproject(xi, rho, a, dw);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* PPMC (App. A.3).                                                                       */
+/* ------------------------------------------------------------------------------------ */
+
+/* Integral averages of the parabola over the domain of dependence of the left face
+ * (alpha <= 0) and of the right face (beta >= 0), as in eq. (integration_PPMC). */
+static double ppm_IL(double alpha, double dw, double w6) {
+  return 0.5 * alpha * (dw + w6 * (1.0 + (2.0 / 3.0) * alpha));
+}
+static double ppm_IR(double beta, double dw, double w6) {
+  return 0.5 * beta * (dw - w6 * (1.0 - (2.0 / 3.0) * beta));
+}
+
+void ref_ppmc(const double w[5][5], double dtodx, double gamma, double WsL[5], double WsR[5],
+              double* WLR_out) {
+  const double* wmm = w[0];
+  const double* wm = w[1];
+  const double* wc = w[2];
+  const double* wp = w[3];
+  const double* wpp = w[4];
+
+  /* Step 1: limited slopes of cells c-1, c, c+1. */
+  double dwm[5], dwc[5], dwp[5];
+  ref_plmc_slope(wmm, wm, wc, gamma, dwm);
+  ref_plmc_slope(wm, wc, wp, gamma, dwc);
+  ref_plmc_slope(wc, wp, wpp, gamma, dwp);
+
+  double WL[5], WR[5], dw[5], w6[5];
+  for (int q = 0; q < 5; ++q) {
+    /* Step 2: parabolic interpolation, eq. (parabolic_interpolation). */
+    double wl = 0.5 * (wc[q] + wm[q]) - (dwc[q] - dwm[q]) / 6.0;
+    double wr = 0.5 * (wp[q] + wc[q]) - (dwp[q] - dwc[q]) / 6.0;
+    double c = wc[q];
+    /* Step 3: local extremum, eq. (max_min). */
+    if ((wr - c) * (c - wl) <= 0.0) {
+      wl = c;
+      wr = c;
+    }
+    /* Step 4: steep gradients, eq. (steep_gradient), applied in the printed order; after
+     * the first fix fires the second test evaluates to 9 (wr - c)^2 >= 0 and cannot fire. */
+    if ((wr - wl) * (wl - (3.0 * c - 2.0 * wr)) < 0.0) wl = 3.0 * c - 2.0 * wr;
+    if ((wr - wl) * ((3.0 * c - 2.0 * wl) - wr) < 0.0) wr = 3.0 * c - 2.0 * wl;
+    /* Step 5: bound the face values by the neighbouring cell averages. */
+    double lo = fmin(c, wm[q]), hi = fmax(c, wm[q]);
+    wl = fmin(hi, fmax(lo, wl));
+    lo = fmin(c, wp[q]);
+    hi = fmax(c, wp[q]);
+    wr = fmin(hi, fmax(lo, wr));
+    WL[q] = wl;
+    WR[q] = wr;
+    /* Step 6: parabola coefficients.  [Q5] w6 is printed 6w - 3(W_L - W_R); the parabola
+     * with mean w, ends W_L and W_R has w6 = 6w - 3(W_L + W_R), as in the PPMP section. */
+    dw[q] = wr - wl;
+    w6[q] = 6.0 * c - 3.0 * (wl + wr);
+  }
+  if (WLR_out) {
+    for (int q = 0; q < 5; ++q) {
+      WLR_out[q] = WL[q];
+      WLR_out[5 + q] = WR[q];
+    }
+  }
+
+  /* Step 7: characteristic speeds of cell c and the unit-free alpha/beta. */
+  double rho = wc[0];
+  double a = sound_speed(wc, gamma);
+  double a2 = a * a;
+  double lm = wc[1] - a, l0 = wc[1], lp = wc[1] + a;
+  double am = dtodx * fmin(lm, 0.0), bm = dtodx * fmax(lm, 0.0);
+  double a0 = dtodx * fmin(l0, 0.0), b0 = dtodx * fmax(l0, 0.0);
+  double ap = dtodx * fmin(lp, 0.0), bp = dtodx * fmax(lp, 0.0);
+
+  /* Step 8: reference states, traced with the fastest wave toward each face. */
+  double E[5], B[5], C[5], D[5];
+  for (int q = 0; q < 5; ++q) {
+    double ILm = ppm_IL(am, dw[q], w6[q]);
+    double IRp = ppm_IR(bp, dw[q], w6[q]);
+    WsL[q] = WL[q] - ILm;
+    WsR[q] = WR[q] - IRp;
+    /* [Q3] B is printed with (1 + 2/3 alpha^p) in its first term; as for E it is the
+     * difference of the alpha^m and alpha^p integrals.  [Q4] D's second term is the
+     * right-face integral with beta^0, matching C. */
+    E[q] = ILm - ppm_IL(a0, dw[q], w6[q]);
+    B[q] = ILm - ppm_IL(ap, dw[q], w6[q]);
+    C[q] = IRp - ppm_IR(bm, dw[q], w6[q]);
+    D[q] = IRp - ppm_IR(b0, dw[q], w6[q]);
+  }
+
+  /* Step 9: corrections for the other waves moving toward each face [Q9: strict
+   * inequalities as printed; Q6: waves not moving toward a face get no correction]. */
+  if (l0 < 0.0) {
+    WsL[0] += E[0] - E[4] / a2;
+    WsL[2] += E[2];
+    WsL[3] += E[3];
+  }
+  if (lp < 0.0) {
+    WsL[0] += 0.5 * (rho * B[1] / a + B[4] / a2);
+    WsL[1] += 0.5 * (B[1] + B[4] / (a * rho));
+    WsL[4] += 0.5 * (rho * B[1] * a + B[4]);
+  }
+  if (lm > 0.0) {
+    WsR[0] += 0.5 * (-rho * C[1] / a + C[4] / a2);
+    WsR[1] += 0.5 * (C[1] - C[4] / (a * rho));
+    WsR[4] += 0.5 * (-rho * C[1] * a + C[4]);
+  }
+  if (l0 > 0.0) {
+    WsR[0] += D[0] - D[4] / a2;
+    WsR[2] += D[2];
+    WsR[3] += D[3];
+  }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Exact Riemann solver (App. B.1).                                                       */
+/* ------------------------------------------------------------------------------------ */
+
+/* Pressure function f_k and its derivative, eq. (pressure_functions), written as printed. */
+static void pressure_function(double p, double rho_k, double p_k, double a_k, double gamma,
+                              double* f, double* df) {
+  if (p <= p_k) {
+    *f = 2.0 * a_k / (gamma - 1.0) * (pow(p / p_k, (gamma - 1.0) / (2.0 * gamma)) - 1.0);
+    *df = 1.0 / (rho_k * a_k) * pow(p / p_k, -(gamma + 1.0) / (2.0 * gamma));
+  } else {
+    double A = 2.0 / ((gamma + 1.0) * rho_k);
+    double B = (gamma - 1.0) / (gamma + 1.0) * p_k;
+    *f = (p - p_k) * sqrt(A / (p + B));
+    *df = sqrt(A / (B + p)) * (1.0 - (p - p_k) / (2.0 * (B + p)));
+  }
+}
+
+int ref_riemann_star(const double WL[3], const double WR[3], double gamma, double tol,
+                     int max_iter, double p_floor, double* pstar, double* ustar, int* capped) {
+  double rl = WL[0], ul = WL[1], pl = WL[2];
+  double rr = WR[0], ur = WR[1], pr = WR[2];
+  double al = sqrt(gamma * pl / rl);
+  double ar = sqrt(gamma * pr / rr);
+
+  /* Primitive-variable (PVRS) first guess, clipped at zero. */
+  double ptilde = 0.5 * (pl + pr) + 0.125 * (ul - ur) * (rl + rr) * (al + ar);
+  if (ptilde < 0.0) ptilde = 0.0;
+
+  /* Two-shock (TSRS) estimate used as the Newton start, floored at 1e-6. */
+  double Al = 2.0 / ((gamma + 1.0) * rl), Bl = (gamma - 1.0) / (gamma + 1.0) * pl;
+  double Ar = 2.0 / ((gamma + 1.0) * rr), Br = (gamma - 1.0) / (gamma + 1.0) * pr;
+  double gl = sqrt(Al / (ptilde + Bl));
+  double gr = sqrt(Ar / (ptilde + Br));
+  double p = (gl * pl + gr * pr - (ur - ul)) / (gl + gr);
+  if (p < 1.0e-6) p = 1.0e-6;
+
+  /* Newton-Raphson on f_L(p) + f_R(p) + (u_R - u_L) = 0, stopping on the relative change
+   * 2|p_new - p|/|p_new + p| < tol.  [Q10] the paper sets no cap; max_iter bounds the
+   * loop and iterates are kept at or above the global pressure floor. */
+  int it = 0;
+  int conv = 0;
+  while (it < max_iter) {
+    double fl, dfl, fr, dfr;
+    pressure_function(p, rl, pl, al, gamma, &fl, &dfl);
+    pressure_function(p, rr, pr, ar, gamma, &fr, &dfr);
+    double pn = p - (fl + fr + ur - ul) / (dfl + dfr);
+    if (!(pn >= p_floor)) pn = p_floor;
+    double delta = 2.0 * fabs(pn - p) / fabs(pn + p);
+    p = pn;
+    ++it;
+    if (delta < tol) {
+      conv = 1;
+      break;
+    }
+  }
+  /* [Q12] u* from f_L, f_R evaluated at the final star pressure. */
+  double fl, dfl, fr, dfr;
+  pressure_function(p, rl, pl, al, gamma, &fl, &dfl);
+  pressure_function(p, rr, pr, ar, gamma, &fr, &dfr);
+  *pstar = p;
+  *ustar = 0.5 * (ul + ur + fr - fl);
+  if (capped) *capped = !conv;
+  return it;
+}
+
+/* Sampling of App. B.1, written for a general similarity coordinate S = x/t; at S = 0
+ * every test below is the printed one, with the printed tie-breaks.  The fan formulas
+ * at S follow from the characteristic u -/+ a = S through the fan.
+ * [Q13] the right-fan sound speed is 2/(gamma+1)(a_R - (gamma-1)/2 u_R) at S = 0 (the
+ * printed '+' contradicts u + a = 0 on the characteristic through x/t = 0). */
+int ref_riemann_sample(const double WL[3], const double WR[3], double pstar, double ustar,
+                       double gamma, double S, double out[3]) {
+  double rl = WL[0], ul = WL[1], pl = WL[2];
+  double rr = WR[0], ur = WR[1], pr = WR[2];
+  double al = sqrt(gamma * pl / rl);
+  double ar = sqrt(gamma * pr / rr);
+  double gm = (gamma - 1.0) / (gamma + 1.0);
+  if (ustar >= S) {
+    /* Contact to the right of the sample point: left side of the solution. */
+    if (pstar <= pl) {
+      /* Left rarefaction. */
+      if (ul - al >= S) {
+        out[0] = rl;
+        out[1] = ul;
+        out[2] = pl;
+      } else if (ustar - al * pow(pstar / pl, (gamma - 1.0) / (2.0 * gamma)) < S) {
+        out[0] = rl * pow(pstar / pl, 1.0 / gamma);
+        out[1] = ustar;
+        out[2] = pstar;
+      } else {
+        double c = 2.0 / (gamma + 1.0) * (al + 0.5 * (gamma - 1.0) * (ul - S));
+        out[0] = rl * pow(c / al, 2.0 / (gamma - 1.0));
+        out[1] = c + S;
+        out[2] = pl * pow(c / al, 2.0 * gamma / (gamma - 1.0));
+      }
+    } else {
+      /* Left shock. */
+      double sl =
+          ul - al * sqrt((gamma + 1.0) / (2.0 * gamma) * pstar / pl + (gamma - 1.0) / (2.0 * gamma));
+      if (sl >= S) {
+        out[0] = rl;
+        out[1] = ul;
+        out[2] = pl;
+      } else {
+        out[0] = rl * (pstar / pl + gm) / (pstar / pl * gm + 1.0);
+        out[1] = ustar;
+        out[2] = pstar;
+      }
+    }
+    return 0;
+  }
+  /* Contact to the left of the sample point: right side of the solution. */
+  if (pstar <= pr) {
+    /* Right rarefaction. */
+    if (ur + ar <= S) {
+      out[0] = rr;
+      out[1] = ur;
+      out[2] = pr;
+    } else if (ustar + ar * pow(pstar / pr, (gamma - 1.0) / (2.0 * gamma)) >= S) {
+      out[0] = rr * pow(pstar / pr, 1.0 / gamma);
+      out[1] = ustar;
+      out[2] = pstar;
+    } else {
+      double c = 2.0 / (gamma + 1.0) * (ar - 0.5 * (gamma - 1.0) * (ur - S));
+      out[0] = rr * pow(c / ar, 2.0 / (gamma - 1.0));
+      out[1] = S - c;
+      out[2] = pr * pow(c / ar, 2.0 * gamma / (gamma - 1.0));
+    }
+  } else {
+    /* Right shock.  [Q14] the printed label s_LR is the right shock speed s_R. */
+    double sr =
+        ur + ar * sqrt((gamma + 1.0) / (2.0 * gamma) * pstar / pr + (gamma - 1.0) / (2.0 * gamma));
+    if (sr <= S) {
+      out[0] = rr;
+      out[1] = ur;
+      out[2] = pr;
+    } else {
+      out[0] = rr * (pstar / pr + gm) / (pstar / pr * gm + 1.0);
+      out[1] = ustar;
+      out[2] = pstar;
+    }
+  }
+  return 1;
+}
+
+void ref_riemann_wave_speeds(const double WL[3], const double WR[3], double pstar,
+                             double ustar, double gamma, double out[5]) {
+  double rl = WL[0], ul = WL[1], pl = WL[2];
+  double rr = WR[0], ur = WR[1], pr = WR[2];
+  double al = sqrt(gamma * pl / rl);
+  double ar = sqrt(gamma * pr / rr);
+  if (pstar <= pl) {
+    out[0] = ul - al;
+    out[1] = ustar - al * pow(pstar / pl, (gamma - 1.0) / (2.0 * gamma));
+  } else {
+    out[0] = ul - al * sqrt((gamma + 1.0) / (2.0 * gamma) * pstar / pl + (gamma - 1.0) / (2.0 * gamma));
+    out[1] = out[0];
+  }
+  out[2] = ustar;
+  if (pstar <= pr) {
+    out[4] = ur + ar;
+    out[3] = ustar + ar * pow(pstar / pr, (gamma - 1.0) / (2.0 * gamma));
+  } else {
+    out[4] = ur + ar * sqrt((gamma + 1.0) / (2.0 * gamma) * pstar / pr + (gamma - 1.0) / (2.0 * gamma));
+    out[3] = out[4];
+  }
+}
+
+void ref_riemann_flux(const double UL[5], const double UR[5], double gamma, double tol,
+                      int max_iter, double p_floor, double F[5], ref_stats* st) {
+  double WL[5], WR[5];
+  int fl = ref_cons_to_prim(UL, gamma, p_floor, WL);
+  int fr = ref_cons_to_prim(UR, gamma, p_floor, WR);
+  double wl3[3] = {WL[0], WL[1], WL[4]};
+  double wr3[3] = {WR[0], WR[1], WR[4]};
+  double pstar, ustar;
+  int capped = 0;
+  int it = ref_riemann_star(wl3, wr3, gamma, tol, max_iter, p_floor, &pstar, &ustar, &capped);
+  double s[3];
+  ref_riemann_sample(wl3, wr3, pstar, ustar, gamma, 0.0, s);
+  double rho = s[0], u = s[1], p = s[2];
+  /* Transverse velocities are advected: taken from the left state when the sampled normal
+   * velocity is >= 0, else from the right [Q15]. */
+  double vt = (u >= 0.0) ? WL[2] : WR[2];
+  double wt = (u >= 0.0) ? WL[3] : WR[3];
+  double E = p / (gamma - 1.0) + 0.5 * rho * (u * u + vt * vt + wt * wt);
+  F[0] = rho * u;
+  F[1] = rho * u * u + p;
+  F[2] = rho * u * vt;
+  F[3] = rho * u * wt;
+  F[4] = (E + p) * u;
+  if (st) {
+    st->solves += 1;
+    st->newton_iters += it;
+    st->newton_capped += capped;
+    st->p_floored += fl + fr;
+  }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Grid helpers.                                                                          */
+/* ------------------------------------------------------------------------------------ */
+
+static long alloc_index(const ref_config* c, int i, int j, int k) {
+  long NX = c->nx + 2 * NG, NY = c->ny + 2 * NG;
+  return (long)(i + NG) + NX * ((long)(j + NG) + NY * (long)(k + NG));
+}
+
+static int wrap_index(int q, int n) {
+  int r = q % n;
+  return r < 0 ? r + n : r;
+}
+
+void ref_bc_fill(const ref_config* c, double* const u[5]) {
+  int n[3] = {c->nx, c->ny, c->nz};
+  for (int axis = 0; axis < 3; ++axis) {
+    for (int k = -NG; k < c->nz + NG; ++k)
+      for (int j = -NG; j < c->ny + NG; ++j)
+        for (int i = -NG; i < c->nx + NG; ++i) {
+          int pos[3] = {i, j, k};
+          int q = pos[axis];
+          if (q >= 0 && q < n[axis]) continue;
+          int side = (q < 0) ? 0 : 1;
+          int bc = c->bc[2 * axis + side];
+          int src;
+          if (bc == REF_BC_PERIODIC)
+            src = wrap_index(q, n[axis]);
+          else /* transmissive: zero-gradient copy of the edge cell [Q17] */
+            src = (q < 0) ? 0 : n[axis] - 1;
+          int spos[3] = {i, j, k};
+          spos[axis] = src;
+          long dst_i = alloc_index(c, i, j, k);
+          long src_i = alloc_index(c, spos[0], spos[1], spos[2]);
+          for (int f = 0; f < 5; ++f) u[f][dst_i] = u[f][src_i];
+        }
+  }
+}
+
+double ref_compute_dt(const ref_config* c, double* const u[5]) {
+  double best = INFINITY;
+  for (int k = 0; k < c->nz; ++k)
+    for (int j = 0; j < c->ny; ++j)
+      for (int i = 0; i < c->nx; ++i) {
+        long id = alloc_index(c, i, j, k);
+        double U[5], W[5];
+        for (int f = 0; f < 5; ++f) U[f] = u[f][id];
+        ref_cons_to_prim(U, c->gamma, c->p_floor, W);
+        double a = sqrt(c->gamma * W[4] / W[0]);
+        double tx = c->dx / (fabs(W[1]) + a);
+        double ty = c->dy / (fabs(W[2]) + a);
+        double tz = c->dz / (fabs(W[3]) + a);
+        double t = fmin(tx, fmin(ty, tz));
+        if (t < best) best = t;
+      }
+  return c->cfl * best;
+}
+
+/* A box of cells [lo, hi) in real-cell coordinates with its own compact storage. */
+typedef struct {
+  int lo[3], hi[3];
+  long n[3];
+} box;
+
+static box make_box(const int lo[3], const int hi[3]) {
+  box b;
+  for (int a = 0; a < 3; ++a) {
+    b.lo[a] = lo[a];
+    b.hi[a] = hi[a];
+    b.n[a] = hi[a] - lo[a];
+  }
+  return b;
+}
+
+static long box_index(const box* b, int i, int j, int k) {
+  return (long)(i - b->lo[0]) + b->n[0] * ((long)(j - b->lo[1]) + b->n[1] * (long)(k - b->lo[2]));
+}
+
+static long box_size(const box* b) { return b->n[0] * b->n[1] * b->n[2]; }
+
+/* Rotation of the momentum components for a sweep along direction d (cyclic, [Q24]):
+ * rotated slot s holds global component rot[d][s]. */
+static const int rot[3][5] = {{0, 1, 2, 3, 4}, {0, 2, 3, 1, 4}, {0, 3, 1, 2, 4}};
+
+int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const int lo[3],
+                       const int hi[3], double* const out[5], double* const* fstar,
+                       double* const* fhalf, ref_stats* st) {
+  int n[3] = {c->nx, c->ny, c->nz};
+  double dd[3] = {c->dx, c->dy, c->dz};
+  for (int a = 0; a < 3; ++a)
+    if (lo[a] < 0 || hi[a] > n[a] || lo[a] >= hi[a]) return -1;
+  double g = c->gamma;
+
+  /* Boxes: R = cells to update; X = R grown by one cell (cells whose traced states and
+   * first-stage fluxes the transverse correction reads); P = R grown by three (stencil). */
+  int xlo[3], xhi[3], plo[3], phi[3];
+  for (int a = 0; a < 3; ++a) {
+    xlo[a] = lo[a] - 1;
+    xhi[a] = hi[a] + 1;
+    plo[a] = lo[a] - NG;
+    phi[a] = hi[a] + NG;
+  }
+  box R = make_box(lo, hi), X = make_box(xlo, xhi), P = make_box(plo, phi);
+
+  /* Primitive variables of every stencil cell (Sec. 2, with the pressure floor). */
+  long nP = box_size(&P);
+  double* W[5];
+  for (int f = 0; f < 5; ++f) W[f] = (double*)malloc(sizeof(double) * nP);
+  for (int k = P.lo[2]; k < P.hi[2]; ++k)
+    for (int j = P.lo[1]; j < P.hi[1]; ++j)
+      for (int i = P.lo[0]; i < P.hi[0]; ++i) {
+        double U[5], w[5];
+        long id = alloc_index(c, i, j, k);
+        for (int f = 0; f < 5; ++f) U[f] = u[f][id];
+        if (ref_cons_to_prim(U, g, c->p_floor, w) && st) st->p_floored += 1;
+        long pb = box_index(&P, i, j, k);
+        for (int f = 0; f < 5; ++f) W[f][pb] = w[f];
+      }
+
+  /* Per direction: conserved traced states of every cell of X (cell-centred labels:
+   * Us[d][0] = U*_L at the cell's left face, Us[d][1] = U*_R at its right face), and
+   * first-stage fluxes on the faces between neighbouring X cells along d. */
+  long nX = box_size(&X);
+  double* Us[3][2][5];
+  double* Fs[3][5];
+  for (int d = 0; d < 3; ++d) {
+    for (int s = 0; s < 2; ++s)
+      for (int f = 0; f < 5; ++f) Us[d][s][f] = (double*)malloc(sizeof(double) * nX);
+    for (int f = 0; f < 5; ++f) Fs[d][f] = (double*)malloc(sizeof(double) * nX);
+  }
+
+  for (int d = 0; d < 3; ++d) {
+    double dtodx = dt / dd[d];
+    /* Step 1 of Sec. 2.1: reconstruction and half-step characteristic tracing. */
+    for (int k = X.lo[2]; k < X.hi[2]; ++k)
+      for (int j = X.lo[1]; j < X.hi[1]; ++j)
+        for (int i = X.lo[0]; i < X.hi[0]; ++i) {
+          double w[5][5];
+          for (int s = -2; s <= 2; ++s) {
+            int pos[3] = {i, j, k};
+            pos[d] += s;
+            long pb = box_index(&P, pos[0], pos[1], pos[2]);
+            for (int q = 0; q < 5; ++q) w[s + 2][q] = W[rot[d][q]][pb];
+          }
+          double wsl[5], wsr[5], usl[5], usr[5];
+          ref_ppmc(w, dtodx, g, wsl, wsr, NULL);
+          /* Between stages the interface states are kept in conserved form (App. B.1). */
+          ref_prim_to_cons(wsl, g, usl);
+          ref_prim_to_cons(wsr, g, usr);
+          long xb = box_index(&X, i, j, k);
+          for (int q = 0; q < 5; ++q) {
+            Us[d][0][rot[d][q]][xb] = usl[q];
+            Us[d][1][rot[d][q]][xb] = usr[q];
+          }
+        }
+    /* Step 2: first Riemann solve at each d-face between cells of X.  [Q30] the right
+     * face state W*_R of cell c is the left input U*_L of face c+1/2, and W*_L of cell
+     * c+1 is its right input U*_R. */
+    for (int k = X.lo[2]; k < X.hi[2]; ++k)
+      for (int j = X.lo[1]; j < X.hi[1]; ++j)
+        for (int i = X.lo[0]; i < X.hi[0]; ++i) {
+          int pos[3] = {i, j, k};
+          if (pos[d] + 1 >= X.hi[d]) continue;
+          int nb[3] = {i, j, k};
+          nb[d] += 1;
+          long xc = box_index(&X, i, j, k);
+          long xn = box_index(&X, nb[0], nb[1], nb[2]);
+          double ul[5], ur[5], fl[5];
+          for (int q = 0; q < 5; ++q) {
+            ul[q] = Us[d][1][rot[d][q]][xc];
+            ur[q] = Us[d][0][rot[d][q]][xn];
+          }
+          ref_riemann_flux(ul, ur, g, c->newton_tol, c->newton_max_iter, c->p_floor, fl, st);
+          for (int q = 0; q < 5; ++q) Fs[d][rot[d][q]][xc] = fl[q];
+          if (fstar) {
+            long ai = alloc_index(c, i, j, k);
+            for (int q = 0; q < 5; ++q) fstar[d * 5 + rot[d][q]][ai] = fl[q];
+          }
+        }
+  }
+
+  /* Steps 3-4: transverse correction (eq. transverse_evolution) and the second Riemann
+   * solve on the faces of R's cells.  Fh[d] is stored on the box R grown by one cell
+   * toward -d, face c+1/2 at cell c. */
+  double* Fh[3][5];
+  box H[3];
+  for (int d = 0; d < 3; ++d) {
+    int hlo[3] = {lo[0], lo[1], lo[2]};
+    hlo[d] -= 1;
+    H[d] = make_box(hlo, hi);
+    for (int f = 0; f < 5; ++f) Fh[d][f] = (double*)malloc(sizeof(double) * box_size(&H[d]));
+  }
+  for (int d = 0; d < 3; ++d) {
+    int t1 = (d + 1) % 3, t2 = (d + 2) % 3; /* cyclic permutation of Sec. 2.1 step 3 */
+    double h1 = 0.5 * dt / dd[t1];
+    double h2 = 0.5 * dt / dd[t2];
+    for (int k = H[d].lo[2]; k < H[d].hi[2]; ++k)
+      for (int j = H[d].lo[1]; j < H[d].hi[1]; ++j)
+        for (int i = H[d].lo[0]; i < H[d].hi[0]; ++i) {
+          int cl[3] = {i, j, k};
+          int cr[3] = {i, j, k};
+          cr[d] += 1;
+          double Uh[2][5];
+          for (int side = 0; side < 2; ++side) {
+            const int* cc = side == 0 ? cl : cr;
+            long xc = box_index(&X, cc[0], cc[1], cc[2]);
+            int m1[3] = {cc[0], cc[1], cc[2]};
+            int m2[3] = {cc[0], cc[1], cc[2]};
+            m1[t1] -= 1;
+            m2[t2] -= 1;
+            long x1 = box_index(&X, m1[0], m1[1], m1[2]); /* face c - 1/2 along t1 */
+            long x2 = box_index(&X, m2[0], m2[1], m2[2]); /* face c - 1/2 along t2 */
+            for (int f = 0; f < 5; ++f) {
+              double ustar = side == 0 ? Us[d][1][f][xc] : Us[d][0][f][xc];
+              Uh[side][f] = ustar + h1 * (Fs[t1][f][x1] - Fs[t1][f][xc]) +
+                            h2 * (Fs[t2][f][x2] - Fs[t2][f][xc]);
+            }
+          }
+          double ul[5], ur[5], fl[5];
+          for (int q = 0; q < 5; ++q) {
+            ul[q] = Uh[0][rot[d][q]];
+            ur[q] = Uh[1][rot[d][q]];
+          }
+          ref_riemann_flux(ul, ur, g, c->newton_tol, c->newton_max_iter, c->p_floor, fl, st);
+          long hb = box_index(&H[d], i, j, k);
+          for (int q = 0; q < 5; ++q) Fh[d][rot[d][q]][hb] = fl[q];
+          if (fhalf) {
+            long ai = alloc_index(c, i, j, k);
+            for (int q = 0; q < 5; ++q) fhalf[d * 5 + rot[d][q]][ai] = fl[q];
+          }
+        }
+  }
+
+  /* Step 5: conservative update, eq. (conserved_update), terms added left to right. */
+  double dtd[3] = {dt / dd[0], dt / dd[1], dt / dd[2]};
+  for (int k = R.lo[2]; k < R.hi[2]; ++k)
+    for (int j = R.lo[1]; j < R.hi[1]; ++j)
+      for (int i = R.lo[0]; i < R.hi[0]; ++i) {
+        long ai = alloc_index(c, i, j, k);
+        long rb = box_index(&R, i, j, k);
+        long hm[3], hp[3];
+        for (int d = 0; d < 3; ++d) {
+          int m[3] = {i, j, k};
+          m[d] -= 1;
+          hm[d] = box_index(&H[d], m[0], m[1], m[2]);
+          hp[d] = box_index(&H[d], i, j, k);
+        }
+        for (int f = 0; f < 5; ++f) {
+          double v = u[f][ai];
+          v = v + dtd[0] * (Fh[0][f][hm[0]] - Fh[0][f][hp[0]]);
+          v = v + dtd[1] * (Fh[1][f][hm[1]] - Fh[1][f][hp[1]]);
+          v = v + dtd[2] * (Fh[2][f][hm[2]] - Fh[2][f][hp[2]]);
+          out[f][rb] = v;
+        }
+      }
+
+  for (int f = 0; f < 5; ++f) free(W[f]);
+  for (int d = 0; d < 3; ++d) {
+    for (int f = 0; f < 5; ++f) {
+      free(Us[d][0][f]);
+      free(Us[d][1][f]);
+      free(Fs[d][f]);
+      free(Fh[d][f]);
+    }
+  }
+  return 0;
+}
+
+int ref_ctu_step(const ref_config* c, double* const u[5], double dt, ref_stats* st) {
+  ref_bc_fill(c, u);
+  int lo[3] = {0, 0, 0};
+  int hi[3] = {c->nx, c->ny, c->nz};
+  long nr = (long)c->nx * c->ny * c->nz;
+  double* out[5];
+  for (int f = 0; f < 5; ++f) out[f] = (double*)malloc(sizeof(double) * nr);
+  int rc = ref_ctu_update_box(c, u, dt, lo, hi, out, NULL, NULL, st);
+  if (rc == 0) {
+    for (int k = 0; k < c->nz; ++k)
+      for (int j = 0; j < c->ny; ++j)
+        for (int i = 0; i < c->nx; ++i) {
+          long ai = alloc_index(c, i, j, k);
+          long rb = (long)i + (long)c->nx * ((long)j + (long)c->ny * k);
+          for (int f = 0; f < 5; ++f) u[f][ai] = out[f][rb];
+        }
+  }
+  for (int f = 0; f < 5; ++f) free(out[f]);
+  return rc;
+}

@@ -1,0 +1,124 @@
+/*
+ * ctu_oracle.h -- CPU oracle for one unsplit CTU timestep of the 3D Euler equations
+ * (PPMC reconstruction with characteristic tracing + exact Riemann solver).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library against the
+ * paper (Schneider & Robertson, "Cholla", arXiv:1410.4194).  Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark load it.  The GPU product path never links,
+ * loads or calls it, and it shares no source, header, table or helper with the GPU library.
+ *
+ * Plain, serial, double precision C, built with -O2 -ffp-contract=off (no FMA contraction).
+ * Every function follows the algorithm steps in the order the paper states them; where the
+ * printed equations are garbled the reading taken is stated beside the code.
+ *
+ * Parity status: every function here is pinned by tests against closed forms, conservation
+ * laws, jump conditions, invariants or brute force (see tests/test_oracle_*.py).
+ *
+ * Layout: conserved state is structure-of-arrays, 5 fields (rho, rho*u, rho*v, rho*w, E),
+ * each over the allocated box (nx+6)(ny+6)(nz+6) with x fastest; real cell (i,j,k),
+ * 0 <= i < nx, sits at (i+3) + NX*((j+3) + NY*(k+3)), NX = nx+6, NY = ny+6.  Three ghost
+ * layers: the PPMC stencil reaches two cells to each side and the CTU transverse
+ * correction one more.
+ */
+#ifndef CTU_ORACLE_H
+#define CTU_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define REF_NG 3
+#define REF_BC_PERIODIC 0
+#define REF_BC_OUTFLOW 1
+
+typedef struct {
+  int nx, ny, nz;          /* real cells per axis, >= 1 */
+  double dx, dy, dz;       /* cell widths */
+  double gamma;            /* ratio of specific heats */
+  int bc[6];               /* x-, x+, y-, y+, z-, z+ : REF_BC_* */
+  double cfl;              /* Courant number C0 */
+  double newton_tol;       /* relative tolerance on the star-pressure change */
+  int newton_max_iter;     /* iteration cap of the Newton loop */
+  double p_floor;          /* pressure floor applied on every primitive conversion */
+} ref_config;
+
+typedef struct {
+  long solves;             /* Riemann problems solved */
+  long newton_iters;       /* Newton iterations summed over all solves */
+  long newton_capped;      /* solves that hit newton_max_iter without converging */
+  long p_floored;          /* primitive conversions whose pressure was raised to p_floor */
+} ref_stats;
+
+/* --- pointwise pieces (exposed for the pin tests) ------------------------------------ */
+
+/* Conserved (rho, m1, m2, m3, E) -> primitive (rho, v1, v2, v3, p) with p >= p_floor.
+ * Returns 1 when the floor was applied, else 0.  Ideal-gas EOS p = (gamma-1) rho e. */
+int ref_cons_to_prim(const double U[5], double gamma, double p_floor, double W[5]);
+void ref_prim_to_cons(const double W[5], double gamma, double U[5]);
+
+/* Projection of a primitive difference d = (drho, du, dv, dw, dp) onto the characteristic
+ * variables of a cell with density rho and sound speed a, and back. */
+void ref_char_project(const double d[5], double rho, double a, double xi[5]);
+void ref_char_unproject(const double xi[5], double rho, double a, double d[5]);
+
+/* Monotonized-central limited slope of cell c from the characteristic differences
+ * (the PLMC slope step that PPMC applies to cells c-1, c, c+1).  w_m, w_0, w_p are the
+ * rotated primitives (rho, normal v, two transverse v, p) of cells c-1, c, c+1. */
+void ref_plmc_slope(const double wm[5], const double w0[5], const double wp[5], double gamma,
+                    double dw[5]);
+
+/* PPMC: given rotated primitives of cells c-2..c+2 (w[0]..w[4]) and dtodx = dt/dx along
+ * the sweep, return the time-evolved face states W*_L (left face of cell c) and W*_R
+ * (right face of cell c), in rotated primitives.  If WLR_out is not NULL it receives the
+ * monotonized face values before tracing: WLR_out[0..4] = W_L, WLR_out[5..9] = W_R. */
+void ref_ppmc(const double w[5][5], double dtodx, double gamma, double WsL[5], double WsR[5],
+              double* WLR_out);
+
+/* Exact Riemann problem, star region: left (rho, u, p), right (rho, u, p).
+ * Returns the Newton iteration count; *capped = 1 if the cap was reached. */
+int ref_riemann_star(const double WL[3], const double WR[3], double gamma, double tol,
+                     int max_iter, double p_floor, double* pstar, double* ustar, int* capped);
+
+/* Exact Riemann solution sampled at similarity coordinate S = x/t.  The solver itself
+ * samples at S = 0; other S serve the exact-solution checks.  out = (rho, u, p).
+ * Returns 0 when the sample lies left of the contact, 1 when right. */
+int ref_riemann_sample(const double WL[3], const double WR[3], double pstar, double ustar,
+                       double gamma, double S, double out[3]);
+
+/* Wave speeds of the exact solution: out[0..4] = left wave head, left wave tail (equal to
+ * the shock speed for a shock), contact, right wave tail, right wave head. */
+void ref_riemann_wave_speeds(const double WL[3], const double WR[3], double pstar,
+                             double ustar, double gamma, double out[5]);
+
+/* Exact-solver interface flux from rotated conserved states UL, UR (normal momentum in
+ * slot 1).  F is in the same rotated order. */
+void ref_riemann_flux(const double UL[5], const double UR[5], double gamma, double tol,
+                      int max_iter, double p_floor, double F[5], ref_stats* st);
+
+/* --- whole-grid operations ----------------------------------------------------------- */
+
+/* Ghost fill: x faces, then y, then z, each over the full extent of the other two axes
+ * (ghosts included), so edge and corner ghosts end up consistent. */
+void ref_bc_fill(const ref_config* c, double* const u[5]);
+
+/* CFL time step over the real cells: C0 * min(dx/(|u|+a), dy/(|v|+a), dz/(|w|+a)). */
+double ref_compute_dt(const ref_config* c, double* const u[5]);
+
+/* u^{n+1} for the real cells of the box [lo, hi) (per-axis, real-cell coordinates) from a
+ * ghost-filled state u (not modified).  out[q] are compact arrays of the box, x fastest.
+ * Optional debug outputs (NULL to skip), each an array of 3*5 pointers (dir-major) to
+ * arrays over the allocated box, face i+1/2 stored at cell i:
+ *   fstar: first-stage fluxes F*, G*, H* on the extended range;
+ *   fhalf: CTU fluxes F^{n+1/2}, G^{n+1/2}, H^{n+1/2} on the faces of the box's cells.
+ * Returns 0 on success, -1 on an invalid box. */
+int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const int lo[3],
+                       const int hi[3], double* const out[5], double* const* fstar,
+                       double* const* fhalf, ref_stats* st);
+
+/* One full CTU step in place: ghost fill, then u^{n+1} on every real cell. */
+int ref_ctu_step(const ref_config* c, double* const u[5], double dt, ref_stats* st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,66 @@
+"""Mutation sweep: plants plausible mistakes in the oracle (on the CPU) and checks that the
+pin tests catch every one.  Each mutation is a garbled equation of the paper taken
+literally, a sign or index slip, or a dropped term.  Opt-in (about five minutes): run with
+CTU_MUTATIONS=1.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+REPO = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(REPO, "oracle", "ctu_oracle.c")
+
+M=[
+ ("xi0 printed sign", "xi[0] = 0.5 * (d[4] / a2 - rho * d[1] / a);", "xi[0] = -0.5 * (d[4] / a2 + rho * d[1] / a);"),
+ ("B printed alpha^p", "B[q] = ILm - ppm_IL(ap, dw[q], w6[q]);", "B[q] = 0.5 * am * (dw[q] + w6[q] * (1.0 + (2.0 / 3.0) * ap)) - ppm_IL(ap, dw[q], w6[q]);"),
+ ("D printed", "D[q] = IRp - ppm_IR(b0, dw[q], w6[q]);", "D[q] = IRp - 0.5 * b0 * (dw[q] + w6[q] * (1.0 + (2.0 / 3.0) * b0));"),
+ ("w6 printed", "w6[q] = 6.0 * c - 3.0 * (wl + wr);", "w6[q] = 6.0 * c - 3.0 * (wl - wr);"),
+ ("right fan +", "double c = 2.0 / (gamma + 1.0) * (ar - 0.5 * (gamma - 1.0) * (ur - S));", "double c = 2.0 / (gamma + 1.0) * (ar + 0.5 * (gamma - 1.0) * (ur - S));"),
+ ("transverse sign", "Uh[side][f] = ustar + h1 * (Fs[t1][f][x1] - Fs[t1][f][xc]) +", "Uh[side][f] = ustar - h1 * (Fs[t1][f][x1] - Fs[t1][f][xc]) +"),
+ ("transverse t2 drop", "h2 * (Fs[t2][f][x2] - Fs[t2][f][xc]);", "0.0 * (Fs[t2][f][x2] - Fs[t2][f][xc]);"),
+ ("update sign y", "v = v + dtd[1] * (Fh[1][f][hm[1]] - Fh[1][f][hp[1]]);", "v = v - dtd[1] * (Fh[1][f][hm[1]] - Fh[1][f][hp[1]]);"),
+ ("transverse vel side", "double vt = (u >= 0.0) ? WL[2] : WR[2];", "double vt = (u >= 0.0) ? WR[2] : WL[2];"),
+ ("minmod not MC", "if (2.0 * fabs(dl) < m) m = 2.0 * fabs(dl);", "if (fabs(dl) < m) m = fabs(dl);"),
+ ("Q30 swap", "ul[q] = Us[d][1][rot[d][q]][xc];\n            ur[q] = Us[d][0][rot[d][q]][xn];", "ul[q] = Us[d][0][rot[d][q]][xc];\n            ur[q] = Us[d][1][rot[d][q]][xn];"),
+ ("IR sign", "return 0.5 * beta * (dw - w6 * (1.0 - (2.0 / 3.0) * beta));", "return 0.5 * beta * (dw - w6 * (1.0 + (2.0 / 3.0) * beta));"),
+ ("IL half", "return 0.5 * alpha * (dw + w6 * (1.0 + (2.0 / 3.0) * alpha));", "return alpha * (dw + w6 * (1.0 + (2.0 / 3.0) * alpha));"),
+ ("shock density", "out[0] = rl * (pstar / pl + gm) / (pstar / pl * gm + 1.0);", "out[0] = rl * (pstar / pl + gm) / (pstar / pl + gm * 1.0);"),
+ ("rare density exp", "out[0] = rl * pow(pstar / pl, 1.0 / gamma);", "out[0] = rl * pow(pstar / pl, gamma);"),
+ ("ustar sign", "*ustar = 0.5 * (ul + ur + fr - fl);", "*ustar = 0.5 * (ul + ur + fl - fr);"),
+ ("energy flux no transverse KE", "double E = p / (gamma - 1.0) + 0.5 * rho * (u * u + vt * vt + wt * wt);", "double E = p / (gamma - 1.0) + 0.5 * rho * (u * u);"),
+ ("contact corr sign", "WsL[0] += E[0] - E[4] / a2;", "WsL[0] += E[0] + E[4] / a2;"),
+ ("acoustic corr u", "WsR[1] += 0.5 * (C[1] - C[4] / (a * rho));", "WsR[1] += 0.5 * (C[1] + C[4] / (a * rho));"),
+ ("lambda0 cond", "if (l0 > 0.0) {\n    WsR[0] += D[0]", "if (l0 < 0.0) {\n    WsR[0] += D[0]"),
+ ("parabola WR", "double wr = 0.5 * (wp[q] + wc[q]) - (dwp[q] - dwc[q]) / 6.0;", "double wr = 0.5 * (wp[q] + wc[q]) + (dwp[q] - dwc[q]) / 6.0;"),
+ ("steep fix", "if ((wr - wl) * (wl - (3.0 * c - 2.0 * wr)) < 0.0) wl = 3.0 * c - 2.0 * wr;", "if ((wr - wl) * (wl - (3.0 * c - 2.0 * wr)) < 0.0) wl = 2.0 * c - wr;"),
+ ("clamp dropped", "wl = fmin(hi, fmax(lo, wl));", "wl = wl;"),
+ ("dt direction", "double ty = c->dy / (fabs(W[2]) + a);", "double ty = c->dx / (fabs(W[2]) + a);"),
+ ("outflow mirror", "src = (q < 0) ? 0 : n[axis] - 1;", "src = (q < 0) ? -q - 1 : 2 * n[axis] - q - 1;"),
+ ("fprime rare exponent", "*df = 1.0 / (rho_k * a_k) * pow(p / p_k, -(gamma + 1.0) / (2.0 * gamma));", "*df = 1.0 / (rho_k * a_k) * pow(p / p_k, (gamma + 1.0) / (2.0 * gamma));"),
+ ("fan u", "out[1] = c + S;", "out[1] = c;"),
+ ("half dt transverse", "double h1 = 0.5 * dt / dd[t1];", "double h1 = dt / dd[t1];"),
+ ("own rho for slopes", "  double rho = w0[0];\n  double a = sound_speed(w0, gamma);", "  double rho = wm[0];\n  double a = sound_speed(wm, gamma);"),
+]
+
+PINS = ["tests/test_oracle_riemann.py", "tests/test_oracle_ppmc.py", "tests/test_oracle_step.py"]
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(not os.environ.get("CTU_MUTATIONS"), reason="opt-in: set CTU_MUTATIONS=1")
+@pytest.mark.parametrize("name,old,new", M, ids=[m[0] for m in M])
+def test_pins_catch_mutation(name, old, new, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, name
+    c = tmp_path / "mutant.c"
+    c.write_text(src.replace(old, new, 1))
+    so = tmp_path / "mutant.so"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-I" + os.path.join(REPO, "oracle"), str(c), "-o", str(so), "-lm"], check=True)
+    env = dict(os.environ, CTU_ORACLE_LIB=str(so))
+    env.pop("CTU_MUTATIONS", None)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] + PINS,
+                       cwd=REPO, env=env, capture_output=True, text=True, timeout=900)
+    assert r.returncode != 0, f"mutation '{name}' survived the pin tests"
