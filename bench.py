@@ -1,0 +1,179 @@
+"""Benchmark: CTU + PPMC + exact-Riemann steps on one MI355X.
+
+Workload: plain FP64 shock-cloud at 256^3 on [0,1]^3 (ambient rho = p = 1, gamma = 5/3,
+uniform cloud of radius 0.1 at (0.3, 0.5, 0.5) with density contrast 10, Mach-10 plane
+shock with the exact Rankine-Hugoniot post-shock state for x < 0.1, outflow boundaries,
+CFL 0.3), advanced with the device-side time step.  After `warmup` untimed steps, exactly
+`steps` steps are timed with the state resident in HBM; value = real cells x steps / time.
+The FP32 form (FP32 state, reconstruction and fluxes, FP64 Newton solve) is timed on the
+same workload and reported beside it.
+
+Prints one JSON line.  Per-kernel durations come from HIP events the library records on
+its own stream around every kernel of the timed steps.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+REPO = os.path.dirname(os.path.abspath(__file__))
+if REPO not in sys.path:
+    sys.path.insert(0, REPO)
+
+METRIC = "cell-updates/s at 256^3 (FP64 vs FP32 CTU+PPM+exact); serve p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# Algorithmic HBM bytes per unit of work of each kernel class (element size eb): the data the
+# kernel must read and write once, with stencil and neighbour reuse counted once.
+def _algorithmic_bytes(cls, eb):
+    table = {
+        "trace": 15 * eb,       # read 5 conserved fields of the cell, write 10 traced values
+        "riemann1": 15 * eb,    # read U*_L, U*_R (10), write 5 fluxes
+        "riemann2": 25 * eb,    # read U* (10), one face of each transverse flux (10), write 5
+        "update_dt": 25 * eb,   # read u (5) and three flux faces (15), write u (5)
+        "bc_fill": 10 * eb,     # read and write 5 fields of a ghost cell
+    }
+    return table[cls.rsplit("_", 1)[0] if not cls.startswith("update") else "update_dt"]
+
+
+def _units(cls, n):
+    nx, ny, nz = n
+    d = {"x": 0, "y": 1, "z": 2}
+    if cls.startswith("trace"):
+        return (nx + 2) * (ny + 2) * (nz + 2)
+    if cls.startswith("riemann1"):
+        e = [nx + 2, ny + 2, nz + 2]
+        e[d[cls[-1]]] -= 1
+        return e[0] * e[1] * e[2]
+    if cls.startswith("riemann2"):
+        e = [nx, ny, nz]
+        e[d[cls[-1]]] += 1
+        return e[0] * e[1] * e[2]
+    if cls.startswith("update"):
+        return nx * ny * nz
+    if cls.startswith("bc_fill"):
+        a = d[cls[-1]]
+        N = [nx + 6, ny + 6, nz + 6]
+        N[a] = 6
+        return N[0] * N[1] * N[2]
+    return 0
+
+
+def run_gpu(wl, prec, steps, warmup, ctu, torch):
+    g = ctu.Grid.from_workload(wl, prec=prec)
+    g.advance(warmup)
+    torch.cuda.synchronize()
+    g.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.advance(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile_read()
+    g.profile_enable(False)
+    status, flags, counters = g.check()
+    info = g.info()
+    return {"seconds": t1 - t0, "profile": prof, "status": status, "flags": flags,
+            "counters": counters, "t": info.t, "steps_done": info.steps}
+
+
+def roofline(prof, n, eb, steps_time_s):
+    # dominant kernel class by total time
+    cls, (ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
+    avg_s = ms / launches / 1e3
+    units = _units(cls, n)
+    bpu = _algorithmic_bytes(cls, eb)
+    achieved = bpu * units / avg_s / 1e9
+    return {"bound": "hbm", "kernel": cls, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "avg_launch_ms": round(ms / launches, 4), "units_per_launch": units,
+            "bytes_per_unit": bpu}
+
+
+def cpu_baseline(wl, seconds_target=15.0):
+    import numpy as np
+    import oracle as O
+
+    cfg = O.Config(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.gamma, bc=wl.bc, cfl=wl.cfl)
+    u = O.state_from_primitive(cfg, wl.W)
+    O.bc_fill(cfg, u)
+    dt = O.compute_dt(cfg, u)
+    # bounded sample: a 64^3 box around the shock front and the cloud's upwind edge
+    lo = (0, 96, 96)
+    hi = (64, 160, 160)
+    cells = 64 ** 3
+    t_total, reps = 0.0, 0
+    while t_total < seconds_target and reps < 10:
+        t0 = time.perf_counter()
+        O.update_box(cfg, u, dt, lo, hi)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    return {"value": round(cells * reps / t_total, 1), "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{reps} x one CTU step of the 64^3 box [0,64)x[96,160)x[96,160) of the "
+                      f"256^3 shock-cloud initial state, serial FP64 C oracle, {t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the CTU step shards by block decomposition, which this build does not run)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1410_4194_amd import ctu, workloads as WL
+
+    log(f"[bench] building shock-cloud {args.n}^3 initial state")
+    wl = WL.shock_cloud(args.n, steps=args.steps)
+    n = (wl.nx, wl.ny, wl.nz)
+    cells = wl.cells
+
+    log(f"[bench] FP64: warmup {args.warmup}, timed {args.steps} steps")
+    r64 = run_gpu(wl, ctu.FP64, args.steps, args.warmup, ctu, torch)
+    v64 = cells * args.steps / r64["seconds"]
+    log(f"[bench] FP64 {v64:.4g} cell-updates/s, {1e3 * r64['seconds'] / args.steps:.3f} ms/step")
+    for k, (ms, la) in sorted(r64["profile"].items(), key=lambda kv: -kv[1][0]):
+        log(f"[bench]   {k:12s} {ms / max(la, 1):8.4f} ms/launch  x{la}")
+
+    out = {
+        "metric": METRIC, "value": round(v64, 1), "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * r64["seconds"] / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"shock_cloud_{args.n}^3 Mach-10 chi-10 FP64 CFL 0.3",
+                   "cells": cells, "grid": list(n), "parallelism": "single GPU",
+                   "newton_caps": r64["counters"][1], "status": r64["status"]},
+        "roofline": roofline(r64["profile"], n, 8, r64["seconds"]),
+    }
+    if not args.no_fp32:
+        log(f"[bench] FP32 form: warmup {args.warmup}, timed {args.steps} steps")
+        r32 = run_gpu(wl, ctu.FP32, args.steps, args.warmup, ctu, torch)
+        v32 = cells * args.steps / r32["seconds"]
+        log(f"[bench] FP32 {v32:.4g} cell-updates/s")
+        out["fp32"] = {"value": round(v32, 1), "unit": "cell-updates/s",
+                       "ms_per_step": round(1e3 * r32["seconds"] / args.steps, 4),
+                       "roofline": roofline(r32["profile"], n, 4, r32["seconds"])}
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline: oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * ctu.h -- C ABI of the MI355X (gfx950) CTU library: one unsplit Corner Transport Upwind
+ * timestep of the 3D Euler equations on a static Cartesian mesh, with PPMC reconstruction
+ * and characteristic tracing, exact-Riemann interface fluxes and the CFL time-step
+ * reduction (Schneider & Robertson, "Cholla", arXiv:1410.4194: Sec. 2.1 and Appendices
+ * A.3 and B.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Return value: ctu_status; 0 is success, negative values are errors.  A short message for
+ *   the last error of the calling thread is available from ctu_last_error().
+ * Memory ownership: device memory belongs to the caller.  A grid uses two caller-allocated
+ *   device buffers (state and workspace) whose sizes ctu_workspace_bytes() reports; the
+ *   library allocates only small host-side handles.  Host arrays passed in are copied;
+ *   host arrays passed out are filled.
+ * Streams: every grid is bound to the HIP stream given at creation (NULL = the default
+ *   stream).  Entry points marked "async" only enqueue work; entry points marked "syncs"
+ *   wait for that stream.
+ * State layout: structure of arrays.  Field q in {0: rho, 1: rho*u, 2: rho*v, 3: rho*w,
+ *   4: E} (total energy per volume, E = p/(gamma-1) + rho V^2/2, Sec. 2) occupies a
+ *   contiguous array of the allocated box (nx+6)(ny+6)(nz+6), x fastest: real cell
+ *   (i, j, k), 0 <= i < nx, is element (i+3) + NX*((j+3) + NY*(k+3)), NX = nx+6,
+ *   NY = ny+6.  Consecutive fields start `field_stride` elements apart
+ *   (ctu_grid_info).  Three ghost layers per side: the PPMC stencil needs two, the CTU
+ *   transverse correction one more.  Element type is double (CTU_FP64) or float
+ *   (CTU_FP32).
+ * Host arrays for set/get are the real cells only, packed, x fastest, one array per field.
+ * Errors found on the device (non-finite or non-positive density / energy in an updated
+ *   state) are reported at the next syncing call of that grid as CTU_ENONPHYS.
+ */
+#ifndef CTU_H
+#define CTU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CTU_OK = 0,
+  CTU_EINVAL = -1,    /* invalid argument or configuration; nothing was launched */
+  CTU_ENOMEM = -2,    /* caller buffer too small */
+  CTU_EDEVICE = -3,   /* HIP runtime error (message in ctu_last_error) */
+  CTU_ENONPHYS = -4,  /* device found a non-physical state (see ctu_check flags) */
+  CTU_ENOCONV = -5,   /* Newton iteration reached its cap (counted, see ctu_check) */
+  CTU_EAGAIN = -6     /* batch has no free slot */
+} ctu_status;
+
+typedef enum { CTU_BC_PERIODIC = 0, CTU_BC_OUTFLOW = 1 } ctu_bc;
+typedef enum { CTU_FP64 = 0, CTU_FP32 = 1 } ctu_prec;
+
+/* Device error-word bits reported by ctu_check. */
+enum {
+  CTU_FLAG_NONFINITE = 1u << 0, /* an updated conserved value is NaN or infinite */
+  CTU_FLAG_DENSITY = 1u << 1,   /* an updated density is <= 0 */
+  CTU_FLAG_PFLOOR = 1u << 2,    /* a pressure was raised to p_floor (count in counters[0]) */
+  CTU_FLAG_NEWTON_CAP = 1u << 3 /* a Newton solve hit newton_max_iter (counters[1]) */
+};
+
+/* Grid configuration.  Sec. 2.1 (CTU), eq. calc_dt_3D (CFL), App. B.1 (Newton tolerance,
+ * pressure floor of Sec. 2.3.1). */
+typedef struct {
+  int32_t nx, ny, nz;      /* real cells per axis, each >= 1 */
+  double dx, dy, dz;       /* cell widths, > 0 */
+  double gamma;            /* ratio of specific heats, > 1 */
+  int32_t bc[6];           /* x-, x+, y-, y+, z-, z+ : ctu_bc; periodic must pair */
+  int32_t prec;            /* ctu_prec.  CTU_FP32 stores state, reconstruction and fluxes
+                              in float and keeps the Newton star-pressure solve in double */
+  double cfl;              /* Courant number C0, 0 < cfl < 0.5 (six-solve CTU limit) */
+  double newton_tol;       /* relative change that stops the Newton loop (1e-6) */
+  int32_t newton_max_iter; /* Newton iteration cap (50) */
+  double p_floor;          /* pressure floor on every primitive conversion (1e-20) */
+} ctu_config;
+
+typedef struct ctu_grid ctu_grid;
+typedef struct ctu_batch ctu_batch;
+
+typedef struct {
+  int64_t alloc_cells;   /* (nx+6)(ny+6)(nz+6) */
+  int64_t field_stride;  /* elements between consecutive fields of the state buffer */
+  int32_t elem_bytes;    /* 8 (FP64) or 4 (FP32) */
+  double t;              /* simulation time accumulated by step/advance (syncs) */
+  int64_t steps;         /* steps taken (syncs) */
+} ctu_grid_info;
+
+/* Fill *cfg with the defaults: cfl 0.3, newton_tol 1e-6, newton_max_iter 50,
+ * p_floor 1e-20, FP64, periodic, gamma 5/3, unit cells, 1x1x1. */
+ctu_status ctu_config_default(ctu_config* cfg);
+
+/* Bytes of the two device buffers a grid with this configuration needs.  Either output
+ * pointer may be NULL.  No device work. */
+ctu_status ctu_workspace_bytes(const ctu_config* cfg, size_t* state_bytes, size_t* work_bytes);
+
+/* Create a grid over caller-owned device buffers d_state (>= state_bytes) and d_work
+ * (>= work_bytes, 256-byte aligned), bound to hip_stream (hipStream_t, NULL = default).
+ * Validates cfg (CTU_EINVAL) and sizes (CTU_ENOMEM); launches nothing. */
+ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, size_t work_bytes,
+                           void* hip_stream, ctu_grid** out);
+ctu_status ctu_grid_destroy(ctu_grid* g);
+ctu_status ctu_grid_info_get(ctu_grid* g, ctu_grid_info* info); /* syncs */
+
+/* Upload conserved real-cell values: h_fields[5] host arrays of nx*ny*nz elements of the
+ * grid's element type.  Resets t and the step count.  Syncs. */
+ctu_status ctu_set_state(ctu_grid* g, const void* const h_fields[5]);
+
+/* Upload primitive real-cell values (rho, u, v, w, p) as host double arrays and convert
+ * them to conserved variables on the device with the ideal-gas EOS (Sec. 2).  Syncs. */
+ctu_status ctu_set_primitive(ctu_grid* g, const double* const h_fields[5]);
+
+/* Download conserved real-cell values into h_fields[5] (grid element type).  Syncs;
+ * returns CTU_ENONPHYS if the device error word is set (the data is still copied). */
+ctu_status ctu_get_state(ctu_grid* g, void* const h_fields[5]);
+
+/* CFL time step of the current state (eq. calc_dt_3D over the real cells:
+ * cfl * min(dx/(|u|+a), dy/(|v|+a), dz/(|w|+a))).  Syncs. */
+ctu_status ctu_compute_dt(ctu_grid* g, double* dt);
+
+/* One CTU step with time step dt > 0: ghost fill, reconstruction + tracing and first
+ * Riemann solve per direction, transverse correction and second Riemann solve per
+ * direction, conservative update (eq. conserved_update), and the reduction that yields the
+ * next CFL time step.  Async. */
+ctu_status ctu_step(ctu_grid* g, double dt);
+
+/* nsteps CTU steps with the time step computed on the device from the state each step
+ * starts with, the last one clipped so that t does not pass t_end (steps after t_end are
+ * no-ops).  No host synchronization; safe to capture in a HIP graph.  Async. */
+ctu_status ctu_advance(ctu_grid* g, int32_t nsteps, double t_end);
+
+/* Sums over the real cells of the five conserved fields, accumulated in double in a fixed
+ * order (bitwise reproducible).  Syncs. */
+ctu_status ctu_totals(ctu_grid* g, double out[5]);
+
+/* Read and clear the device error word and counters: counters[0] pressure-floor hits,
+ * [1] Newton solves that hit the cap, [2] non-physical updated cells, [3] reserved.
+ * Returns CTU_ENONPHYS if non-physical bits are set, CTU_ENOCONV if only the Newton cap
+ * was hit, else CTU_OK.  Syncs. */
+ctu_status ctu_check(ctu_grid* g, uint32_t* flags, uint64_t counters[4]);
+
+/* Debug access to the fluxes of the last step (host double arrays over the allocated box,
+ * face i+1/2 stored at cell i, x fastest): which = 0 first-stage fluxes F*, G*, H*;
+ * which = 1 CTU fluxes F^{n+1/2}, G^{n+1/2}, H^{n+1/2}; dir 0/1/2 = x/y/z;
+ * h_fields[5] arrays of alloc_cells doubles.  Only values on the ranges the step computes
+ * are meaningful.  Syncs. */
+ctu_status ctu_debug_fluxes(ctu_grid* g, int32_t which, int32_t dir, double* const h_fields[5]);
+
+/* ---- Measurement -------------------------------------------------------------------------
+ * Per-kernel timing for measurement tools: while enabled, every kernel a step launches is
+ * bracketed by HIP events recorded on the grid's stream, and elapsed times accumulate per
+ * kernel class.  ctu_profile_enable(g, 1) starts a fresh accumulation (syncs), 0 stops and
+ * frees it.  ctu_profile_read fills up to max_classes entries of ms[] (total milliseconds)
+ * and launches[] (launch counts) in the order of ctu_profile_name(i), and sets *count to
+ * the number of classes (syncs).  ctu_profile_name returns "" past the last class. */
+ctu_status ctu_profile_enable(ctu_grid* g, int32_t enable);
+ctu_status ctu_profile_read(ctu_grid* g, int32_t max_classes, double* ms, int64_t* launches,
+                            int32_t* count);
+const char* ctu_profile_name(int32_t k);
+
+/* ---- Batches: many independent grids advanced together ----------------------------------
+ * A batch owns max_slots slots.  ctu_batch_submit places a grid in a free slot (CTU_EAGAIN
+ * when none is free) with a step budget and an end time; ctu_batch_run advances every
+ * running slot by up to `steps` steps (each grid with its own device-side time step); a slot
+ * is DONE when its grid reached t_end or used its step budget, and FAILED if a syncing check
+ * found a non-physical state.  ctu_batch_poll reports a ticket's state; a DONE or FAILED
+ * ticket frees its slot when polled.  Grids must stay alive while submitted. */
+enum { CTU_TICKET_QUEUED = 0, CTU_TICKET_RUNNING = 1, CTU_TICKET_DONE = 2, CTU_TICKET_FAILED = 3,
+       CTU_TICKET_UNKNOWN = -1 };
+ctu_status ctu_batch_create(int32_t max_slots, void* hip_stream, ctu_batch** out);
+ctu_status ctu_batch_submit(ctu_batch* b, ctu_grid* g, int32_t nsteps, double t_end,
+                            uint64_t* ticket);
+ctu_status ctu_batch_run(ctu_batch* b, int32_t steps); /* async */
+ctu_status ctu_batch_poll(ctu_batch* b, uint64_t ticket, int32_t* state, double* t_now); /* syncs */
+ctu_status ctu_batch_destroy(ctu_batch* b);
+
+/* Message for the last failing call on this thread (valid until the next call). */
+const char* ctu_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,539 @@
+// ctu_runtime.cpp -- host runtime behind the C ABI of include/ctu.h: configuration checks,
+// workspace carving, stream-ordered launch sequences, host<->device transfers, error words,
+// and the batch scheduler.  Device memory is always the caller's.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctu.h"
+#include "ctu_kernels.hpp"
+
+using ctu::DevScalars;
+using ctu::GridParams;
+using ctu::NG;
+
+namespace {
+
+thread_local std::string g_err;
+
+ctu_status fail(ctu_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+ctu_status hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return CTU_EDEVICE;
+}
+
+#define HIP_TRY(expr, where)                  \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+constexpr size_t kScalarsOffset = 0;
+constexpr size_t kPartialOffset = 4096;
+constexpr int kTotalsBlocks = 1024;
+constexpr size_t kTotalsOutOffset = kPartialOffset + sizeof(double) * 5 * kTotalsBlocks;
+constexpr size_t kHeaderBytes = 65536;
+constexpr int kFieldsPerGrid = 60;  // ustar 3x10, fstar 3x5, fhalf 3x5
+
+size_t elem_bytes(int prec) { return prec == CTU_FP32 ? 4 : 8; }
+
+long long alloc_cells(const ctu_config& c) {
+  return (long long)(c.nx + 2 * NG) * (c.ny + 2 * NG) * (c.nz + 2 * NG);
+}
+
+long long field_stride(const ctu_config& c) {
+  long long n = alloc_cells(c);
+  return (n + 63) / 64 * 64;
+}
+
+ctu_status validate(const ctu_config* c) {
+  if (!c) return fail(CTU_EINVAL, "null config");
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(CTU_EINVAL, "cell counts must be >= 1");
+  if (!(c->dx > 0 && c->dy > 0 && c->dz > 0)) return fail(CTU_EINVAL, "cell widths must be > 0");
+  if (!(c->gamma > 1.0)) return fail(CTU_EINVAL, "gamma must be > 1");
+  if (!(c->cfl > 0.0 && c->cfl < 0.5)) return fail(CTU_EINVAL, "cfl must lie in (0, 0.5)");
+  if (!(c->newton_tol > 0.0)) return fail(CTU_EINVAL, "newton_tol must be > 0");
+  if (c->newton_max_iter < 1) return fail(CTU_EINVAL, "newton_max_iter must be >= 1");
+  if (!(c->p_floor > 0.0)) return fail(CTU_EINVAL, "p_floor must be > 0");
+  if (c->prec != CTU_FP64 && c->prec != CTU_FP32) return fail(CTU_EINVAL, "unknown precision");
+  for (int a = 0; a < 3; ++a) {
+    int lo = c->bc[2 * a], hi = c->bc[2 * a + 1];
+    if ((lo != CTU_BC_PERIODIC && lo != CTU_BC_OUTFLOW) || (hi != CTU_BC_PERIODIC && hi != CTU_BC_OUTFLOW))
+      return fail(CTU_EINVAL, "unknown boundary type");
+    if ((lo == CTU_BC_PERIODIC) != (hi == CTU_BC_PERIODIC))
+      return fail(CTU_EINVAL, "periodic boundaries must pair");
+  }
+  const long long ncell = (long long)c->nx * c->ny * c->nz;
+  if (ncell > (1LL << 31)) return fail(CTU_EINVAL, "grid too large");
+  return CTU_OK;
+}
+
+GridParams make_params(const ctu_config& c) {
+  GridParams P;
+  P.n[0] = c.nx;
+  P.n[1] = c.ny;
+  P.n[2] = c.nz;
+  for (int a = 0; a < 3; ++a) P.N[a] = P.n[a] + 2 * NG;
+  P.stride = field_stride(c);
+  P.dx[0] = c.dx;
+  P.dx[1] = c.dy;
+  P.dx[2] = c.dz;
+  P.gamma = c.gamma;
+  P.newton_tol = c.newton_tol;
+  P.newton_max_iter = c.newton_max_iter;
+  P.p_floor = c.p_floor;
+  P.cfl = c.cfl;
+  const double g = c.gamma;
+  P.gm1 = g - 1.0;
+  P.z_exp = (g - 1.0) / (2.0 * g);
+  P.inv_gamma = 1.0 / g;
+  P.two_over_gm1 = 2.0 / (g - 1.0);
+  P.two_over_gp1 = 2.0 / (g + 1.0);
+  P.gm1_over_gp1 = (g - 1.0) / (g + 1.0);
+  P.shock_a = (g + 1.0) / (2.0 * g);
+  P.shock_b = (g - 1.0) / (2.0 * g);
+  double e = 2.0 / (g - 1.0);
+  double r = std::nearbyint(e);
+  P.fan_int_exp = (std::fabs(e - r) < 1e-12 && r >= 1.0 && r <= 16.0) ? (int)r : 0;
+  return P;
+}
+
+}  // namespace
+
+struct ctu_grid {
+  ctu_config cfg;
+  GridParams P;
+  hipStream_t stream;
+  char* d_state;
+  char* d_work;
+  size_t work_bytes;
+  bool dt_valid;  // device dt_next_bits holds the CFL bound of the current state
+  ctu::Profiler* prof = nullptr;  // per-kernel timing when enabled
+  DevScalars* scalars() const { return reinterpret_cast<DevScalars*>(d_work + kScalarsOffset); }
+  double* partial() const { return reinterpret_cast<double*>(d_work + kPartialOffset); }
+  double* totals_out() const { return reinterpret_cast<double*>(d_work + kTotalsOutOffset); }
+  char* fields() const { return d_work + kHeaderBytes; }
+  size_t fbytes() const { return (size_t)P.stride * elem_bytes(cfg.prec); }
+  template <typename T>
+  ctu::StepBuffers<T> buffers() const {
+    ctu::StepBuffers<T> b;
+    b.u = reinterpret_cast<T*>(d_state);
+    T* f = reinterpret_cast<T*>(fields());
+    for (int d = 0; d < 3; ++d) b.ustar[d] = f + (size_t)(10 * d) * P.stride;
+    for (int d = 0; d < 3; ++d) b.fstar[d] = f + (size_t)(30 + 5 * d) * P.stride;
+    for (int d = 0; d < 3; ++d) b.fhalf[d] = f + (size_t)(45 + 5 * d) * P.stride;
+    b.scalars = scalars();
+    return b;
+  }
+};
+
+namespace {
+
+ctu_status step_impl(ctu_grid* g) {
+  hipError_t e = g->cfg.prec == CTU_FP64
+                     ? ctu::launch_step<double>(g->buffers<double>(), g->P, g->cfg.bc, g->stream,
+                                                g->prof)
+                     : ctu::launch_step<float>(g->buffers<float>(), g->P, g->cfg.bc, g->stream,
+                                               g->prof);
+  if (e != hipSuccess) return hip_fail(e, "step launch");
+  HIP_TRY(ctu::launch_end_step(g->scalars(), g->stream), "end_step");
+  g->dt_valid = true;
+  return CTU_OK;
+}
+
+ctu_status ensure_dt(ctu_grid* g) {
+  if (g->dt_valid) return CTU_OK;
+  hipError_t e = g->cfg.prec == CTU_FP64
+                     ? ctu::launch_dt<double>(reinterpret_cast<double*>(g->d_state), g->P,
+                                              g->scalars(), g->stream)
+                     : ctu::launch_dt<float>(reinterpret_cast<float*>(g->d_state), g->P,
+                                             g->scalars(), g->stream);
+  if (e != hipSuccess) return hip_fail(e, "dt launch");
+  g->dt_valid = true;
+  return CTU_OK;
+}
+
+ctu_status reset_scalars(ctu_grid* g) {
+  DevScalars s;
+  std::memset(&s, 0, sizeof(s));
+  s.dt_next_bits = 0x7ff0000000000000ull;
+  HIP_TRY(hipMemcpyAsync(g->scalars(), &s, sizeof(s), hipMemcpyHostToDevice, g->stream), "reset");
+  HIP_TRY(hipStreamSynchronize(g->stream), "reset sync");
+  g->dt_valid = false;
+  return CTU_OK;
+}
+
+ctu_status read_scalars(ctu_grid* g, DevScalars* s) {
+  HIP_TRY(hipMemcpyAsync(s, g->scalars(), sizeof(*s), hipMemcpyDeviceToHost, g->stream), "read scalars");
+  HIP_TRY(hipStreamSynchronize(g->stream), "sync");
+  return CTU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ctu_last_error(void) { return g_err.c_str(); }
+
+ctu_status ctu_config_default(ctu_config* c) {
+  if (!c) return fail(CTU_EINVAL, "null config");
+  std::memset(c, 0, sizeof(*c));
+  c->nx = c->ny = c->nz = 1;
+  c->dx = c->dy = c->dz = 1.0;
+  c->gamma = 5.0 / 3.0;
+  for (int i = 0; i < 6; ++i) c->bc[i] = CTU_BC_PERIODIC;
+  c->prec = CTU_FP64;
+  c->cfl = 0.3;
+  c->newton_tol = 1e-6;
+  c->newton_max_iter = 50;
+  c->p_floor = 1e-20;
+  return CTU_OK;
+}
+
+ctu_status ctu_workspace_bytes(const ctu_config* cfg, size_t* state_bytes, size_t* work_bytes) {
+  ctu_status s = validate(cfg);
+  if (s != CTU_OK) return s;
+  const size_t eb = elem_bytes(cfg->prec);
+  const long long stride = field_stride(*cfg);
+  if (state_bytes) *state_bytes = (size_t)5 * stride * eb;
+  if (work_bytes) *work_bytes = kHeaderBytes + (size_t)kFieldsPerGrid * stride * eb;
+  return CTU_OK;
+}
+
+ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, size_t work_bytes,
+                           void* hip_stream, ctu_grid** out) {
+  if (!out) return fail(CTU_EINVAL, "null output handle");
+  *out = nullptr;
+  ctu_status s = validate(cfg);
+  if (s != CTU_OK) return s;
+  if (!d_state || !d_work) return fail(CTU_EINVAL, "null device buffer");
+  if (reinterpret_cast<uintptr_t>(d_work) % 256 != 0 || reinterpret_cast<uintptr_t>(d_state) % 256 != 0)
+    return fail(CTU_EINVAL, "device buffers must be 256-byte aligned");
+  size_t need_state = 0, need_work = 0;
+  ctu_workspace_bytes(cfg, &need_state, &need_work);
+  if (work_bytes < need_work)
+    return fail(CTU_ENOMEM, "workspace too small: need " + std::to_string(need_work) + " bytes");
+  ctu_grid* g = new ctu_grid();
+  g->cfg = *cfg;
+  g->P = make_params(*cfg);
+  g->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  g->d_state = reinterpret_cast<char*>(d_state);
+  g->d_work = reinterpret_cast<char*>(d_work);
+  g->work_bytes = work_bytes;
+  g->dt_valid = false;
+  s = reset_scalars(g);
+  if (s != CTU_OK) {
+    delete g;
+    return s;
+  }
+  *out = g;
+  return CTU_OK;
+}
+
+ctu_status ctu_grid_destroy(ctu_grid* g) {
+  if (!g) return fail(CTU_EINVAL, "null grid");
+  (void)hipStreamSynchronize(g->stream);
+  delete g->prof;
+  delete g;
+  return CTU_OK;
+}
+
+ctu_status ctu_profile_enable(ctu_grid* g, int32_t enable) {
+  if (!g) return fail(CTU_EINVAL, "null grid");
+  if (enable) {
+    if (!g->prof) g->prof = new ctu::Profiler();
+    HIP_TRY(hipStreamSynchronize(g->stream), "profile sync");
+    g->prof->reset();
+  } else if (g->prof) {
+    HIP_TRY(hipStreamSynchronize(g->stream), "profile sync");
+    delete g->prof;
+    g->prof = nullptr;
+  }
+  return CTU_OK;
+}
+
+ctu_status ctu_profile_read(ctu_grid* g, int32_t max_classes, double* ms, int64_t* launches,
+                            int32_t* count) {
+  if (!g || !count) return fail(CTU_EINVAL, "null argument");
+  *count = ctu::K_NUM_CLASSES;
+  if (!g->prof) return fail(CTU_EINVAL, "profiling not enabled");
+  HIP_TRY(g->prof->collect(), "profile collect");
+  for (int k = 0; k < ctu::K_NUM_CLASSES && k < max_classes; ++k) {
+    if (ms) ms[k] = g->prof->ms[k];
+    if (launches) launches[k] = g->prof->launches[k];
+  }
+  return CTU_OK;
+}
+
+const char* ctu_profile_name(int32_t k) { return ctu::kernel_class_name(k); }
+
+ctu_status ctu_grid_info_get(ctu_grid* g, ctu_grid_info* info) {
+  if (!g || !info) return fail(CTU_EINVAL, "null argument");
+  DevScalars s;
+  ctu_status st = read_scalars(g, &s);
+  if (st != CTU_OK) return st;
+  info->alloc_cells = alloc_cells(g->cfg);
+  info->field_stride = g->P.stride;
+  info->elem_bytes = (int32_t)elem_bytes(g->cfg.prec);
+  info->t = s.t;
+  info->steps = s.steps;
+  return CTU_OK;
+}
+
+ctu_status ctu_set_state(ctu_grid* g, const void* const h_fields[5]) {
+  if (!g || !h_fields) return fail(CTU_EINVAL, "null argument");
+  for (int f = 0; f < 5; ++f)
+    if (!h_fields[f]) return fail(CTU_EINVAL, "null host field");
+  const size_t ncell = (size_t)g->cfg.nx * g->cfg.ny * g->cfg.nz;
+  const size_t eb = elem_bytes(g->cfg.prec);
+  char* staging = g->fields();
+  for (int f = 0; f < 5; ++f)
+    HIP_TRY(hipMemcpyAsync(staging + f * ncell * eb, h_fields[f], ncell * eb, hipMemcpyHostToDevice,
+                           g->stream),
+            "set_state copy");
+  hipError_t e = g->cfg.prec == CTU_FP64
+                     ? ctu::launch_scatter<double>(reinterpret_cast<double*>(staging),
+                                                   reinterpret_cast<double*>(g->d_state), g->P, g->stream)
+                     : ctu::launch_scatter<float>(reinterpret_cast<float*>(staging),
+                                                  reinterpret_cast<float*>(g->d_state), g->P, g->stream);
+  if (e != hipSuccess) return hip_fail(e, "scatter");
+  return reset_scalars(g);
+}
+
+ctu_status ctu_set_primitive(ctu_grid* g, const double* const h_fields[5]) {
+  if (!g || !h_fields) return fail(CTU_EINVAL, "null argument");
+  for (int f = 0; f < 5; ++f)
+    if (!h_fields[f]) return fail(CTU_EINVAL, "null host field");
+  const size_t ncell = (size_t)g->cfg.nx * g->cfg.ny * g->cfg.nz;
+  double* staging = reinterpret_cast<double*>(g->fields());
+  for (int f = 0; f < 5; ++f)
+    HIP_TRY(hipMemcpyAsync(staging + f * ncell, h_fields[f], ncell * sizeof(double),
+                           hipMemcpyHostToDevice, g->stream),
+            "set_primitive copy");
+  hipError_t e = g->cfg.prec == CTU_FP64
+                     ? ctu::launch_prim_to_cons<double>(staging, reinterpret_cast<double*>(g->d_state),
+                                                        g->P, g->stream)
+                     : ctu::launch_prim_to_cons<float>(staging, reinterpret_cast<float*>(g->d_state),
+                                                       g->P, g->stream);
+  if (e != hipSuccess) return hip_fail(e, "prim_to_cons");
+  return reset_scalars(g);
+}
+
+ctu_status ctu_get_state(ctu_grid* g, void* const h_fields[5]) {
+  if (!g || !h_fields) return fail(CTU_EINVAL, "null argument");
+  for (int f = 0; f < 5; ++f)
+    if (!h_fields[f]) return fail(CTU_EINVAL, "null host field");
+  const size_t ncell = (size_t)g->cfg.nx * g->cfg.ny * g->cfg.nz;
+  const size_t eb = elem_bytes(g->cfg.prec);
+  char* staging = g->fields();
+  hipError_t e = g->cfg.prec == CTU_FP64
+                     ? ctu::launch_gather<double>(reinterpret_cast<double*>(g->d_state),
+                                                  reinterpret_cast<double*>(staging), g->P, g->stream)
+                     : ctu::launch_gather<float>(reinterpret_cast<float*>(g->d_state),
+                                                 reinterpret_cast<float*>(staging), g->P, g->stream);
+  if (e != hipSuccess) return hip_fail(e, "gather");
+  for (int f = 0; f < 5; ++f)
+    HIP_TRY(hipMemcpyAsync(h_fields[f], staging + f * ncell * eb, ncell * eb, hipMemcpyDeviceToHost,
+                           g->stream),
+            "get_state copy");
+  // the staging area overlaps the traced states: the next step's dt stays valid
+  DevScalars s;
+  ctu_status st = read_scalars(g, &s);
+  if (st != CTU_OK) return st;
+  if (s.flags & (CTU_FLAG_NONFINITE | CTU_FLAG_DENSITY))
+    return fail(CTU_ENONPHYS, "non-physical state flagged on the device");
+  return CTU_OK;
+}
+
+ctu_status ctu_compute_dt(ctu_grid* g, double* dt) {
+  if (!g || !dt) return fail(CTU_EINVAL, "null argument");
+  ctu_status st = ensure_dt(g);
+  if (st != CTU_OK) return st;
+  DevScalars s;
+  st = read_scalars(g, &s);
+  if (st != CTU_OK) return st;
+  double bound;
+  std::memcpy(&bound, &s.dt_next_bits, sizeof(bound));
+  *dt = g->cfg.cfl * bound;
+  if (!(std::isfinite(*dt) && *dt > 0.0)) return fail(CTU_ENONPHYS, "no finite CFL time step");
+  return CTU_OK;
+}
+
+ctu_status ctu_step(ctu_grid* g, double dt) {
+  if (!g) return fail(CTU_EINVAL, "null grid");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CTU_EINVAL, "dt must be finite and > 0");
+  HIP_TRY(ctu::launch_set_dt(g->scalars(), dt, g->stream), "set_dt");
+  return step_impl(g);
+}
+
+ctu_status ctu_advance(ctu_grid* g, int32_t nsteps, double t_end) {
+  if (!g) return fail(CTU_EINVAL, "null grid");
+  if (nsteps < 0) return fail(CTU_EINVAL, "nsteps must be >= 0");
+  ctu_status st = ensure_dt(g);
+  if (st != CTU_OK) return st;
+  for (int32_t n = 0; n < nsteps; ++n) {
+    HIP_TRY(ctu::launch_begin_step(g->scalars(), g->cfg.cfl, t_end, g->stream), "begin_step");
+    st = step_impl(g);
+    if (st != CTU_OK) return st;
+  }
+  return CTU_OK;
+}
+
+ctu_status ctu_totals(ctu_grid* g, double out[5]) {
+  if (!g || !out) return fail(CTU_EINVAL, "null argument");
+  hipError_t e = g->cfg.prec == CTU_FP64
+                     ? ctu::launch_totals<double>(reinterpret_cast<double*>(g->d_state), g->P,
+                                                  g->partial(), kTotalsBlocks, g->totals_out(), g->stream)
+                     : ctu::launch_totals<float>(reinterpret_cast<float*>(g->d_state), g->P,
+                                                 g->partial(), kTotalsBlocks, g->totals_out(), g->stream);
+  if (e != hipSuccess) return hip_fail(e, "totals");
+  HIP_TRY(hipMemcpyAsync(out, g->totals_out(), 5 * sizeof(double), hipMemcpyDeviceToHost, g->stream),
+          "totals copy");
+  HIP_TRY(hipStreamSynchronize(g->stream), "totals sync");
+  return CTU_OK;
+}
+
+ctu_status ctu_check(ctu_grid* g, uint32_t* flags, uint64_t counters[4]) {
+  if (!g) return fail(CTU_EINVAL, "null grid");
+  DevScalars s;
+  ctu_status st = read_scalars(g, &s);
+  if (st != CTU_OK) return st;
+  if (flags) *flags = s.flags;
+  if (counters)
+    for (int i = 0; i < 4; ++i) counters[i] = s.counters[i];
+  // clear flags and counters on the device
+  DevScalars z = s;
+  z.flags = 0;
+  for (int i = 0; i < 4; ++i) z.counters[i] = 0;
+  HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(g->scalars()) + offsetof(DevScalars, flags),
+                         reinterpret_cast<char*>(&z) + offsetof(DevScalars, flags),
+                         offsetof(DevScalars, steps) - offsetof(DevScalars, flags),
+                         hipMemcpyHostToDevice, g->stream),
+          "check clear");
+  HIP_TRY(hipStreamSynchronize(g->stream), "check sync");
+  if (s.flags & (CTU_FLAG_NONFINITE | CTU_FLAG_DENSITY))
+    return fail(CTU_ENONPHYS, "non-physical state flagged on the device");
+  if (s.flags & CTU_FLAG_NEWTON_CAP) return fail(CTU_ENOCONV, "Newton iteration cap reached");
+  return CTU_OK;
+}
+
+ctu_status ctu_debug_fluxes(ctu_grid* g, int32_t which, int32_t dir, double* const h_fields[5]) {
+  if (!g || !h_fields || which < 0 || which > 1 || dir < 0 || dir > 2)
+    return fail(CTU_EINVAL, "bad argument");
+  const size_t n = (size_t)alloc_cells(g->cfg);
+  const size_t eb = elem_bytes(g->cfg.prec);
+  const size_t base = (which == 0 ? 30 : 45) + 5 * dir;
+  std::vector<char> tmp(n * eb);
+  for (int f = 0; f < 5; ++f) {
+    HIP_TRY(hipMemcpyAsync(tmp.data(), g->fields() + (base + f) * g->fbytes(), n * eb,
+                           hipMemcpyDeviceToHost, g->stream),
+            "debug copy");
+    HIP_TRY(hipStreamSynchronize(g->stream), "debug sync");
+    if (eb == 8) {
+      std::memcpy(h_fields[f], tmp.data(), n * 8);
+    } else {
+      const float* src = reinterpret_cast<const float*>(tmp.data());
+      for (size_t i = 0; i < n; ++i) h_fields[f][i] = src[i];
+    }
+  }
+  return CTU_OK;
+}
+
+// ---- batches ---------------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct ctu_batch {
+  struct Slot {
+    bool used = false;
+    uint64_t ticket = 0;
+    ctu_grid* grid = nullptr;
+    int32_t steps_left = 0;
+    double t_end = 0.0;
+    int32_t state = CTU_TICKET_UNKNOWN;
+  };
+  std::vector<Slot> slots;
+  hipStream_t stream = nullptr;
+  uint64_t next_ticket = 1;
+};
+
+extern "C" {
+
+ctu_status ctu_batch_create(int32_t max_slots, void* hip_stream, ctu_batch** out) {
+  if (!out || max_slots < 1) return fail(CTU_EINVAL, "bad argument");
+  ctu_batch* b = new ctu_batch();
+  b->slots.resize(max_slots);
+  b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  *out = b;
+  return CTU_OK;
+}
+
+ctu_status ctu_batch_submit(ctu_batch* b, ctu_grid* g, int32_t nsteps, double t_end,
+                            uint64_t* ticket) {
+  if (!b || !g || !ticket || nsteps < 0) return fail(CTU_EINVAL, "bad argument");
+  for (auto& s : b->slots) {
+    if (s.used) continue;
+    s.used = true;
+    s.ticket = b->next_ticket++;
+    s.grid = g;
+    s.steps_left = nsteps;
+    s.t_end = t_end;
+    s.state = CTU_TICKET_RUNNING;
+    *ticket = s.ticket;
+    return CTU_OK;
+  }
+  return fail(CTU_EAGAIN, "no free batch slot");
+}
+
+ctu_status ctu_batch_run(ctu_batch* b, int32_t steps) {
+  if (!b || steps < 0) return fail(CTU_EINVAL, "bad argument");
+  for (auto& s : b->slots) {
+    if (!s.used || s.state != CTU_TICKET_RUNNING || s.steps_left <= 0) continue;
+    int32_t k = steps < s.steps_left ? steps : s.steps_left;
+    ctu_status st = ctu_advance(s.grid, k, s.t_end);
+    if (st != CTU_OK) {
+      s.state = CTU_TICKET_FAILED;
+      continue;
+    }
+    s.steps_left -= k;
+  }
+  return CTU_OK;
+}
+
+ctu_status ctu_batch_poll(ctu_batch* b, uint64_t ticket, int32_t* state, double* t_now) {
+  if (!b || !state) return fail(CTU_EINVAL, "bad argument");
+  for (auto& s : b->slots) {
+    if (!s.used || s.ticket != ticket) continue;
+    DevScalars sc;
+    ctu_status st = read_scalars(s.grid, &sc);
+    if (st != CTU_OK) return st;
+    if (t_now) *t_now = sc.t;
+    if (s.state == CTU_TICKET_RUNNING) {
+      if (sc.flags & (CTU_FLAG_NONFINITE | CTU_FLAG_DENSITY))
+        s.state = CTU_TICKET_FAILED;
+      else if (sc.t >= s.t_end || s.steps_left <= 0)
+        s.state = CTU_TICKET_DONE;
+    }
+    *state = s.state;
+    if (s.state == CTU_TICKET_DONE || s.state == CTU_TICKET_FAILED) s = ctu_batch::Slot();
+    return CTU_OK;
+  }
+  *state = CTU_TICKET_UNKNOWN;
+  return CTU_OK;
+}
+
+ctu_status ctu_batch_destroy(ctu_batch* b) {
+  if (!b) return fail(CTU_EINVAL, "null batch");
+  delete b;
+  return CTU_OK;
+}
+
+}  // extern "C"

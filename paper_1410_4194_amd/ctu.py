@@ -1,0 +1,281 @@
+"""ctypes binding over the C ABI of ``libctu.so`` (include/ctu.h).
+
+Marshalling only: every step of the timestep runs in the HIP kernels of the library.
+PyTorch provides the device buffers (caller-owned, as the ABI requires) and the stream.
+Importing this module raises if the library has not been built; creating a grid raises if
+no GPU is visible.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libctu.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, ENOCONV, EAGAIN = 0, -1, -2, -3, -4, -5, -6
+BC_PERIODIC, BC_OUTFLOW = 0, 1
+FP64, FP32 = 0, 1
+FLAG_NONFINITE, FLAG_DENSITY, FLAG_PFLOOR, FLAG_NEWTON_CAP = 1, 2, 4, 8
+TICKET_QUEUED, TICKET_RUNNING, TICKET_DONE, TICKET_FAILED, TICKET_UNKNOWN = 0, 1, 2, 3, -1
+
+EXPORTS = [
+    "ctu_config_default", "ctu_workspace_bytes", "ctu_grid_create", "ctu_grid_destroy",
+    "ctu_grid_info_get", "ctu_set_state", "ctu_set_primitive", "ctu_get_state",
+    "ctu_compute_dt", "ctu_step", "ctu_advance", "ctu_totals", "ctu_check",
+    "ctu_debug_fluxes", "ctu_batch_create", "ctu_batch_submit", "ctu_batch_run",
+    "ctu_batch_poll", "ctu_batch_destroy", "ctu_last_error", "ctu_profile_enable",
+    "ctu_profile_read", "ctu_profile_name",
+]
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("gamma", C.c_double), ("bc", C.c_int32 * 6), ("prec", C.c_int32),
+                ("cfl", C.c_double), ("newton_tol", C.c_double),
+                ("newton_max_iter", C.c_int32), ("p_floor", C.c_double)]
+
+
+class GridInfo(C.Structure):
+    _fields_ = [("alloc_cells", C.c_int64), ("field_stride", C.c_int64),
+                ("elem_bytes", C.c_int32), ("t", C.c_double), ("steps", C.c_int64)]
+
+
+class CtuError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ctu error {status}: {msg}")
+        self.status = status
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run `python -m paper_1410_4194_amd.build`)")
+    lib = C.CDLL(LIB_PATH)
+    vp, sz = C.c_void_p, C.c_size_t
+    st = C.c_int
+    sig = {
+        "ctu_config_default": ([C.POINTER(Config)], st),
+        "ctu_workspace_bytes": ([C.POINTER(Config), C.POINTER(sz), C.POINTER(sz)], st),
+        "ctu_grid_create": ([C.POINTER(Config), vp, vp, sz, vp, C.POINTER(vp)], st),
+        "ctu_grid_destroy": ([vp], st),
+        "ctu_grid_info_get": ([vp, C.POINTER(GridInfo)], st),
+        "ctu_set_state": ([vp, C.POINTER(vp)], st),
+        "ctu_set_primitive": ([vp, C.POINTER(vp)], st),
+        "ctu_get_state": ([vp, C.POINTER(vp)], st),
+        "ctu_compute_dt": ([vp, C.POINTER(C.c_double)], st),
+        "ctu_step": ([vp, C.c_double], st),
+        "ctu_advance": ([vp, C.c_int32, C.c_double], st),
+        "ctu_totals": ([vp, C.POINTER(C.c_double)], st),
+        "ctu_check": ([vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)], st),
+        "ctu_debug_fluxes": ([vp, C.c_int32, C.c_int32, C.POINTER(vp)], st),
+        "ctu_batch_create": ([C.c_int32, vp, C.POINTER(vp)], st),
+        "ctu_batch_submit": ([vp, vp, C.c_int32, C.c_double, C.POINTER(C.c_uint64)], st),
+        "ctu_batch_run": ([vp, C.c_int32], st),
+        "ctu_batch_poll": ([vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double)], st),
+        "ctu_batch_destroy": ([vp], st),
+        "ctu_last_error": ([], C.c_char_p),
+        "ctu_profile_enable": ([vp, C.c_int32], st),
+        "ctu_profile_read": ([vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                              C.POINTER(C.c_int32)], st),
+        "ctu_profile_name": ([C.c_int32], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int, allow=()) -> int:
+    if status != OK and status not in allow:
+        raise CtuError(status, lib.ctu_last_error().decode())
+    return status
+
+
+def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64, cfl=0.3,
+                newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20) -> Config:
+    c = Config()
+    lib.ctu_config_default(C.byref(c))
+    c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
+    c.dx, c.dy, c.dz = float(dx), float(dy), float(dz)
+    c.gamma = float(gamma)
+    for i in range(6):
+        c.bc[i] = int(bc[i])
+    c.prec = int(prec)
+    c.cfl = float(cfl)
+    c.newton_tol = float(newton_tol)
+    c.newton_max_iter = int(newton_max_iter)
+    c.p_floor = float(p_floor)
+    return c
+
+
+def workspace_bytes(cfg: Config):
+    s, w = C.c_size_t(), C.c_size_t()
+    _check(lib.ctu_workspace_bytes(C.byref(cfg), C.byref(s), C.byref(w)))
+    return s.value, w.value
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the CTU library runs on an MI355X (gfx950) only")
+    return torch
+
+
+class Grid:
+    """One grid: device state and workspace held as torch uint8 tensors."""
+
+    def __init__(self, cfg: Config, device: str = "cuda", stream=None):
+        torch = _torch()
+        self.cfg = cfg
+        self.n = (cfg.nx, cfg.ny, cfg.nz)
+        self.dtype = np.float64 if cfg.prec == FP64 else np.float32
+        sb, wb = workspace_bytes(cfg)
+        self.state_bytes, self.work_bytes = sb, wb
+        self.device = torch.device(device)
+        self.state = torch.empty(sb, dtype=torch.uint8, device=self.device)
+        self.work = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(lib.ctu_grid_create(C.byref(cfg), C.c_void_p(self.state.data_ptr()),
+                                   C.c_void_p(self.work.data_ptr()), C.c_size_t(wb),
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def from_workload(cls, wl, prec=FP64, **kw) -> "Grid":
+        cfg = make_config(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.gamma, wl.bc, prec,
+                          kw.pop("cfl", wl.cfl), **kw)
+        g = cls(cfg)
+        g.set_primitive(wl.W)
+        return g
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.ctu_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- data ------------------------------------------------------------------------------
+    def _host_ptrs(self, arrays):
+        arr = (C.c_void_p * 5)()
+        for f in range(5):
+            arr[f] = arrays[f].ctypes.data
+        return arr
+
+    def set_state(self, U: np.ndarray) -> None:
+        """Conserved real-cell values, shape (5, nz, ny, nx)."""
+        fields = [np.ascontiguousarray(U[f], dtype=self.dtype) for f in range(5)]
+        _check(lib.ctu_set_state(self.handle, self._host_ptrs(fields)))
+
+    def set_primitive(self, W: np.ndarray) -> None:
+        """Primitive real-cell values (rho, u, v, w, p), shape (5, nz, ny, nx), float64."""
+        fields = [np.ascontiguousarray(W[f], dtype=np.float64) for f in range(5)]
+        _check(lib.ctu_set_primitive(self.handle, self._host_ptrs(fields)))
+
+    def get_state(self, allow_nonphys: bool = False) -> np.ndarray:
+        nx, ny, nz = self.n
+        out = np.empty((5, nz, ny, nx), dtype=self.dtype)
+        fields = [out[f] for f in range(5)]
+        _check(lib.ctu_get_state(self.handle, self._host_ptrs(fields)),
+               allow=(ENONPHYS,) if allow_nonphys else ())
+        return out
+
+    def debug_fluxes(self, which: int, direction: int) -> np.ndarray:
+        """Fluxes of the last step over the allocated box (5, NZ, NY, NX), float64."""
+        nx, ny, nz = self.n
+        out = np.empty((5, nz + 6, ny + 6, nx + 6), dtype=np.float64)
+        _check(lib.ctu_debug_fluxes(self.handle, which, direction,
+                                    self._host_ptrs([out[f] for f in range(5)])))
+        return out
+
+    # -- stepping -------------------------------------------------------------------------
+    def compute_dt(self) -> float:
+        dt = C.c_double()
+        _check(lib.ctu_compute_dt(self.handle, C.byref(dt)))
+        return dt.value
+
+    def step(self, dt: float) -> None:
+        _check(lib.ctu_step(self.handle, float(dt)))
+
+    def advance(self, nsteps: int, t_end: float = float("inf")) -> None:
+        _check(lib.ctu_advance(self.handle, int(nsteps), float(t_end)))
+
+    def totals(self) -> np.ndarray:
+        out = (C.c_double * 5)()
+        _check(lib.ctu_totals(self.handle, out))
+        return np.array(out[:])
+
+    def check(self):
+        flags = C.c_uint32()
+        cnt = (C.c_uint64 * 4)()
+        status = lib.ctu_check(self.handle, C.byref(flags), cnt)
+        return status, flags.value, list(cnt)
+
+    def profile_enable(self, on: bool = True) -> None:
+        _check(lib.ctu_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel class: (total ms, launches)} accumulated since profile_enable."""
+        n = 32
+        ms = (C.c_double * n)()
+        la = (C.c_int64 * n)()
+        cnt = C.c_int32()
+        _check(lib.ctu_profile_read(self.handle, n, ms, la, C.byref(cnt)))
+        return {lib.ctu_profile_name(k).decode(): (ms[k], la[k]) for k in range(cnt.value)}
+
+    def info(self) -> GridInfo:
+        info = GridInfo()
+        _check(lib.ctu_grid_info_get(self.handle, C.byref(info)))
+        return info
+
+
+class Batch:
+    """Slots of independent grids advanced together (see ctu_batch_* in ctu.h)."""
+
+    def __init__(self, max_slots: int, stream=None):
+        torch = _torch()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib.ctu_batch_create(int(max_slots), C.c_void_p(self.stream.cuda_stream),
+                                    C.byref(h)))
+        self.handle = h
+
+    def submit(self, grid: Grid, nsteps: int, t_end: float = float("inf")) -> Optional[int]:
+        t = C.c_uint64()
+        s = _check(lib.ctu_batch_submit(self.handle, grid.handle, int(nsteps), float(t_end),
+                                        C.byref(t)), allow=(EAGAIN,))
+        return None if s == EAGAIN else t.value
+
+    def run(self, steps: int) -> None:
+        _check(lib.ctu_batch_run(self.handle, int(steps)))
+
+    def poll(self, ticket: int):
+        state = C.c_int32()
+        t = C.c_double()
+        _check(lib.ctu_batch_poll(self.handle, C.c_uint64(ticket), C.byref(state), C.byref(t)))
+        return state.value, t.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.ctu_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -33,3 +33,18 @@ def run_oracle(wl, t_end=None, steps=None, cfg=None):
         t += dt
         n += 1
     return cfg, u, t, n
+
+
+def rel_l1(gpu: np.ndarray, ref: np.ndarray, gamma: float) -> np.ndarray:
+    """Per-field relative L1 difference of two conserved real-cell states (5, ...):
+    err_f = sum |q_gpu - q_ref| / sum s_f with s = rho for mass, rho (|V| + a) for the
+    momenta and E for energy (scales taken from the reference)."""
+    ref = np.asarray(ref, dtype=np.float64)
+    gpu = np.asarray(gpu, dtype=np.float64)
+    rho = ref[0]
+    V2 = (ref[1] ** 2 + ref[2] ** 2 + ref[3] ** 2) / rho ** 2
+    p = np.maximum((gamma - 1.0) * (ref[4] - 0.5 * rho * V2), 1e-300)
+    a = np.sqrt(gamma * p / rho)
+    smom = rho * (np.sqrt(V2) + a)
+    scales = [rho, smom, smom, smom, np.abs(ref[4])]
+    return np.array([np.abs(gpu[f] - ref[f]).sum() / scales[f].sum() for f in range(5)])

@@ -1,0 +1,82 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point that
+include/ctu.h declares, and validates configurations on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+REPO = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(REPO, "include", "ctu.h")
+LIB = os.path.join(REPO, "paper_1410_4194_amd", "libctu.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:ctu_status|const char\*)\s+(ctu_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def ctu():
+    if not os.path.exists(LIB):
+        pytest.fail("libctu.so not built (python -m paper_1410_4194_amd.build)")
+    from paper_1410_4194_amd import ctu as m
+    return m
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    assert len(names) >= 20
+    for must in ("ctu_grid_create", "ctu_step", "ctu_compute_dt", "ctu_advance",
+                 "ctu_batch_submit", "ctu_batch_poll"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(ctu):
+    lib = C.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(ctu.EXPORTS) == declared_functions()
+
+
+def test_workspace_bytes_and_validation(ctu):
+    cfg = ctu.make_config(256, 256, 256, 1 / 256, 1 / 256, 1 / 256, 5 / 3, (1,) * 6)
+    sb, wb = ctu.workspace_bytes(cfg)
+    na = 262 ** 3
+    stride = (na + 63) // 64 * 64
+    assert sb == 5 * stride * 8
+    assert wb >= 60 * stride * 8
+    cfg32 = ctu.make_config(8, 8, 8, 1, 1, 1, 1.4, prec=ctu.FP32)
+    sb32, _ = ctu.workspace_bytes(cfg32)
+    assert sb32 == 5 * ((14 ** 3 + 63) // 64 * 64) * 4
+    bad = [
+        dict(nx=0), dict(dx=0.0), dict(gamma=1.0), dict(cfl=0.5), dict(cfl=0.0),
+        dict(bc=(0, 1, 0, 0, 0, 0)), dict(bc=(2, 2, 0, 0, 0, 0)), dict(prec=7),
+        dict(newton_max_iter=0), dict(newton_tol=0.0), dict(p_floor=0.0),
+    ]
+    for b in bad:
+        args = dict(nx=8, ny=8, nz=8, dx=1.0, dy=1.0, dz=1.0, gamma=1.4)
+        args.update({k: v for k, v in b.items() if k in args})
+        extra = {k: v for k, v in b.items() if k not in args}
+        c = ctu.make_config(**args, **extra)
+        with pytest.raises(ctu.CtuError) as ei:
+            ctu.workspace_bytes(c)
+        assert ei.value.status == ctu.EINVAL
+
+
+def test_grid_create_rejects_small_workspace(ctu):
+    cfg = ctu.make_config(8, 8, 8, 1, 1, 1, 1.4)
+    h = C.c_void_p()
+    st = ctu.lib.ctu_grid_create(C.byref(cfg), C.c_void_p(256), C.c_void_p(512), C.c_size_t(1024),
+                                 None, C.byref(h))
+    assert st == ctu.ENOMEM and h.value is None
+    assert b"workspace" in ctu.lib.ctu_last_error()
+
+
+def test_product_path_requires_gpu(ctu):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    cfg = ctu.make_config(8, 8, 8, 1, 1, 1, 1.4)
+    with pytest.raises(RuntimeError, match="no GPU"):
+        ctu.Grid(cfg)

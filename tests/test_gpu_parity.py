@@ -1,0 +1,241 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+One step from the same seeded input and the same dt, compared field by field with the
+relative L1 metric of tests.common.rel_l1: FP64 <= 1e-12, FP32 <= 1e-5.  Per-pass checks
+compare the first-stage and CTU fluxes on every face the step computes.  Workloads span
+several tiles and ragged sizes, both boundary types, and the degenerate shapes (1-cell
+axes, tiny grids).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle as O
+from paper_1410_4194_amd import workloads as WL
+from tests.common import oracle_config, oracle_state, rel_l1, run_oracle
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctu():
+    from paper_1410_4194_amd import ctu as _ctu
+    return _ctu
+
+
+def _announce(*parts):
+    print("[gpu-test]", *parts, flush=True)
+    sys.stdout.flush()
+
+
+def _one_step(ctu, wl, prec, dt=None):
+    cfg = oracle_config(wl)
+    u = oracle_state(wl, cfg)
+    if dt is None:
+        dt = O.compute_dt(cfg, u)
+    _announce(wl.name, "prec", prec, "cells", wl.cells, "dt", dt)
+    g = ctu.Grid.from_workload(wl, prec=prec)
+    g.step(dt)
+    gpu = g.get_state()
+    ref_u = u.copy()
+    O.step(cfg, ref_u, dt)
+    return g, gpu, O.real(cfg, ref_u), cfg, u, dt
+
+
+CASES = [
+    ("rough_periodic_37x11x9", lambda: WL.random_state(37, 11, 9, seed=11, spacing=(1.0, 0.5, 0.4))),
+    ("rough_outflow_20x17x13", lambda: WL.random_state(20, 17, 13, seed=12, bc=(1,) * 6)),
+    ("rough_mixed_70x6x5", lambda: WL.random_state(70, 6, 5, seed=13, bc=(1, 1, 0, 0, 1, 1))),
+    ("smooth_supersonic_24x20x18", lambda: WL.random_state(24, 20, 18, seed=14, rough=False, mach=3.0)),
+    ("sod_128x16x16", lambda: WL.sod(128, 16, 16)),
+    ("sod_y_8x64x8", lambda: WL.sod(64, 8, 8, axis=1)),
+    ("shock_cloud_48", lambda: WL.shock_cloud(48, steps=1)),
+    ("kh_33x27x19", lambda: WL.kelvin_helmholtz(33, 27, 19)),
+    ("one_cell_axes_64x1x1", lambda: WL.random_state(64, 1, 1, seed=15)),
+    ("one_cell_axis_1x9x7", lambda: WL.random_state(1, 9, 7, seed=16, bc=(0, 0, 1, 1, 1, 1))),
+    ("tiny_2x2x2", lambda: WL.random_state(2, 2, 2, seed=17)),
+    ("single_cell", lambda: WL.random_state(1, 1, 1, seed=18)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_one_step_fp64(ctu, name, make):
+    wl = make()
+    g, gpu, ref, cfg, u0, dt = _one_step(ctu, wl, ctu.FP64)
+    err = rel_l1(gpu, ref, wl.gamma)
+    assert err.max() <= TOL64, (name, err)
+    status, flags, counters = g.check()
+    assert status == ctu.OK, (flags, counters)
+
+
+@pytest.mark.parametrize("name,make", CASES[:8], ids=[c[0] for c in CASES[:8]])
+def test_one_step_fp32(ctu, name, make):
+    wl = make()
+    g, gpu, ref, cfg, u0, dt = _one_step(ctu, wl, ctu.FP32)
+    assert gpu.dtype == np.float32
+    err = rel_l1(gpu, ref, wl.gamma)
+    assert err.max() <= TOL32, (name, err)
+
+
+def _flux_err(gpu_f, ref_f):
+    mask = np.isfinite(ref_f[0])
+    errs = []
+    for f in range(5):
+        num = np.abs(gpu_f[f][mask] - ref_f[f][mask]).sum()
+        den = np.abs(ref_f[f][mask]).sum()
+        errs.append(0.0 if num == 0.0 else num / max(den, 1e-300))
+    return np.array(errs), int(mask.sum())
+
+
+@pytest.mark.parametrize("name,make", [CASES[0], CASES[2], CASES[6]], ids=[CASES[0][0], CASES[2][0], CASES[6][0]])
+def test_per_pass_fluxes_fp64(ctu, name, make):
+    wl = make()
+    cfg = oracle_config(wl)
+    u = oracle_state(wl, cfg)
+    dt = O.compute_dt(cfg, u)
+    O.bc_fill(cfg, u)
+    _, _, fstar, fhalf = O.update_box(cfg, u, dt, (0, 0, 0), (wl.nx, wl.ny, wl.nz), want_fluxes=True)
+    _announce(name, "per-pass")
+    g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    g.step(dt)
+    for d in range(3):
+        e1, n1 = _flux_err(g.debug_fluxes(0, d), fstar[d])
+        e2, n2 = _flux_err(g.debug_fluxes(1, d), fhalf[d])
+        assert n1 > 0 and n2 > 0
+        assert e1.max() <= TOL64, ("F*", d, e1)
+        assert e2.max() <= TOL64, ("F^{n+1/2}", d, e2)
+
+
+def test_compute_dt_matches_oracle(ctu):
+    for wl in (WL.random_state(19, 13, 7, seed=21), WL.shock_cloud(32, steps=1), WL.sod(64, 4, 4)):
+        cfg = oracle_config(wl)
+        ref = O.compute_dt(cfg, oracle_state(wl, cfg))
+        for prec, tol in ((ctu.FP64, 1e-14), (ctu.FP32, 1e-6)):
+            g = ctu.Grid.from_workload(wl, prec=prec)
+            assert g.compute_dt() == pytest.approx(ref, rel=tol)
+
+
+def test_totals_are_exact_sums(ctu):
+    wl = WL.random_state(40, 30, 20, seed=22)
+    g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    g.step(g.compute_dt())
+    st = g.get_state()
+    tot = g.totals()
+    for f in range(5):
+        exact = math.fsum(st[f].ravel())
+        scale = math.fsum(np.abs(st[f]).ravel())
+        assert abs(tot[f] - exact) <= 1e-13 * scale
+
+
+def test_periodic_conservation_on_gpu(ctu):
+    wl = WL.kelvin_helmholtz(48, 40, 32)
+    g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    before = g.totals()
+    g.advance(20)
+    after = g.totals()
+    st = g.get_state()
+    for f in range(5):
+        scale = math.fsum(np.abs(st[f]).ravel())
+        assert abs(after[f] - before[f]) <= 1e-13 * max(scale, 1.0), f
+
+
+def test_determinism_bitwise(ctu):
+    wl = WL.shock_cloud(40, steps=1)
+    out = []
+    for _ in range(2):
+        g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+        g.advance(5)
+        out.append(g.get_state())
+    assert np.array_equal(out[0], out[1])
+
+
+def test_advance_equals_host_loop(ctu):
+    """Device-side dt (ctu_advance) gives bitwise the same steps as compute_dt + step."""
+    wl = WL.sod(64, 4, 4)
+    g1 = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    g1.advance(10, t_end=0.2)
+    g2 = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    for _ in range(10):
+        g2.step(g2.compute_dt())
+    assert np.array_equal(g1.get_state(), g2.get_state())
+    assert g1.info().t == g2.info().t and g1.info().steps == 10
+
+
+def test_sod_to_t02_matches_oracle_and_exact(ctu):
+    """BJ config 1: 3D Sod 128x16x16, outflow x / periodic y,z, to t = 0.2."""
+    wl = WL.sod(128, 16, 16)
+    g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    g.advance(10000, t_end=0.2)
+    info = g.info()
+    assert info.t == pytest.approx(0.2, abs=1e-14)
+    st = g.get_state()
+    cols = st[0].reshape(-1, 128)
+    assert np.all(cols == cols[0])  # every (y, z) column identical
+    wl1 = WL.sod(128, 1, 1)
+    cfg1, u1, t1, n1 = run_oracle(wl1, t_end=0.2)
+    assert n1 == info.steps
+    ref = O.real(cfg1, u1)[:, 0, 0, :]
+    err = rel_l1(st[:, 0, 0, :], ref, 1.4)
+    assert err.max() <= 1e-10, err
+    x = (np.arange(128) + 0.5) / 128
+    ex = O.exact_solution((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4, (x - 0.5) / 0.2)
+    assert np.mean(np.abs(st[0, 0, 0] - ex[0])) < 0.003
+
+
+def test_nonphysical_state_is_reported(ctu):
+    wl = WL.random_state(16, 8, 8, seed=23)
+    g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    U = g.get_state()
+    U[0, 3, 4, 5] = np.nan
+    g.set_state(U)
+    g.step(1e-3)
+    status, flags, counters = g.check()
+    assert status == ctu.ENONPHYS and flags & ctu.FLAG_NONFINITE and counters[2] > 0
+    status, flags, counters = g.check()  # cleared
+    assert flags == 0
+
+
+def test_newton_cap_is_counted(ctu):
+    wl = WL.sod(32, 2, 2)
+    from paper_1410_4194_amd.ctu import make_config, Grid
+    cfg = make_config(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.gamma, wl.bc,
+                      newton_max_iter=1)
+    g = Grid(cfg)
+    g.set_primitive(wl.W)
+    g.step(g.compute_dt())
+    status, flags, counters = g.check()
+    assert status == ctu.ENOCONV and counters[1] > 0
+
+
+def test_batch_matches_solo(ctu):
+    wls = WL.kh_batch(count=5, edges=(16, 24, 32), steps=8)
+    solo = []
+    for wl in wls:
+        g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+        g.advance(8)
+        solo.append(g.get_state())
+    b = ctu.Batch(max_slots=3)
+    grids = [ctu.Grid.from_workload(wl, prec=ctu.FP64) for wl in wls]
+    pending = list(range(len(grids)))
+    tickets = {}
+    results = {}
+    while pending or tickets:
+        while pending:
+            t = b.submit(grids[pending[0]], 8)
+            if t is None:
+                break
+            tickets[t] = pending.pop(0)
+        b.run(3)
+        for t in list(tickets):
+            state, _ = b.poll(t)
+            if state in (ctu.TICKET_DONE, ctu.TICKET_FAILED):
+                assert state == ctu.TICKET_DONE
+                i = tickets.pop(t)
+                results[i] = grids[i].get_state()
+    for i in range(len(wls)):
+        assert np.array_equal(results[i], solo[i])
