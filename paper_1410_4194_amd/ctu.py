@@ -4,6 +4,10 @@ Marshalling only: every step of the timestep runs in the HIP kernels of the libr
 PyTorch provides the device buffers (caller-owned, as the ABI requires) and the stream.
 Importing this module raises if the library has not been built; creating a grid raises if
 no GPU is visible.
+
+torch is imported before the library is loaded so that the process holds a single HIP
+runtime: torch ships its own libamdhip64 with the same soname as the system one, and
+libctu.so then binds to the copy torch already loaded.
 """
 from __future__ import annotations
 
@@ -12,6 +16,7 @@ import os
 from typing import Optional, Sequence
 
 import numpy as np
+import torch  # noqa: F401  (must precede loading libctu.so, see above)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libctu.so")
