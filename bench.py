@@ -23,7 +23,20 @@ if REPO not in sys.path:
 
 METRIC = "cell-updates/s at 256^3 (FP64 vs FP32 CTU+PPM+exact); serve p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP64_VECTOR_PEAK_TFLOPS = 78.6    # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_shock_cloud_256.json")
+
+# Algorithmic floating-point operations per unit of work, counted operation by operation
+# along the paper's formulas (+, -, *, /, sqrt, pow, min, max, abs each count one), for the
+# common path: subsonic cell, one Newton iteration with both sides on the rarefaction branch.
+#   primitive conversion 12, slope step (App. A.2) 103, parabola + monotonicity + tracing
+#   (App. A.3) 419, two conversions to conserved 24  -> one cell's traced states: 558
+#   exact Riemann solve (App. B.1): primitives 24, sound speeds 6, PVRS 9, TSRS 19, one
+#   Newton iteration 32, final f 12, u* 4, sampling 6, flux 16 -> 128
+#   transverse correction (eq. transverse_evolution) of one cell: 30
+#   update (eq. conserved_update) 45 + CFL bound of the new state 26 -> 71
+FLOPS_PER_UNIT = {"sweep1": 558 + 128, "sweep2": 558 + 30 + 128, "update": 71}
 
 
 def log(*a):
@@ -32,32 +45,35 @@ def log(*a):
 
 # Algorithmic HBM bytes per unit of work of each kernel class (element size eb): the data the
 # kernel must read and write once, with stencil and neighbour reuse counted once.
+#   sweep1_d: read the 5 conserved fields of a cell, write the 5 first-stage fluxes of a face
+#   sweep2_d: read 5 conserved fields and one face of each transverse first-stage flux (10),
+#             write the 5 CTU fluxes of a face
+#   update:   read u (5) and one face of each CTU flux (15), write u (5)
+#   bc_fill:  read and write the 5 fields of a ghost cell
+BYTES_PER_UNIT = {"sweep1": 10, "sweep2": 20, "update": 25, "bc": 10, "dt": 1}
+
+
 def _algorithmic_bytes(cls, eb):
-    table = {
-        "trace": 15 * eb,       # read 5 conserved fields of the cell, write 10 traced values
-        "riemann1": 15 * eb,    # read U*_L, U*_R (10), write 5 fluxes
-        "riemann2": 25 * eb,    # read U* (10), one face of each transverse flux (10), write 5
-        "update_dt": 25 * eb,   # read u (5) and three flux faces (15), write u (5)
-        "bc_fill": 10 * eb,     # read and write 5 fields of a ghost cell
-    }
-    return table[cls.rsplit("_", 1)[0] if not cls.startswith("update") else "update_dt"]
+    if cls == "dt_final":
+        return 8
+    return BYTES_PER_UNIT[cls.split("_")[0]] * eb
 
 
 def _units(cls, n):
     nx, ny, nz = n
     d = {"x": 0, "y": 1, "z": 2}
-    if cls.startswith("trace"):
-        return (nx + 2) * (ny + 2) * (nz + 2)
-    if cls.startswith("riemann1"):
+    if cls.startswith("sweep1"):
         e = [nx + 2, ny + 2, nz + 2]
-        e[d[cls[-1]]] -= 1
+        e[d[cls[-1]]] = n[d[cls[-1]]] + 1
         return e[0] * e[1] * e[2]
-    if cls.startswith("riemann2"):
+    if cls.startswith("sweep2"):
         e = [nx, ny, nz]
         e[d[cls[-1]]] += 1
         return e[0] * e[1] * e[2]
-    if cls.startswith("update"):
+    if cls == "update":
         return nx * ny * nz
+    if cls == "dt_final":
+        return (nx * ny * nz + 255) // 256
     if cls.startswith("bc_fill"):
         a = d[cls[-1]]
         N = [nx + 6, ny + 6, nz + 6]
@@ -84,17 +100,55 @@ def run_gpu(wl, prec, steps, warmup, ctu, torch):
             "counters": counters, "t": info.t, "steps_done": info.steps}
 
 
-def roofline(prof, n, eb, steps_time_s):
-    # dominant kernel class by total time
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(REPO, "paper_1410_4194_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(cls, prec_name):
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE counters, scaled
+    by the plain-copy calibration; None when the kernels changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != _source_hash():
+        return None
+    k = t.get(prec_name, {}).get(cls)
+    if not k:
+        return None
+    return round(k["fetch_kib"] * t["fetch_scale"] * 1024 + k["write_kib"] * t["write_scale"] * 1024)
+
+
+def roofline(prof, n, eb, prec_name):
+    # dominant kernel class by total time over the timed steps
     cls, (ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
     avg_s = ms / launches / 1e3
     units = _units(cls, n)
-    bpu = _algorithmic_bytes(cls, eb)
-    achieved = bpu * units / avg_s / 1e9
-    return {"bound": "hbm", "kernel": cls, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-            "avg_launch_ms": round(ms / launches, 4), "units_per_launch": units,
-            "bytes_per_unit": bpu}
+    kind = cls.split("_")[0]
+    out = {"kernel": cls, "avg_launch_ms": round(ms / launches, 4), "launches": launches,
+           "units_per_launch": units, "traffic": _traffic(cls, prec_name)}
+    if kind in FLOPS_PER_UNIT and kind != "update":
+        peak = FP64_VECTOR_PEAK_TFLOPS if eb == 8 else FP32_VECTOR_PEAK_TFLOPS
+        achieved = FLOPS_PER_UNIT[kind] * units / avg_s / 1e12
+        out.update({"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                    "flops_per_unit": FLOPS_PER_UNIT[kind],
+                    "algorithmic_bytes_per_launch": _algorithmic_bytes(cls, eb) * units})
+    else:
+        bpu = _algorithmic_bytes(cls, eb)
+        achieved = bpu * units / avg_s / 1e9
+        out.update({"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "bytes_per_unit": bpu})
+    return out
 
 
 def cpu_baseline(wl, seconds_target=15.0):
@@ -110,7 +164,7 @@ def cpu_baseline(wl, seconds_target=15.0):
     hi = (64, 160, 160)
     cells = 64 ** 3
     t_total, reps = 0.0, 0
-    while t_total < seconds_target and reps < 10:
+    while t_total < seconds_target and reps < 60:
         t0 = time.perf_counter()
         O.update_box(cfg, u, dt, lo, hi)
         t_total += time.perf_counter() - t0
@@ -129,7 +183,14 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the hash of the kernel sources that traffic figures are tied to")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain device copy of 2 GiB x 5 (counter calibration)")
     args = ap.parse_args()
+    if args.source_hash:
+        print(_source_hash())
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the CTU step shards by block decomposition, which this build does not run)",
@@ -137,6 +198,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        # plain copy kernel of known size: 2 GiB read + 2 GiB written per launch
+        src = torch.empty(2 << 30, dtype=torch.uint8, device="cuda").random_(0, 255)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy probe: 5 launches of a 2 GiB device-to-device copy")
+        return
     from paper_1410_4194_amd import ctu, workloads as WL
 
     log(f"[bench] building shock-cloud {args.n}^3 initial state")
@@ -159,7 +229,8 @@ def main():
         "config": {"workload": f"shock_cloud_{args.n}^3 Mach-10 chi-10 FP64 CFL 0.3",
                    "cells": cells, "grid": list(n), "parallelism": "single GPU",
                    "newton_caps": r64["counters"][1], "status": r64["status"]},
-        "roofline": roofline(r64["profile"], n, 8, r64["seconds"]),
+        "roofline": roofline(r64["profile"], n, 8, "fp64"),
+        "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in r64["profile"].items()},
     }
     if not args.no_fp32:
         log(f"[bench] FP32 form: warmup {args.warmup}, timed {args.steps} steps")
@@ -168,7 +239,7 @@ def main():
         log(f"[bench] FP32 {v32:.4g} cell-updates/s")
         out["fp32"] = {"value": round(v32, 1), "unit": "cell-updates/s",
                        "ms_per_step": round(1e3 * r32["seconds"] / args.steps, 4),
-                       "roofline": roofline(r32["profile"], n, 4, r32["seconds"])}
+                       "roofline": roofline(r32["profile"], n, 4, "fp32")}
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline: oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(wl)

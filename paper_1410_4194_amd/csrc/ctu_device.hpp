@@ -36,6 +36,9 @@ struct GridParams {
   double shock_a;       // (gamma + 1) / (2 gamma)
   double shock_b;       // (gamma - 1) / (2 gamma)
   int fan_int_exp;      // 2/(gamma-1) when it is an integer (3 for 5/3, 5 for 7/5), else 0
+  int root_m;           // 2 gamma/(gamma-1) when it is an integer (5 for 5/3, 7 for 7/5), else 0
+  double inv_root_m;    // (gamma - 1) / (2 gamma)
+  double inv_gm1;       // 1 / (gamma - 1)
 };
 
 // Device scalars of one grid (in the workspace).
@@ -363,6 +366,347 @@ __device__ __forceinline__ void exact_flux(const T UL[5], const T UR[5], const G
   F[3] = rho * u * wt;
   F[4] = (E + pres) * u;
   (void)g;
+}
+
+// ======================================================================================
+// Fast forms used by the fused sweep kernels.  Same operations as above, rearranged for the
+// gfx950 VALU: one reciprocal per cell instead of repeated divisions, and the power
+// (p/p_k)^((g-1)/(2g)) of the Riemann solver taken as an integer root when 2g/(g-1) is an
+// integer.  Results differ from the plain forms only by rounding.
+// ======================================================================================
+
+// Inverse integer root y = r^(-1/m) for r > 0 and integer m >= 2: a float estimate from
+// the hardware log2/exp2 units, then two Newton steps y <- y + y (1 - r y^m) / m in double,
+// which need no division and converge quadratically from ~1e-6 relative error to full
+// double precision.  Returns y and y^(m-1); then r^(1/m) = r y^(m-1).
+__device__ __forceinline__ void inv_root_int(double r, int m, double inv_m, double& y,
+                                             double& ym1) {
+  const float rf = (float)r;
+  if (!(rf > 1.0e-30f && rf < 1.0e30f)) {
+    y = pow(r, -inv_m);
+    ym1 = pow(r, -(1.0 - inv_m));
+    return;
+  }
+  y = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(rf) * (float)inv_m);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    double yp = y;
+    for (int i = 1; i < m; ++i) yp *= y;  // y^m
+    y = fma(y * inv_m, fma(-r, yp, 1.0), y);
+  }
+  ym1 = y;
+  for (int i = 2; i < m; ++i) ym1 *= y;
+}
+
+// Primitive variables of one cell in the rotated frame of a sweep, with its sound speed
+// and 1/rho.
+template <typename T>
+struct Prim {
+  T w[5];
+  T a;
+  T ia;    // 1 / a
+  T irho;  // 1 / rho
+};
+
+template <typename T>
+__device__ __forceinline__ void make_prim(const T Ur[5], T gamma, T gm1, T p_floor, Prim<T>& c) {
+  const T rho = Ur[0];
+  const T ir = T(1) / rho;
+  const T u = Ur[1] * ir, v = Ur[2] * ir, w = Ur[3] * ir;
+  T p = gm1 * (Ur[4] - T(0.5) * rho * (u * u + v * v + w * w));
+  if (!(p >= p_floor)) p = p_floor;
+  c.w[0] = rho;
+  c.w[1] = u;
+  c.w[2] = v;
+  c.w[3] = w;
+  c.w[4] = p;
+  c.irho = ir;
+  c.a = tsqrt(gamma * p * ir);
+  c.ia = T(1) / c.a;
+}
+
+// PLMC slope step of cell c (App. A.2) with the cell's own rho and a.
+template <typename T>
+__device__ __forceinline__ void slope_fast(const Prim<T>& m, const Prim<T>& c, const Prim<T>& p,
+                                           T dw[5]) {
+  const T rho = c.w[0];
+  const T ia = c.ia;
+  const T ia2 = ia * ia;
+  const T ra = rho * ia;
+  T d[3][5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    d[0][q] = c.w[q] - m.w[q];
+    d[1][q] = p.w[q] - c.w[q];
+    d[2][q] = T(0.5) * (p.w[q] - m.w[q]);
+  }
+  T x0[3], x1[3], x4[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T dp = d[k][4] * ia2;
+    const T du = ra * d[k][1];
+    x0[k] = T(0.5) * (dp - du);
+    x1[k] = d[k][0] - dp;
+    x4[k] = T(0.5) * (dp + du);
+  }
+  const T xi0 = mc_limit(x0[0], x0[1], x0[2]);
+  const T xi1 = mc_limit(x1[0], x1[1], x1[2]);
+  const T xi4 = mc_limit(x4[0], x4[1], x4[2]);
+  dw[0] = xi0 + xi1 + xi4;
+  dw[1] = (c.a * c.irho) * (xi4 - xi0);
+  dw[2] = mc_limit(d[0][2], d[1][2], d[2][2]);
+  dw[3] = mc_limit(d[0][3], d[1][3], d[2][3]);
+  dw[4] = (c.a * c.a) * (xi0 + xi4);
+}
+
+// PPMC parabola, monotonicity and characteristic tracing (App. A.3) of cell c from the
+// primitives of c-1, c, c+1 and the limited slopes of the same three cells.
+template <typename T>
+__device__ __forceinline__ void trace_fast(const Prim<T>& m, const Prim<T>& c, const Prim<T>& p,
+                                           const T dwm[5], const T dwc[5], const T dwp[5],
+                                           T dtodx, T WsL[5], T WsR[5]) {
+  const T sixth = T(1) / T(6);
+  const T rho = c.w[0];
+  const T a = c.a;
+  const T ia = c.ia;
+  const T ia2 = ia * ia;
+  const T lm = c.w[1] - a, l0 = c.w[1], lp = c.w[1] + a;
+  const T am = dtodx * tmin(lm, T(0)), bm = dtodx * tmax(lm, T(0));
+  const T a0 = dtodx * tmin(l0, T(0)), b0 = dtodx * tmax(l0, T(0));
+  const T ap = dtodx * tmin(lp, T(0)), bp = dtodx * tmax(lp, T(0));
+  T dwv[5], w6v[5], ILm[5], IRp[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const T cq = c.w[q];
+    T wl = T(0.5) * (cq + m.w[q]) - (dwc[q] - dwm[q]) * sixth;
+    T wr = T(0.5) * (p.w[q] + cq) - (dwp[q] - dwc[q]) * sixth;
+    if ((wr - cq) * (cq - wl) <= T(0)) {
+      wl = cq;
+      wr = cq;
+    }
+    if ((wr - wl) * (wl - (T(3) * cq - T(2) * wr)) < T(0)) wl = T(3) * cq - T(2) * wr;
+    if ((wr - wl) * ((T(3) * cq - T(2) * wl) - wr) < T(0)) wr = T(3) * cq - T(2) * wl;
+    wl = tmin(tmax(cq, m.w[q]), tmax(tmin(cq, m.w[q]), wl));
+    wr = tmin(tmax(cq, p.w[q]), tmax(tmin(cq, p.w[q]), wr));
+    dwv[q] = wr - wl;
+    w6v[q] = T(6) * cq - T(3) * (wl + wr);
+    ILm[q] = ppm_IL(am, dwv[q], w6v[q]);
+    IRp[q] = ppm_IR(bp, dwv[q], w6v[q]);
+    WsL[q] = wl - ILm[q];
+    WsR[q] = wr - IRp[q];
+  }
+  // Corrections for the other waves moving toward each face; each integral difference is
+  // formed only for the components its correction uses.
+  if (l0 < T(0)) {
+    T E[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+      if (q != 1) E[q] = ILm[q] - ppm_IL(a0, dwv[q], w6v[q]);
+    WsL[0] += E[0] - E[4] * ia2;
+    WsL[2] += E[2];
+    WsL[3] += E[3];
+  }
+  if (lp < T(0)) {
+    const T B1 = ILm[1] - ppm_IL(ap, dwv[1], w6v[1]);
+    const T B4 = ILm[4] - ppm_IL(ap, dwv[4], w6v[4]);
+    WsL[0] += T(0.5) * (rho * B1 * ia + B4 * ia2);
+    WsL[1] += T(0.5) * (B1 + B4 * ia * c.irho);
+    WsL[4] += T(0.5) * (rho * B1 * a + B4);
+  }
+  if (lm > T(0)) {
+    const T C1 = IRp[1] - ppm_IR(bm, dwv[1], w6v[1]);
+    const T C4 = IRp[4] - ppm_IR(bm, dwv[4], w6v[4]);
+    WsR[0] += T(0.5) * (-rho * C1 * ia + C4 * ia2);
+    WsR[1] += T(0.5) * (C1 - C4 * ia * c.irho);
+    WsR[4] += T(0.5) * (-rho * C1 * a + C4);
+  }
+  if (l0 > T(0)) {
+    T D[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+      if (q != 1) D[q] = IRp[q] - ppm_IR(b0, dwv[q], w6v[q]);
+    WsR[0] += D[0] - D[4] * ia2;
+    WsR[2] += D[2];
+    WsR[3] += D[3];
+  }
+}
+
+// Pressure function and derivative at p for one side, given 1/p and the side's constants.
+struct SideK {
+  double rho, u, p, a;
+  double ip;     // 1 / p_k
+  double irhoa;  // 1 / (rho_k a_k)
+  double A, B;   // 2/((g+1) rho_k), (g-1)/(g+1) p_k
+};
+
+__device__ __forceinline__ void pfun_fast(double p, const SideK& k, const GridParams& P,
+                                          double& f, double& df, double& z) {
+  if (p <= k.p) {
+    const double r = p * k.ip;
+    if (P.root_m) {
+      // z = r^((g-1)/(2g)) = r y^(m-1) with y = r^(-1/m); f' = z/(r rho a) = y^(m-1)/(rho a)
+      double y, ym1;
+      inv_root_int(r, P.root_m, P.inv_root_m, y, ym1);
+      z = r * ym1;
+      df = ym1 * k.irhoa;
+    } else {
+      z = pow(r, P.z_exp);
+      df = z / r * k.irhoa;
+    }
+    f = P.two_over_gm1 * k.a * (z - 1.0);
+  } else {
+    const double ipb = 1.0 / (p + k.B);
+    const double q = sqrt(k.A * ipb);
+    f = (p - k.p) * q;
+    df = q * (1.0 - 0.5 * (p - k.p) * ipb);
+    z = 0.0;
+  }
+}
+
+// Exact Riemann flux from rotated conserved states (App. B.1), fast form.
+template <typename T>
+__device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], const GridParams& P,
+                                                T F[5], RiemannCounts& cnt) {
+  const T gm1 = T(P.gm1);
+  const T pf = T(P.p_floor);
+  Prim<T> L, R;
+  make_prim(UL, T(P.gamma), gm1, pf, L);
+  make_prim(UR, T(P.gamma), gm1, pf, R);
+  // floor hits: make_prim applied the floor when the pressure equals p_floor after the check
+  cnt.floors += (L.w[4] == pf) + (R.w[4] == pf);
+
+  SideK kl, kr;
+  kl.rho = L.w[0];
+  kl.u = L.w[1];
+  kl.p = L.w[4];
+  kr.rho = R.w[0];
+  kr.u = R.w[1];
+  kr.p = R.w[4];
+  if (sizeof(T) == sizeof(double)) {
+    kl.a = L.a;
+    kr.a = R.a;
+    kl.irhoa = (double)L.irho * (double)L.ia;
+    kr.irhoa = (double)R.irho * (double)R.ia;
+  } else {
+    kl.a = sqrt(P.gamma * kl.p / kl.rho);
+    kr.a = sqrt(P.gamma * kr.p / kr.rho);
+    kl.irhoa = 1.0 / (kl.rho * kl.a);
+    kr.irhoa = 1.0 / (kr.rho * kr.a);
+  }
+  kl.ip = 1.0 / kl.p;
+  kr.ip = 1.0 / kr.p;
+  kl.A = P.two_over_gp1 * (double)L.irho;
+  kr.A = P.two_over_gp1 * (double)R.irho;
+  kl.B = P.gm1_over_gp1 * kl.p;
+  kr.B = P.gm1_over_gp1 * kr.p;
+
+  double pt = 0.5 * (kl.p + kr.p) + 0.125 * (kl.u - kr.u) * (kl.rho + kr.rho) * (kl.a + kr.a);
+  pt = pt < 0.0 ? 0.0 : pt;
+  const double gl = sqrt(kl.A / (pt + kl.B));
+  const double gr = sqrt(kr.A / (pt + kr.B));
+  double p = (gl * kl.p + gr * kr.p - (kr.u - kl.u)) / (gl + gr);
+  p = p < 1.0e-6 ? 1.0e-6 : p;
+  const double du = kr.u - kl.u;
+  double fl, dfl, fr, dfr, zl, zr;
+  bool conv = false;
+  bool same = false;  // the last Newton step left p unchanged
+  for (int it = 0; it < P.newton_max_iter; ++it) {
+    pfun_fast(p, kl, P, fl, dfl, zl);
+    pfun_fast(p, kr, P, fr, dfr, zr);
+    double pn = p - (fl + fr + du) / (dfl + dfr);
+    if (!(pn >= P.p_floor)) pn = P.p_floor;
+    // relative change 2|pn - p|/|pn + p| < tol, without the division
+    const bool done = 2.0 * fabs(pn - p) < P.newton_tol * fabs(pn + p);
+    same = pn == p;
+    p = pn;
+    if (done) {
+      conv = true;
+      break;
+    }
+  }
+  cnt.caps += conv ? 0u : 1u;
+  // u* from f_L, f_R at the final star pressure; when the last step did not move p the
+  // values just computed are already those.
+  if (!same) {
+    pfun_fast(p, kl, P, fl, dfl, zl);
+    pfun_fast(p, kr, P, fr, dfr, zr);
+  }
+  const double ps = p;
+  const double us = 0.5 * (kl.u + kr.u + fr - fl);
+
+  T rho, u, pres;
+  if (us >= 0.0) {
+    if (ps <= kl.p) {
+      if (kl.u - kl.a >= 0.0) {
+        rho = L.w[0];
+        u = L.w[1];
+        pres = L.w[4];
+      } else if (us - kl.a * zl < 0.0) {
+        rho = T(kl.rho * (P.fan_int_exp ? ipow(zl, P.fan_int_exp) : pow(zl, P.two_over_gm1)));
+        u = T(us);
+        pres = T(ps);
+      } else {
+        const T c = T(P.two_over_gp1) * (T(kl.a) + T(0.5) * gm1 * L.w[1]);
+        const T r = c / T(kl.a);
+        const T rr_ = P.fan_int_exp ? ipow(r, P.fan_int_exp) : tpow(r, T(P.two_over_gm1));
+        rho = L.w[0] * rr_;
+        u = c;
+        pres = L.w[4] * rr_ * r * r;
+      }
+    } else {
+      const double sl = kl.u - kl.a * sqrt(P.shock_a * ps * kl.ip + P.shock_b);
+      if (sl >= 0.0) {
+        rho = L.w[0];
+        u = L.w[1];
+        pres = L.w[4];
+      } else {
+        const double q = ps * kl.ip;
+        rho = T(kl.rho * (q + P.gm1_over_gp1) / (q * P.gm1_over_gp1 + 1.0));
+        u = T(us);
+        pres = T(ps);
+      }
+    }
+  } else {
+    if (ps <= kr.p) {
+      if (kr.u + kr.a <= 0.0) {
+        rho = R.w[0];
+        u = R.w[1];
+        pres = R.w[4];
+      } else if (us + kr.a * zr >= 0.0) {
+        rho = T(kr.rho * (P.fan_int_exp ? ipow(zr, P.fan_int_exp) : pow(zr, P.two_over_gm1)));
+        u = T(us);
+        pres = T(ps);
+      } else {
+        const T c = T(P.two_over_gp1) * (T(kr.a) - T(0.5) * gm1 * R.w[1]);
+        const T r = c / T(kr.a);
+        const T rr_ = P.fan_int_exp ? ipow(r, P.fan_int_exp) : tpow(r, T(P.two_over_gm1));
+        rho = R.w[0] * rr_;
+        u = -c;
+        pres = R.w[4] * rr_ * r * r;
+      }
+    } else {
+      const double sr = kr.u + kr.a * sqrt(P.shock_a * ps * kr.ip + P.shock_b);
+      if (sr <= 0.0) {
+        rho = R.w[0];
+        u = R.w[1];
+        pres = R.w[4];
+      } else {
+        const double q = ps * kr.ip;
+        rho = T(kr.rho * (q + P.gm1_over_gp1) / (q * P.gm1_over_gp1 + 1.0));
+        u = T(us);
+        pres = T(ps);
+      }
+    }
+  }
+  const T vt = (u >= T(0)) ? L.w[2] : R.w[2];
+  const T wt = (u >= T(0)) ? L.w[3] : R.w[3];
+  const T mu = rho * u;
+  const T E = pres * T(P.inv_gm1) + T(0.5) * rho * (u * u + vt * vt + wt * wt);
+  F[0] = mu;
+  F[1] = mu * u + pres;
+  F[2] = mu * vt;
+  F[3] = mu * wt;
+  F[4] = (E + pres) * u;
 }
 
 }  // namespace ctu

@@ -34,23 +34,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block-wide minimum folded into *bits with an exact, order-free atomicMin on the IEEE bit
-// pattern (monotone for non-negative doubles).  Every thread of the block must call it.
-__device__ void block_min_atomic(double v, unsigned long long* bits) {
-  __shared__ double smin[32];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  v = wave_min(v);
-  if (lane == 0) smin[wave] = v;
-  __syncthreads();
-  if (wave == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    double m = lane < nw ? smin[lane] : INFINITY;
-    m = wave_min(m);
-    if (lane == 0 && m < INFINITY) atomicMin(bits, (unsigned long long)__double_as_longlong(m));
-  }
-}
-
 // Per-cell CFL bound min(dx/(|u|+a), dy/(|v|+a), dz/(|w|+a)) (eq. calc_dt_3D without C0).
 template <typename T>
 __device__ __forceinline__ double cell_dt_bound(const T U[5], const GridParams& P) {
@@ -64,17 +47,13 @@ __device__ __forceinline__ double cell_dt_bound(const T U[5], const GridParams& 
 }
 
 // ---- step bookkeeping ----------------------------------------------------------------------
-__global__ void k_set_dt(DevScalars* s, double dt) {
-  s->dt = dt;
-  s->dt_next_bits = 0x7ff0000000000000ull;  // +inf
-}
+__global__ void k_set_dt(DevScalars* s, double dt) { s->dt = dt; }
 
 // Device-side time step for ctu_advance: C0 * (min CFL bound), clipped to t_end - t.
 __global__ void k_begin_step(DevScalars* s, double cfl, double t_end) {
   double bound = ordered_min_to_double(s->dt_next_bits);
   double dt = fmin(cfl * bound, t_end - s->t);
   s->dt = dt;
-  if (dt > 0.0) s->dt_next_bits = 0x7ff0000000000000ull;
 }
 
 __global__ void k_end_step(DevScalars* s) {
@@ -84,7 +63,6 @@ __global__ void k_end_step(DevScalars* s) {
   }
 }
 
-__global__ void k_reset_dt_bits(DevScalars* s) { s->dt_next_bits = 0x7ff0000000000000ull; }
 
 // ---- a1: ghost fill (Sec. 3.1) ------------------------------------------------------------
 // Axis `axis` ghosts over the full extent of the other two axes (ghosts included), so
@@ -138,44 +116,80 @@ __global__ void k_bc_fill(T* __restrict__ u, GridParams P, int axis, int bc_lo, 
   for (int f = 0; f < 5; ++f) u[f * P.stride + d] = u[f * P.stride + s];
 }
 
-// ---- a2-a4: primitives, PPMC and tracing per cell, along D -------------------------------
-// One thread per cell of the extended box [-1, n+1)^3.  Writes the conserved traced states
-// of the cell's two faces (global component order): ustar[0..4] = U*_L (left face),
-// ustar[5..9] = U*_R (right face).
+// ---- fused sweeps --------------------------------------------------------------------------
+// Stage 1 (a2-a5) and stage 2 (a2-a4 re-traced, a6-a7) of one direction D each run as one
+// kernel.  Along y and z a thread owns one column and marches along D over a segment of SEG
+// faces, keeping a register window of primitives (cells c-1..c+2) and limited slopes
+// (c-1..c+1): every primitive, slope and trace is computed once per cell (plus a short
+// warm-up per segment) and each face's Riemann problem once.  Lanes run along x, so every
+// load and store of a wavefront is contiguous.  Along x a wavefront covers 64 consecutive
+// cells of one row and exchanges neighbours with lane shuffles; it yields 59 faces.
+constexpr int SEG = 32;
+constexpr int XW = 59;  // x-faces per wavefront in the shuffle kernels
+
+// Workgroups are assigned to XCDs round robin by the hardware; xcd_block gives each XCD a
+// contiguous range of logical blocks so neighbouring rows share one L2.
+__device__ __forceinline__ long long xcd_block(long long nblocks) {
+  const long long b = blockIdx.x;
+  const long long per = (nblocks + 7) / 8;
+  return (b % 8) * per + b / 8;
+}
+
 template <typename T, int D>
-__global__ void k_trace(const T* __restrict__ u, T* __restrict__ ustar, GridParams P,
-                        const DevScalars* __restrict__ s) {
-  const double dt = s->dt;
-  if (!(dt > 0.0)) return;
-  const int ex = P.n[0] + 2, ey = P.n[1] + 2, ez = P.n[2] + 2;
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= (long long)ex * ey * ez) return;
-  const int i = (int)(tid % ex) - 1;
-  const int j = (int)((tid / ex) % ey) - 1;
-  const int k = (int)(tid / ((long long)ex * ey)) - 1;
-  const long long c = cell_index(P, i, j, k);
-  long long step = D == 0 ? 1 : (D == 1 ? (long long)P.N[0] : (long long)P.N[0] * P.N[1]);
-  const T gm1 = T(P.gm1), pf = T(P.p_floor);
-  T w[5][5];
+__device__ __forceinline__ void load_prim(const T* __restrict__ u, long long stride, long long id,
+                                          const GridParams& P, Prim<T>& c) {
+  T Ur[5];
 #pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    const long long id = c + (m - 2) * step;
-    T U[5], Ur[5];
+  for (int sl = 0; sl < 5; ++sl) Ur[sl] = u[rot<D>(sl) * stride + id];
+  make_prim(Ur, T(P.gamma), T(P.gm1), T(P.p_floor), c);
+}
+
+template <typename T>
+__device__ __forceinline__ void safe_prim(Prim<T>& c) {
+  c.w[0] = T(1);
+  c.w[1] = c.w[2] = c.w[3] = T(0);
+  c.w[4] = T(1);
+  c.a = T(1);
+  c.ia = T(1);
+  c.irho = T(1);
+}
+
+template <typename T>
+__device__ __forceinline__ Prim<T> shfl_prim(const Prim<T>& p, int src) {
+  Prim<T> r;
 #pragma unroll
-    for (int f = 0; f < 5; ++f) U[f] = u[f * P.stride + id];
-#pragma unroll
-    for (int sl = 0; sl < 5; ++sl) Ur[sl] = U[rot<D>(sl)];
-    cons_to_prim(Ur, gm1, pf, w[m]);
-  }
-  T WsL[5], WsR[5], UsL[5], UsR[5];
-  ppmc(w, T(dt / P.dx[D]), T(P.gamma), WsL, WsR);
-  prim_to_cons(WsL, gm1, UsL);
-  prim_to_cons(WsR, gm1, UsR);
+  for (int q = 0; q < 5; ++q) r.w[q] = __shfl(p.w[q], src, 64);
+  r.a = __shfl(p.a, src, 64);
+  r.ia = __shfl(p.ia, src, 64);
+  r.irho = __shfl(p.irho, src, 64);
+  return r;
+}
+
+// Transverse flux difference of a cell (eq. transverse_evolution), rotated to the sweep
+// frame: dT = h1 (F_t1(c - e_t1) - F_t1(c)) + h2 (F_t2(c - e_t2) - F_t2(c)).
+template <typename T, int D>
+__device__ __forceinline__ void transverse_delta(const T* __restrict__ fstar_all, long long fds,
+                                                 long long stride, long long c, long long st1,
+                                                 long long st2, T h1, T h2, T dT[5]) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const T* F1 = fstar_all + T1 * fds;
+  const T* F2 = fstar_all + T2 * fds;
 #pragma unroll
   for (int sl = 0; sl < 5; ++sl) {
-    ustar[rot<D>(sl) * P.stride + c] = UsL[sl];
-    ustar[(5 + rot<D>(sl)) * P.stride + c] = UsR[sl];
+    const long long o = rot<D>(sl) * stride + c;
+    dT[sl] = h1 * (F1[o - st1] - F1[o]) + h2 * (F2[o - st2] - F2[o]);
   }
+}
+
+// Primitive -> conserved with E = p/(g-1) + rho V^2/2, multiplying by 1/(g-1).
+template <typename T>
+__device__ __forceinline__ void to_cons(const T W[5], T inv_gm1, T U[5]) {
+  const T rho = W[0];
+  U[0] = rho;
+  U[1] = rho * W[1];
+  U[2] = rho * W[2];
+  U[3] = rho * W[3];
+  U[4] = W[4] * inv_gm1 + T(0.5) * rho * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
 }
 
 __device__ __forceinline__ void flush_counts(const RiemannCounts& cnt, DevScalars* s) {
@@ -189,93 +203,229 @@ __device__ __forceinline__ void flush_counts(const RiemannCounts& cnt, DevScalar
   }
 }
 
-// ---- a5: first Riemann solve on D-faces ----------------------------------------------------
-// Faces c+1/2 for c in [-1, n_D - 1] along D and [-1, n_t] across.  The left input is the
-// right-face state of cell c, the right input the left-face state of cell c+1.
-template <typename T, int D>
-__global__ void k_riemann1(const T* __restrict__ ustar, T* __restrict__ fstar, GridParams P,
-                           DevScalars* __restrict__ s) {
-  if (!(s->dt > 0.0)) return;
-  const int e0 = P.n[0] + (D == 0 ? 1 : 2);
-  const int e1 = P.n[1] + (D == 1 ? 1 : 2);
-  const int e2 = P.n[2] + (D == 2 ? 1 : 2);
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= (long long)e0 * e1 * e2) return;
-  const int i = (int)(tid % e0) - 1;
-  const int j = (int)((tid / e0) % e1) - 1;
-  const int k = (int)(tid / ((long long)e0 * e1)) - 1;
-  const long long c = cell_index(P, i, j, k);
-  const long long step = D == 0 ? 1 : (D == 1 ? (long long)P.N[0] : (long long)P.N[0] * P.N[1]);
-  T UL[5], UR[5], F[5];
-#pragma unroll
-  for (int sl = 0; sl < 5; ++sl) {
-    UL[sl] = ustar[(5 + rot<D>(sl)) * P.stride + c];
-    UR[sl] = ustar[rot<D>(sl) * P.stride + c + step];
-  }
-  RiemannCounts cnt{0u, 0u};
-  exact_flux(UL, UR, P, F, cnt);
-  flush_counts(cnt, s);
-#pragma unroll
-  for (int sl = 0; sl < 5; ++sl) fstar[rot<D>(sl) * P.stride + c] = F[sl];
-}
-
-// ---- a6-a7: transverse correction and second Riemann solve on D-faces --------------------
-// Faces c+1/2 for c in [-1, n_D - 1] along D and the real range across (eq.
-// transverse_evolution, cyclic order: x uses y then z, y uses z then x, z uses x then y).
-template <typename T, int D>
-__global__ void k_riemann2(const T* __restrict__ ustar, const T* __restrict__ fstar_all,
-                           T* __restrict__ fhalf, GridParams P, DevScalars* __restrict__ s,
-                           long long fstar_dir_stride) {
+// STAGE = 1: first-stage fluxes F*_D on faces c-1/2, c in [0, n_D], transverse range
+//            [-1, n] on both other axes; written to out at cell c-1.
+// STAGE = 2: CTU fluxes F^{n+1/2}_D on the same faces over the real transverse range, from
+//            the re-traced states plus the transverse flux differences of stage 1.
+template <typename T, int D, int STAGE>
+__global__ __launch_bounds__(256, 2) void k_sweep_march(const T* __restrict__ u,
+                                                     const T* __restrict__ fstar_all,
+                                                     T* __restrict__ out, GridParams P,
+                                                     DevScalars* __restrict__ s, long long fds) {
+  static_assert(D == 1 || D == 2, "marching sweeps run along y or z");
   const double dt = s->dt;
   if (!(dt > 0.0)) return;
+  constexpr int B = (D == 1) ? 2 : 1;  // the transverse axis other than x
+  const int lo = STAGE == 1 ? -1 : 0;
+  const int ea = P.n[0] + (STAGE == 1 ? 2 : 0);
+  const int eb = P.n[B] + (STAGE == 1 ? 2 : 0);
+  const int nd = P.n[D];
+  // block = (plane block, segment), plane blocks fastest (a contiguous-in-x column set per
+  // block; measured faster than an XCD-grouped order for these sweeps)
+  const long long nbx = ((long long)ea * eb + blockDim.x - 1) / blockDim.x;
+  const long long nseg = (nd + 1 + SEG - 1) / SEG;
+  const long long lb = blockIdx.x;
+  if (lb >= nbx * nseg) return;
+  const long long tid = (lb % nbx) * blockDim.x + threadIdx.x;
+  if (tid >= (long long)ea * eb) return;
+  const int i = (int)(tid % ea) + lo;
+  const int o = (int)(tid / ea) + lo;
+  const int f0 = (int)(lb / nbx) * SEG;
+  if (f0 > nd) return;
+  const int f1 = min(f0 + SEG, nd + 1);
+  const long long stx = 1, sty = P.N[0], stz = (long long)P.N[0] * P.N[1];
+  const long long sd = D == 1 ? sty : stz;
+  const long long c0 = D == 1 ? cell_index(P, i, 0, o) : cell_index(P, i, o, 0);
+  const T dtodx = T(dt / P.dx[D]);
+  const T igm1 = T(P.inv_gm1);
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const int e0 = P.n[0] + (D == 0 ? 1 : 0);
-  const int e1 = P.n[1] + (D == 1 ? 1 : 0);
-  const int e2 = P.n[2] + (D == 2 ? 1 : 0);
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= (long long)e0 * e1 * e2) return;
-  const int i = (int)(tid % e0) - (D == 0 ? 1 : 0);
-  const int j = (int)((tid / e0) % e1) - (D == 1 ? 1 : 0);
-  const int k = (int)(tid / ((long long)e0 * e1)) - (D == 2 ? 1 : 0);
-  const long long st[3] = {1, (long long)P.N[0], (long long)P.N[0] * P.N[1]};
-  const long long cl = cell_index(P, i, j, k);
-  const long long cr = cl + st[D];
-  const T* F1 = fstar_all + T1 * fstar_dir_stride;
-  const T* F2 = fstar_all + T2 * fstar_dir_stride;
+  const long long st1 = T1 == 0 ? stx : (T1 == 1 ? sty : stz);
+  const long long st2 = T2 == 0 ? stx : (T2 == 1 ? sty : stz);
   const T h1 = T(0.5 * dt / P.dx[T1]);
   const T h2 = T(0.5 * dt / P.dx[T2]);
-  T Uh[2][5];
+
+  Prim<T> q0, q1, q2, q3;  // cells c-1, c, c+1, c+2 around the traced cell c
+  T s0[5], s1[5], s2[5];   // limited slopes of c-1, c, c+1
+  {
+    Prim<T> qm;
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 - 3) * sd, P, qm);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 - 2) * sd, P, q0);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 - 1) * sd, P, q1);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0)*sd, P, q2);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 + 1) * sd, P, q3);
+    slope_fast(qm, q0, q1, s0);
+    slope_fast(q0, q1, q2, s1);
+    slope_fast(q1, q2, q3, s2);
+  }
+  // warm-up: trace cell f0-1 (window: q0 = f0-2, q1 = f0-1, q2 = f0, q3 = f0+1)
+  T prevR[5];
+  {
+    T WL[5], WR[5];
+    trace_fast(q0, q1, q2, s0, s1, s2, dtodx, WL, WR);
+    to_cons(WR, igm1, prevR);
+    if (STAGE == 2) {
+      T dT[5];
+      transverse_delta<T, D>(fstar_all, fds, P.stride, c0 + (long long)(f0 - 1) * sd, st1, st2, h1,
+                             h2, dT);
 #pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    const long long cc = side == 0 ? cl : cr;
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      T us = side == 0 ? ustar[(5 + f) * P.stride + cc] : ustar[f * P.stride + cc];
-      T d1 = F1[f * P.stride + cc - st[T1]] - F1[f * P.stride + cc];
-      T d2 = F2[f * P.stride + cc - st[T2]] - F2[f * P.stride + cc];
-      Uh[side][f] = us + h1 * d1 + h2 * d2;
+      for (int q = 0; q < 5; ++q) prevR[q] += dT[q];
     }
   }
-  T UL[5], UR[5], F[5];
+  // shift so that the window is centred on f0 at the top of the loop
+  q0 = q1;
+  q1 = q2;
+  q2 = q3;
 #pragma unroll
-  for (int sl = 0; sl < 5; ++sl) {
-    UL[sl] = Uh[0][rot<D>(sl)];
-    UR[sl] = Uh[1][rot<D>(sl)];
+  for (int q = 0; q < 5; ++q) {
+    s0[q] = s1[q];
+    s1[q] = s2[q];
   }
-  RiemannCounts cnt{0u, 0u};
-  exact_flux(UL, UR, P, F, cnt);
-  flush_counts(cnt, s);
+  // the conserved values of cell c+2 are loaded one iteration ahead (software pipelining)
+  T raw[5];
 #pragma unroll
-  for (int sl = 0; sl < 5; ++sl) fhalf[rot<D>(sl) * P.stride + cl] = F[sl];
+  for (int sl = 0; sl < 5; ++sl) raw[sl] = u[rot<D>(sl) * P.stride + c0 + (long long)(f0 + 2) * sd];
+  RiemannCounts cnt{0u, 0u};
+  for (int c = f0; c < f1; ++c) {
+    // window: q0 = c-1, q1 = c, q2 = c+1, slopes s0 = c-1, s1 = c
+    make_prim(raw, T(P.gamma), T(P.gm1), T(P.p_floor), q3);  // cell c+2
+    if (c + 1 < f1) {
+      const long long nid = c0 + (long long)(c + 3) * sd;
+#pragma unroll
+      for (int sl = 0; sl < 5; ++sl) raw[sl] = u[rot<D>(sl) * P.stride + nid];
+    }
+    slope_fast(q1, q2, q3, s2);  // slope of c+1
+    T WL[5], WR[5], UL[5], UR[5], F[5];
+    trace_fast(q0, q1, q2, s0, s1, s2, dtodx, WL, WR);
+    to_cons(WL, igm1, UL);
+    to_cons(WR, igm1, UR);
+    if (STAGE == 2) {
+      T dT[5];
+      transverse_delta<T, D>(fstar_all, fds, P.stride, c0 + (long long)c * sd, st1, st2, h1, h2,
+                             dT);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        UL[q] += dT[q];
+        UR[q] += dT[q];
+      }
+    }
+    exact_flux_fast(prevR, UL, P, F, cnt);
+    const long long fo = c0 + (long long)(c - 1) * sd;
+#pragma unroll
+    for (int sl = 0; sl < 5; ++sl) out[rot<D>(sl) * P.stride + fo] = F[sl];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      prevR[q] = UR[q];
+      s0[q] = s1[q];
+      s1[q] = s2[q];
+    }
+    q0 = q1;
+    q1 = q2;
+    q2 = q3;
+  }
+  flush_counts(cnt, s);
+}
+
+// x-direction sweep: one wavefront per (row, segment of XW faces).  Lane l holds cell
+// cw - 3 + l; slopes are valid on lanes 1..62, traces on 2..61, faces c-1/2 on 3..61.
+template <typename T, int STAGE>
+__global__ __launch_bounds__(256) void k_sweep_x(const T* __restrict__ u,
+                                                 const T* __restrict__ fstar_all,
+                                                 T* __restrict__ out, GridParams P,
+                                                 DevScalars* __restrict__ s, long long fds) {
+  const double dt = s->dt;
+  if (!(dt > 0.0)) return;
+  const int lane = threadIdx.x & 63;
+  const long long task = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lo = STAGE == 1 ? -1 : 0;
+  const int ey = P.n[1] + (STAGE == 1 ? 2 : 0);
+  const int ez = P.n[2] + (STAGE == 1 ? 2 : 0);
+  const int nseg = (P.n[0] + 1 + XW - 1) / XW;
+  if (task >= (long long)nseg * ey * ez) return;  // whole wavefront exits together
+  const int sx = (int)(task % nseg);
+  const long long row = task / nseg;
+  const int j = (int)(row % ey) + lo;
+  const int k = (int)(row / ey) + lo;
+  const int cw = sx * XW;
+  const int c = cw - 3 + lane;  // this lane's cell along x
+  const long long id = cell_index(P, c, j, k);
+  const bool in_alloc = c >= -NG && c < P.n[0] + NG;
+  const T dtodx = T(dt / P.dx[0]);
+  const T igm1 = T(P.inv_gm1);
+
+  Prim<T> me;
+  if (in_alloc)
+    load_prim<T, 0>(u, P.stride, id, P, me);
+  else
+    safe_prim(me);
+  const int lm1 = lane > 0 ? lane - 1 : 0;
+  const int lp1 = lane < 63 ? lane + 1 : 63;
+  const Prim<T> left = shfl_prim(me, lm1);
+  const Prim<T> right = shfl_prim(me, lp1);
+  T sl[5];
+  slope_fast(left, me, right, sl);
+  T slm[5], slp[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    slm[q] = __shfl(sl[q], lm1, 64);
+    slp[q] = __shfl(sl[q], lp1, 64);
+  }
+  T WL[5], WR[5], UL[5], UR[5];
+  trace_fast(left, me, right, slm, sl, slp, dtodx, WL, WR);
+  to_cons(WL, igm1, UL);
+  to_cons(WR, igm1, UR);
+  const bool traced = lane >= 2 && lane <= 61 && c >= -1 && c <= P.n[0];
+  if (STAGE == 2 && traced) {
+    T dT[5];
+    transverse_delta<T, 0>(fstar_all, fds, P.stride, id, (long long)P.N[0],
+                           (long long)P.N[0] * P.N[1], T(0.5 * dt / P.dx[1]),
+                           T(0.5 * dt / P.dx[2]), dT);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      UL[q] += dT[q];
+      UR[q] += dT[q];
+    }
+  }
+  T prevR[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) prevR[q] = __shfl(UR[q], lm1, 64);
+  if (lane >= 3 && lane <= 61 && c >= 0 && c <= P.n[0]) {
+    RiemannCounts cnt{0u, 0u};
+    T F[5];
+    exact_flux_fast(prevR, UL, P, F, cnt);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[q * P.stride + id - 1] = F[q];
+    flush_counts(cnt, s);
+  }
 }
 
 // ---- a8-a9: conservative update and CFL reduction ------------------------------------------
+
+// Block minimum of v written to part[lb] (no atomics); every thread must call it.
+__device__ __forceinline__ void block_min_store(double v, double* part, long long lb) {
+  __shared__ double smin[32];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  v = wave_min(v);
+  if (lane == 0) smin[wave] = v;
+  __syncthreads();
+  if (wave == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double m = lane < nw ? smin[lane] : INFINITY;
+    m = wave_min(m);
+    if (lane == 0) part[lb] = m;
+  }
+}
+
 template <typename T>
-__global__ void k_update(T* __restrict__ u, const T* __restrict__ fhalf_all, GridParams P,
-                         DevScalars* __restrict__ s, long long fdir_stride) {
+__global__ __launch_bounds__(256) void k_update(T* __restrict__ u, const T* __restrict__ fhalf_all,
+                                                GridParams P, DevScalars* __restrict__ s,
+                                                long long fdir_stride, double* __restrict__ part,
+                                                long long nblocks) {
   const double dt = s->dt;
   if (!(dt > 0.0)) return;
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long lb = xcd_block(nblocks);
+  if (lb >= nblocks) return;  // whole block idle
+  const long long tid = lb * blockDim.x + threadIdx.x;
   const long long total = (long long)P.n[0] * P.n[1] * P.n[2];
   double bound = INFINITY;
   if (tid < total) {
@@ -309,12 +459,15 @@ __global__ void k_update(T* __restrict__ u, const T* __restrict__ fhalf_all, Gri
       bound = cell_dt_bound(U, P);
     }
   }
-  block_min_atomic(bound, &s->dt_next_bits);
+  block_min_store(bound, part, lb);
 }
 
 template <typename T>
-__global__ void k_dt(const T* __restrict__ u, GridParams P, DevScalars* __restrict__ s) {
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_dt(const T* __restrict__ u, GridParams P,
+                                            double* __restrict__ part, long long nblocks) {
+  const long long lb = xcd_block(nblocks);
+  if (lb >= nblocks) return;
+  const long long tid = lb * blockDim.x + threadIdx.x;
   const long long total = (long long)P.n[0] * P.n[1] * P.n[2];
   double bound = INFINITY;
   if (tid < total) {
@@ -327,7 +480,25 @@ __global__ void k_dt(const T* __restrict__ u, GridParams P, DevScalars* __restri
     for (int f = 0; f < 5; ++f) U[f] = u[f * P.stride + c];
     bound = cell_dt_bound(U, P);
   }
-  block_min_atomic(bound, &s->dt_next_bits);
+  block_min_store(bound, part, lb);
+}
+
+// Minimum of the block partials into dt_next_bits (one block of 1024 threads).
+__global__ __launch_bounds__(1024) void k_dt_final(const double* __restrict__ part, long long nblocks,
+                                                   DevScalars* __restrict__ s) {
+  // After a no-op step (dt <= 0) the partials still hold the bound of the unchanged state.
+  double m = INFINITY;
+  for (long long b = threadIdx.x; b < nblocks; b += blockDim.x) m = fmin(m, part[b]);
+  __shared__ double smin[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  m = wave_min(m);
+  if (lane == 0) smin[wave] = m;
+  __syncthreads();
+  if (wave == 0) {
+    double v = lane < (int)(blockDim.x >> 6) ? smin[lane] : INFINITY;
+    v = wave_min(v);
+    if (lane == 0) s->dt_next_bits = (unsigned long long)__double_as_longlong(v);
+  }
 }
 
 // ---- conservation totals (fixed-order, deterministic) -------------------------------------
@@ -417,9 +588,8 @@ __global__ void k_prim_to_cons(const double* __restrict__ packed, T* __restrict_
 // ---- per-kernel timing ----------------------------------------------------------------------
 const char* kernel_class_name(int k) {
   static const char* names[K_NUM_CLASSES] = {
-      "bc_fill_x", "bc_fill_y", "bc_fill_z", "trace_x", "trace_y", "trace_z",
-      "riemann1_x", "riemann1_y", "riemann1_z", "riemann2_x", "riemann2_y", "riemann2_z",
-      "update_dt"};
+      "bc_fill_x", "bc_fill_y", "bc_fill_z", "sweep1_x", "sweep1_y", "sweep1_z",
+      "sweep2_x", "sweep2_y", "sweep2_z", "update", "dt_final"};
   return (k >= 0 && k < K_NUM_CLASSES) ? names[k] : "";
 }
 
@@ -482,6 +652,16 @@ Profiler::~Profiler() {
 // ---- launch wrappers ------------------------------------------------------------------------
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// 1D grid of a marching sweep along D: (plane blocks x segments), padded to a multiple of 8
+// for the XCD remap.
+static inline unsigned march_blocks(const GridParams& P, int D, bool extended, int bs) {
+  const int B = D == 1 ? 2 : 1;
+  const long long ea = P.n[0] + (extended ? 2 : 0), eb = P.n[B] + (extended ? 2 : 0);
+  const long long nbx = (ea * eb + bs - 1) / bs;
+  const long long nseg = (P.n[D] + 1 + SEG - 1) / SEG;
+  return (unsigned)((nbx * nseg + 7) / 8 * 8);
+}
+
 #define TIMED(cls, launch)              \
   do {                                  \
     if (prof) prof->begin(cls, stream); \
@@ -501,63 +681,54 @@ hipError_t launch_step(const StepBuffers<T>& b, const GridParams& P, const int b
           hipLaunchKernelGGL(k_bc_fill<T>, dim3(blocks_for(total, BS)), dim3(BS), 0, stream, b.u,
                              P, axis, bc[2 * axis], bc[2 * axis + 1]));
   }
-  const long long ext = (long long)(P.n[0] + 2) * (P.n[1] + 2) * (P.n[2] + 2);
-  // a2-a5 per direction
-  TIMED(K_TRACE_X, hipLaunchKernelGGL((k_trace<T, 0>), dim3(blocks_for(ext, BS)), dim3(BS), 0,
-                                      stream, b.u, b.ustar[0], P, b.scalars));
-  {
-    long long nf = (long long)(P.n[0] + 1) * (P.n[1] + 2) * (P.n[2] + 2);
-    TIMED(K_RIEMANN1_X, hipLaunchKernelGGL((k_riemann1<T, 0>), dim3(blocks_for(nf, BS)), dim3(BS),
-                                           0, stream, b.ustar[0], b.fstar[0], P, b.scalars));
-  }
-  TIMED(K_TRACE_Y, hipLaunchKernelGGL((k_trace<T, 1>), dim3(blocks_for(ext, BS)), dim3(BS), 0,
-                                      stream, b.u, b.ustar[1], P, b.scalars));
-  {
-    long long nf = (long long)(P.n[0] + 2) * (P.n[1] + 1) * (P.n[2] + 2);
-    TIMED(K_RIEMANN1_Y, hipLaunchKernelGGL((k_riemann1<T, 1>), dim3(blocks_for(nf, BS)), dim3(BS),
-                                           0, stream, b.ustar[1], b.fstar[1], P, b.scalars));
-  }
-  TIMED(K_TRACE_Z, hipLaunchKernelGGL((k_trace<T, 2>), dim3(blocks_for(ext, BS)), dim3(BS), 0,
-                                      stream, b.u, b.ustar[2], P, b.scalars));
-  {
-    long long nf = (long long)(P.n[0] + 2) * (P.n[1] + 2) * (P.n[2] + 1);
-    TIMED(K_RIEMANN1_Z, hipLaunchKernelGGL((k_riemann1<T, 2>), dim3(blocks_for(nf, BS)), dim3(BS),
-                                           0, stream, b.ustar[2], b.fstar[2], P, b.scalars));
-  }
-  // a6-a7 per direction
   const long long fds = b.fstar[1] - b.fstar[0];
+  const int nseg = (P.n[0] + 1 + XW - 1) / XW;
+  // stage 1 (a2-a5): F*, G*, H* on the extended transverse range
   {
-    long long nf = (long long)(P.n[0] + 1) * P.n[1] * P.n[2];
-    TIMED(K_RIEMANN2_X, hipLaunchKernelGGL((k_riemann2<T, 0>), dim3(blocks_for(nf, BS)), dim3(BS),
-                                           0, stream, b.ustar[0], b.fstar[0], b.fhalf[0], P,
-                                           b.scalars, fds));
+    long long tasks = (long long)nseg * (P.n[1] + 2) * (P.n[2] + 2);
+    TIMED(K_SWEEP1_X, hipLaunchKernelGGL((k_sweep_x<T, 1>), dim3(blocks_for(tasks, BS / 64)),
+                                         dim3(BS), 0, stream, b.u, b.fstar[0], b.fstar[0], P,
+                                         b.scalars, fds));
+    TIMED(K_SWEEP1_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 1>),
+                                         dim3(march_blocks(P, 1, true, BS)), dim3(BS), 0, stream,
+                                         b.u, b.fstar[0], b.fstar[1], P, b.scalars, fds));
+    TIMED(K_SWEEP1_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 1>),
+                                         dim3(march_blocks(P, 2, true, BS)), dim3(BS), 0, stream,
+                                         b.u, b.fstar[0], b.fstar[2], P, b.scalars, fds));
   }
+  // stage 2 (a2-a4 re-traced, a6-a7): F^{n+1/2}, G^{n+1/2}, H^{n+1/2} on the real faces
   {
-    long long nf = (long long)P.n[0] * (P.n[1] + 1) * P.n[2];
-    TIMED(K_RIEMANN2_Y, hipLaunchKernelGGL((k_riemann2<T, 1>), dim3(blocks_for(nf, BS)), dim3(BS),
-                                           0, stream, b.ustar[1], b.fstar[0], b.fhalf[1], P,
-                                           b.scalars, fds));
-  }
-  {
-    long long nf = (long long)P.n[0] * P.n[1] * (P.n[2] + 1);
-    TIMED(K_RIEMANN2_Z, hipLaunchKernelGGL((k_riemann2<T, 2>), dim3(blocks_for(nf, BS)), dim3(BS),
-                                           0, stream, b.ustar[2], b.fstar[0], b.fhalf[2], P,
-                                           b.scalars, fds));
+    long long tasks = (long long)nseg * P.n[1] * P.n[2];
+    TIMED(K_SWEEP2_X, hipLaunchKernelGGL((k_sweep_x<T, 2>), dim3(blocks_for(tasks, BS / 64)),
+                                         dim3(BS), 0, stream, b.u, b.fstar[0], b.fhalf[0], P,
+                                         b.scalars, fds));
+    TIMED(K_SWEEP2_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 2>),
+                                         dim3(march_blocks(P, 1, false, BS)), dim3(BS), 0, stream,
+                                         b.u, b.fstar[0], b.fhalf[1], P, b.scalars, fds));
+    TIMED(K_SWEEP2_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 2>),
+                                         dim3(march_blocks(P, 2, false, BS)), dim3(BS), 0, stream,
+                                         b.u, b.fstar[0], b.fhalf[2], P, b.scalars, fds));
   }
   // a8-a9
   const long long real = (long long)P.n[0] * P.n[1] * P.n[2];
+  const long long nblocks = blocks_for(real, BS);
   const long long hds = b.fhalf[1] - b.fhalf[0];
-  TIMED(K_UPDATE, hipLaunchKernelGGL(k_update<T>, dim3(blocks_for(real, BS)), dim3(BS), 0, stream,
-                                     b.u, b.fhalf[0], P, b.scalars, hds));
+  TIMED(K_UPDATE, hipLaunchKernelGGL(k_update<T>, dim3((unsigned)((nblocks + 7) / 8 * 8)), dim3(BS),
+                                     0, stream, b.u, b.fhalf[0], P, b.scalars, hds, b.part,
+                                     nblocks));
+  TIMED(K_DT_FINAL, hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, stream, b.part,
+                                       nblocks, b.scalars));
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_dt(T* u, const GridParams& P, DevScalars* s, hipStream_t stream) {
+hipError_t launch_dt(T* u, const GridParams& P, DevScalars* s, double* part, hipStream_t stream) {
   constexpr int BS = 256;
-  hipLaunchKernelGGL(k_reset_dt_bits, dim3(1), dim3(1), 0, stream, s);
   const long long real = (long long)P.n[0] * P.n[1] * P.n[2];
-  hipLaunchKernelGGL(k_dt<T>, dim3(blocks_for(real, BS)), dim3(BS), 0, stream, u, P, s);
+  const long long nblocks = blocks_for(real, BS);
+  hipLaunchKernelGGL(k_dt<T>, dim3((unsigned)((nblocks + 7) / 8 * 8)), dim3(BS), 0, stream, u, P,
+                     part, nblocks);
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, stream, part, nblocks, s);
   return hipGetLastError();
 }
 
@@ -607,7 +778,7 @@ hipError_t launch_end_step(DevScalars* s, hipStream_t stream) {
 #define CTU_INSTANTIATE(T)                                                                        \
   template hipError_t launch_step<T>(const StepBuffers<T>&, const GridParams&, const int*,       \
                                      hipStream_t, Profiler*);                                    \
-  template hipError_t launch_dt<T>(T*, const GridParams&, DevScalars*, hipStream_t);            \
+  template hipError_t launch_dt<T>(T*, const GridParams&, DevScalars*, double*, hipStream_t);   \
   template hipError_t launch_totals<T>(const T*, const GridParams&, double*, int, double*,      \
                                        hipStream_t);                                             \
   template hipError_t launch_scatter<T>(const T*, T*, const GridParams&, hipStream_t);          \

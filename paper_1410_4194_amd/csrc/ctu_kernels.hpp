@@ -9,23 +9,24 @@
 
 namespace ctu {
 
-// Device buffers of one grid.  ustar[d]: 10 fields (U*_L then U*_R of each cell);
-// fstar[d], fhalf[d]: 5 fields each; all with the grid's field stride.  fstar[0..2] and
-// fhalf[0..2] are equally spaced (the kernels address them from [0]).
+// Device buffers of one grid.  fstar[d] (first-stage fluxes) and fhalf[d] (CTU fluxes):
+// 5 fields each with the grid's field stride, face c+1/2 at the index of cell c;
+// fstar[0..2] and fhalf[0..2] are equally spaced (kernels address them from [0]).
+// part: one double per update block for the CFL reduction.
 template <typename T>
 struct StepBuffers {
   T* u;
-  T* ustar[3];
   T* fstar[3];
   T* fhalf[3];
   DevScalars* scalars;
+  double* part;
 };
 
 // Optional per-kernel timing: HIP events recorded on the launch stream around every kernel
 // of a step, accumulated per kernel class.
 enum KernelClass {
-  K_BC_X, K_BC_Y, K_BC_Z, K_TRACE_X, K_TRACE_Y, K_TRACE_Z, K_RIEMANN1_X, K_RIEMANN1_Y,
-  K_RIEMANN1_Z, K_RIEMANN2_X, K_RIEMANN2_Y, K_RIEMANN2_Z, K_UPDATE, K_NUM_CLASSES
+  K_BC_X, K_BC_Y, K_BC_Z, K_SWEEP1_X, K_SWEEP1_Y, K_SWEEP1_Z, K_SWEEP2_X, K_SWEEP2_Y,
+  K_SWEEP2_Z, K_UPDATE, K_DT_FINAL, K_NUM_CLASSES
 };
 const char* kernel_class_name(int k);
 
@@ -50,7 +51,7 @@ template <typename T>
 hipError_t launch_step(const StepBuffers<T>& b, const GridParams& P, const int bc[6],
                        hipStream_t stream, Profiler* prof);
 template <typename T>
-hipError_t launch_dt(T* u, const GridParams& P, DevScalars* s, hipStream_t stream);
+hipError_t launch_dt(T* u, const GridParams& P, DevScalars* s, double* part, hipStream_t stream);
 template <typename T>
 hipError_t launch_totals(const T* u, const GridParams& P, double* part, int nblocks, double* out,
                          hipStream_t stream);

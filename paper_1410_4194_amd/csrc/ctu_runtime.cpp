@@ -41,9 +41,16 @@ constexpr size_t kPartialOffset = 4096;
 constexpr int kTotalsBlocks = 1024;
 constexpr size_t kTotalsOutOffset = kPartialOffset + sizeof(double) * 5 * kTotalsBlocks;
 constexpr size_t kHeaderBytes = 65536;
-constexpr int kFieldsPerGrid = 60;  // ustar 3x10, fstar 3x5, fhalf 3x5
+constexpr int kFieldsPerGrid = 30;  // fstar 3x5, fhalf 3x5
 
 size_t elem_bytes(int prec) { return prec == CTU_FP32 ? 4 : 8; }
+
+// One double per 256-cell update block, for the block-partial CFL reduction.
+size_t partial_bytes(const ctu_config& c) {
+  const long long cells = (long long)c.nx * c.ny * c.nz;
+  const long long blocks = (cells + 255) / 256 + 64;
+  return (size_t)((blocks * 8 + 255) / 256 * 256);
+}
 
 long long alloc_cells(const ctu_config& c) {
   return (long long)(c.nx + 2 * NG) * (c.ny + 2 * NG) * (c.nz + 2 * NG);
@@ -103,6 +110,11 @@ GridParams make_params(const ctu_config& c) {
   double e = 2.0 / (g - 1.0);
   double r = std::nearbyint(e);
   P.fan_int_exp = (std::fabs(e - r) < 1e-12 && r >= 1.0 && r <= 16.0) ? (int)r : 0;
+  double m = 2.0 * g / (g - 1.0);
+  double mr = std::nearbyint(m);
+  P.root_m = (std::fabs(m - mr) < 1e-12 && mr >= 2.0 && mr <= 16.0) ? (int)mr : 0;
+  P.inv_root_m = (g - 1.0) / (2.0 * g);
+  P.inv_gm1 = 1.0 / (g - 1.0);
   return P;
 }
 
@@ -121,16 +133,19 @@ struct ctu_grid {
   double* partial() const { return reinterpret_cast<double*>(d_work + kPartialOffset); }
   double* totals_out() const { return reinterpret_cast<double*>(d_work + kTotalsOutOffset); }
   char* fields() const { return d_work + kHeaderBytes; }
+  double* partials() const {
+    return reinterpret_cast<double*>(d_work + kHeaderBytes + (size_t)kFieldsPerGrid * fbytes());
+  }
   size_t fbytes() const { return (size_t)P.stride * elem_bytes(cfg.prec); }
   template <typename T>
   ctu::StepBuffers<T> buffers() const {
     ctu::StepBuffers<T> b;
     b.u = reinterpret_cast<T*>(d_state);
     T* f = reinterpret_cast<T*>(fields());
-    for (int d = 0; d < 3; ++d) b.ustar[d] = f + (size_t)(10 * d) * P.stride;
-    for (int d = 0; d < 3; ++d) b.fstar[d] = f + (size_t)(30 + 5 * d) * P.stride;
-    for (int d = 0; d < 3; ++d) b.fhalf[d] = f + (size_t)(45 + 5 * d) * P.stride;
+    for (int d = 0; d < 3; ++d) b.fstar[d] = f + (size_t)(5 * d) * P.stride;
+    for (int d = 0; d < 3; ++d) b.fhalf[d] = f + (size_t)(15 + 5 * d) * P.stride;
     b.scalars = scalars();
+    b.part = partials();
     return b;
   }
 };
@@ -153,9 +168,9 @@ ctu_status ensure_dt(ctu_grid* g) {
   if (g->dt_valid) return CTU_OK;
   hipError_t e = g->cfg.prec == CTU_FP64
                      ? ctu::launch_dt<double>(reinterpret_cast<double*>(g->d_state), g->P,
-                                              g->scalars(), g->stream)
+                                              g->scalars(), g->partials(), g->stream)
                      : ctu::launch_dt<float>(reinterpret_cast<float*>(g->d_state), g->P,
-                                             g->scalars(), g->stream);
+                                             g->scalars(), g->partials(), g->stream);
   if (e != hipSuccess) return hip_fail(e, "dt launch");
   g->dt_valid = true;
   return CTU_OK;
@@ -204,7 +219,8 @@ ctu_status ctu_workspace_bytes(const ctu_config* cfg, size_t* state_bytes, size_
   const size_t eb = elem_bytes(cfg->prec);
   const long long stride = field_stride(*cfg);
   if (state_bytes) *state_bytes = (size_t)5 * stride * eb;
-  if (work_bytes) *work_bytes = kHeaderBytes + (size_t)kFieldsPerGrid * stride * eb;
+  if (work_bytes)
+    *work_bytes = kHeaderBytes + (size_t)kFieldsPerGrid * stride * eb + partial_bytes(*cfg);
   return CTU_OK;
 }
 
@@ -344,7 +360,7 @@ ctu_status ctu_get_state(ctu_grid* g, void* const h_fields[5]) {
     HIP_TRY(hipMemcpyAsync(h_fields[f], staging + f * ncell * eb, ncell * eb, hipMemcpyDeviceToHost,
                            g->stream),
             "get_state copy");
-  // the staging area overlaps the traced states: the next step's dt stays valid
+  // the staging area is the flux scratch: the device CFL bound stays valid
   DevScalars s;
   ctu_status st = read_scalars(g, &s);
   if (st != CTU_OK) return st;
@@ -430,7 +446,7 @@ ctu_status ctu_debug_fluxes(ctu_grid* g, int32_t which, int32_t dir, double* con
     return fail(CTU_EINVAL, "bad argument");
   const size_t n = (size_t)alloc_cells(g->cfg);
   const size_t eb = elem_bytes(g->cfg.prec);
-  const size_t base = (which == 0 ? 30 : 45) + 5 * dir;
+  const size_t base = (which == 0 ? 0 : 15) + 5 * dir;
   std::vector<char> tmp(n * eb);
   for (int f = 0; f < 5; ++f) {
     HIP_TRY(hipMemcpyAsync(tmp.data(), g->fields() + (base + f) * g->fbytes(), n * eb,

@@ -19,7 +19,8 @@ import numpy as np
 import torch  # noqa: F401  (must precede loading libctu.so, see above)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libctu.so")
+# CTU_LIBRARY selects another build of the same library (A/B timing of builds)
+LIB_PATH = os.environ.get("CTU_LIBRARY") or os.path.join(_HERE, "libctu.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, ENOCONV, EAGAIN = 0, -1, -2, -3, -4, -5, -6
 BC_PERIODIC, BC_OUTFLOW = 0, 1

@@ -165,7 +165,7 @@ def gaussian_random_field(n: int, slope: float, seed: int) -> np.ndarray:
     filt = k2 ** (slope / 4.0)
     filt[0, 0, 0] = 0.0
     fk *= filt
-    g = np.fft.irfftn(fk, s=(n, n, n))
+    g = np.fft.irfftn(fk, s=(n, n, n), axes=(0, 1, 2))
     return g
 
 

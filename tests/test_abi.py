@@ -45,7 +45,7 @@ def test_workspace_bytes_and_validation(ctu):
     na = 262 ** 3
     stride = (na + 63) // 64 * 64
     assert sb == 5 * stride * 8
-    assert wb >= 60 * stride * 8
+    assert wb >= 30 * stride * 8  # first-stage and CTU fluxes, 15 fields each
     cfg32 = ctu.make_config(8, 8, 8, 1, 1, 1, 1.4, prec=ctu.FP32)
     sb32, _ = ctu.workspace_bytes(cfg32)
     assert sb32 == 5 * ((14 ** 3 + 63) // 64 * 64) * 4
