@@ -124,8 +124,9 @@ ctu_status ctu_compute_dt(ctu_grid* g, double* dt);
 ctu_status ctu_step(ctu_grid* g, double dt);
 
 /* nsteps CTU steps with the time step computed on the device from the state each step
- * starts with, the last one clipped so that t does not pass t_end (steps after t_end are
- * no-ops).  No host synchronization; safe to capture in a HIP graph.  Async. */
+ * starts with, the last one clipped so that t does not pass t_end (steps after t_end, and
+ * steps after an update was flagged non-physical, are no-ops).  No host synchronization.
+ * Async. */
 ctu_status ctu_advance(ctu_grid* g, int32_t nsteps, double t_end);
 
 /* Sums over the real cells of the five conserved fields, accumulated in double in a fixed
@@ -158,17 +159,36 @@ ctu_status ctu_profile_read(ctu_grid* g, int32_t max_classes, double* ms, int64_
 const char* ctu_profile_name(int32_t k);
 
 /* ---- Batches: many independent grids advanced together ----------------------------------
- * A batch owns max_slots slots.  ctu_batch_submit places a grid in a free slot (CTU_EAGAIN
- * when none is free) with a step budget and an end time; ctu_batch_run advances every
- * running slot by up to `steps` steps (each grid with its own device-side time step); a slot
- * is DONE when its grid reached t_end or used its step budget, and FAILED if a syncing check
- * found a non-physical state.  ctu_batch_poll reports a ticket's state; a DONE or FAILED
- * ticket frees its slot when polled.  Grids must stay alive while submitted. */
+ * Continuous batching of independent grids (each created as above, any sizes, boundary
+ * types and precisions).  Every pass of a step is one launch over all running grids of a
+ * precision, each grid taking its own device-side time step as in ctu_advance, so small
+ * grids share the GPU instead of running one after another.
+ *
+ * ctu_batch_workspace_bytes: device bytes a batch of max_slots slots needs (1..65536).
+ * ctu_batch_create: a batch over a caller-owned device buffer d_work (>= those bytes,
+ *   256-byte aligned), ordered after and before the work of hip_stream (NULL = default
+ *   stream); batch work itself runs on a stream of the batch's own, of default priority.
+ *   flags: CTU_BATCH_GRAPH captures one step of the current set of grids in a HIP graph and
+ *   replays it (recaptured whenever the set changes).  Creates a stream and two events.
+ * ctu_batch_submit: places grid g in a free slot (CTU_EAGAIN when none is free) with a step
+ *   budget nsteps >= 0 and an end time t_end; enqueues its CFL reduction on the grid's
+ *   stream and orders the batch after it.  Until its ticket ends, every other call on g
+ *   fails with CTU_EINVAL.  Async.
+ * ctu_batch_run: enqueues `steps` steps of every running grid; grids that used their budget,
+ *   reached t_end or were found non-physical take no-op steps.  Async.
+ * ctu_batch_poll: state of a ticket (CTU_TICKET_RUNNING, DONE, FAILED = non-physical state,
+ *   UNKNOWN = no such ticket) and its simulation time.  A DONE or FAILED ticket releases its
+ *   slot and its grid, whose state can then be read with ctu_get_state.  Syncs the batch
+ *   stream (one read-back for all slots until the next submit or run).
+ * ctu_batch_destroy: waits for the batch stream and releases every grid. */
 enum { CTU_TICKET_QUEUED = 0, CTU_TICKET_RUNNING = 1, CTU_TICKET_DONE = 2, CTU_TICKET_FAILED = 3,
        CTU_TICKET_UNKNOWN = -1 };
-ctu_status ctu_batch_create(int32_t max_slots, void* hip_stream, ctu_batch** out);
+enum { CTU_BATCH_GRAPH = 1 };
+ctu_status ctu_batch_workspace_bytes(int32_t max_slots, size_t* work_bytes);
+ctu_status ctu_batch_create(int32_t max_slots, void* d_work, size_t work_bytes, void* hip_stream,
+                            int32_t flags, ctu_batch** out);
 ctu_status ctu_batch_submit(ctu_batch* b, ctu_grid* g, int32_t nsteps, double t_end,
-                            uint64_t* ticket);
+                            uint64_t* ticket); /* async */
 ctu_status ctu_batch_run(ctu_batch* b, int32_t steps); /* async */
 ctu_status ctu_batch_poll(ctu_batch* b, uint64_t ticket, int32_t* state, double* t_now); /* syncs */
 ctu_status ctu_batch_destroy(ctu_batch* b);

@@ -50,7 +50,8 @@ struct DevScalars {
   unsigned int pad0;
   unsigned long long counters[4];   // p-floor hits, Newton caps, non-physical cells, reserved
   long long steps;
-  double t_end;                     // end time used by the device-side dt of ctu_advance
+  double t_end;                     // end time of the device-side time step
+  long long steps_left;             // step budget of the device-side time step
 };
 
 __device__ __forceinline__ long long cell_index(const GridParams& P, int i, int j, int k) {

@@ -3,9 +3,9 @@
 // correction and second Riemann solve, conservative update fused with the CFL reduction.
 //
 // Data layout: structure of arrays over the allocated box, x fastest, three ghost layers
-// (see ctu.h).  Interface arrays store face c+1/2 at the index of cell c.  All kernels are
-// one thread per cell or face with x as the fastest thread index, so every global access
-// of a wavefront is a contiguous run along x.
+// (see ctu.h).  Interface arrays store face c+1/2 at the index of cell c.  Threads run along
+// x, so every global access of a wavefront is a contiguous run along x.  Each launch serves a
+// table of grids (ctu_kernels.hpp); a block finds its grid and local block index first.
 #include "ctu_kernels.hpp"
 
 namespace ctu {
@@ -17,8 +17,33 @@ __device__ __forceinline__ int rot(int s) {
   return 1 + ((s - 1 + D) % 3);
 }
 
-__device__ __forceinline__ double ordered_min_to_double(unsigned long long b) {
-  return __longlong_as_double((long long)b);
+// Grid owning block b of a launch: start[g] <= b < start[g+1].
+__device__ __forceinline__ int find_grid(const int* __restrict__ start, int ngrids, int b) {
+  int lo = 0, hi = ngrids;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+struct BlockRef {
+  const GridDesc* G;
+  long long lb;  // block index within the grid's range
+  long long nb;  // padded block count of the grid's range
+};
+
+__device__ __forceinline__ BlockRef block_ref(const LaunchTab& tab) {
+  const int b = blockIdx.x;
+  const int g = find_grid(tab.start, tab.ngrids, b);
+  BlockRef r;
+  r.G = tab.grids + g;
+  r.lb = b - tab.start[g];
+  r.nb = tab.start[g + 1] - tab.start[g];
+  return r;
 }
 
 // ---- reductions --------------------------------------------------------------------------
@@ -34,6 +59,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Block minimum of v written to part[lb] (no atomics); every thread must call it.
+__device__ __forceinline__ void block_min_store(double v, double* part, long long lb) {
+  __shared__ double smin[32];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  v = wave_min(v);
+  if (lane == 0) smin[wave] = v;
+  __syncthreads();
+  if (wave == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double m = lane < nw ? smin[lane] : INFINITY;
+    m = wave_min(m);
+    if (lane == 0) part[lb] = m;
+  }
+}
+
 // Per-cell CFL bound min(dx/(|u|+a), dy/(|v|+a), dz/(|w|+a)) (eq. calc_dt_3D without C0).
 template <typename T>
 __device__ __forceinline__ double cell_dt_bound(const T U[5], const GridParams& P) {
@@ -46,59 +87,90 @@ __device__ __forceinline__ double cell_dt_bound(const T U[5], const GridParams& 
   return fmin(tx, fmin(ty, tz));
 }
 
+// Workgroups are dealt to the 8 XCDs round robin; within a grid's block range (which starts
+// at a multiple of 8) this gives each XCD a contiguous run of logical blocks.
+__device__ __forceinline__ long long xcd_local(long long lb, long long nb) {
+  const long long per = nb / 8;
+  return (lb % 8) * per + lb / 8;
+}
+
 // ---- step bookkeeping ----------------------------------------------------------------------
 __global__ void k_set_dt(DevScalars* s, double dt) { s->dt = dt; }
 
-// Device-side time step for ctu_advance: C0 * (min CFL bound), clipped to t_end - t.
-__global__ void k_begin_step(DevScalars* s, double cfl, double t_end) {
-  double bound = ordered_min_to_double(s->dt_next_bits);
-  double dt = fmin(cfl * bound, t_end - s->t);
-  s->dt = dt;
+__global__ void k_set_end(DevScalars* s, double t_end, long long steps_left) {
+  s->t_end = t_end;
+  s->steps_left = steps_left;
 }
 
-__global__ void k_end_step(DevScalars* s) {
-  if (s->dt > 0.0) {
-    s->t += s->dt;
-    s->steps += 1;
+// Device-side time step of every grid: C0 * (min CFL bound), clipped to t_end - t; a grid
+// whose step budget is used up, or whose state was flagged non-physical, takes dt = 0 (its
+// passes become no-ops).
+__global__ void k_begin_step(const GridDesc* __restrict__ grids, int ngrids) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ngrids; g += gridDim.x * blockDim.x) {
+    DevScalars* s = grids[g].s;
+    const double bound = __longlong_as_double((long long)s->dt_next_bits);
+    double dt = fmin(grids[g].P.cfl * bound, s->t_end - s->t);
+    if (s->steps_left <= 0 || (s->flags & 3u)) dt = 0.0;  // budget used up, or non-physical
+    s->dt = dt;
   }
 }
 
+__global__ void k_end_step(const GridDesc* __restrict__ grids, int ngrids) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ngrids; g += gridDim.x * blockDim.x) {
+    DevScalars* s = grids[g].s;
+    if (s->dt > 0.0) {
+      s->t += s->dt;
+      s->steps += 1;
+      s->steps_left -= 1;
+    }
+  }
+}
+
+// Copies of the scalars of n grids into one array (one read-back for a whole batch).
+__global__ void k_gather_scalars(DevScalars* const* __restrict__ src, int n, DevScalars* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = *src[i];
+}
 
 // ---- a1: ghost fill (Sec. 3.1) ------------------------------------------------------------
-// Axis `axis` ghosts over the full extent of the other two axes (ghosts included), so
+// Axis AXIS ghosts over the full extent of the other two axes (ghosts included), so
 // running x, then y, then z fills edges and corners consistently.
-template <typename T>
-__global__ void k_bc_fill(T* __restrict__ u, GridParams P, int axis, int bc_lo, int bc_hi) {
-  const int n = P.n[axis];
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+template <typename T, int AXIS>
+__global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab) {
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  if (!(r.G->s->dt > 0.0)) return;
+  T* __restrict__ u = reinterpret_cast<T*>(r.G->u);
+  const int n = P.n[AXIS];
+  const long long tid = r.lb * blockDim.x + threadIdx.x;
   int i, j, k, layer;
-  if (axis == 0) {
-    long long total = 2LL * NG * P.N[1] * P.N[2];
+  if (AXIS == 0) {
+    const long long total = 2LL * NG * P.N[1] * P.N[2];
     if (tid >= total) return;
     layer = (int)(tid % (2 * NG));
-    long long r = tid / (2 * NG);
-    j = (int)(r % P.N[1]) - NG;
-    k = (int)(r / P.N[1]) - NG;
+    const long long q = tid / (2 * NG);
+    j = (int)(q % P.N[1]) - NG;
+    k = (int)(q / P.N[1]) - NG;
     i = 0;
-  } else if (axis == 1) {
-    long long total = 2LL * NG * P.N[0] * P.N[2];
+  } else if (AXIS == 1) {
+    const long long total = 2LL * NG * P.N[0] * P.N[2];
     if (tid >= total) return;
     i = (int)(tid % P.N[0]) - NG;
-    long long r = tid / P.N[0];
-    layer = (int)(r % (2 * NG));
-    k = (int)(r / (2 * NG)) - NG;
+    const long long q = tid / P.N[0];
+    layer = (int)(q % (2 * NG));
+    k = (int)(q / (2 * NG)) - NG;
     j = 0;
   } else {
-    long long total = 2LL * NG * P.N[0] * P.N[1];
+    const long long total = 2LL * NG * P.N[0] * P.N[1];
     if (tid >= total) return;
     i = (int)(tid % P.N[0]) - NG;
-    long long r = tid / P.N[0];
-    j = (int)(r % P.N[1]) - NG;
-    layer = (int)(r / P.N[1]);
+    const long long q = tid / P.N[0];
+    j = (int)(q % P.N[1]) - NG;
+    layer = (int)(q / P.N[1]);
     k = 0;
   }
   const int q = layer < NG ? layer - NG : n + (layer - NG);
-  const int bc = layer < NG ? bc_lo : bc_hi;
+  const int bc = layer < NG ? r.G->bc[2 * AXIS] : r.G->bc[2 * AXIS + 1];
   int src;
   if (bc == 0) {
     src = q % n;
@@ -106,14 +178,11 @@ __global__ void k_bc_fill(T* __restrict__ u, GridParams P, int axis, int bc_lo, 
   } else {
     src = q < 0 ? 0 : n - 1;
   }
-  int dst_pos[3] = {i, j, k};
-  int src_pos[3] = {i, j, k};
-  dst_pos[axis] = q;
-  src_pos[axis] = src;
-  const long long d = cell_index(P, dst_pos[0], dst_pos[1], dst_pos[2]);
-  const long long s = cell_index(P, src_pos[0], src_pos[1], src_pos[2]);
+  const long long d = cell_index(P, AXIS == 0 ? q : i, AXIS == 1 ? q : j, AXIS == 2 ? q : k);
+  const long long sidx =
+      cell_index(P, AXIS == 0 ? src : i, AXIS == 1 ? src : j, AXIS == 2 ? src : k);
 #pragma unroll
-  for (int f = 0; f < 5; ++f) u[f * P.stride + d] = u[f * P.stride + s];
+  for (int f = 0; f < 5; ++f) u[f * P.stride + d] = u[f * P.stride + sidx];
 }
 
 // ---- fused sweeps --------------------------------------------------------------------------
@@ -121,19 +190,9 @@ __global__ void k_bc_fill(T* __restrict__ u, GridParams P, int axis, int bc_lo, 
 // kernel.  Along y and z a thread owns one column and marches along D over a segment of SEG
 // faces, keeping a register window of primitives (cells c-1..c+2) and limited slopes
 // (c-1..c+1): every primitive, slope and trace is computed once per cell (plus a short
-// warm-up per segment) and each face's Riemann problem once.  Lanes run along x, so every
-// load and store of a wavefront is contiguous.  Along x a wavefront covers 64 consecutive
-// cells of one row and exchanges neighbours with lane shuffles; it yields 59 faces.
-constexpr int SEG = 32;
-constexpr int XW = 59;  // x-faces per wavefront in the shuffle kernels
-
-// Workgroups are assigned to XCDs round robin by the hardware; xcd_block gives each XCD a
-// contiguous range of logical blocks so neighbouring rows share one L2.
-__device__ __forceinline__ long long xcd_block(long long nblocks) {
-  const long long b = blockIdx.x;
-  const long long per = (nblocks + 7) / 8;
-  return (b % 8) * per + b / 8;
-}
+// warm-up per segment) and each face's Riemann problem once.  Along x a wavefront covers 64
+// consecutive cells of one row and exchanges neighbours with lane shuffles; it yields XW
+// faces.
 
 template <typename T, int D>
 __device__ __forceinline__ void load_prim(const T* __restrict__ u, long long stride, long long id,
@@ -204,34 +263,35 @@ __device__ __forceinline__ void flush_counts(const RiemannCounts& cnt, DevScalar
 }
 
 // STAGE = 1: first-stage fluxes F*_D on faces c-1/2, c in [0, n_D], transverse range
-//            [-1, n] on both other axes; written to out at cell c-1.
+//            [-1, n] on both other axes; written at cell c-1.
 // STAGE = 2: CTU fluxes F^{n+1/2}_D on the same faces over the real transverse range, from
 //            the re-traced states plus the transverse flux differences of stage 1.
+// Block layout per grid: (plane block of kBlock columns, segment), plane blocks fastest.
 template <typename T, int D, int STAGE>
-__global__ __launch_bounds__(256, 2) void k_sweep_march(const T* __restrict__ u,
-                                                     const T* __restrict__ fstar_all,
-                                                     T* __restrict__ out, GridParams P,
-                                                     DevScalars* __restrict__ s, long long fds) {
+__global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   static_assert(D == 1 || D == 2, "marching sweeps run along y or z");
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  DevScalars* __restrict__ s = r.G->s;
   const double dt = s->dt;
   if (!(dt > 0.0)) return;
+  const T* __restrict__ u = reinterpret_cast<const T*>(r.G->u);
+  const T* __restrict__ fstar_all = reinterpret_cast<const T*>(r.G->flux);
+  const long long fds = 5 * P.stride;
+  T* __restrict__ out = reinterpret_cast<T*>(r.G->flux) + (STAGE == 1 ? D : 3 + D) * fds;
   constexpr int B = (D == 1) ? 2 : 1;  // the transverse axis other than x
   const int lo = STAGE == 1 ? -1 : 0;
   const int ea = P.n[0] + (STAGE == 1 ? 2 : 0);
   const int eb = P.n[B] + (STAGE == 1 ? 2 : 0);
   const int nd = P.n[D];
-  // block = (plane block, segment), plane blocks fastest (a contiguous-in-x column set per
-  // block; measured faster than an XCD-grouped order for these sweeps)
-  const long long nbx = ((long long)ea * eb + blockDim.x - 1) / blockDim.x;
+  const long long nbx = ((long long)ea * eb + kBlock - 1) / kBlock;
   const long long nseg = (nd + 1 + SEG - 1) / SEG;
-  const long long lb = blockIdx.x;
-  if (lb >= nbx * nseg) return;
-  const long long tid = (lb % nbx) * blockDim.x + threadIdx.x;
+  if (r.lb >= nbx * nseg) return;
+  const long long tid = (r.lb % nbx) * kBlock + threadIdx.x;
   if (tid >= (long long)ea * eb) return;
   const int i = (int)(tid % ea) + lo;
   const int o = (int)(tid / ea) + lo;
-  const int f0 = (int)(lb / nbx) * SEG;
-  if (f0 > nd) return;
+  const int f0 = (int)(r.lb / nbx) * SEG;
   const int f1 = min(f0 + SEG, nd + 1);
   const long long stx = 1, sty = P.N[0], stz = (long long)P.N[0] * P.N[1];
   const long long sd = D == 1 ? sty : stz;
@@ -328,14 +388,18 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(const T* __restrict__ u,
 // x-direction sweep: one wavefront per (row, segment of XW faces).  Lane l holds cell
 // cw - 3 + l; slopes are valid on lanes 1..62, traces on 2..61, faces c-1/2 on 3..61.
 template <typename T, int STAGE>
-__global__ __launch_bounds__(256) void k_sweep_x(const T* __restrict__ u,
-                                                 const T* __restrict__ fstar_all,
-                                                 T* __restrict__ out, GridParams P,
-                                                 DevScalars* __restrict__ s, long long fds) {
+__global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  DevScalars* __restrict__ s = r.G->s;
   const double dt = s->dt;
   if (!(dt > 0.0)) return;
+  const T* __restrict__ u = reinterpret_cast<const T*>(r.G->u);
+  const T* __restrict__ fstar_all = reinterpret_cast<const T*>(r.G->flux);
+  const long long fds = 5 * P.stride;
+  T* __restrict__ out = reinterpret_cast<T*>(r.G->flux) + (STAGE == 1 ? 0 : 3) * fds;
   const int lane = threadIdx.x & 63;
-  const long long task = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const long long task = r.lb * (kBlock / 64) + (threadIdx.x >> 6);
   const int lo = STAGE == 1 ? -1 : 0;
   const int ey = P.n[1] + (STAGE == 1 ? 2 : 0);
   const int ez = P.n[2] + (STAGE == 1 ? 2 : 0);
@@ -399,34 +463,23 @@ __global__ __launch_bounds__(256) void k_sweep_x(const T* __restrict__ u,
 }
 
 // ---- a8-a9: conservative update and CFL reduction ------------------------------------------
-
-// Block minimum of v written to part[lb] (no atomics); every thread must call it.
-__device__ __forceinline__ void block_min_store(double v, double* part, long long lb) {
-  __shared__ double smin[32];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  v = wave_min(v);
-  if (lane == 0) smin[wave] = v;
-  __syncthreads();
-  if (wave == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    double m = lane < nw ? smin[lane] : INFINITY;
-    m = wave_min(m);
-    if (lane == 0) part[lb] = m;
-  }
-}
-
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(T* __restrict__ u, const T* __restrict__ fhalf_all,
-                                                GridParams P, DevScalars* __restrict__ s,
-                                                long long fdir_stride, double* __restrict__ part,
-                                                long long nblocks) {
+__global__ __launch_bounds__(256) void k_update(LaunchTab tab) {
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  DevScalars* __restrict__ s = r.G->s;
   const double dt = s->dt;
-  if (!(dt > 0.0)) return;
-  const long long lb = xcd_block(nblocks);
-  if (lb >= nblocks) return;  // whole block idle
-  const long long tid = lb * blockDim.x + threadIdx.x;
+  if (!(dt > 0.0)) return;  // a no-op step keeps the previous partials (state unchanged)
   const long long total = (long long)P.n[0] * P.n[1] * P.n[2];
+  const long long nblocks = (total + kBlock - 1) / kBlock;
+  const long long lb = xcd_local(r.lb, r.nb);
+  if (lb >= nblocks) return;  // whole block idle
+  T* __restrict__ u = reinterpret_cast<T*>(r.G->u);
+  const long long fds = 5 * P.stride;
+  const T* __restrict__ Fx = reinterpret_cast<const T*>(r.G->flux) + 3 * fds;
+  const T* __restrict__ Fy = Fx + fds;
+  const T* __restrict__ Fz = Fy + fds;
+  const long long tid = lb * kBlock + threadIdx.x;
   double bound = INFINITY;
   if (tid < total) {
     const int i = (int)(tid % P.n[0]);
@@ -435,9 +488,6 @@ __global__ __launch_bounds__(256) void k_update(T* __restrict__ u, const T* __re
     const long long c = cell_index(P, i, j, k);
     const long long st[3] = {1, (long long)P.N[0], (long long)P.N[0] * P.N[1]};
     const T dtdx = T(dt / P.dx[0]), dtdy = T(dt / P.dx[1]), dtdz = T(dt / P.dx[2]);
-    const T* Fx = fhalf_all;
-    const T* Fy = fhalf_all + fdir_stride;
-    const T* Fz = fhalf_all + 2 * fdir_stride;
     T U[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
@@ -459,16 +509,19 @@ __global__ __launch_bounds__(256) void k_update(T* __restrict__ u, const T* __re
       bound = cell_dt_bound(U, P);
     }
   }
-  block_min_store(bound, part, lb);
+  block_min_store(bound, r.G->part, lb);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_dt(const T* __restrict__ u, GridParams P,
-                                            double* __restrict__ part, long long nblocks) {
-  const long long lb = xcd_block(nblocks);
-  if (lb >= nblocks) return;
-  const long long tid = lb * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_dt(LaunchTab tab) {
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
   const long long total = (long long)P.n[0] * P.n[1] * P.n[2];
+  const long long nblocks = (total + kBlock - 1) / kBlock;
+  const long long lb = xcd_local(r.lb, r.nb);
+  if (lb >= nblocks) return;
+  const T* __restrict__ u = reinterpret_cast<const T*>(r.G->u);
+  const long long tid = lb * kBlock + threadIdx.x;
   double bound = INFINITY;
   if (tid < total) {
     const int i = (int)(tid % P.n[0]);
@@ -480,15 +533,16 @@ __global__ __launch_bounds__(256) void k_dt(const T* __restrict__ u, GridParams 
     for (int f = 0; f < 5; ++f) U[f] = u[f * P.stride + c];
     bound = cell_dt_bound(U, P);
   }
-  block_min_store(bound, part, lb);
+  block_min_store(bound, r.G->part, lb);
 }
 
-// Minimum of the block partials into dt_next_bits (one block of 1024 threads).
-__global__ __launch_bounds__(1024) void k_dt_final(const double* __restrict__ part, long long nblocks,
-                                                   DevScalars* __restrict__ s) {
-  // After a no-op step (dt <= 0) the partials still hold the bound of the unchanged state.
+// Minimum of each grid's block partials into its dt_next_bits: block g reduces grid g.
+__global__ __launch_bounds__(1024) void k_dt_final(const GridDesc* __restrict__ grids) {
+  const GridDesc& G = grids[blockIdx.x];
+  const long long total = (long long)G.P.n[0] * G.P.n[1] * G.P.n[2];
+  const long long nblocks = (total + kBlock - 1) / kBlock;
   double m = INFINITY;
-  for (long long b = threadIdx.x; b < nblocks; b += blockDim.x) m = fmin(m, part[b]);
+  for (long long b = threadIdx.x; b < nblocks; b += blockDim.x) m = fmin(m, G.part[b]);
   __shared__ double smin[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   m = wave_min(m);
@@ -497,7 +551,7 @@ __global__ __launch_bounds__(1024) void k_dt_final(const double* __restrict__ pa
   if (wave == 0) {
     double v = lane < (int)(blockDim.x >> 6) ? smin[lane] : INFINITY;
     v = wave_min(v);
-    if (lane == 0) s->dt_next_bits = (unsigned long long)__double_as_longlong(v);
+    if (lane == 0) G.s->dt_next_bits = (unsigned long long)__double_as_longlong(v);
   }
 }
 
@@ -649,17 +703,27 @@ Profiler::~Profiler() {
   for (auto e : pool) (void)hipEventDestroy(e);
 }
 
-// ---- launch wrappers ------------------------------------------------------------------------
-static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+// ---- launch sizes and sequence ----------------------------------------------------------------
+static inline long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 
-// 1D grid of a marching sweep along D: (plane blocks x segments), padded to a multiple of 8
-// for the XCD remap.
-static inline unsigned march_blocks(const GridParams& P, int D, bool extended, int bs) {
-  const int B = D == 1 ? 2 : 1;
-  const long long ea = P.n[0] + (extended ? 2 : 0), eb = P.n[B] + (extended ? 2 : 0);
-  const long long nbx = (ea * eb + bs - 1) / bs;
-  const long long nseg = (P.n[D] + 1 + SEG - 1) / SEG;
-  return (unsigned)((nbx * nseg + 7) / 8 * 8);
+long long pass_blocks(const GridParams& P, int pass) {
+  const long long n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const long long N0 = P.N[0], N1 = P.N[1], N2 = P.N[2];
+  const long long nseg_x = cdiv(n0 + 1, XW);
+  switch (pass) {
+    case P_BC_X: return cdiv(2LL * NG * N1 * N2, kBlock);
+    case P_BC_Y: return cdiv(2LL * NG * N0 * N2, kBlock);
+    case P_BC_Z: return cdiv(2LL * NG * N0 * N1, kBlock);
+    case P_S1_X: return cdiv(nseg_x * (n1 + 2) * (n2 + 2), kBlock / 64);
+    case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1 + 1, SEG);
+    case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2 + 1, SEG);
+    case P_S2_X: return cdiv(nseg_x * n1 * n2, kBlock / 64);
+    case P_S2_Y: return cdiv(n0 * n2, kBlock) * cdiv(n1 + 1, SEG);
+    case P_S2_Z: return cdiv(n0 * n1, kBlock) * cdiv(n2 + 1, SEG);
+    case P_UPDATE:
+    case P_DT: return cdiv(n0 * n1 * n2, kBlock);
+  }
+  return 0;
 }
 
 #define TIMED(cls, launch)              \
@@ -670,65 +734,81 @@ static inline unsigned march_blocks(const GridParams& P, int D, bool extended, i
   } while (0)
 
 template <typename T>
-hipError_t launch_step(const StepBuffers<T>& b, const GridParams& P, const int bc[6],
-                       hipStream_t stream, Profiler* prof) {
-  constexpr int BS = 256;
+static void enqueue_step(const PlanView& v, bool device_dt, hipStream_t stream, Profiler* prof) {
+  const int stride = v.ngrids + 1;
+  auto tab = [&](int pass) { return LaunchTab{v.d_grids, v.d_start + pass * stride, v.ngrids}; };
+  auto nblocks = [&](int pass) { return dim3((unsigned)v.h_start[pass * stride + v.ngrids]); };
+  const dim3 B(kBlock);
+  const dim3 gsmall((unsigned)cdiv(v.ngrids, kBlock));
+  if (device_dt) hipLaunchKernelGGL(k_begin_step, gsmall, B, 0, stream, v.d_grids, v.ngrids);
   // a1: ghost fill x, then y, then z
-  for (int axis = 0; axis < 3; ++axis) {
-    const int o1 = axis == 0 ? 1 : 0, o2 = axis == 2 ? 1 : 2;
-    long long total = 2LL * NG * P.N[o1] * P.N[o2];
-    TIMED(K_BC_X + axis,
-          hipLaunchKernelGGL(k_bc_fill<T>, dim3(blocks_for(total, BS)), dim3(BS), 0, stream, b.u,
-                             P, axis, bc[2 * axis], bc[2 * axis + 1]));
-  }
-  const long long fds = b.fstar[1] - b.fstar[0];
-  const int nseg = (P.n[0] + 1 + XW - 1) / XW;
+  TIMED(K_BC_X,
+        hipLaunchKernelGGL((k_bc_fill<T, 0>), nblocks(P_BC_X), B, 0, stream, tab(P_BC_X)));
+  TIMED(K_BC_Y,
+        hipLaunchKernelGGL((k_bc_fill<T, 1>), nblocks(P_BC_Y), B, 0, stream, tab(P_BC_Y)));
+  TIMED(K_BC_Z,
+        hipLaunchKernelGGL((k_bc_fill<T, 2>), nblocks(P_BC_Z), B, 0, stream, tab(P_BC_Z)));
   // stage 1 (a2-a5): F*, G*, H* on the extended transverse range
-  {
-    long long tasks = (long long)nseg * (P.n[1] + 2) * (P.n[2] + 2);
-    TIMED(K_SWEEP1_X, hipLaunchKernelGGL((k_sweep_x<T, 1>), dim3(blocks_for(tasks, BS / 64)),
-                                         dim3(BS), 0, stream, b.u, b.fstar[0], b.fstar[0], P,
-                                         b.scalars, fds));
-    TIMED(K_SWEEP1_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 1>),
-                                         dim3(march_blocks(P, 1, true, BS)), dim3(BS), 0, stream,
-                                         b.u, b.fstar[0], b.fstar[1], P, b.scalars, fds));
-    TIMED(K_SWEEP1_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 1>),
-                                         dim3(march_blocks(P, 2, true, BS)), dim3(BS), 0, stream,
-                                         b.u, b.fstar[0], b.fstar[2], P, b.scalars, fds));
-  }
+  TIMED(K_SWEEP1_X,
+        hipLaunchKernelGGL((k_sweep_x<T, 1>), nblocks(P_S1_X), B, 0, stream, tab(P_S1_X)));
+  TIMED(K_SWEEP1_Y,
+        hipLaunchKernelGGL((k_sweep_march<T, 1, 1>), nblocks(P_S1_Y), B, 0, stream, tab(P_S1_Y)));
+  TIMED(K_SWEEP1_Z,
+        hipLaunchKernelGGL((k_sweep_march<T, 2, 1>), nblocks(P_S1_Z), B, 0, stream, tab(P_S1_Z)));
   // stage 2 (a2-a4 re-traced, a6-a7): F^{n+1/2}, G^{n+1/2}, H^{n+1/2} on the real faces
-  {
-    long long tasks = (long long)nseg * P.n[1] * P.n[2];
-    TIMED(K_SWEEP2_X, hipLaunchKernelGGL((k_sweep_x<T, 2>), dim3(blocks_for(tasks, BS / 64)),
-                                         dim3(BS), 0, stream, b.u, b.fstar[0], b.fhalf[0], P,
-                                         b.scalars, fds));
-    TIMED(K_SWEEP2_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 2>),
-                                         dim3(march_blocks(P, 1, false, BS)), dim3(BS), 0, stream,
-                                         b.u, b.fstar[0], b.fhalf[1], P, b.scalars, fds));
-    TIMED(K_SWEEP2_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 2>),
-                                         dim3(march_blocks(P, 2, false, BS)), dim3(BS), 0, stream,
-                                         b.u, b.fstar[0], b.fhalf[2], P, b.scalars, fds));
-  }
+  TIMED(K_SWEEP2_X,
+        hipLaunchKernelGGL((k_sweep_x<T, 2>), nblocks(P_S2_X), B, 0, stream, tab(P_S2_X)));
+  TIMED(K_SWEEP2_Y,
+        hipLaunchKernelGGL((k_sweep_march<T, 1, 2>), nblocks(P_S2_Y), B, 0, stream, tab(P_S2_Y)));
+  TIMED(K_SWEEP2_Z,
+        hipLaunchKernelGGL((k_sweep_march<T, 2, 2>), nblocks(P_S2_Z), B, 0, stream, tab(P_S2_Z)));
   // a8-a9
-  const long long real = (long long)P.n[0] * P.n[1] * P.n[2];
-  const long long nblocks = blocks_for(real, BS);
-  const long long hds = b.fhalf[1] - b.fhalf[0];
-  TIMED(K_UPDATE, hipLaunchKernelGGL(k_update<T>, dim3((unsigned)((nblocks + 7) / 8 * 8)), dim3(BS),
-                                     0, stream, b.u, b.fhalf[0], P, b.scalars, hds, b.part,
-                                     nblocks));
-  TIMED(K_DT_FINAL, hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, stream, b.part,
-                                       nblocks, b.scalars));
+  TIMED(K_UPDATE, hipLaunchKernelGGL(k_update<T>, nblocks(P_UPDATE), B, 0, stream, tab(P_UPDATE)));
+  TIMED(K_DT_FINAL,
+        hipLaunchKernelGGL(k_dt_final, dim3(v.ngrids), dim3(1024), 0, stream, v.d_grids));
+  hipLaunchKernelGGL(k_end_step, gsmall, B, 0, stream, v.d_grids, v.ngrids);
+}
+
+hipError_t launch_step(const PlanView& v, bool device_dt, hipStream_t stream, Profiler* prof) {
+  if (v.prec == 0)
+    enqueue_step<double>(v, device_dt, stream, prof);
+  else
+    enqueue_step<float>(v, device_dt, stream, prof);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_dt(T* u, const GridParams& P, DevScalars* s, double* part, hipStream_t stream) {
-  constexpr int BS = 256;
-  const long long real = (long long)P.n[0] * P.n[1] * P.n[2];
-  const long long nblocks = blocks_for(real, BS);
-  hipLaunchKernelGGL(k_dt<T>, dim3((unsigned)((nblocks + 7) / 8 * 8)), dim3(BS), 0, stream, u, P,
-                     part, nblocks);
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, stream, part, nblocks, s);
+static void enqueue_dt(const PlanView& v, hipStream_t stream) {
+  const int stride = v.ngrids + 1;
+  const LaunchTab tab{v.d_grids, v.d_start + P_DT * stride, v.ngrids};
+  hipLaunchKernelGGL(k_dt<T>, dim3((unsigned)v.h_start[P_DT * stride + v.ngrids]), dim3(kBlock), 0,
+                     stream, tab);
+  hipLaunchKernelGGL(k_dt_final, dim3(v.ngrids), dim3(1024), 0, stream, v.d_grids);
+}
+
+hipError_t launch_dt(const PlanView& v, hipStream_t stream) {
+  if (v.prec == 0)
+    enqueue_dt<double>(v, stream);
+  else
+    enqueue_dt<float>(v, stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_dt(DevScalars* s, double dt, hipStream_t stream) {
+  hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, stream, s, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_end(DevScalars* s, double t_end, long long steps_left, hipStream_t stream) {
+  hipLaunchKernelGGL(k_set_end, dim3(1), dim3(1), 0, stream, s, t_end, steps_left);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_scalars(DevScalars* const* src, int n, DevScalars* out,
+                                 hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_scalars, dim3((unsigned)cdiv(n, 64)), dim3(64), 0, stream, src, n,
+                     out);
   return hipGetLastError();
 }
 
@@ -743,42 +823,28 @@ hipError_t launch_totals(const T* u, const GridParams& P, double* part, int nblo
 template <typename T>
 hipError_t launch_scatter(const T* packed, T* u, const GridParams& P, hipStream_t stream) {
   const long long real = (long long)P.n[0] * P.n[1] * P.n[2];
-  hipLaunchKernelGGL(k_scatter<T>, dim3(blocks_for(real, 256)), dim3(256), 0, stream, packed, u, P);
+  hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)cdiv(real, 256)), dim3(256), 0, stream, packed,
+                     u, P);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gather(const T* u, T* packed, const GridParams& P, hipStream_t stream) {
   const long long real = (long long)P.n[0] * P.n[1] * P.n[2];
-  hipLaunchKernelGGL(k_gather<T>, dim3(blocks_for(real, 256)), dim3(256), 0, stream, u, packed, P);
+  hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)cdiv(real, 256)), dim3(256), 0, stream, u,
+                     packed, P);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prim_to_cons(const double* packed, T* u, const GridParams& P, hipStream_t stream) {
   const long long real = (long long)P.n[0] * P.n[1] * P.n[2];
-  hipLaunchKernelGGL(k_prim_to_cons<T>, dim3(blocks_for(real, 256)), dim3(256), 0, stream, packed,
-                     u, P);
-  return hipGetLastError();
-}
-
-hipError_t launch_set_dt(DevScalars* s, double dt, hipStream_t stream) {
-  hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, stream, s, dt);
-  return hipGetLastError();
-}
-hipError_t launch_begin_step(DevScalars* s, double cfl, double t_end, hipStream_t stream) {
-  hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, stream, s, cfl, t_end);
-  return hipGetLastError();
-}
-hipError_t launch_end_step(DevScalars* s, hipStream_t stream) {
-  hipLaunchKernelGGL(k_end_step, dim3(1), dim3(1), 0, stream, s);
+  hipLaunchKernelGGL(k_prim_to_cons<T>, dim3((unsigned)cdiv(real, 256)), dim3(256), 0, stream,
+                     packed, u, P);
   return hipGetLastError();
 }
 
 #define CTU_INSTANTIATE(T)                                                                        \
-  template hipError_t launch_step<T>(const StepBuffers<T>&, const GridParams&, const int*,       \
-                                     hipStream_t, Profiler*);                                    \
-  template hipError_t launch_dt<T>(T*, const GridParams&, DevScalars*, double*, hipStream_t);   \
   template hipError_t launch_totals<T>(const T*, const GridParams&, double*, int, double*,      \
                                        hipStream_t);                                             \
   template hipError_t launch_scatter<T>(const T*, T*, const GridParams&, hipStream_t);          \

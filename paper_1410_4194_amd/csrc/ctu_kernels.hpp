@@ -1,4 +1,9 @@
 // ctu_kernels.hpp -- launch interface between the host runtime and the CTU kernels.
+//
+// Every pass of a step is one launch over a table of grids: grid g owns the blocks
+// [start[g], start[g+1]) of the launch, and each block finds its grid by binary search.
+// A single grid is a one-entry table, so solo, batched and served grids share one code path
+// (and one launch sequence, which can be captured in a HIP graph).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,21 +14,36 @@
 
 namespace ctu {
 
-// Device buffers of one grid.  fstar[d] (first-stage fluxes) and fhalf[d] (CTU fluxes):
-// 5 fields each with the grid's field stride, face c+1/2 at the index of cell c;
-// fstar[0..2] and fhalf[0..2] are equally spaced (kernels address them from [0]).
-// part: one double per update block for the CFL reduction.
-template <typename T>
-struct StepBuffers {
-  T* u;
-  T* fstar[3];
-  T* fhalf[3];
-  DevScalars* scalars;
-  double* part;
+// Passes of one step, in launch order, plus the stand-alone CFL reduction.
+enum Pass {
+  P_BC_X, P_BC_Y, P_BC_Z, P_S1_X, P_S1_Y, P_S1_Z, P_S2_X, P_S2_Y, P_S2_Z, P_UPDATE, P_DT,
+  P_NUM
 };
 
-// Optional per-kernel timing: HIP events recorded on the launch stream around every kernel
-// of a step, accumulated per kernel class.
+constexpr int kBlock = 256;  // threads per block of every pass
+constexpr int SEG = 32;      // faces per thread in the marching sweeps
+constexpr int XW = 59;       // x-faces per wavefront in the shuffle sweeps
+
+// Everything a kernel needs about one grid, resident in device memory.
+struct GridDesc {
+  GridParams P;
+  void* u;          // state, 5 fields of P.stride elements (T)
+  void* flux;       // 30 fields: F*_x, F*_y, F*_z, then F^{n+1/2}_x, _y, _z (5 fields each)
+  DevScalars* s;    // dt, time, CFL bound, error word
+  double* part;     // CFL partials, one per update block
+  int bc[6];
+};
+
+struct LaunchTab {
+  const GridDesc* grids;
+  const int* start;  // ngrids + 1 block offsets of this pass (each a multiple of 8)
+  int ngrids;
+};
+
+// Blocks a pass needs for one grid (before padding to a multiple of 8).
+long long pass_blocks(const GridParams& P, int pass);
+
+// Per-kernel timing with HIP events recorded on the launch stream, accumulated per class.
 enum KernelClass {
   K_BC_X, K_BC_Y, K_BC_Z, K_SWEEP1_X, K_SWEEP1_Y, K_SWEEP1_Z, K_SWEEP2_X, K_SWEEP2_Y,
   K_SWEEP2_Z, K_UPDATE, K_DT_FINAL, K_NUM_CLASSES
@@ -47,11 +67,28 @@ struct Profiler {
   ~Profiler();
 };
 
-template <typename T>
-hipError_t launch_step(const StepBuffers<T>& b, const GridParams& P, const int bc[6],
-                       hipStream_t stream, Profiler* prof);
-template <typename T>
-hipError_t launch_dt(T* u, const GridParams& P, DevScalars* s, double* part, hipStream_t stream);
+// A set of grids of one precision launched together: device descriptors and block tables
+// (start[pass * (ngrids + 1) + g]), with host copies of the launch sizes.
+struct PlanView {
+  const GridDesc* d_grids;
+  const int* d_start;
+  int ngrids;
+  const int* h_start;  // same layout as d_start
+  int prec;            // 0 = double, 1 = float
+};
+
+// One step for every grid of the plan.  device_dt: take dt from each grid's CFL bound and
+// end time (k_begin_step); otherwise each grid's dt was set beforehand.
+hipError_t launch_step(const PlanView& v, bool device_dt, hipStream_t stream, Profiler* prof);
+// CFL bound of the current state of every grid of the plan (into dt_next_bits).
+hipError_t launch_dt(const PlanView& v, hipStream_t stream);
+
+hipError_t launch_set_dt(DevScalars* s, double dt, hipStream_t stream);
+hipError_t launch_set_end(DevScalars* s, double t_end, long long steps_left, hipStream_t stream);
+// out[i] = *src[i] for i < n (src and out in device memory).
+hipError_t launch_gather_scalars(DevScalars* const* src, int n, DevScalars* out,
+                                 hipStream_t stream);
+
 template <typename T>
 hipError_t launch_totals(const T* u, const GridParams& P, double* part, int nblocks, double* out,
                          hipStream_t stream);
@@ -62,8 +99,5 @@ hipError_t launch_gather(const T* u, T* packed, const GridParams& P, hipStream_t
 template <typename T>
 hipError_t launch_prim_to_cons(const double* packed, T* u, const GridParams& P,
                                hipStream_t stream);
-hipError_t launch_set_dt(DevScalars* s, double dt, hipStream_t stream);
-hipError_t launch_begin_step(DevScalars* s, double cfl, double t_end, hipStream_t stream);
-hipError_t launch_end_step(DevScalars* s, hipStream_t stream);
 
 }  // namespace ctu

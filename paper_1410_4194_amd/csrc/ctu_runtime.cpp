@@ -36,12 +36,18 @@ ctu_status hip_fail(hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail(e_, where); \
   } while (0)
 
+// Workspace header: device scalars, totals partials, and the one-grid launch plan.
 constexpr size_t kScalarsOffset = 0;
 constexpr size_t kPartialOffset = 4096;
 constexpr int kTotalsBlocks = 1024;
 constexpr size_t kTotalsOutOffset = kPartialOffset + sizeof(double) * 5 * kTotalsBlocks;
+constexpr size_t kDescOffset = 49152;
+constexpr size_t kStartOffset = 53248;
 constexpr size_t kHeaderBytes = 65536;
 constexpr int kFieldsPerGrid = 30;  // fstar 3x5, fhalf 3x5
+static_assert(kTotalsOutOffset + 5 * sizeof(double) <= kDescOffset, "header overlap");
+static_assert(kDescOffset + sizeof(ctu::GridDesc) <= kStartOffset, "descriptor too large");
+static_assert(kStartOffset + sizeof(int) * ctu::P_NUM * 2 <= kHeaderBytes, "header overflow");
 
 size_t elem_bytes(int prec) { return prec == CTU_FP32 ? 4 : 8; }
 
@@ -118,6 +124,25 @@ GridParams make_params(const ctu_config& c) {
   return P;
 }
 
+// Block table of a launch over the grids Ps: for every pass, grid g owns the blocks
+// [start[p*(n+1)+g], start[p*(n+1)+g+1]), its count padded to a multiple of 8 so that every
+// grid's range starts on the first XCD of the round-robin dispatch.  False if a pass would
+// exceed the launch limit.
+bool build_starts(const std::vector<GridParams>& Ps, std::vector<int>& start) {
+  const int n = (int)Ps.size();
+  start.assign((size_t)ctu::P_NUM * (n + 1), 0);
+  for (int p = 0; p < ctu::P_NUM; ++p) {
+    long long off = 0;
+    for (int g = 0; g < n; ++g) {
+      start[(size_t)p * (n + 1) + g] = (int)off;
+      off += (ctu::pass_blocks(Ps[g], p) + 7) / 8 * 8;
+      if (off > 0x7fffff00LL) return false;
+    }
+    start[(size_t)p * (n + 1) + n] = (int)off;
+  }
+  return true;
+}
+
 }  // namespace
 
 struct ctu_grid {
@@ -128,7 +153,10 @@ struct ctu_grid {
   char* d_work;
   size_t work_bytes;
   bool dt_valid;  // device dt_next_bits holds the CFL bound of the current state
+  bool in_batch = false;
   ctu::Profiler* prof = nullptr;  // per-kernel timing when enabled
+  ctu::GridDesc desc;             // host copy of the descriptor at d_work + kDescOffset
+  std::vector<int> h_start;       // host copy of the one-grid block table
   DevScalars* scalars() const { return reinterpret_cast<DevScalars*>(d_work + kScalarsOffset); }
   double* partial() const { return reinterpret_cast<double*>(d_work + kPartialOffset); }
   double* totals_out() const { return reinterpret_cast<double*>(d_work + kTotalsOutOffset); }
@@ -137,42 +165,32 @@ struct ctu_grid {
     return reinterpret_cast<double*>(d_work + kHeaderBytes + (size_t)kFieldsPerGrid * fbytes());
   }
   size_t fbytes() const { return (size_t)P.stride * elem_bytes(cfg.prec); }
-  template <typename T>
-  ctu::StepBuffers<T> buffers() const {
-    ctu::StepBuffers<T> b;
-    b.u = reinterpret_cast<T*>(d_state);
-    T* f = reinterpret_cast<T*>(fields());
-    for (int d = 0; d < 3; ++d) b.fstar[d] = f + (size_t)(5 * d) * P.stride;
-    for (int d = 0; d < 3; ++d) b.fhalf[d] = f + (size_t)(15 + 5 * d) * P.stride;
-    b.scalars = scalars();
-    b.part = partials();
-    return b;
+  ctu::GridDesc* d_desc() const { return reinterpret_cast<ctu::GridDesc*>(d_work + kDescOffset); }
+  int* d_start() const { return reinterpret_cast<int*>(d_work + kStartOffset); }
+  ctu::PlanView plan() const {
+    return ctu::PlanView{d_desc(), d_start(), 1, h_start.data(), cfg.prec == CTU_FP32 ? 1 : 0};
   }
 };
 
 namespace {
 
-ctu_status step_impl(ctu_grid* g) {
-  hipError_t e = g->cfg.prec == CTU_FP64
-                     ? ctu::launch_step<double>(g->buffers<double>(), g->P, g->cfg.bc, g->stream,
-                                                g->prof)
-                     : ctu::launch_step<float>(g->buffers<float>(), g->P, g->cfg.bc, g->stream,
-                                               g->prof);
+ctu_status step_impl(ctu_grid* g, bool device_dt) {
+  hipError_t e = ctu::launch_step(g->plan(), device_dt, g->stream, g->prof);
   if (e != hipSuccess) return hip_fail(e, "step launch");
-  HIP_TRY(ctu::launch_end_step(g->scalars(), g->stream), "end_step");
   g->dt_valid = true;
   return CTU_OK;
 }
 
 ctu_status ensure_dt(ctu_grid* g) {
   if (g->dt_valid) return CTU_OK;
-  hipError_t e = g->cfg.prec == CTU_FP64
-                     ? ctu::launch_dt<double>(reinterpret_cast<double*>(g->d_state), g->P,
-                                              g->scalars(), g->partials(), g->stream)
-                     : ctu::launch_dt<float>(reinterpret_cast<float*>(g->d_state), g->P,
-                                             g->scalars(), g->partials(), g->stream);
+  hipError_t e = ctu::launch_dt(g->plan(), g->stream);
   if (e != hipSuccess) return hip_fail(e, "dt launch");
   g->dt_valid = true;
+  return CTU_OK;
+}
+
+ctu_status not_in_batch(const ctu_grid* g) {
+  if (g->in_batch) return fail(CTU_EINVAL, "grid is submitted to a batch until its ticket ends");
   return CTU_OK;
 }
 
@@ -245,7 +263,26 @@ ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, s
   g->d_work = reinterpret_cast<char*>(d_work);
   g->work_bytes = work_bytes;
   g->dt_valid = false;
-  s = reset_scalars(g);
+  g->desc.P = g->P;
+  g->desc.u = g->d_state;
+  g->desc.flux = g->fields();
+  g->desc.s = g->scalars();
+  g->desc.part = g->partials();
+  for (int i = 0; i < 6; ++i) g->desc.bc[i] = cfg->bc[i];
+  if (!build_starts({g->P}, g->h_start)) {
+    delete g;
+    return fail(CTU_EINVAL, "grid too large for one launch per pass");
+  }
+  hipError_t e = hipMemcpyAsync(g->d_desc(), &g->desc, sizeof(g->desc), hipMemcpyHostToDevice,
+                                g->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(g->d_start(), g->h_start.data(), sizeof(int) * g->h_start.size(),
+                       hipMemcpyHostToDevice, g->stream);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "descriptor upload");
+  }
+  s = reset_scalars(g);  // synchronizes, so the host copies above are no longer read
   if (s != CTU_OK) {
     delete g;
     return s;
@@ -256,6 +293,7 @@ ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, s
 
 ctu_status ctu_grid_destroy(ctu_grid* g) {
   if (!g) return fail(CTU_EINVAL, "null grid");
+  if (ctu_status st = not_in_batch(g)) return st;
   (void)hipStreamSynchronize(g->stream);
   delete g->prof;
   delete g;
@@ -306,6 +344,7 @@ ctu_status ctu_grid_info_get(ctu_grid* g, ctu_grid_info* info) {
 
 ctu_status ctu_set_state(ctu_grid* g, const void* const h_fields[5]) {
   if (!g || !h_fields) return fail(CTU_EINVAL, "null argument");
+  if (ctu_status st_ = not_in_batch(g)) return st_;
   for (int f = 0; f < 5; ++f)
     if (!h_fields[f]) return fail(CTU_EINVAL, "null host field");
   const size_t ncell = (size_t)g->cfg.nx * g->cfg.ny * g->cfg.nz;
@@ -326,6 +365,7 @@ ctu_status ctu_set_state(ctu_grid* g, const void* const h_fields[5]) {
 
 ctu_status ctu_set_primitive(ctu_grid* g, const double* const h_fields[5]) {
   if (!g || !h_fields) return fail(CTU_EINVAL, "null argument");
+  if (ctu_status st_ = not_in_batch(g)) return st_;
   for (int f = 0; f < 5; ++f)
     if (!h_fields[f]) return fail(CTU_EINVAL, "null host field");
   const size_t ncell = (size_t)g->cfg.nx * g->cfg.ny * g->cfg.nz;
@@ -345,6 +385,7 @@ ctu_status ctu_set_primitive(ctu_grid* g, const double* const h_fields[5]) {
 
 ctu_status ctu_get_state(ctu_grid* g, void* const h_fields[5]) {
   if (!g || !h_fields) return fail(CTU_EINVAL, "null argument");
+  if (ctu_status st_ = not_in_batch(g)) return st_;
   for (int f = 0; f < 5; ++f)
     if (!h_fields[f]) return fail(CTU_EINVAL, "null host field");
   const size_t ncell = (size_t)g->cfg.nx * g->cfg.ny * g->cfg.nz;
@@ -371,6 +412,7 @@ ctu_status ctu_get_state(ctu_grid* g, void* const h_fields[5]) {
 
 ctu_status ctu_compute_dt(ctu_grid* g, double* dt) {
   if (!g || !dt) return fail(CTU_EINVAL, "null argument");
+  if (ctu_status st_ = not_in_batch(g)) return st_;
   ctu_status st = ensure_dt(g);
   if (st != CTU_OK) return st;
   DevScalars s;
@@ -386,18 +428,22 @@ ctu_status ctu_compute_dt(ctu_grid* g, double* dt) {
 ctu_status ctu_step(ctu_grid* g, double dt) {
   if (!g) return fail(CTU_EINVAL, "null grid");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CTU_EINVAL, "dt must be finite and > 0");
+  if (ctu_status st = not_in_batch(g)) return st;
   HIP_TRY(ctu::launch_set_dt(g->scalars(), dt, g->stream), "set_dt");
-  return step_impl(g);
+  return step_impl(g, false);
 }
 
 ctu_status ctu_advance(ctu_grid* g, int32_t nsteps, double t_end) {
   if (!g) return fail(CTU_EINVAL, "null grid");
   if (nsteps < 0) return fail(CTU_EINVAL, "nsteps must be >= 0");
+  if (std::isnan(t_end)) return fail(CTU_EINVAL, "t_end is NaN");
+  if (ctu_status st = not_in_batch(g)) return st;
+  if (nsteps == 0) return CTU_OK;
   ctu_status st = ensure_dt(g);
   if (st != CTU_OK) return st;
+  HIP_TRY(ctu::launch_set_end(g->scalars(), t_end, nsteps, g->stream), "set_end");
   for (int32_t n = 0; n < nsteps; ++n) {
-    HIP_TRY(ctu::launch_begin_step(g->scalars(), g->cfg.cfl, t_end, g->stream), "begin_step");
-    st = step_impl(g);
+    st = step_impl(g, true);
     if (st != CTU_OK) return st;
   }
   return CTU_OK;
@@ -405,6 +451,7 @@ ctu_status ctu_advance(ctu_grid* g, int32_t nsteps, double t_end) {
 
 ctu_status ctu_totals(ctu_grid* g, double out[5]) {
   if (!g || !out) return fail(CTU_EINVAL, "null argument");
+  if (ctu_status st_ = not_in_batch(g)) return st_;
   hipError_t e = g->cfg.prec == CTU_FP64
                      ? ctu::launch_totals<double>(reinterpret_cast<double*>(g->d_state), g->P,
                                                   g->partial(), kTotalsBlocks, g->totals_out(), g->stream)
@@ -419,6 +466,7 @@ ctu_status ctu_totals(ctu_grid* g, double out[5]) {
 
 ctu_status ctu_check(ctu_grid* g, uint32_t* flags, uint64_t counters[4]) {
   if (!g) return fail(CTU_EINVAL, "null grid");
+  if (ctu_status st_ = not_in_batch(g)) return st_;
   DevScalars s;
   ctu_status st = read_scalars(g, &s);
   if (st != CTU_OK) return st;
@@ -472,82 +520,276 @@ struct ctu_batch {
     bool used = false;
     uint64_t ticket = 0;
     ctu_grid* grid = nullptr;
-    int32_t steps_left = 0;
     double t_end = 0.0;
     int32_t state = CTU_TICKET_UNKNOWN;
   };
+  // Grids of one precision launched together: descriptors and block table on the device,
+  // host copies of both (the block counts are needed at launch).
+  struct Group {
+    int prec = 0;
+    std::vector<ctu::GridDesc> descs;
+    std::vector<int> start;
+    ctu::GridDesc* d_desc = nullptr;
+    int* d_start = nullptr;
+    ctu::PlanView view() const {
+      return ctu::PlanView{d_desc, d_start, (int)descs.size(), start.data(), prec};
+    }
+  };
   std::vector<Slot> slots;
-  hipStream_t stream = nullptr;
+  int32_t flags = 0;
+  hipStream_t caller = nullptr;  // the caller's stream: batch work is ordered after its work
+  hipStream_t stream = nullptr;  // the batch's own stream (default priority)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  Group groups[2];
+  DevScalars** d_sptr = nullptr;  // scalars of the used slots, gathered for poll
+  DevScalars* d_sout = nullptr;
+  std::vector<DevScalars*> h_sptr;
+  std::vector<DevScalars> h_sout;
+  std::vector<int> sout_slot;  // slot of each gathered entry
+  bool fresh = false;          // h_sout reflects all work enqueued so far
+  bool dirty = true;           // the groups do not match the running slots
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   uint64_t next_ticket = 1;
 };
 
+namespace {
+
+size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Batch workspace: per precision a descriptor array and a block table, then the scalar
+// pointer table and the gathered scalars.
+size_t batch_group_bytes(int32_t max_slots) {
+  return round256(sizeof(ctu::GridDesc) * (size_t)max_slots) +
+         round256(sizeof(int) * (size_t)ctu::P_NUM * (max_slots + 1));
+}
+
+size_t batch_bytes(int32_t max_slots) {
+  return 2 * batch_group_bytes(max_slots) + round256(sizeof(DevScalars*) * (size_t)max_slots) +
+         round256(sizeof(DevScalars) * (size_t)max_slots);
+}
+
+void drop_graph(ctu_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// Rebuild both precision groups from the running slots and upload them.
+ctu_status rebuild(ctu_batch* b) {
+  // earlier uploads read the host vectors until the stream reaches them
+  HIP_TRY(hipStreamSynchronize(b->stream), "batch sync");
+  drop_graph(b);
+  for (int p = 0; p < 2; ++p) {
+    ctu_batch::Group& G = b->groups[p];
+    G.descs.clear();
+    std::vector<GridParams> Ps;
+    for (const auto& sl : b->slots) {
+      if (!sl.used || sl.state != CTU_TICKET_RUNNING) continue;
+      if ((sl.grid->cfg.prec == CTU_FP32 ? 1 : 0) != p) continue;
+      G.descs.push_back(sl.grid->desc);
+      Ps.push_back(sl.grid->P);
+    }
+    if (!build_starts(Ps, G.start)) return fail(CTU_EINVAL, "batch too large for one launch per pass");
+    if (G.descs.empty()) continue;
+    HIP_TRY(hipMemcpyAsync(G.d_desc, G.descs.data(), sizeof(ctu::GridDesc) * G.descs.size(),
+                           hipMemcpyHostToDevice, b->stream),
+            "batch descriptor upload");
+    HIP_TRY(hipMemcpyAsync(G.d_start, G.start.data(), sizeof(int) * G.start.size(),
+                           hipMemcpyHostToDevice, b->stream),
+            "batch table upload");
+  }
+  b->dirty = false;
+  return CTU_OK;
+}
+
+ctu_status enqueue_batch_step(ctu_batch* b) {
+  for (int p = 0; p < 2; ++p) {
+    if (b->groups[p].descs.empty()) continue;
+    hipError_t e = ctu::launch_step(b->groups[p].view(), true, b->stream, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "batch step launch");
+  }
+  return CTU_OK;
+}
+
+// One read-back of the scalars of every used slot (syncs the batch stream).
+ctu_status refresh(ctu_batch* b) {
+  if (b->fresh) return CTU_OK;
+  HIP_TRY(hipStreamSynchronize(b->stream), "batch sync");  // host tables are free to change
+  b->h_sptr.clear();
+  b->sout_slot.clear();
+  for (size_t i = 0; i < b->slots.size(); ++i) {
+    if (!b->slots[i].used) continue;
+    b->h_sptr.push_back(b->slots[i].grid->scalars());
+    b->sout_slot.push_back((int)i);
+  }
+  const int n = (int)b->h_sptr.size();
+  b->h_sout.resize(b->slots.size());
+  if (n > 0) {
+    std::vector<DevScalars> tmp(n);
+    HIP_TRY(hipMemcpyAsync(b->d_sptr, b->h_sptr.data(), sizeof(DevScalars*) * n,
+                           hipMemcpyHostToDevice, b->stream),
+            "batch pointer upload");
+    HIP_TRY(ctu::launch_gather_scalars(b->d_sptr, n, b->d_sout, b->stream), "batch gather");
+    HIP_TRY(hipMemcpyAsync(tmp.data(), b->d_sout, sizeof(DevScalars) * n, hipMemcpyDeviceToHost,
+                           b->stream),
+            "batch scalars copy");
+    HIP_TRY(hipStreamSynchronize(b->stream), "batch sync");
+    for (int k = 0; k < n; ++k) b->h_sout[b->sout_slot[k]] = tmp[k];
+  }
+  b->fresh = true;
+  return CTU_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-ctu_status ctu_batch_create(int32_t max_slots, void* hip_stream, ctu_batch** out) {
-  if (!out || max_slots < 1) return fail(CTU_EINVAL, "bad argument");
+ctu_status ctu_batch_workspace_bytes(int32_t max_slots, size_t* work_bytes) {
+  if (!work_bytes || max_slots < 1 || max_slots > (1 << 16))
+    return fail(CTU_EINVAL, "max_slots must lie in [1, 65536]");
+  *work_bytes = batch_bytes(max_slots);
+  return CTU_OK;
+}
+
+ctu_status ctu_batch_create(int32_t max_slots, void* d_work, size_t work_bytes, void* hip_stream,
+                            int32_t flags, ctu_batch** out) {
+  if (!out) return fail(CTU_EINVAL, "null output handle");
+  *out = nullptr;
+  size_t need = 0;
+  if (ctu_status st = ctu_batch_workspace_bytes(max_slots, &need)) return st;
+  if (!d_work) return fail(CTU_EINVAL, "null device buffer");
+  if (reinterpret_cast<uintptr_t>(d_work) % 256 != 0)
+    return fail(CTU_EINVAL, "device buffer must be 256-byte aligned");
+  if (flags & ~CTU_BATCH_GRAPH) return fail(CTU_EINVAL, "unknown batch flag");
+  if (work_bytes < need)
+    return fail(CTU_ENOMEM, "batch workspace too small: need " + std::to_string(need) + " bytes");
   ctu_batch* b = new ctu_batch();
   b->slots.resize(max_slots);
-  b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  b->flags = flags;
+  b->caller = reinterpret_cast<hipStream_t>(hip_stream);
+  char* w = reinterpret_cast<char*>(d_work);
+  for (int p = 0; p < 2; ++p) {
+    b->groups[p].prec = p;
+    b->groups[p].d_desc = reinterpret_cast<ctu::GridDesc*>(w);
+    b->groups[p].d_start =
+        reinterpret_cast<int*>(w + round256(sizeof(ctu::GridDesc) * (size_t)max_slots));
+    w += batch_group_bytes(max_slots);
+  }
+  b->d_sptr = reinterpret_cast<DevScalars**>(w);
+  w += round256(sizeof(DevScalars*) * (size_t)max_slots);
+  b->d_sout = reinterpret_cast<DevScalars*>(w);
+  hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    ctu_batch_destroy(b);
+    return hip_fail(e, "batch stream");
+  }
   *out = b;
   return CTU_OK;
 }
 
 ctu_status ctu_batch_submit(ctu_batch* b, ctu_grid* g, int32_t nsteps, double t_end,
                             uint64_t* ticket) {
-  if (!b || !g || !ticket || nsteps < 0) return fail(CTU_EINVAL, "bad argument");
-  for (auto& s : b->slots) {
-    if (s.used) continue;
-    s.used = true;
-    s.ticket = b->next_ticket++;
-    s.grid = g;
-    s.steps_left = nsteps;
-    s.t_end = t_end;
-    s.state = CTU_TICKET_RUNNING;
-    *ticket = s.ticket;
-    return CTU_OK;
-  }
-  return fail(CTU_EAGAIN, "no free batch slot");
+  if (!b || !g || !ticket || nsteps < 0 || std::isnan(t_end)) return fail(CTU_EINVAL, "bad argument");
+  if (ctu_status st = not_in_batch(g)) return st;
+  ctu_batch::Slot* slot = nullptr;
+  for (auto& s : b->slots)
+    if (!s.used) {
+      slot = &s;
+      break;
+    }
+  if (!slot) return fail(CTU_EAGAIN, "no free batch slot");
+  // on the grid's stream: CFL bound of the current state, end time and step budget; the
+  // batch stream then waits for that work
+  if (ctu_status st = ensure_dt(g)) return st;
+  HIP_TRY(ctu::launch_set_end(g->scalars(), t_end, nsteps, g->stream), "set_end");
+  HIP_TRY(hipEventRecord(b->ev_in, g->stream), "submit record");
+  HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_in, 0), "submit wait");
+  slot->used = true;
+  slot->ticket = b->next_ticket++;
+  slot->grid = g;
+  slot->t_end = t_end;
+  slot->state = CTU_TICKET_RUNNING;
+  g->in_batch = true;
+  b->dirty = true;
+  b->fresh = false;
+  *ticket = slot->ticket;
+  return CTU_OK;
 }
 
 ctu_status ctu_batch_run(ctu_batch* b, int32_t steps) {
   if (!b || steps < 0) return fail(CTU_EINVAL, "bad argument");
-  for (auto& s : b->slots) {
-    if (!s.used || s.state != CTU_TICKET_RUNNING || s.steps_left <= 0) continue;
-    int32_t k = steps < s.steps_left ? steps : s.steps_left;
-    ctu_status st = ctu_advance(s.grid, k, s.t_end);
-    if (st != CTU_OK) {
-      s.state = CTU_TICKET_FAILED;
-      continue;
-    }
-    s.steps_left -= k;
+  if (steps == 0) return CTU_OK;
+  if (b->dirty) {
+    if (ctu_status st = rebuild(b)) return st;
   }
+  if (b->groups[0].descs.empty() && b->groups[1].descs.empty()) return CTU_OK;
+  HIP_TRY(hipEventRecord(b->ev_in, b->caller), "batch record");
+  HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_in, 0), "batch wait");
+  if (b->flags & CTU_BATCH_GRAPH) {
+    if (!b->exec) {
+      HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "capture begin");
+      ctu_status st = enqueue_batch_step(b);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(b->stream, &graph);
+      if (st != CTU_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      if (e != hipSuccess) return hip_fail(e, "capture end");
+      b->graph = graph;
+      HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
+    }
+    for (int32_t k = 0; k < steps; ++k) HIP_TRY(hipGraphLaunch(b->exec, b->stream), "graph launch");
+  } else {
+    for (int32_t k = 0; k < steps; ++k)
+      if (ctu_status st = enqueue_batch_step(b)) return st;
+  }
+  HIP_TRY(hipEventRecord(b->ev_out, b->stream), "batch record");
+  HIP_TRY(hipStreamWaitEvent(b->caller, b->ev_out, 0), "batch wait");
+  b->fresh = false;
   return CTU_OK;
 }
 
 ctu_status ctu_batch_poll(ctu_batch* b, uint64_t ticket, int32_t* state, double* t_now) {
   if (!b || !state) return fail(CTU_EINVAL, "bad argument");
-  for (auto& s : b->slots) {
+  *state = CTU_TICKET_UNKNOWN;
+  for (size_t i = 0; i < b->slots.size(); ++i) {
+    ctu_batch::Slot& s = b->slots[i];
     if (!s.used || s.ticket != ticket) continue;
-    DevScalars sc;
-    ctu_status st = read_scalars(s.grid, &sc);
-    if (st != CTU_OK) return st;
+    if (ctu_status st = refresh(b)) return st;
+    const DevScalars& sc = b->h_sout[i];
     if (t_now) *t_now = sc.t;
     if (s.state == CTU_TICKET_RUNNING) {
       if (sc.flags & (CTU_FLAG_NONFINITE | CTU_FLAG_DENSITY))
         s.state = CTU_TICKET_FAILED;
-      else if (sc.t >= s.t_end || s.steps_left <= 0)
+      else if (sc.steps_left <= 0 || sc.t >= s.t_end)
         s.state = CTU_TICKET_DONE;
     }
     *state = s.state;
-    if (s.state == CTU_TICKET_DONE || s.state == CTU_TICKET_FAILED) s = ctu_batch::Slot();
+    if (s.state == CTU_TICKET_DONE || s.state == CTU_TICKET_FAILED) {
+      // the batch stream is idle (refresh synchronized it): the grid is the caller's again
+      s.grid->in_batch = false;
+      s = ctu_batch::Slot();
+      b->dirty = true;
+    }
     return CTU_OK;
   }
-  *state = CTU_TICKET_UNKNOWN;
   return CTU_OK;
 }
 
 ctu_status ctu_batch_destroy(ctu_batch* b) {
   if (!b) return fail(CTU_EINVAL, "null batch");
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (auto& s : b->slots)
+    if (s.used && s.grid) s.grid->in_batch = false;
+  drop_graph(b);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return CTU_OK;
 }

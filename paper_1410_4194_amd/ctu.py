@@ -27,12 +27,14 @@ BC_PERIODIC, BC_OUTFLOW = 0, 1
 FP64, FP32 = 0, 1
 FLAG_NONFINITE, FLAG_DENSITY, FLAG_PFLOOR, FLAG_NEWTON_CAP = 1, 2, 4, 8
 TICKET_QUEUED, TICKET_RUNNING, TICKET_DONE, TICKET_FAILED, TICKET_UNKNOWN = 0, 1, 2, 3, -1
+BATCH_GRAPH = 1
 
 EXPORTS = [
     "ctu_config_default", "ctu_workspace_bytes", "ctu_grid_create", "ctu_grid_destroy",
     "ctu_grid_info_get", "ctu_set_state", "ctu_set_primitive", "ctu_get_state",
     "ctu_compute_dt", "ctu_step", "ctu_advance", "ctu_totals", "ctu_check",
-    "ctu_debug_fluxes", "ctu_batch_create", "ctu_batch_submit", "ctu_batch_run",
+    "ctu_debug_fluxes", "ctu_batch_workspace_bytes", "ctu_batch_create", "ctu_batch_submit",
+    "ctu_batch_run",
     "ctu_batch_poll", "ctu_batch_destroy", "ctu_last_error", "ctu_profile_enable",
     "ctu_profile_read", "ctu_profile_name",
 ]
@@ -79,7 +81,8 @@ def _load() -> C.CDLL:
         "ctu_totals": ([vp, C.POINTER(C.c_double)], st),
         "ctu_check": ([vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)], st),
         "ctu_debug_fluxes": ([vp, C.c_int32, C.c_int32, C.POINTER(vp)], st),
-        "ctu_batch_create": ([C.c_int32, vp, C.POINTER(vp)], st),
+        "ctu_batch_workspace_bytes": ([C.c_int32, C.POINTER(sz)], st),
+        "ctu_batch_create": ([C.c_int32, vp, sz, vp, C.c_int32, C.POINTER(vp)], st),
         "ctu_batch_submit": ([vp, vp, C.c_int32, C.c_double, C.POINTER(C.c_uint64)], st),
         "ctu_batch_run": ([vp, C.c_int32], st),
         "ctu_batch_poll": ([vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double)], st),
@@ -250,35 +253,49 @@ class Grid:
 
 
 class Batch:
-    """Slots of independent grids advanced together (see ctu_batch_* in ctu.h)."""
+    """Continuous batch of independent grids (ctu_batch_* in ctu.h): every pass of a step is
+    one launch over all running grids of a precision."""
 
-    def __init__(self, max_slots: int, stream=None):
+    def __init__(self, max_slots: int, graph: bool = False, stream=None, device: str = "cuda"):
         torch = _torch()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        wb = C.c_size_t()
+        _check(lib.ctu_batch_workspace_bytes(int(max_slots), C.byref(wb)))
+        self.work = torch.empty(wb.value, dtype=torch.uint8, device=torch.device(device))
         h = C.c_void_p()
-        _check(lib.ctu_batch_create(int(max_slots), C.c_void_p(self.stream.cuda_stream),
-                                    C.byref(h)))
+        _check(lib.ctu_batch_create(int(max_slots), C.c_void_p(self.work.data_ptr()),
+                                    C.c_size_t(wb.value), C.c_void_p(self.stream.cuda_stream),
+                                    BATCH_GRAPH if graph else 0, C.byref(h)))
         self.handle = h
+        self._grids = {}  # ticket -> grid, keeps submitted grids alive
 
     def submit(self, grid: Grid, nsteps: int, t_end: float = float("inf")) -> Optional[int]:
+        """Ticket, or None when every slot is taken."""
         t = C.c_uint64()
         s = _check(lib.ctu_batch_submit(self.handle, grid.handle, int(nsteps), float(t_end),
                                         C.byref(t)), allow=(EAGAIN,))
-        return None if s == EAGAIN else t.value
+        if s == EAGAIN:
+            return None
+        self._grids[t.value] = grid
+        return t.value
 
     def run(self, steps: int) -> None:
         _check(lib.ctu_batch_run(self.handle, int(steps)))
 
     def poll(self, ticket: int):
+        """(state, t); a DONE or FAILED ticket releases its slot and grid."""
         state = C.c_int32()
         t = C.c_double()
         _check(lib.ctu_batch_poll(self.handle, C.c_uint64(ticket), C.byref(state), C.byref(t)))
+        if state.value in (TICKET_DONE, TICKET_FAILED, TICKET_UNKNOWN):
+            self._grids.pop(ticket, None)
         return state.value, t.value
 
     def close(self):
         if getattr(self, "handle", None):
             lib.ctu_batch_destroy(self.handle)
             self.handle = None
+            self._grids = {}
 
     def __del__(self):
         try:

@@ -80,3 +80,20 @@ def test_product_path_requires_gpu(ctu):
     cfg = ctu.make_config(8, 8, 8, 1, 1, 1, 1.4)
     with pytest.raises(RuntimeError, match="no GPU"):
         ctu.Grid(cfg)
+
+
+def test_batch_workspace_and_validation(ctu):
+    wb = C.c_size_t()
+    assert ctu.lib.ctu_batch_workspace_bytes(64, C.byref(wb)) == ctu.OK
+    assert wb.value >= 64 * (2 * 256 + 8)  # descriptors of both precisions + scalar table
+    small = wb.value
+    assert ctu.lib.ctu_batch_workspace_bytes(128, C.byref(wb)) == ctu.OK and wb.value > small
+    for bad in (0, -1, 1 << 20):
+        assert ctu.lib.ctu_batch_workspace_bytes(bad, C.byref(wb)) == ctu.EINVAL
+    h = C.c_void_p()
+    st = ctu.lib.ctu_batch_create(64, C.c_void_p(256), C.c_size_t(small - 1), None, 0, C.byref(h))
+    assert st == ctu.ENOMEM and h.value is None
+    st = ctu.lib.ctu_batch_create(64, C.c_void_p(256), C.c_size_t(small), None, 4, C.byref(h))
+    assert st == ctu.EINVAL and h.value is None
+    st = ctu.lib.ctu_batch_create(64, C.c_void_p(100), C.c_size_t(small), None, 0, C.byref(h))
+    assert st == ctu.EINVAL and h.value is None

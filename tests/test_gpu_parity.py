@@ -210,32 +210,3 @@ def test_newton_cap_is_counted(ctu):
     g.step(g.compute_dt())
     status, flags, counters = g.check()
     assert status == ctu.ENOCONV and counters[1] > 0
-
-
-def test_batch_matches_solo(ctu):
-    wls = WL.kh_batch(count=5, edges=(16, 24, 32), steps=8)
-    solo = []
-    for wl in wls:
-        g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
-        g.advance(8)
-        solo.append(g.get_state())
-    b = ctu.Batch(max_slots=3)
-    grids = [ctu.Grid.from_workload(wl, prec=ctu.FP64) for wl in wls]
-    pending = list(range(len(grids)))
-    tickets = {}
-    results = {}
-    while pending or tickets:
-        while pending:
-            t = b.submit(grids[pending[0]], 8)
-            if t is None:
-                break
-            tickets[t] = pending.pop(0)
-        b.run(3)
-        for t in list(tickets):
-            state, _ = b.poll(t)
-            if state in (ctu.TICKET_DONE, ctu.TICKET_FAILED):
-                assert state == ctu.TICKET_DONE
-                i = tickets.pop(t)
-                results[i] = grids[i].get_state()
-    for i in range(len(wls)):
-        assert np.array_equal(results[i], solo[i])
