@@ -6,7 +6,19 @@ shock with the exact Rankine-Hugoniot post-shock state for x < 0.1, outflow boun
 CFL 0.3), advanced with the device-side time step.  After `warmup` untimed steps, exactly
 `steps` steps are timed with the state resident in HBM; value = real cells x steps / time.
 The FP32 form (FP32 state, reconstruction and fluxes, FP64 Newton solve) is timed on the
-same workload and reported beside it.
+same workload and reported beside it, with its relative L1 distance from the FP64 state.
+
+Beside the primary line's value, the same JSON line carries
+  batched: 64 periodic Kelvin-Helmholtz grids with per-axis edges drawn from
+           {32, 48, 64, 96, 128}, 200 steps each with its own device-side time step, every pass
+           one launch over all grids, replayed from a captured HIP graph; FP64 and FP32, and
+           the same grids advanced one after another for comparison;
+  serve:   Poisson-arriving shock-cloud requests (edges {64, 96, 128, 192}, density contrast
+           log-uniform in [10, 1000], Mach uniform in [1.5, 10], radius in [0.08, 0.15], run
+           to 1.5 cloud-crushing times, FP32 with the FP64 Newton solve) admitted by HBM
+           footprint into a continuous batch: p50/p99 time-to-solution and aggregate rate.
+--precision-study runs the 512^3 turbulent cloud for 50 steps in FP64 and FP32 and reports
+their relative L1 distance; --serve-sweep sweeps the serving arrival rate.
 
 Prints one JSON line.  Per-kernel durations come from HIP events the library records on
 its own stream around every kernel of the timed steps.
@@ -82,7 +94,7 @@ def _units(cls, n):
     return 0
 
 
-def run_gpu(wl, prec, steps, warmup, ctu, torch):
+def run_gpu(wl, prec, steps, warmup, ctu, torch, keep_state=False):
     g = ctu.Grid.from_workload(wl, prec=prec)
     g.advance(warmup)
     torch.cuda.synchronize()
@@ -96,8 +108,93 @@ def run_gpu(wl, prec, steps, warmup, ctu, torch):
     g.profile_enable(False)
     status, flags, counters = g.check()
     info = g.info()
-    return {"seconds": t1 - t0, "profile": prof, "status": status, "flags": flags,
-            "counters": counters, "t": info.t, "steps_done": info.steps}
+    out = {"seconds": t1 - t0, "profile": prof, "status": status, "flags": flags,
+           "counters": counters, "t": info.t, "steps_done": info.steps}
+    if keep_state:
+        out["state"] = g.get_state()
+    g.close()
+    return out
+
+
+def rel_l1(got, ref, gamma):
+    """Per-field relative L1 distance of two conserved states (5, ...): sum |got - ref| over
+    sum of the reference scale (rho; rho (|V| + a) for the momenta; |E|)."""
+    import numpy as np
+    ref = np.asarray(ref, dtype=np.float64)
+    got = np.asarray(got, dtype=np.float64)
+    rho = ref[0]
+    V2 = (ref[1] ** 2 + ref[2] ** 2 + ref[3] ** 2) / rho ** 2
+    p = np.maximum((gamma - 1.0) * (ref[4] - 0.5 * rho * V2), 1e-300)
+    smom = rho * (np.sqrt(V2) + np.sqrt(gamma * p / rho))
+    scales = [rho, smom, smom, smom, np.abs(ref[4])]
+    return [float(np.abs(got[f] - ref[f]).sum() / scales[f].sum()) for f in range(5)]
+
+
+def run_batched(ctu, torch, WL, prec, steps, warmup, count=64, compare_solo_steps=0):
+    """Batched Kelvin-Helmholtz grids: warmup steps (which also capture the graph), then
+    `steps` timed steps of every grid; optionally the same grids advanced one at a time."""
+    wls = WL.kh_batch(count=count, steps=steps)
+    cells = sum(w.cells for w in wls)
+    grids = [ctu.Grid.from_workload(w, prec=prec) for w in wls]
+    b = ctu.Batch(count, graph=True)
+    tickets = [b.submit(g, warmup + steps) for g in grids]
+    b.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(steps)
+    states = [b.poll(t)[0] for t in tickets]   # syncs the batch stream
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert all(s == ctu.TICKET_DONE for s in states), states
+    b.close()
+    out = {"grids": count, "cells": cells, "steps": steps, "warmup": warmup,
+           "value": round(cells * steps / (t1 - t0), 1), "unit": "cell-updates/s",
+           "ms_per_step": round(1e3 * (t1 - t0) / steps, 4), "graph": True}
+    if compare_solo_steps:
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for g in grids:
+            g.advance(compare_solo_steps)
+        torch.cuda.synchronize()
+        s1 = time.perf_counter()
+        out["one_grid_at_a_time"] = {"steps": compare_solo_steps,
+                                     "value": round(cells * compare_solo_steps / (s1 - s0), 1)}
+    for g in grids:
+        g.close()
+    return out
+
+
+def run_serve(ctu, WL, rate, count, hbm_budget, seed, steps_per_round=4, keep=False):
+    from paper_1410_4194_amd import serve as S
+    reqs = WL.shock_cloud_requests(count, rate=rate, seed=seed)
+    requests = [S.Request(q["rid"], q["arrival"], WL.request_workload(q), q["t_end"], ctu.FP32)
+                for q in reqs]
+    stats = S.serve(requests, hbm_budget=hbm_budget, max_slots=64,
+                    steps_per_round=steps_per_round, graph=True, keep_states=keep)
+    out = stats.summary()
+    out.update({"rate_per_s": rate, "hbm_budget_gb": round(hbm_budget / 1e9, 2)})
+    return out
+
+
+def precision_study(ctu, torch, WL, n=512, steps=50):
+    """FP32 form vs FP64 on the turbulent cloud: both advanced with the FP64 grid's time step
+    (read back every step), so the difference is the precision alone."""
+    wl = WL.turbulent_cloud(n)
+    g64 = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    g32 = ctu.Grid.from_workload(wl, prec=ctu.FP32)
+    out = {"workload": f"turbulent_cloud_{n}^3 Mach-10", "steps": steps, "l1_by_step": {}}
+    for k in range(1, steps + 1):
+        dt = g64.compute_dt()
+        g64.step(dt)
+        g32.step(dt)
+        if k in (1, steps // 2, steps):
+            out["l1_by_step"][k] = rel_l1(g32.get_state(), g64.get_state(), wl.gamma)
+            log(f"[bench] precision study step {k}: L1 {out['l1_by_step'][k]}")
+    for g in (g64, g32):
+        st = g.check()[0]
+        out.setdefault("status", []).append(st)
+        g.close()
+    return out
 
 
 def _source_hash():
@@ -183,6 +280,17 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-load", type=float, default=0.5,
+                    help="arrival rate as a fraction of the estimated capacity")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="also sweep the arrival rate over 0.25, 0.5, 1, 2, 4 x capacity")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="512^3 turbulent cloud, 50 steps, FP32 vs FP64 relative L1")
     ap.add_argument("--source-hash", action="store_true",
                     help="print the hash of the kernel sources that traffic figures are tied to")
     ap.add_argument("--copy-probe", action="store_true",
@@ -215,7 +323,7 @@ def main():
     cells = wl.cells
 
     log(f"[bench] FP64: warmup {args.warmup}, timed {args.steps} steps")
-    r64 = run_gpu(wl, ctu.FP64, args.steps, args.warmup, ctu, torch)
+    r64 = run_gpu(wl, ctu.FP64, args.steps, args.warmup, ctu, torch, keep_state=not args.no_fp32)
     v64 = cells * args.steps / r64["seconds"]
     log(f"[bench] FP64 {v64:.4g} cell-updates/s, {1e3 * r64['seconds'] / args.steps:.3f} ms/step")
     for k, (ms, la) in sorted(r64["profile"].items(), key=lambda kv: -kv[1][0]):
@@ -234,12 +342,49 @@ def main():
     }
     if not args.no_fp32:
         log(f"[bench] FP32 form: warmup {args.warmup}, timed {args.steps} steps")
-        r32 = run_gpu(wl, ctu.FP32, args.steps, args.warmup, ctu, torch)
+        r32 = run_gpu(wl, ctu.FP32, args.steps, args.warmup, ctu, torch, keep_state=True)
         v32 = cells * args.steps / r32["seconds"]
         log(f"[bench] FP32 {v32:.4g} cell-updates/s")
+        l1 = rel_l1(r32.pop("state"), r64.pop("state"), wl.gamma)
+        log(f"[bench] FP32 vs FP64 relative L1 after {args.warmup + args.steps} steps: {l1}")
         out["fp32"] = {"value": round(v32, 1), "unit": "cell-updates/s",
                        "ms_per_step": round(1e3 * r32["seconds"] / args.steps, 4),
+                       "vs_fp64": round(v32 / v64, 3),
+                       "rel_l1_vs_fp64": [float(f"{e:.3e}") for e in l1],
+                       "t_minus_t_fp64": r32["t"] - r64["t"],
                        "roofline": roofline(r32["profile"], n, 4, "fp32")}
+    if not args.no_batched:
+        for name, prec in (("fp64", ctu.FP64), ("fp32", ctu.FP32)):
+            log(f"[bench] batched Kelvin-Helmholtz, 64 grids, {name}")
+            rb = run_batched(ctu, torch, WL, prec, args.batch_steps, args.warmup,
+                             compare_solo_steps=20)
+            log(f"[bench]   {rb['value']:.4g} cell-updates/s over {rb['cells']} cells")
+            rb["vs_plain_fp64_256"] = round(rb["value"] / v64, 3)
+            out.setdefault("batched", {})[name] = rb
+    if not args.no_serve:
+        import numpy as np
+        cap_rate = out.get("batched", {}).get("fp32", {}).get("value") or v64
+        probe = WL.shock_cloud_requests(256, rate=1.0, seed=WL.BASE_SEED + 5)
+        mean_work = float(np.mean([WL.estimated_steps(q) * q["n"] ** 3 for q in probe]))
+        capacity = cap_rate / mean_work
+        budget = int(args.serve_budget_gb * 1e9)
+        loads = [args.serve_load] + ([0.25, 0.5, 1.0, 2.0, 4.0] if args.serve_sweep else [])
+        for i, load in enumerate(loads):
+            rate = load * capacity
+            log(f"[bench] serving: {args.serve_requests} requests at {rate:.3f}/s "
+                f"({load} x estimated capacity {capacity:.3f}/s)")
+            rs = run_serve(ctu, WL, rate, args.serve_requests, budget, WL.BASE_SEED + 5)
+            rs["load"] = load
+            rs["capacity_estimate_per_s"] = round(capacity, 4)
+            log(f"[bench]   p50 {rs['p50_s']} s, p99 {rs['p99_s']} s, "
+                f"{rs['cell_updates_per_s']:.4g} cell-updates/s")
+            if i == 0:
+                out["serve"] = rs
+            else:
+                out.setdefault("serve_sweep", []).append(rs)
+    if args.precision_study:
+        log("[bench] precision study: 512^3 turbulent cloud, 50 steps, FP64 and FP32")
+        out["precision_study"] = precision_study(ctu, torch, WL)
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline: oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(wl)

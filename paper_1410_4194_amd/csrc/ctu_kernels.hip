@@ -30,6 +30,10 @@ __device__ __forceinline__ int find_grid(const int* __restrict__ start, int ngri
   return lo;
 }
 
+// Pointers read from a descriptor are generic; holding them in global-address-space pointer
+// types lets the compiler emit global (not flat) loads and stores through them.
+#define GLOBAL __attribute__((address_space(1)))
+
 struct BlockRef {
   const GridDesc* G;
   long long lb;  // block index within the grid's range
@@ -60,7 +64,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Block minimum of v written to part[lb] (no atomics); every thread must call it.
-__device__ __forceinline__ void block_min_store(double v, double* part, long long lb) {
+__device__ __forceinline__ void block_min_store(double v, GLOBAL double* part, long long lb) {
   __shared__ double smin[32];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -140,7 +144,7 @@ __global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab) {
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
   if (!(r.G->s->dt > 0.0)) return;
-  T* __restrict__ u = reinterpret_cast<T*>(r.G->u);
+  GLOBAL T* __restrict__ u = (GLOBAL T*)r.G->u;
   const int n = P.n[AXIS];
   const long long tid = r.lb * blockDim.x + threadIdx.x;
   int i, j, k, layer;
@@ -195,7 +199,7 @@ __global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab) {
 // faces.
 
 template <typename T, int D>
-__device__ __forceinline__ void load_prim(const T* __restrict__ u, long long stride, long long id,
+__device__ __forceinline__ void load_prim(const GLOBAL T* __restrict__ u, long long stride, long long id,
                                           const GridParams& P, Prim<T>& c) {
   T Ur[5];
 #pragma unroll
@@ -227,12 +231,12 @@ __device__ __forceinline__ Prim<T> shfl_prim(const Prim<T>& p, int src) {
 // Transverse flux difference of a cell (eq. transverse_evolution), rotated to the sweep
 // frame: dT = h1 (F_t1(c - e_t1) - F_t1(c)) + h2 (F_t2(c - e_t2) - F_t2(c)).
 template <typename T, int D>
-__device__ __forceinline__ void transverse_delta(const T* __restrict__ fstar_all, long long fds,
+__device__ __forceinline__ void transverse_delta(const GLOBAL T* __restrict__ fstar_all, long long fds,
                                                  long long stride, long long c, long long st1,
                                                  long long st2, T h1, T h2, T dT[5]) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const T* F1 = fstar_all + T1 * fds;
-  const T* F2 = fstar_all + T2 * fds;
+  const GLOBAL T* F1 = fstar_all + T1 * fds;
+  const GLOBAL T* F2 = fstar_all + T2 * fds;
 #pragma unroll
   for (int sl = 0; sl < 5; ++sl) {
     const long long o = rot<D>(sl) * stride + c;
@@ -275,10 +279,10 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   DevScalars* __restrict__ s = r.G->s;
   const double dt = s->dt;
   if (!(dt > 0.0)) return;
-  const T* __restrict__ u = reinterpret_cast<const T*>(r.G->u);
-  const T* __restrict__ fstar_all = reinterpret_cast<const T*>(r.G->flux);
+  const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
+  const GLOBAL T* __restrict__ fstar_all = (const GLOBAL T*)r.G->flux;
   const long long fds = 5 * P.stride;
-  T* __restrict__ out = reinterpret_cast<T*>(r.G->flux) + (STAGE == 1 ? D : 3 + D) * fds;
+  GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + (STAGE == 1 ? D : 3 + D) * fds;
   constexpr int B = (D == 1) ? 2 : 1;  // the transverse axis other than x
   const int lo = STAGE == 1 ? -1 : 0;
   const int ea = P.n[0] + (STAGE == 1 ? 2 : 0);
@@ -394,10 +398,10 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   DevScalars* __restrict__ s = r.G->s;
   const double dt = s->dt;
   if (!(dt > 0.0)) return;
-  const T* __restrict__ u = reinterpret_cast<const T*>(r.G->u);
-  const T* __restrict__ fstar_all = reinterpret_cast<const T*>(r.G->flux);
+  const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
+  const GLOBAL T* __restrict__ fstar_all = (const GLOBAL T*)r.G->flux;
   const long long fds = 5 * P.stride;
-  T* __restrict__ out = reinterpret_cast<T*>(r.G->flux) + (STAGE == 1 ? 0 : 3) * fds;
+  GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + (STAGE == 1 ? 0 : 3) * fds;
   const int lane = threadIdx.x & 63;
   const long long task = r.lb * (kBlock / 64) + (threadIdx.x >> 6);
   const int lo = STAGE == 1 ? -1 : 0;
@@ -474,11 +478,11 @@ __global__ __launch_bounds__(256) void k_update(LaunchTab tab) {
   const long long nblocks = (total + kBlock - 1) / kBlock;
   const long long lb = xcd_local(r.lb, r.nb);
   if (lb >= nblocks) return;  // whole block idle
-  T* __restrict__ u = reinterpret_cast<T*>(r.G->u);
+  GLOBAL T* __restrict__ u = (GLOBAL T*)r.G->u;
   const long long fds = 5 * P.stride;
-  const T* __restrict__ Fx = reinterpret_cast<const T*>(r.G->flux) + 3 * fds;
-  const T* __restrict__ Fy = Fx + fds;
-  const T* __restrict__ Fz = Fy + fds;
+  const GLOBAL T* __restrict__ Fx = (const GLOBAL T*)r.G->flux + 3 * fds;
+  const GLOBAL T* __restrict__ Fy = Fx + fds;
+  const GLOBAL T* __restrict__ Fz = Fy + fds;
   const long long tid = lb * kBlock + threadIdx.x;
   double bound = INFINITY;
   if (tid < total) {
@@ -509,7 +513,7 @@ __global__ __launch_bounds__(256) void k_update(LaunchTab tab) {
       bound = cell_dt_bound(U, P);
     }
   }
-  block_min_store(bound, r.G->part, lb);
+  block_min_store(bound, (GLOBAL double*)r.G->part, lb);
 }
 
 template <typename T>
@@ -520,7 +524,7 @@ __global__ __launch_bounds__(256) void k_dt(LaunchTab tab) {
   const long long nblocks = (total + kBlock - 1) / kBlock;
   const long long lb = xcd_local(r.lb, r.nb);
   if (lb >= nblocks) return;
-  const T* __restrict__ u = reinterpret_cast<const T*>(r.G->u);
+  const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
   const long long tid = lb * kBlock + threadIdx.x;
   double bound = INFINITY;
   if (tid < total) {
@@ -533,7 +537,7 @@ __global__ __launch_bounds__(256) void k_dt(LaunchTab tab) {
     for (int f = 0; f < 5; ++f) U[f] = u[f * P.stride + c];
     bound = cell_dt_bound(U, P);
   }
-  block_min_store(bound, r.G->part, lb);
+  block_min_store(bound, (GLOBAL double*)r.G->part, lb);
 }
 
 // Minimum of each grid's block partials into its dt_next_bits: block g reduces grid g.
@@ -541,8 +545,9 @@ __global__ __launch_bounds__(1024) void k_dt_final(const GridDesc* __restrict__ 
   const GridDesc& G = grids[blockIdx.x];
   const long long total = (long long)G.P.n[0] * G.P.n[1] * G.P.n[2];
   const long long nblocks = (total + kBlock - 1) / kBlock;
+  const GLOBAL double* __restrict__ part = (const GLOBAL double*)G.part;
   double m = INFINITY;
-  for (long long b = threadIdx.x; b < nblocks; b += blockDim.x) m = fmin(m, G.part[b]);
+  for (long long b = threadIdx.x; b < nblocks; b += blockDim.x) m = fmin(m, part[b]);
   __shared__ double smin[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   m = wave_min(m);
@@ -551,7 +556,8 @@ __global__ __launch_bounds__(1024) void k_dt_final(const GridDesc* __restrict__ 
   if (wave == 0) {
     double v = lane < (int)(blockDim.x >> 6) ? smin[lane] : INFINITY;
     v = wave_min(v);
-    if (lane == 0) G.s->dt_next_bits = (unsigned long long)__double_as_longlong(v);
+    if (lane == 0)
+      G.s->dt_next_bits = (unsigned long long)__double_as_longlong(v);
   }
 }
 

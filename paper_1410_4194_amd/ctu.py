@@ -160,10 +160,10 @@ class Grid:
         self.handle = h
 
     @classmethod
-    def from_workload(cls, wl, prec=FP64, **kw) -> "Grid":
+    def from_workload(cls, wl, prec=FP64, stream=None, **kw) -> "Grid":
         cfg = make_config(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.gamma, wl.bc, prec,
                           kw.pop("cfl", wl.cfl), **kw)
-        g = cls(cfg)
+        g = cls(cfg, stream=stream)
         g.set_primitive(wl.W)
         return g
 

@@ -152,6 +152,47 @@ def shock_cloud(n: int = 256, mach: float = 10.0, chi: float = 10.0, radius: flo
                           "post_shock": (rho2, u2, p2), "t_cc": cloud_crushing_time(radius, chi, vs)})
 
 
+def shock_cloud_requests(count: int, rate: float, seed: int = BASE_SEED + 5,
+                         sizes: Sequence[int] = (64, 96, 128, 192),
+                         chi_range=(10.0, 1000.0), mach_range=(1.5, 10.0),
+                         radius_range=(0.08, 0.15), t_cc_factor: float = 1.5,
+                         gamma: float = 5.0 / 3.0):
+    """Poisson-arriving shock-cloud solve requests: arrival times (seconds after the first
+    possible arrival, exponential gaps of mean 1/rate) and per request a grid edge drawn
+    from `sizes`, a cloud density contrast log-uniform in chi_range, a shock Mach number
+    uniform in mach_range and a cloud radius uniform in radius_range; each runs to
+    t_cc_factor cloud-crushing times.  Returns a list of dicts; the initial state is built
+    by ``request_workload``."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(count):
+        n = int(rng.choice(np.asarray(sizes)))
+        chi = float(10.0 ** rng.uniform(math.log10(chi_range[0]), math.log10(chi_range[1])))
+        mach = float(rng.uniform(*mach_range))
+        radius = float(rng.uniform(*radius_range))
+        vs = normal_shock(mach, 1.0, 1.0, gamma)[3]
+        out.append({"rid": i, "arrival": float(arrivals[i]), "n": n, "chi": chi, "mach": mach,
+                    "radius": radius, "gamma": gamma,
+                    "t_end": t_cc_factor * cloud_crushing_time(radius, chi, vs)})
+    return out
+
+
+def request_workload(req: dict) -> Workload:
+    """Initial state of one request from ``shock_cloud_requests``."""
+    return shock_cloud(req["n"], mach=req["mach"], chi=req["chi"], radius=req["radius"],
+                       gamma=req["gamma"], steps=None)
+
+
+def estimated_steps(req: dict, cfl: float = 0.3) -> float:
+    """Rough step count of a request: t_end over the CFL step of the post-shock gas (the
+    fastest signal of the initial state)."""
+    rho2, u2, p2, _ = normal_shock(req["mach"], 1.0, 1.0, req["gamma"])
+    speed = u2 + math.sqrt(req["gamma"] * p2 / rho2)
+    return req["t_end"] / (cfl / req["n"] / speed)
+
+
 def gaussian_random_field(n: int, slope: float, seed: int) -> np.ndarray:
     """Zero-mean Gaussian random field on an n^3 periodic grid with power spectrum
     P(k) ~ k^slope (white noise filtered by |k|^(slope/2), k = 0 removed)."""
