@@ -94,7 +94,7 @@ def _units(cls, n):
     return 0
 
 
-def run_gpu(wl, prec, steps, warmup, ctu, torch, keep_state=False):
+def run_gpu(wl, prec, steps, warmup, ctu, torch, keep_state=False, newton_hist=False):
     g = ctu.Grid.from_workload(wl, prec=prec)
     g.advance(warmup)
     torch.cuda.synchronize()
@@ -112,6 +112,12 @@ def run_gpu(wl, prec, steps, warmup, ctu, torch, keep_state=False):
            "counters": counters, "t": info.t, "steps_done": info.steps}
     if keep_state:
         out["state"] = g.get_state()
+    if newton_hist:
+        # one more (untimed) step through the instrumented sweeps
+        g.profile_enable(False, newton=True)
+        g.advance(1)
+        out["newton_hist"] = g.newton_histogram()
+        g.profile_enable(False)
     g.close()
     return out
 
@@ -323,7 +329,8 @@ def main():
     cells = wl.cells
 
     log(f"[bench] FP64: warmup {args.warmup}, timed {args.steps} steps")
-    r64 = run_gpu(wl, ctu.FP64, args.steps, args.warmup, ctu, torch, keep_state=not args.no_fp32)
+    r64 = run_gpu(wl, ctu.FP64, args.steps, args.warmup, ctu, torch, keep_state=not args.no_fp32,
+                  newton_hist=True)
     v64 = cells * args.steps / r64["seconds"]
     log(f"[bench] FP64 {v64:.4g} cell-updates/s, {1e3 * r64['seconds'] / args.steps:.3f} ms/step")
     for k, (ms, la) in sorted(r64["profile"].items(), key=lambda kv: -kv[1][0]):
@@ -336,7 +343,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"shock_cloud_{args.n}^3 Mach-10 chi-10 FP64 CFL 0.3",
                    "cells": cells, "grid": list(n), "parallelism": "single GPU",
-                   "newton_caps": r64["counters"][1], "status": r64["status"]},
+                   "newton_caps": r64["counters"][1], "status": r64["status"],
+                   "newton_iterations_per_solve": r64.get("newton_hist")},
         "roofline": roofline(r64["profile"], n, 8, "fp64"),
         "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in r64["profile"].items()},
     }

@@ -72,6 +72,11 @@ typedef struct {
   double newton_tol;       /* relative change that stops the Newton loop (1e-6) */
   int32_t newton_max_iter; /* Newton iteration cap (50) */
   double p_floor;          /* pressure floor on every primitive conversion (1e-20) */
+  int32_t march_seg[2];    /* tile shape: target faces per thread of the y and z sweeps, which
+                              march along their axis; 0 = the library default (32).  The
+                              n+1 faces of an axis are split into round((n+1)/target) equal
+                              segments.  Changes the launch shape; results change only by
+                              rounding (last-bit differences in a segment's first trace). */
 } ctu_config;
 
 typedef struct ctu_grid ctu_grid;
@@ -147,16 +152,24 @@ ctu_status ctu_check(ctu_grid* g, uint32_t* flags, uint64_t counters[4]);
 ctu_status ctu_debug_fluxes(ctu_grid* g, int32_t which, int32_t dir, double* const h_fields[5]);
 
 /* ---- Measurement -------------------------------------------------------------------------
- * Per-kernel timing for measurement tools: while enabled, every kernel a step launches is
- * bracketed by HIP events recorded on the grid's stream, and elapsed times accumulate per
- * kernel class.  ctu_profile_enable(g, 1) starts a fresh accumulation (syncs), 0 stops and
- * frees it.  ctu_profile_read fills up to max_classes entries of ms[] (total milliseconds)
- * and launches[] (launch counts) in the order of ctu_profile_name(i), and sets *count to
- * the number of classes (syncs).  ctu_profile_name returns "" past the last class. */
-ctu_status ctu_profile_enable(ctu_grid* g, int32_t enable);
+ * ctu_profile_enable(g, mode) starts a fresh accumulation (syncs); mode 0 stops and frees it.
+ *   CTU_PROFILE_TIMING: every kernel a step launches is bracketed by HIP events recorded on
+ *     the grid's stream, and elapsed times accumulate per kernel class.
+ *   CTU_PROFILE_NEWTON: the sweeps run instrumented copies that count, for every exact
+ *     Riemann solve (App. B.1), the Newton iterations it took, in 8 bins: 1, 2, 3, 4, 5-8,
+ *     9-16, more than 16, and the cap (newton_max_iter reached).  The copies are slower;
+ *     time with CTU_PROFILE_TIMING alone.
+ * ctu_profile_read fills up to max_classes entries of ms[] (total milliseconds) and
+ *   launches[] (launch counts) in the order of ctu_profile_name(i), and sets *count to the
+ *   number of classes (syncs).  ctu_profile_name returns "" past the last class.
+ * ctu_newton_histogram fills hist[8] with the bins accumulated since the histogram was
+ *   enabled (syncs). */
+enum { CTU_PROFILE_TIMING = 1, CTU_PROFILE_NEWTON = 2 };
+ctu_status ctu_profile_enable(ctu_grid* g, int32_t mode);
 ctu_status ctu_profile_read(ctu_grid* g, int32_t max_classes, double* ms, int64_t* launches,
                             int32_t* count);
 const char* ctu_profile_name(int32_t k);
+ctu_status ctu_newton_histogram(ctu_grid* g, uint64_t hist[8]);
 
 /* ---- Batches: many independent grids advanced together ----------------------------------
  * Continuous batching of independent grids (each created as above, any sizes, boundary

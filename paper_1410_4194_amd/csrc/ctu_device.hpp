@@ -39,6 +39,7 @@ struct GridParams {
   int root_m;           // 2 gamma/(gamma-1) when it is an integer (5 for 5/3, 7 for 7/5), else 0
   double inv_root_m;    // (gamma - 1) / (2 gamma)
   double inv_gm1;       // 1 / (gamma - 1)
+  int seg[3];           // faces per thread segment of the marching sweeps along y and z
 };
 
 // Device scalars of one grid (in the workspace).
@@ -52,6 +53,8 @@ struct DevScalars {
   long long steps;
   double t_end;                     // end time of the device-side time step
   long long steps_left;             // step budget of the device-side time step
+  unsigned long long newton_hist[8];  // Newton iterations per solve: 1, 2, 3, 4, 5-8, 9-16,
+                                      // >16, cap (instrumented steps only)
 };
 
 __device__ __forceinline__ long long cell_index(const GridParams& P, int i, int j, int k) {
@@ -116,37 +119,6 @@ __device__ __forceinline__ T mc_limit(T dl, T dr, T dc) {
   return T(0);
 }
 
-// Limited slope of the middle cell from the characteristic differences (PLMC slope step).
-template <typename T>
-__device__ __forceinline__ void char_slope(const T wm[5], const T w0[5], const T wp[5], T gamma,
-                                           T dw[5]) {
-  T rho = w0[0];
-  T a = tsqrt(gamma * w0[4] / rho);
-  T a2 = a * a;
-  T xi[5];
-  {
-    // project left, right and centred differences and limit each characteristic field
-    T dl1 = w0[1] - wm[1], dr1 = wp[1] - w0[1], dc1 = T(0.5) * (wp[1] - wm[1]);
-    T dl4 = w0[4] - wm[4], dr4 = wp[4] - w0[4], dc4 = T(0.5) * (wp[4] - wm[4]);
-    T dl0 = w0[0] - wm[0], dr0 = wp[0] - w0[0], dc0 = T(0.5) * (wp[0] - wm[0]);
-    T l0 = T(0.5) * (dl4 / a2 - rho * dl1 / a), r0 = T(0.5) * (dr4 / a2 - rho * dr1 / a),
-      c0 = T(0.5) * (dc4 / a2 - rho * dc1 / a);
-    T l1 = dl0 - dl4 / a2, r1 = dr0 - dr4 / a2, c1 = dc0 - dc4 / a2;
-    T l4 = T(0.5) * (dl4 / a2 + rho * dl1 / a), r4 = T(0.5) * (dr4 / a2 + rho * dr1 / a),
-      c4 = T(0.5) * (dc4 / a2 + rho * dc1 / a);
-    xi[0] = mc_limit(l0, r0, c0);
-    xi[1] = mc_limit(l1, r1, c1);
-    xi[4] = mc_limit(l4, r4, c4);
-    xi[2] = mc_limit(w0[2] - wm[2], wp[2] - w0[2], T(0.5) * (wp[2] - wm[2]));
-    xi[3] = mc_limit(w0[3] - wm[3], wp[3] - w0[3], T(0.5) * (wp[3] - wm[3]));
-  }
-  dw[0] = xi[0] + xi[1] + xi[4];
-  dw[1] = (a / rho) * (xi[4] - xi[0]);
-  dw[2] = xi[2];
-  dw[3] = xi[3];
-  dw[4] = a2 * (xi[0] + xi[4]);
-}
-
 template <typename T>
 __device__ __forceinline__ T ppm_IL(T alpha, T dw, T w6) {
   return T(0.5) * alpha * (dw + w6 * (T(1) + (T(2) / T(3)) * alpha));
@@ -156,224 +128,18 @@ __device__ __forceinline__ T ppm_IR(T beta, T dw, T w6) {
   return T(0.5) * beta * (dw - w6 * (T(1) - (T(2) / T(3)) * beta));
 }
 
-// PPMC of the centre cell c of a five-cell stencil w[0..4] = cells c-2..c+2 (rotated
-// primitives).  Returns W*_L (left face of c) and W*_R (right face of c).
-template <typename T>
-__device__ __forceinline__ void ppmc(const T w[5][5], T dtodx, T gamma, T WsL[5], T WsR[5]) {
-  T dwm[5], dwc[5], dwp[5];
-  char_slope(w[0], w[1], w[2], gamma, dwm);
-  char_slope(w[1], w[2], w[3], gamma, dwc);
-  char_slope(w[2], w[3], w[4], gamma, dwp);
-
-  const T* wc = w[2];
-  T rho = wc[0];
-  T a = tsqrt(gamma * wc[4] / rho);
-  T a2 = a * a;
-  T lm = wc[1] - a, l0 = wc[1], lp = wc[1] + a;
-  T am = dtodx * tmin(lm, T(0)), bm = dtodx * tmax(lm, T(0));
-  T a0 = dtodx * tmin(l0, T(0)), b0 = dtodx * tmax(l0, T(0));
-  T ap = dtodx * tmin(lp, T(0)), bp = dtodx * tmax(lp, T(0));
-
-  T E[5], B[5], C[5], D[5];
-#pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    T c = wc[q];
-    T wl = T(0.5) * (c + w[1][q]) - (dwc[q] - dwm[q]) / T(6);
-    T wr = T(0.5) * (w[3][q] + c) - (dwp[q] - dwc[q]) / T(6);
-    if ((wr - c) * (c - wl) <= T(0)) {
-      wl = c;
-      wr = c;
-    }
-    if ((wr - wl) * (wl - (T(3) * c - T(2) * wr)) < T(0)) wl = T(3) * c - T(2) * wr;
-    if ((wr - wl) * ((T(3) * c - T(2) * wl) - wr) < T(0)) wr = T(3) * c - T(2) * wl;
-    wl = tmin(tmax(c, w[1][q]), tmax(tmin(c, w[1][q]), wl));
-    wr = tmin(tmax(c, w[3][q]), tmax(tmin(c, w[3][q]), wr));
-    T dw = wr - wl;
-    T w6 = T(6) * c - T(3) * (wl + wr);
-    T ILm = ppm_IL(am, dw, w6);
-    T IRp = ppm_IR(bp, dw, w6);
-    WsL[q] = wl - ILm;
-    WsR[q] = wr - IRp;
-    E[q] = ILm - ppm_IL(a0, dw, w6);
-    B[q] = ILm - ppm_IL(ap, dw, w6);
-    C[q] = IRp - ppm_IR(bm, dw, w6);
-    D[q] = IRp - ppm_IR(b0, dw, w6);
-  }
-  if (l0 < T(0)) {
-    WsL[0] += E[0] - E[4] / a2;
-    WsL[2] += E[2];
-    WsL[3] += E[3];
-  }
-  if (lp < T(0)) {
-    WsL[0] += T(0.5) * (rho * B[1] / a + B[4] / a2);
-    WsL[1] += T(0.5) * (B[1] + B[4] / (a * rho));
-    WsL[4] += T(0.5) * (rho * B[1] * a + B[4]);
-  }
-  if (lm > T(0)) {
-    WsR[0] += T(0.5) * (-rho * C[1] / a + C[4] / a2);
-    WsR[1] += T(0.5) * (C[1] - C[4] / (a * rho));
-    WsR[4] += T(0.5) * (-rho * C[1] * a + C[4]);
-  }
-  if (l0 > T(0)) {
-    WsR[0] += D[0] - D[4] / a2;
-    WsR[2] += D[2];
-    WsR[3] += D[3];
-  }
-}
-
 // ---- exact Riemann solver (App. B.1) -----------------------------------------------------
-// Pressure function f_k(p) and derivative.  In a rarefaction both come from one power
-// z = (p/p_k)^((g-1)/(2g)): f' = (1/(rho_k a_k)) (p/p_k)^(-(g+1)/(2g)) = z / ((p/p_k) rho_k a_k).
-__device__ __forceinline__ void pressure_fn(double p, double rk, double pk, double ak,
-                                            const GridParams& P, double& f, double& df,
-                                            double& z) {
-  if (p <= pk) {
-    double r = p / pk;
-    z = pow(r, P.z_exp);
-    f = P.two_over_gm1 * ak * (z - 1.0);
-    df = z / (r * rk * ak);
-  } else {
-    double A = P.two_over_gp1 / rk;
-    double B = P.gm1_over_gp1 * pk;
-    double q = sqrt(A / (p + B));
-    f = (p - pk) * q;
-    df = q * (1.0 - (p - pk) / (2.0 * (B + p)));
-    z = 0.0;
-  }
-}
-
 struct RiemannCounts {
   unsigned floors;
   unsigned caps;
+  int iters;  // Newton iterations of the last solve, 0 when it hit the cap
 };
 
-// Interface flux from rotated conserved states UL, UR (normal momentum in slot 1).
-template <typename T>
-__device__ __forceinline__ void exact_flux(const T UL[5], const T UR[5], const GridParams& P,
-                                           T F[5], RiemannCounts& cnt) {
-  const T g = T(P.gamma);
-  const T gm1 = T(P.gm1);
-  const T pf = T(P.p_floor);
-  T WL[5], WR[5];
-  cnt.floors += cons_to_prim(UL, gm1, pf, WL) ? 1u : 0u;
-  cnt.floors += cons_to_prim(UR, gm1, pf, WR) ? 1u : 0u;
-
-  // Star region in double.
-  const double rl = WL[0], ul = WL[1], pl = WL[4];
-  const double rr = WR[0], ur = WR[1], pr = WR[4];
-  const double al = sqrt(P.gamma * pl / rl);
-  const double ar = sqrt(P.gamma * pr / rr);
-  double pt = 0.5 * (pl + pr) + 0.125 * (ul - ur) * (rl + rr) * (al + ar);
-  pt = pt < 0.0 ? 0.0 : pt;
-  const double Al = P.two_over_gp1 / rl, Bl = P.gm1_over_gp1 * pl;
-  const double Ar = P.two_over_gp1 / rr, Br = P.gm1_over_gp1 * pr;
-  const double gl = sqrt(Al / (pt + Bl));
-  const double gr = sqrt(Ar / (pt + Br));
-  double p = (gl * pl + gr * pr - (ur - ul)) / (gl + gr);
-  p = p < 1.0e-6 ? 1.0e-6 : p;
-  double fl, dfl, fr, dfr, zl, zr;
-  bool conv = false;
-  for (int it = 0; it < P.newton_max_iter; ++it) {
-    pressure_fn(p, rl, pl, al, P, fl, dfl, zl);
-    pressure_fn(p, rr, pr, ar, P, fr, dfr, zr);
-    double pn = p - (fl + fr + ur - ul) / (dfl + dfr);
-    if (!(pn >= P.p_floor)) pn = P.p_floor;
-    double delta = 2.0 * fabs(pn - p) / fabs(pn + p);
-    p = pn;
-    if (delta < P.newton_tol) {
-      conv = true;
-      break;
-    }
-  }
-  cnt.caps += conv ? 0u : 1u;
-  pressure_fn(p, rl, pl, al, P, fl, dfl, zl);
-  pressure_fn(p, rr, pr, ar, P, fr, dfr, zr);
-  const double ps = p;
-  const double us = 0.5 * (ul + ur + fr - fl);
-
-  // Sample the solution at x/t = 0.
-  T rho, u, pres;
-  if (us >= 0.0) {
-    if (ps <= pl) {
-      if (ul - al >= 0.0) {
-        rho = WL[0];
-        u = WL[1];
-        pres = WL[4];
-      } else if (us - al * zl < 0.0) {
-        // star state left of the contact: rho_L (p*/p_L)^(1/g) = rho_L z^(2/(g-1))
-        rho = T(rl * (P.fan_int_exp ? ipow(zl, P.fan_int_exp) : pow(zl, P.two_over_gm1)));
-        u = T(us);
-        pres = T(ps);
-      } else {
-        T c = T(P.two_over_gp1) * (T(al) + T(0.5) * gm1 * WL[1]);
-        T r = c / T(al);
-        T rr_ = P.fan_int_exp ? ipow(r, P.fan_int_exp) : tpow(r, T(P.two_over_gm1));
-        rho = WL[0] * rr_;
-        u = c;
-        pres = WL[4] * rr_ * r * r;
-      }
-    } else {
-      double sl = ul - al * sqrt(P.shock_a * ps / pl + P.shock_b);
-      if (sl >= 0.0) {
-        rho = WL[0];
-        u = WL[1];
-        pres = WL[4];
-      } else {
-        double q = ps / pl;
-        rho = T(rl * (q + P.gm1_over_gp1) / (q * P.gm1_over_gp1 + 1.0));
-        u = T(us);
-        pres = T(ps);
-      }
-    }
-  } else {
-    if (ps <= pr) {
-      if (ur + ar <= 0.0) {
-        rho = WR[0];
-        u = WR[1];
-        pres = WR[4];
-      } else if (us + ar * zr >= 0.0) {
-        rho = T(rr * (P.fan_int_exp ? ipow(zr, P.fan_int_exp) : pow(zr, P.two_over_gm1)));
-        u = T(us);
-        pres = T(ps);
-      } else {
-        T c = T(P.two_over_gp1) * (T(ar) - T(0.5) * gm1 * WR[1]);
-        T r = c / T(ar);
-        T rr_ = P.fan_int_exp ? ipow(r, P.fan_int_exp) : tpow(r, T(P.two_over_gm1));
-        rho = WR[0] * rr_;
-        u = -c;
-        pres = WR[4] * rr_ * r * r;
-      }
-    } else {
-      double sr = ur + ar * sqrt(P.shock_a * ps / pr + P.shock_b);
-      if (sr <= 0.0) {
-        rho = WR[0];
-        u = WR[1];
-        pres = WR[4];
-      } else {
-        double q = ps / pr;
-        rho = T(rr * (q + P.gm1_over_gp1) / (q * P.gm1_over_gp1 + 1.0));
-        u = T(us);
-        pres = T(ps);
-      }
-    }
-  }
-  // Transverse velocities are advected with the flow: upwind by the sampled velocity.
-  T vt = (u >= T(0)) ? WL[2] : WR[2];
-  T wt = (u >= T(0)) ? WL[3] : WR[3];
-  T E = pres / gm1 + T(0.5) * rho * (u * u + vt * vt + wt * wt);
-  F[0] = rho * u;
-  F[1] = rho * u * u + pres;
-  F[2] = rho * u * vt;
-  F[3] = rho * u * wt;
-  F[4] = (E + pres) * u;
-  (void)g;
-}
-
 // ======================================================================================
-// Fast forms used by the fused sweep kernels.  Same operations as above, rearranged for the
-// gfx950 VALU: one reciprocal per cell instead of repeated divisions, and the power
-// (p/p_k)^((g-1)/(2g)) of the Riemann solver taken as an integer root when 2g/(g-1) is an
-// integer.  Results differ from the plain forms only by rounding.
+// Forms used by the fused sweep kernels, arranged for the gfx950 VALU: one reciprocal per
+// cell instead of repeated divisions, and the power (p/p_k)^((g-1)/(2g)) of the Riemann
+// solver taken as an integer root when 2g/(g-1) is an integer.  They differ from the
+// textbook formulas only by rounding.
 // ======================================================================================
 
 // Inverse integer root y = r^(-1/m) for r > 0 and integer m >= 2: a float estimate from
@@ -622,10 +388,12 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
     p = pn;
     if (done) {
       conv = true;
+      cnt.iters = it + 1;
       break;
     }
   }
   cnt.caps += conv ? 0u : 1u;
+  if (!conv) cnt.iters = 0;
   // u* from f_L, f_R at the final star pressure; when the last step did not move p the
   // values just computed are already those.
   if (!same) {

@@ -191,10 +191,10 @@ __global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab) {
 
 // ---- fused sweeps --------------------------------------------------------------------------
 // Stage 1 (a2-a5) and stage 2 (a2-a4 re-traced, a6-a7) of one direction D each run as one
-// kernel.  Along y and z a thread owns one column and marches along D over a segment of SEG
-// faces, keeping a register window of primitives (cells c-1..c+2) and limited slopes
-// (c-1..c+1): every primitive, slope and trace is computed once per cell (plus a short
-// warm-up per segment) and each face's Riemann problem once.  Along x a wavefront covers 64
+// kernel.  Along y and z a thread owns one column and marches along D over a segment of
+// P.seg[D] faces, keeping a register window of primitives (cells c-1..c+2) and limited
+// slopes (c-1..c+1): every primitive, slope and trace is computed once per cell (plus a
+// short warm-up per segment) and each face's Riemann problem once.  Along x a wavefront covers 64
 // consecutive cells of one row and exchanges neighbours with lane shuffles; it yields XW
 // faces.
 
@@ -266,12 +266,34 @@ __device__ __forceinline__ void flush_counts(const RiemannCounts& cnt, DevScalar
   }
 }
 
+// Newton-iteration histogram of the solves of one wavefront (instrumented sweeps only):
+// each solve's bin is counted over the active lanes with a ballot, so lanes that left the
+// kernel early are simply not counted.
+struct NewtonHist {
+  unsigned long long n[8];
+  __device__ void add(int iters) {
+    const int b = iters == 0 ? 7
+                  : iters <= 4 ? iters - 1 : (iters <= 8 ? 4 : (iters <= 16 ? 5 : 6));
+#pragma unroll
+    for (int k = 0; k < 8; ++k) n[k] += __popcll(__ballot(b == k));
+  }
+  // The first active lane adds the wave's counts to the grid's histogram.
+  __device__ void flush(DevScalars* s) const {
+    const unsigned long long act = __ballot(1);
+    if ((int)__lane_id() == __ffsll((long long)act) - 1) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (n[k]) atomicAdd(&s->newton_hist[k], n[k]);
+    }
+  }
+};
+
 // STAGE = 1: first-stage fluxes F*_D on faces c-1/2, c in [0, n_D], transverse range
 //            [-1, n] on both other axes; written at cell c-1.
 // STAGE = 2: CTU fluxes F^{n+1/2}_D on the same faces over the real transverse range, from
 //            the re-traced states plus the transverse flux differences of stage 1.
 // Block layout per grid: (plane block of kBlock columns, segment), plane blocks fastest.
-template <typename T, int D, int STAGE>
+template <typename T, int D, int STAGE, bool HIST>
 __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   static_assert(D == 1 || D == 2, "marching sweeps run along y or z");
   const BlockRef r = block_ref(tab);
@@ -289,14 +311,15 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   const int eb = P.n[B] + (STAGE == 1 ? 2 : 0);
   const int nd = P.n[D];
   const long long nbx = ((long long)ea * eb + kBlock - 1) / kBlock;
-  const long long nseg = (nd + 1 + SEG - 1) / SEG;
+  const int seg = P.seg[D];
+  const long long nseg = (nd + 1 + seg - 1) / seg;
   if (r.lb >= nbx * nseg) return;
   const long long tid = (r.lb % nbx) * kBlock + threadIdx.x;
   if (tid >= (long long)ea * eb) return;
   const int i = (int)(tid % ea) + lo;
   const int o = (int)(tid / ea) + lo;
-  const int f0 = (int)(r.lb / nbx) * SEG;
-  const int f1 = min(f0 + SEG, nd + 1);
+  const int f0 = (int)(r.lb / nbx) * seg;
+  const int f1 = min(f0 + seg, nd + 1);
   const long long stx = 1, sty = P.N[0], stz = (long long)P.N[0] * P.N[1];
   const long long sd = D == 1 ? sty : stz;
   const long long c0 = D == 1 ? cell_index(P, i, 0, o) : cell_index(P, i, o, 0);
@@ -348,7 +371,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   T raw[5];
 #pragma unroll
   for (int sl = 0; sl < 5; ++sl) raw[sl] = u[rot<D>(sl) * P.stride + c0 + (long long)(f0 + 2) * sd];
-  RiemannCounts cnt{0u, 0u};
+  RiemannCounts cnt{0u, 0u, 0};
+  NewtonHist hist{};
   for (int c = f0; c < f1; ++c) {
     // window: q0 = c-1, q1 = c, q2 = c+1, slopes s0 = c-1, s1 = c
     make_prim(raw, T(P.gamma), T(P.gm1), T(P.p_floor), q3);  // cell c+2
@@ -373,6 +397,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
       }
     }
     exact_flux_fast(prevR, UL, P, F, cnt);
+    if (HIST) hist.add(cnt.iters);
     const long long fo = c0 + (long long)(c - 1) * sd;
 #pragma unroll
     for (int sl = 0; sl < 5; ++sl) out[rot<D>(sl) * P.stride + fo] = F[sl];
@@ -387,11 +412,12 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
     q2 = q3;
   }
   flush_counts(cnt, s);
+  if (HIST) hist.flush(s);
 }
 
 // x-direction sweep: one wavefront per (row, segment of XW faces).  Lane l holds cell
 // cw - 3 + l; slopes are valid on lanes 1..62, traces on 2..61, faces c-1/2 on 3..61.
-template <typename T, int STAGE>
+template <typename T, int STAGE, bool HIST>
 __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
@@ -457,12 +483,17 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
 #pragma unroll
   for (int q = 0; q < 5; ++q) prevR[q] = __shfl(UR[q], lm1, 64);
   if (lane >= 3 && lane <= 61 && c >= 0 && c <= P.n[0]) {
-    RiemannCounts cnt{0u, 0u};
+    RiemannCounts cnt{0u, 0u, 0};
     T F[5];
     exact_flux_fast(prevR, UL, P, F, cnt);
 #pragma unroll
     for (int q = 0; q < 5; ++q) out[q * P.stride + id - 1] = F[q];
     flush_counts(cnt, s);
+    if (HIST) {
+      NewtonHist hist{};
+      hist.add(cnt.iters);
+      hist.flush(s);
+    }
   }
 }
 
@@ -721,25 +752,25 @@ long long pass_blocks(const GridParams& P, int pass) {
     case P_BC_Y: return cdiv(2LL * NG * N0 * N2, kBlock);
     case P_BC_Z: return cdiv(2LL * NG * N0 * N1, kBlock);
     case P_S1_X: return cdiv(nseg_x * (n1 + 2) * (n2 + 2), kBlock / 64);
-    case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1 + 1, SEG);
-    case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2 + 1, SEG);
+    case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1 + 1, P.seg[1]);
+    case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2 + 1, P.seg[2]);
     case P_S2_X: return cdiv(nseg_x * n1 * n2, kBlock / 64);
-    case P_S2_Y: return cdiv(n0 * n2, kBlock) * cdiv(n1 + 1, SEG);
-    case P_S2_Z: return cdiv(n0 * n1, kBlock) * cdiv(n2 + 1, SEG);
+    case P_S2_Y: return cdiv(n0 * n2, kBlock) * cdiv(n1 + 1, P.seg[1]);
+    case P_S2_Z: return cdiv(n0 * n1, kBlock) * cdiv(n2 + 1, P.seg[2]);
     case P_UPDATE:
     case P_DT: return cdiv(n0 * n1 * n2, kBlock);
   }
   return 0;
 }
 
-#define TIMED(cls, launch)              \
-  do {                                  \
-    if (prof) prof->begin(cls, stream); \
-    launch;                             \
-    if (prof) prof->end(stream);        \
+#define TIMED(cls, launch)                            \
+  do {                                                \
+    if (prof && prof->timing) prof->begin(cls, stream); \
+    launch;                                           \
+    if (prof && prof->timing) prof->end(stream);        \
   } while (0)
 
-template <typename T>
+template <typename T, bool HIST>
 static void enqueue_step(const PlanView& v, bool device_dt, hipStream_t stream, Profiler* prof) {
   const int stride = v.ngrids + 1;
   auto tab = [&](int pass) { return LaunchTab{v.d_grids, v.d_start + pass * stride, v.ngrids}; };
@@ -756,18 +787,18 @@ static void enqueue_step(const PlanView& v, bool device_dt, hipStream_t stream, 
         hipLaunchKernelGGL((k_bc_fill<T, 2>), nblocks(P_BC_Z), B, 0, stream, tab(P_BC_Z)));
   // stage 1 (a2-a5): F*, G*, H* on the extended transverse range
   TIMED(K_SWEEP1_X,
-        hipLaunchKernelGGL((k_sweep_x<T, 1>), nblocks(P_S1_X), B, 0, stream, tab(P_S1_X)));
+        hipLaunchKernelGGL((k_sweep_x<T, 1, HIST>), nblocks(P_S1_X), B, 0, stream, tab(P_S1_X)));
   TIMED(K_SWEEP1_Y,
-        hipLaunchKernelGGL((k_sweep_march<T, 1, 1>), nblocks(P_S1_Y), B, 0, stream, tab(P_S1_Y)));
+        hipLaunchKernelGGL((k_sweep_march<T, 1, 1, HIST>), nblocks(P_S1_Y), B, 0, stream, tab(P_S1_Y)));
   TIMED(K_SWEEP1_Z,
-        hipLaunchKernelGGL((k_sweep_march<T, 2, 1>), nblocks(P_S1_Z), B, 0, stream, tab(P_S1_Z)));
+        hipLaunchKernelGGL((k_sweep_march<T, 2, 1, HIST>), nblocks(P_S1_Z), B, 0, stream, tab(P_S1_Z)));
   // stage 2 (a2-a4 re-traced, a6-a7): F^{n+1/2}, G^{n+1/2}, H^{n+1/2} on the real faces
   TIMED(K_SWEEP2_X,
-        hipLaunchKernelGGL((k_sweep_x<T, 2>), nblocks(P_S2_X), B, 0, stream, tab(P_S2_X)));
+        hipLaunchKernelGGL((k_sweep_x<T, 2, HIST>), nblocks(P_S2_X), B, 0, stream, tab(P_S2_X)));
   TIMED(K_SWEEP2_Y,
-        hipLaunchKernelGGL((k_sweep_march<T, 1, 2>), nblocks(P_S2_Y), B, 0, stream, tab(P_S2_Y)));
+        hipLaunchKernelGGL((k_sweep_march<T, 1, 2, HIST>), nblocks(P_S2_Y), B, 0, stream, tab(P_S2_Y)));
   TIMED(K_SWEEP2_Z,
-        hipLaunchKernelGGL((k_sweep_march<T, 2, 2>), nblocks(P_S2_Z), B, 0, stream, tab(P_S2_Z)));
+        hipLaunchKernelGGL((k_sweep_march<T, 2, 2, HIST>), nblocks(P_S2_Z), B, 0, stream, tab(P_S2_Z)));
   // a8-a9
   TIMED(K_UPDATE, hipLaunchKernelGGL(k_update<T>, nblocks(P_UPDATE), B, 0, stream, tab(P_UPDATE)));
   TIMED(K_DT_FINAL,
@@ -776,10 +807,18 @@ static void enqueue_step(const PlanView& v, bool device_dt, hipStream_t stream, 
 }
 
 hipError_t launch_step(const PlanView& v, bool device_dt, hipStream_t stream, Profiler* prof) {
-  if (v.prec == 0)
-    enqueue_step<double>(v, device_dt, stream, prof);
-  else
-    enqueue_step<float>(v, device_dt, stream, prof);
+  const bool hist = prof && prof->hist;
+  if (v.prec == 0) {
+    if (hist)
+      enqueue_step<double, true>(v, device_dt, stream, prof);
+    else
+      enqueue_step<double, false>(v, device_dt, stream, prof);
+  } else {
+    if (hist)
+      enqueue_step<float, true>(v, device_dt, stream, prof);
+    else
+      enqueue_step<float, false>(v, device_dt, stream, prof);
+  }
   return hipGetLastError();
 }
 

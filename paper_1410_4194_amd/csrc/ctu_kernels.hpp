@@ -21,7 +21,7 @@ enum Pass {
 };
 
 constexpr int kBlock = 256;  // threads per block of every pass
-constexpr int SEG = 32;      // faces per thread in the marching sweeps
+constexpr int kSegDefault = 32;  // target faces per thread in the marching sweeps
 constexpr int XW = 59;       // x-faces per wavefront in the shuffle sweeps
 
 // Everything a kernel needs about one grid, resident in device memory.
@@ -59,6 +59,8 @@ struct Profiler {
   std::vector<hipEvent_t> pool;
   double ms[K_NUM_CLASSES] = {};
   long long launches[K_NUM_CLASSES] = {};
+  bool timing = true;  // bracket kernels with events
+  bool hist = false;   // launch the sweeps that count Newton iterations per solve
   hipEvent_t take();
   void begin(int cls, hipStream_t s);
   void end(hipStream_t s);

@@ -77,6 +77,9 @@ ctu_status validate(const ctu_config* c) {
   if (c->newton_max_iter < 1) return fail(CTU_EINVAL, "newton_max_iter must be >= 1");
   if (!(c->p_floor > 0.0)) return fail(CTU_EINVAL, "p_floor must be > 0");
   if (c->prec != CTU_FP64 && c->prec != CTU_FP32) return fail(CTU_EINVAL, "unknown precision");
+  for (int a = 0; a < 2; ++a)
+    if (c->march_seg[a] < 0 || c->march_seg[a] > 4096)
+      return fail(CTU_EINVAL, "march_seg must lie in [0, 4096]");
   for (int a = 0; a < 3; ++a) {
     int lo = c->bc[2 * a], hi = c->bc[2 * a + 1];
     if ((lo != CTU_BC_PERIODIC && lo != CTU_BC_OUTFLOW) || (hi != CTU_BC_PERIODIC && hi != CTU_BC_OUTFLOW))
@@ -121,6 +124,15 @@ GridParams make_params(const ctu_config& c) {
   P.root_m = (std::fabs(m - mr) < 1e-12 && mr >= 2.0 && mr <= 16.0) ? (int)mr : 0;
   P.inv_root_m = (g - 1.0) / (2.0 * g);
   P.inv_gm1 = 1.0 / (g - 1.0);
+  // march segments: round((n+1)/target) equal segments of the n+1 faces of the axis
+  P.seg[0] = 0;
+  for (int a = 1; a < 3; ++a) {
+    const int faces = P.n[a] + 1;
+    const int target = c.march_seg[a - 1] > 0 ? c.march_seg[a - 1] : ctu::kSegDefault;
+    int nseg = (int)std::lround((double)faces / target);
+    nseg = nseg < 1 ? 1 : (nseg > faces ? faces : nseg);
+    P.seg[a] = (faces + nseg - 1) / nseg;
+  }
   return P;
 }
 
@@ -302,10 +314,20 @@ ctu_status ctu_grid_destroy(ctu_grid* g) {
 
 ctu_status ctu_profile_enable(ctu_grid* g, int32_t enable) {
   if (!g) return fail(CTU_EINVAL, "null grid");
+  if (enable & ~(CTU_PROFILE_TIMING | CTU_PROFILE_NEWTON)) return fail(CTU_EINVAL, "unknown mode");
   if (enable) {
     if (!g->prof) g->prof = new ctu::Profiler();
     HIP_TRY(hipStreamSynchronize(g->stream), "profile sync");
     g->prof->reset();
+    g->prof->timing = (enable & CTU_PROFILE_TIMING) != 0;
+    g->prof->hist = (enable & CTU_PROFILE_NEWTON) != 0;
+    if (g->prof->hist) {
+      HIP_TRY(hipMemsetAsync(reinterpret_cast<char*>(g->scalars()) +
+                                 offsetof(DevScalars, newton_hist),
+                             0, sizeof(DevScalars::newton_hist), g->stream),
+              "histogram clear");
+      HIP_TRY(hipStreamSynchronize(g->stream), "profile sync");
+    }
   } else if (g->prof) {
     HIP_TRY(hipStreamSynchronize(g->stream), "profile sync");
     delete g->prof;
@@ -328,6 +350,16 @@ ctu_status ctu_profile_read(ctu_grid* g, int32_t max_classes, double* ms, int64_
 }
 
 const char* ctu_profile_name(int32_t k) { return ctu::kernel_class_name(k); }
+
+ctu_status ctu_newton_histogram(ctu_grid* g, uint64_t hist[8]) {
+  if (!g || !hist) return fail(CTU_EINVAL, "null argument");
+  if (!g->prof || !g->prof->hist) return fail(CTU_EINVAL, "Newton histogram not enabled");
+  DevScalars s;
+  ctu_status st = read_scalars(g, &s);
+  if (st != CTU_OK) return st;
+  for (int k = 0; k < 8; ++k) hist[k] = s.newton_hist[k];
+  return CTU_OK;
+}
 
 ctu_status ctu_grid_info_get(ctu_grid* g, ctu_grid_info* info) {
   if (!g || !info) return fail(CTU_EINVAL, "null argument");

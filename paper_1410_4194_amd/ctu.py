@@ -28,6 +28,8 @@ FP64, FP32 = 0, 1
 FLAG_NONFINITE, FLAG_DENSITY, FLAG_PFLOOR, FLAG_NEWTON_CAP = 1, 2, 4, 8
 TICKET_QUEUED, TICKET_RUNNING, TICKET_DONE, TICKET_FAILED, TICKET_UNKNOWN = 0, 1, 2, 3, -1
 BATCH_GRAPH = 1
+PROFILE_TIMING, PROFILE_NEWTON = 1, 2
+NEWTON_BINS = ("1", "2", "3", "4", "5-8", "9-16", ">16", "cap")
 
 EXPORTS = [
     "ctu_config_default", "ctu_workspace_bytes", "ctu_grid_create", "ctu_grid_destroy",
@@ -36,7 +38,7 @@ EXPORTS = [
     "ctu_debug_fluxes", "ctu_batch_workspace_bytes", "ctu_batch_create", "ctu_batch_submit",
     "ctu_batch_run",
     "ctu_batch_poll", "ctu_batch_destroy", "ctu_last_error", "ctu_profile_enable",
-    "ctu_profile_read", "ctu_profile_name",
+    "ctu_profile_read", "ctu_profile_name", "ctu_newton_histogram",
 ]
 
 
@@ -45,7 +47,8 @@ class Config(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("gamma", C.c_double), ("bc", C.c_int32 * 6), ("prec", C.c_int32),
                 ("cfl", C.c_double), ("newton_tol", C.c_double),
-                ("newton_max_iter", C.c_int32), ("p_floor", C.c_double)]
+                ("newton_max_iter", C.c_int32), ("p_floor", C.c_double),
+                ("march_seg", C.c_int32 * 2)]
 
 
 class GridInfo(C.Structure):
@@ -92,6 +95,7 @@ def _load() -> C.CDLL:
         "ctu_profile_read": ([vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                               C.POINTER(C.c_int32)], st),
         "ctu_profile_name": ([C.c_int32], C.c_char_p),
+        "ctu_newton_histogram": ([vp, C.POINTER(C.c_uint64)], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -110,7 +114,10 @@ def _check(status: int, allow=()) -> int:
 
 
 def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64, cfl=0.3,
-                newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20) -> Config:
+                newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20, march_seg=None) -> Config:
+    """Grid configuration.  march_seg: target faces per thread of the y and z sweeps; None
+    takes the autotuned table (tiles.json beside this module) when it exists, else the
+    library default."""
     c = Config()
     lib.ctu_config_default(C.byref(c))
     c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
@@ -123,6 +130,10 @@ def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64,
     c.newton_tol = float(newton_tol)
     c.newton_max_iter = int(newton_max_iter)
     c.p_floor = float(p_floor)
+    if march_seg is None:
+        from .autotune import lookup
+        march_seg = lookup(int(prec), int(ny), int(nz))
+    c.march_seg[0], c.march_seg[1] = int(march_seg[0]), int(march_seg[1])
     return c
 
 
@@ -234,8 +245,15 @@ class Grid:
         status = lib.ctu_check(self.handle, C.byref(flags), cnt)
         return status, flags.value, list(cnt)
 
-    def profile_enable(self, on: bool = True) -> None:
-        _check(lib.ctu_profile_enable(self.handle, 1 if on else 0))
+    def profile_enable(self, on: bool = True, newton: bool = False) -> None:
+        """Per-kernel event timing (on), and/or the Newton-iteration histogram (newton)."""
+        mode = (PROFILE_TIMING if on else 0) | (PROFILE_NEWTON if newton else 0)
+        _check(lib.ctu_profile_enable(self.handle, mode))
+
+    def newton_histogram(self) -> dict:
+        out = (C.c_uint64 * 8)()
+        _check(lib.ctu_newton_histogram(self.handle, out))
+        return dict(zip(NEWTON_BINS, [int(v) for v in out]))
 
     def profile_read(self) -> dict:
         """{kernel class: (total ms, launches)} accumulated since profile_enable."""

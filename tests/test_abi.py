@@ -53,6 +53,7 @@ def test_workspace_bytes_and_validation(ctu):
         dict(nx=0), dict(dx=0.0), dict(gamma=1.0), dict(cfl=0.5), dict(cfl=0.0),
         dict(bc=(0, 1, 0, 0, 0, 0)), dict(bc=(2, 2, 0, 0, 0, 0)), dict(prec=7),
         dict(newton_max_iter=0), dict(newton_tol=0.0), dict(p_floor=0.0),
+        dict(march_seg=(-1, 0)), dict(march_seg=(0, 5000)),
     ]
     for b in bad:
         args = dict(nx=8, ny=8, nz=8, dx=1.0, dy=1.0, dz=1.0, gamma=1.4)

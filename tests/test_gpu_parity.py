@@ -210,3 +210,58 @@ def test_newton_cap_is_counted(ctu):
     g.step(g.compute_dt())
     status, flags, counters = g.check()
     assert status == ctu.ENOCONV and counters[1] > 0
+
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_march_segments_do_not_change_results(ctu, prec):
+    """The tile shape of the marching sweeps (faces per thread segment, including one-face
+    segments and one segment per column) changes the launch; the result changes only by
+    rounding (a segment's first trace is a separately compiled copy of the same formulas,
+    whose multiply-adds the compiler may fuse differently), well inside the parity bound."""
+    wl = WL.random_state(12, 37, 29, seed=77, bc=(0, 0, 1, 1, 0, 0))
+    _announce("march segments", prec)
+    ref = None
+    for seg in ((0, 0), (1, 1), (5, 7), (38, 30), (64, 64)):
+        cfg = ctu.make_config(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.gamma, wl.bc, prec,
+                              wl.cfl, march_seg=seg)
+        g = ctu.Grid(cfg)
+        g.set_primitive(wl.W)
+        g.advance(3)
+        U = g.get_state()
+        g.close()
+        if ref is None:
+            ref = U
+        else:
+            err = rel_l1(U, ref, wl.gamma)
+            assert err.max() <= (TOL64 if prec == 0 else TOL32), (seg, err)
+
+
+def test_newton_histogram_counts_every_solve(ctu):
+    """The instrumented sweeps count one Newton-iteration bin per exact Riemann solve: the
+    bins add up to the number of solves a step makes (stage 1 on the extended transverse
+    ranges, stage 2 on the real faces), and the instrumented step gives the same state."""
+    wl = WL.random_state(21, 14, 9, seed=5, bc=(1, 1, 0, 0, 1, 1))
+    nx, ny, nz = wl.nx, wl.ny, wl.nz
+    solves = ((nx + 1) * (ny + 2) * (nz + 2) + (nx + 2) * (ny + 1) * (nz + 2)
+              + (nx + 2) * (ny + 2) * (nz + 1)
+              + (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1))
+    _announce("newton histogram")
+    plain = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    plain.advance(2)
+    ref = plain.get_state()
+    g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    g.profile_enable(False, newton=True)
+    g.advance(2)
+    hist = g.newton_histogram()
+    assert sum(hist.values()) == 2 * solves, hist
+    assert hist["1"] + hist["2"] + hist["3"] > 0 and hist["cap"] == 0
+    err = rel_l1(g.get_state(), ref, wl.gamma)
+    assert err.max() <= TOL64, err
+    capped = ctu.Grid(ctu.make_config(nx, ny, nz, wl.dx, wl.dy, wl.dz, wl.gamma, wl.bc,
+                                      newton_max_iter=1))
+    capped.set_primitive(wl.W)
+    capped.profile_enable(False, newton=True)
+    capped.step(capped.compute_dt())
+    h1 = capped.newton_histogram()
+    assert h1["1"] + h1["cap"] == solves and h1["cap"] > 0, h1
