@@ -11,24 +11,35 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 REPO = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libctu.so")
-SOURCES = ["ctu_kernels.hip", "ctu_runtime.cpp"]
 ARCH = os.environ.get("CTU_OFFLOAD_ARCH", "gfx950")
+# (source, object, extra defines): the sweep kernels are compiled once per storage type and
+# gas class, in parallel
+UNITS = [("ctu_kernels.hip", "ctu_kernels.o", []), ("ctu_runtime.cpp", "ctu_runtime.o", [])] + [
+    ("ctu_sweeps.hip", f"ctu_sweeps_{t[0]}{k}.o", [f"-DCTU_SWEEP_T={t}", f"-DCTU_SWEEP_K={k}"])
+    for t in ("double", "float") for k in (0, 3, 5)]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
-        cmd = [hipcc, "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
-               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-Wall", "-Wno-unused-function",
-               "-I", os.path.join(REPO, "include"), "-I", CSRC,
-               "-c", os.path.join(CSRC, src), "-o", obj]
+    cmds, objs = [], []
+    for src, obj, defs in UNITS:
+        obj = os.path.join(CSRC, obj)
+        cmds.append([hipcc, "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+                     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                     "-Wall", "-Wno-unused-function", *defs,
+                     "-I", os.path.join(REPO, "include"), "-I", CSRC,
+                     "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(run, c) for c in cmds]:
+            f.result()
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)

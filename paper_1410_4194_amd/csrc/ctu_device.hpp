@@ -145,24 +145,56 @@ struct RiemannCounts {
 // Inverse integer root y = r^(-1/m) for r > 0 and integer m >= 2: a float estimate from
 // the hardware log2/exp2 units, then two Newton steps y <- y + y (1 - r y^m) / m in double,
 // which need no division and converge quadratically from ~1e-6 relative error to full
-// double precision.  Returns y and y^(m-1); then r^(1/m) = r y^(m-1).
-__device__ __forceinline__ void inv_root_int(double r, int m, double inv_m, double& y,
+// double precision.  Returns y and y^(m-1); then r^(1/m) = r y^(m-1).  Outside the float
+// range r is first scaled by 2^(-m j) (an exact power of two), so y scales by 2^j.
+// M > 0 fixes m at compile time; M = 0 takes the runtime m.
+template <int M>
+__device__ __forceinline__ void inv_root_int(double r, int m_rt, double inv_m_rt, double& y,
                                              double& ym1) {
-  const float rf = (float)r;
+  const int m = M > 0 ? M : m_rt;
+  const double inv_m = M > 0 ? 1.0 / M : inv_m_rt;
+  float rf = (float)r;
+  int j = 0;
   if (!(rf > 1.0e-30f && rf < 1.0e30f)) {
-    y = pow(r, -inv_m);
-    ym1 = pow(r, -(1.0 - inv_m));
-    return;
+    int e;
+    (void)frexp(r, &e);
+    j = e / m;
+    r = ldexp(r, -m * j);
+    rf = (float)r;
   }
   y = (double)__builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(rf) * (float)inv_m);
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
     double yp = y;
-    for (int i = 1; i < m; ++i) yp *= y;  // y^m
+#pragma unroll
+    for (int i = 1; i < (M > 0 ? M : 16); ++i) {
+      if (M == 0 && i >= m) break;
+      yp *= y;  // y^m
+    }
     y = fma(y * inv_m, fma(-r, yp, 1.0), y);
   }
   ym1 = y;
-  for (int i = 2; i < m; ++i) ym1 *= y;
+#pragma unroll
+  for (int i = 2; i < (M > 0 ? M : 16); ++i) {
+    if (M == 0 && i >= m) break;
+    ym1 *= y;
+  }
+  if (j) {
+    y = ldexp(y, -j);
+    ym1 = ldexp(ym1, -j * (m - 1));
+  }
+}
+
+// x^N for a compile-time N >= 1, or the runtime n when N = 0.
+template <int N, typename T>
+__device__ __forceinline__ T ipow_n(T x, int n) {
+  if (N > 0) {
+    T r = x;
+#pragma unroll
+    for (int i = 1; i < N; ++i) r *= x;
+    return r;
+  }
+  return ipow(x, n);
 }
 
 // Primitive variables of one cell in the rotated frame of a sweep, with its sound speed
@@ -306,14 +338,17 @@ struct SideK {
   double A, B;   // 2/((g+1) rho_k), (g-1)/(g+1) p_k
 };
 
+// K is the gas class: K > 0 when 2/(g-1) = K and 2g/(g-1) = K + 2 are integers (K = 3 for
+// g = 5/3, K = 5 for g = 7/5), fixed at compile time; K = 0 decides from the runtime constants.
+template <int K>
 __device__ __forceinline__ void pfun_fast(double p, const SideK& k, const GridParams& P,
                                           double& f, double& df, double& z) {
   if (p <= k.p) {
     const double r = p * k.ip;
-    if (P.root_m) {
+    if (K > 0 || P.root_m) {
       // z = r^((g-1)/(2g)) = r y^(m-1) with y = r^(-1/m); f' = z/(r rho a) = y^(m-1)/(rho a)
       double y, ym1;
-      inv_root_int(r, P.root_m, P.inv_root_m, y, ym1);
+      inv_root_int<(K > 0 ? K + 2 : 0)>(r, P.root_m, P.inv_root_m, y, ym1);
       z = r * ym1;
       df = ym1 * k.irhoa;
     } else {
@@ -330,8 +365,8 @@ __device__ __forceinline__ void pfun_fast(double p, const SideK& k, const GridPa
   }
 }
 
-// Exact Riemann flux from rotated conserved states (App. B.1), fast form.
-template <typename T>
+// Exact Riemann flux from rotated conserved states (App. B.1), fast form; K as in pfun_fast.
+template <typename T, int K>
 __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], const GridParams& P,
                                                 T F[5], RiemannCounts& cnt) {
   const T gm1 = T(P.gm1);
@@ -378,8 +413,8 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
   bool conv = false;
   bool same = false;  // the last Newton step left p unchanged
   for (int it = 0; it < P.newton_max_iter; ++it) {
-    pfun_fast(p, kl, P, fl, dfl, zl);
-    pfun_fast(p, kr, P, fr, dfr, zr);
+    pfun_fast<K>(p, kl, P, fl, dfl, zl);
+    pfun_fast<K>(p, kr, P, fr, dfr, zr);
     double pn = p - (fl + fr + du) / (dfl + dfr);
     if (!(pn >= P.p_floor)) pn = P.p_floor;
     // relative change 2|pn - p|/|pn + p| < tol, without the division
@@ -397,8 +432,8 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
   // u* from f_L, f_R at the final star pressure; when the last step did not move p the
   // values just computed are already those.
   if (!same) {
-    pfun_fast(p, kl, P, fl, dfl, zl);
-    pfun_fast(p, kr, P, fr, dfr, zr);
+    pfun_fast<K>(p, kl, P, fl, dfl, zl);
+    pfun_fast<K>(p, kr, P, fr, dfr, zr);
   }
   const double ps = p;
   const double us = 0.5 * (kl.u + kr.u + fr - fl);
@@ -411,13 +446,15 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
         u = L.w[1];
         pres = L.w[4];
       } else if (us - kl.a * zl < 0.0) {
-        rho = T(kl.rho * (P.fan_int_exp ? ipow(zl, P.fan_int_exp) : pow(zl, P.two_over_gm1)));
+        rho = T(kl.rho * ((K > 0 || P.fan_int_exp) ? ipow_n<K>(zl, P.fan_int_exp)
+                                                      : pow(zl, P.two_over_gm1)));
         u = T(us);
         pres = T(ps);
       } else {
         const T c = T(P.two_over_gp1) * (T(kl.a) + T(0.5) * gm1 * L.w[1]);
         const T r = c / T(kl.a);
-        const T rr_ = P.fan_int_exp ? ipow(r, P.fan_int_exp) : tpow(r, T(P.two_over_gm1));
+        const T rr_ = (K > 0 || P.fan_int_exp) ? ipow_n<K>(r, P.fan_int_exp)
+                                                 : tpow(r, T(P.two_over_gm1));
         rho = L.w[0] * rr_;
         u = c;
         pres = L.w[4] * rr_ * r * r;
@@ -442,13 +479,15 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
         u = R.w[1];
         pres = R.w[4];
       } else if (us + kr.a * zr >= 0.0) {
-        rho = T(kr.rho * (P.fan_int_exp ? ipow(zr, P.fan_int_exp) : pow(zr, P.two_over_gm1)));
+        rho = T(kr.rho * ((K > 0 || P.fan_int_exp) ? ipow_n<K>(zr, P.fan_int_exp)
+                                                      : pow(zr, P.two_over_gm1)));
         u = T(us);
         pres = T(ps);
       } else {
         const T c = T(P.two_over_gp1) * (T(kr.a) - T(0.5) * gm1 * R.w[1]);
         const T r = c / T(kr.a);
-        const T rr_ = P.fan_int_exp ? ipow(r, P.fan_int_exp) : tpow(r, T(P.two_over_gm1));
+        const T rr_ = (K > 0 || P.fan_int_exp) ? ipow_n<K>(r, P.fan_int_exp)
+                                                 : tpow(r, T(P.two_over_gm1));
         rho = R.w[0] * rr_;
         u = -c;
         pres = R.w[4] * rr_ * r * r;

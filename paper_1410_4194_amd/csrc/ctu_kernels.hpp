@@ -77,7 +77,34 @@ struct PlanView {
   int ngrids;
   const int* h_start;  // same layout as d_start
   int prec;            // 0 = double, 1 = float
+  int gclass;          // gas class of the exact solver: 3 (gamma 5/3), 5 (gamma 7/5), 0 other
 };
+
+// Gas class of a grid: K when 2/(gamma-1) = K and 2 gamma/(gamma-1) = K + 2 for K in {3, 5}.
+inline int gas_class(const GridParams& P) {
+  return ((P.fan_int_exp == 3 || P.fan_int_exp == 5) && P.root_m == P.fan_int_exp + 2)
+             ? P.fan_int_exp
+             : 0;
+}
+
+// The three sweeps of stage 1 or 2 for every grid of a plan; one specialization per
+// (T, K) is compiled in its own translation unit (ctu_sweeps.hip).
+template <typename T, int K>
+hipError_t launch_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof);
+template <> hipError_t launch_sweeps<double, 0>(const PlanView&, int, hipStream_t, Profiler*);
+template <> hipError_t launch_sweeps<double, 3>(const PlanView&, int, hipStream_t, Profiler*);
+template <> hipError_t launch_sweeps<double, 5>(const PlanView&, int, hipStream_t, Profiler*);
+template <> hipError_t launch_sweeps<float, 0>(const PlanView&, int, hipStream_t, Profiler*);
+template <> hipError_t launch_sweeps<float, 3>(const PlanView&, int, hipStream_t, Profiler*);
+template <> hipError_t launch_sweeps<float, 5>(const PlanView&, int, hipStream_t, Profiler*);
+
+// Brackets one launch with profiler events when timing is on.
+#define CTU_TIMED(cls, launch)                                \
+  do {                                                        \
+    if (prof && prof->timing) prof->begin(cls, stream);       \
+    launch;                                                   \
+    if (prof && prof->timing) prof->end(stream);              \
+  } while (0)
 
 // One step for every grid of the plan.  device_dt: take dt from each grid's CFL bound and
 // end time (k_begin_step); otherwise each grid's dt was set beforehand.

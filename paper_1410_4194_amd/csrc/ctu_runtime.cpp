@@ -180,7 +180,8 @@ struct ctu_grid {
   ctu::GridDesc* d_desc() const { return reinterpret_cast<ctu::GridDesc*>(d_work + kDescOffset); }
   int* d_start() const { return reinterpret_cast<int*>(d_work + kStartOffset); }
   ctu::PlanView plan() const {
-    return ctu::PlanView{d_desc(), d_start(), 1, h_start.data(), cfg.prec == CTU_FP32 ? 1 : 0};
+    return ctu::PlanView{d_desc(), d_start(), 1, h_start.data(), cfg.prec == CTU_FP32 ? 1 : 0,
+                         ctu::gas_class(P)};
   }
 };
 
@@ -555,24 +556,26 @@ struct ctu_batch {
     double t_end = 0.0;
     int32_t state = CTU_TICKET_UNKNOWN;
   };
-  // Grids of one precision launched together: descriptors and block table on the device,
-  // host copies of both (the block counts are needed at launch).
+  // Grids of one precision and gas class launched together: descriptors and block table
+  // on the device, host copies of both (the block counts are needed at launch).
   struct Group {
     int prec = 0;
+    int gclass = 0;
     std::vector<ctu::GridDesc> descs;
     std::vector<int> start;
     ctu::GridDesc* d_desc = nullptr;
     int* d_start = nullptr;
     ctu::PlanView view() const {
-      return ctu::PlanView{d_desc, d_start, (int)descs.size(), start.data(), prec};
+      return ctu::PlanView{d_desc, d_start, (int)descs.size(), start.data(), prec, gclass};
     }
   };
+  static constexpr int kGroups = 6;  // {FP64, FP32} x gas class {0, 3, 5}
   std::vector<Slot> slots;
   int32_t flags = 0;
   hipStream_t caller = nullptr;  // the caller's stream: batch work is ordered after its work
   hipStream_t stream = nullptr;  // the batch's own stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  Group groups[2];
+  Group groups[kGroups];
   DevScalars** d_sptr = nullptr;  // scalars of the used slots, gathered for poll
   DevScalars* d_sout = nullptr;
   std::vector<DevScalars*> h_sptr;
@@ -597,8 +600,14 @@ size_t batch_group_bytes(int32_t max_slots) {
 }
 
 size_t batch_bytes(int32_t max_slots) {
-  return 2 * batch_group_bytes(max_slots) + round256(sizeof(DevScalars*) * (size_t)max_slots) +
+  return ctu_batch::kGroups * batch_group_bytes(max_slots) +
+         round256(sizeof(DevScalars*) * (size_t)max_slots) +
          round256(sizeof(DevScalars) * (size_t)max_slots);
+}
+
+int group_of(const ctu_grid* g) {
+  const int c = ctu::gas_class(g->P);
+  return (g->cfg.prec == CTU_FP32 ? 3 : 0) + (c == 3 ? 1 : (c == 5 ? 2 : 0));
 }
 
 void drop_graph(ctu_batch* b) {
@@ -613,13 +622,13 @@ ctu_status rebuild(ctu_batch* b) {
   // earlier uploads read the host vectors until the stream reaches them
   HIP_TRY(hipStreamSynchronize(b->stream), "batch sync");
   drop_graph(b);
-  for (int p = 0; p < 2; ++p) {
+  for (int p = 0; p < ctu_batch::kGroups; ++p) {
     ctu_batch::Group& G = b->groups[p];
     G.descs.clear();
     std::vector<GridParams> Ps;
     for (const auto& sl : b->slots) {
       if (!sl.used || sl.state != CTU_TICKET_RUNNING) continue;
-      if ((sl.grid->cfg.prec == CTU_FP32 ? 1 : 0) != p) continue;
+      if (group_of(sl.grid) != p) continue;
       G.descs.push_back(sl.grid->desc);
       Ps.push_back(sl.grid->P);
     }
@@ -637,7 +646,7 @@ ctu_status rebuild(ctu_batch* b) {
 }
 
 ctu_status enqueue_batch_step(ctu_batch* b) {
-  for (int p = 0; p < 2; ++p) {
+  for (int p = 0; p < ctu_batch::kGroups; ++p) {
     if (b->groups[p].descs.empty()) continue;
     hipError_t e = ctu::launch_step(b->groups[p].view(), true, b->stream, nullptr);
     if (e != hipSuccess) return hip_fail(e, "batch step launch");
@@ -702,8 +711,10 @@ ctu_status ctu_batch_create(int32_t max_slots, void* d_work, size_t work_bytes, 
   b->flags = flags;
   b->caller = reinterpret_cast<hipStream_t>(hip_stream);
   char* w = reinterpret_cast<char*>(d_work);
-  for (int p = 0; p < 2; ++p) {
-    b->groups[p].prec = p;
+  static const int kClass[3] = {0, 3, 5};
+  for (int p = 0; p < ctu_batch::kGroups; ++p) {
+    b->groups[p].prec = p / 3;
+    b->groups[p].gclass = kClass[p % 3];
     b->groups[p].d_desc = reinterpret_cast<ctu::GridDesc*>(w);
     b->groups[p].d_start =
         reinterpret_cast<int*>(w + round256(sizeof(ctu::GridDesc) * (size_t)max_slots));
@@ -758,7 +769,9 @@ ctu_status ctu_batch_run(ctu_batch* b, int32_t steps) {
   if (b->dirty) {
     if (ctu_status st = rebuild(b)) return st;
   }
-  if (b->groups[0].descs.empty() && b->groups[1].descs.empty()) return CTU_OK;
+  bool any = false;
+  for (const auto& G : b->groups) any = any || !G.descs.empty();
+  if (!any) return CTU_OK;
   HIP_TRY(hipEventRecord(b->ev_in, b->caller), "batch record");
   HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_in, 0), "batch wait");
   if (b->flags & CTU_BATCH_GRAPH) {

@@ -1,0 +1,345 @@
+// ctu_sweeps.hpp -- the fused sweep kernels of the CTU step (gfx950): per direction, PPMC
+// reconstruction with characteristic tracing and the exact Riemann solve, for the first stage
+// and, re-traced with the transverse correction, for the second (Sec. 2.1, App. A.3, B.1).
+#pragma once
+
+#include "ctu_common.hpp"
+
+namespace ctu {
+
+// ---- fused sweeps --------------------------------------------------------------------------
+// Stage 1 (a2-a5) and stage 2 (a2-a4 re-traced, a6-a7) of one direction D each run as one
+// kernel.  Along y and z a thread owns one column and marches along D over a segment of
+// P.seg[D] faces, keeping a register window of primitives (cells c-1..c+2) and limited
+// slopes (c-1..c+1): every primitive, slope and trace is computed once per cell (plus a
+// short warm-up per segment) and each face's Riemann problem once.  Along x a wavefront covers 64
+// consecutive cells of one row and exchanges neighbours with lane shuffles; it yields XW
+// faces.
+
+template <typename T, int D>
+__device__ __forceinline__ void load_prim(const GLOBAL T* __restrict__ u, long long stride, long long id,
+                                          const GridParams& P, Prim<T>& c) {
+  T Ur[5];
+#pragma unroll
+  for (int sl = 0; sl < 5; ++sl) Ur[sl] = u[rot<D>(sl) * stride + id];
+  make_prim(Ur, T(P.gamma), T(P.gm1), T(P.p_floor), c);
+}
+
+template <typename T>
+__device__ __forceinline__ void safe_prim(Prim<T>& c) {
+  c.w[0] = T(1);
+  c.w[1] = c.w[2] = c.w[3] = T(0);
+  c.w[4] = T(1);
+  c.a = T(1);
+  c.ia = T(1);
+  c.irho = T(1);
+}
+
+template <typename T>
+__device__ __forceinline__ Prim<T> shfl_prim(const Prim<T>& p, int src) {
+  Prim<T> r;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) r.w[q] = __shfl(p.w[q], src, 64);
+  r.a = __shfl(p.a, src, 64);
+  r.ia = __shfl(p.ia, src, 64);
+  r.irho = __shfl(p.irho, src, 64);
+  return r;
+}
+
+// Transverse flux difference of a cell (eq. transverse_evolution), rotated to the sweep
+// frame: dT = h1 (F_t1(c - e_t1) - F_t1(c)) + h2 (F_t2(c - e_t2) - F_t2(c)).
+template <typename T, int D>
+__device__ __forceinline__ void transverse_delta(const GLOBAL T* __restrict__ fstar_all, long long fds,
+                                                 long long stride, long long c, long long st1,
+                                                 long long st2, T h1, T h2, T dT[5]) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const GLOBAL T* F1 = fstar_all + T1 * fds;
+  const GLOBAL T* F2 = fstar_all + T2 * fds;
+#pragma unroll
+  for (int sl = 0; sl < 5; ++sl) {
+    const long long o = rot<D>(sl) * stride + c;
+    dT[sl] = h1 * (F1[o - st1] - F1[o]) + h2 * (F2[o - st2] - F2[o]);
+  }
+}
+
+// Primitive -> conserved with E = p/(g-1) + rho V^2/2, multiplying by 1/(g-1).
+template <typename T>
+__device__ __forceinline__ void to_cons(const T W[5], T inv_gm1, T U[5]) {
+  const T rho = W[0];
+  U[0] = rho;
+  U[1] = rho * W[1];
+  U[2] = rho * W[2];
+  U[3] = rho * W[3];
+  U[4] = W[4] * inv_gm1 + T(0.5) * rho * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+}
+
+__device__ __forceinline__ void flush_counts(const RiemannCounts& cnt, DevScalars* s) {
+  if (cnt.floors) {
+    atomicAdd(&s->counters[0], (unsigned long long)cnt.floors);
+    atomicOr(&s->flags, 4u);
+  }
+  if (cnt.caps) {
+    atomicAdd(&s->counters[1], (unsigned long long)cnt.caps);
+    atomicOr(&s->flags, 8u);
+  }
+}
+
+// Newton-iteration histogram of the solves of one wavefront (instrumented sweeps only):
+// each solve's bin is counted over the active lanes with a ballot, so lanes that left the
+// kernel early are simply not counted.
+struct NewtonHist {
+  unsigned long long n[8];
+  __device__ void add(int iters) {
+    const int b = iters == 0 ? 7
+                  : iters <= 4 ? iters - 1 : (iters <= 8 ? 4 : (iters <= 16 ? 5 : 6));
+#pragma unroll
+    for (int k = 0; k < 8; ++k) n[k] += __popcll(__ballot(b == k));
+  }
+  // The first active lane adds the wave's counts to the grid's histogram.
+  __device__ void flush(DevScalars* s) const {
+    const unsigned long long act = __ballot(1);
+    if ((int)__lane_id() == __ffsll((long long)act) - 1) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (n[k]) atomicAdd(&s->newton_hist[k], n[k]);
+    }
+  }
+};
+
+// K is the gas class of the exact solver (see pfun_fast).
+// STAGE = 1: first-stage fluxes F*_D on faces c-1/2, c in [0, n_D], transverse range
+//            [-1, n] on both other axes; written at cell c-1.
+// STAGE = 2: CTU fluxes F^{n+1/2}_D on the same faces over the real transverse range, from
+//            the re-traced states plus the transverse flux differences of stage 1.
+// Block layout per grid: (plane block of kBlock columns, segment), plane blocks fastest.
+template <typename T, int D, int STAGE, bool HIST, int K>
+__global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
+  static_assert(D == 1 || D == 2, "marching sweeps run along y or z");
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  DevScalars* __restrict__ s = r.G->s;
+  const double dt = s->dt;
+  if (!(dt > 0.0)) return;
+  const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
+  const GLOBAL T* __restrict__ fstar_all = (const GLOBAL T*)r.G->flux;
+  const long long fds = 5 * P.stride;
+  GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + (STAGE == 1 ? D : 3 + D) * fds;
+  constexpr int B = (D == 1) ? 2 : 1;  // the transverse axis other than x
+  const int lo = STAGE == 1 ? -1 : 0;
+  const int ea = P.n[0] + (STAGE == 1 ? 2 : 0);
+  const int eb = P.n[B] + (STAGE == 1 ? 2 : 0);
+  const int nd = P.n[D];
+  const long long nbx = ((long long)ea * eb + kBlock - 1) / kBlock;
+  const int seg = P.seg[D];
+  const long long nseg = (nd + 1 + seg - 1) / seg;
+  if (r.lb >= nbx * nseg) return;
+  const long long tid = (r.lb % nbx) * kBlock + threadIdx.x;
+  if (tid >= (long long)ea * eb) return;
+  const int i = (int)(tid % ea) + lo;
+  const int o = (int)(tid / ea) + lo;
+  const int f0 = (int)(r.lb / nbx) * seg;
+  const int f1 = min(f0 + seg, nd + 1);
+  const long long stx = 1, sty = P.N[0], stz = (long long)P.N[0] * P.N[1];
+  const long long sd = D == 1 ? sty : stz;
+  const long long c0 = D == 1 ? cell_index(P, i, 0, o) : cell_index(P, i, o, 0);
+  const T dtodx = T(dt / P.dx[D]);
+  const T igm1 = T(P.inv_gm1);
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const long long st1 = T1 == 0 ? stx : (T1 == 1 ? sty : stz);
+  const long long st2 = T2 == 0 ? stx : (T2 == 1 ? sty : stz);
+  const T h1 = T(0.5 * dt / P.dx[T1]);
+  const T h2 = T(0.5 * dt / P.dx[T2]);
+
+  Prim<T> q0, q1, q2, q3;  // cells c-1, c, c+1, c+2 around the traced cell c
+  T s0[5], s1[5], s2[5];   // limited slopes of c-1, c, c+1
+  {
+    Prim<T> qm;
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 - 3) * sd, P, qm);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 - 2) * sd, P, q0);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 - 1) * sd, P, q1);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0)*sd, P, q2);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 + 1) * sd, P, q3);
+    slope_fast(qm, q0, q1, s0);
+    slope_fast(q0, q1, q2, s1);
+    slope_fast(q1, q2, q3, s2);
+  }
+  // warm-up: trace cell f0-1 (window: q0 = f0-2, q1 = f0-1, q2 = f0, q3 = f0+1)
+  T prevR[5];
+  {
+    T WL[5], WR[5];
+    trace_fast(q0, q1, q2, s0, s1, s2, dtodx, WL, WR);
+    to_cons(WR, igm1, prevR);
+    if (STAGE == 2) {
+      T dT[5];
+      transverse_delta<T, D>(fstar_all, fds, P.stride, c0 + (long long)(f0 - 1) * sd, st1, st2, h1,
+                             h2, dT);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) prevR[q] += dT[q];
+    }
+  }
+  // shift so that the window is centred on f0 at the top of the loop
+  q0 = q1;
+  q1 = q2;
+  q2 = q3;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    s0[q] = s1[q];
+    s1[q] = s2[q];
+  }
+  // the conserved values of cell c+2 are loaded one iteration ahead (software pipelining)
+  T raw[5];
+#pragma unroll
+  for (int sl = 0; sl < 5; ++sl) raw[sl] = u[rot<D>(sl) * P.stride + c0 + (long long)(f0 + 2) * sd];
+  RiemannCounts cnt{0u, 0u, 0};
+  NewtonHist hist{};
+  for (int c = f0; c < f1; ++c) {
+    // window: q0 = c-1, q1 = c, q2 = c+1, slopes s0 = c-1, s1 = c
+    make_prim(raw, T(P.gamma), T(P.gm1), T(P.p_floor), q3);  // cell c+2
+    if (c + 1 < f1) {
+      const long long nid = c0 + (long long)(c + 3) * sd;
+#pragma unroll
+      for (int sl = 0; sl < 5; ++sl) raw[sl] = u[rot<D>(sl) * P.stride + nid];
+    }
+    slope_fast(q1, q2, q3, s2);  // slope of c+1
+    T WL[5], WR[5], UL[5], UR[5], F[5];
+    trace_fast(q0, q1, q2, s0, s1, s2, dtodx, WL, WR);
+    to_cons(WL, igm1, UL);
+    to_cons(WR, igm1, UR);
+    if (STAGE == 2) {
+      T dT[5];
+      transverse_delta<T, D>(fstar_all, fds, P.stride, c0 + (long long)c * sd, st1, st2, h1, h2,
+                             dT);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        UL[q] += dT[q];
+        UR[q] += dT[q];
+      }
+    }
+    exact_flux_fast<T, K>(prevR, UL, P, F, cnt);
+    if (HIST) hist.add(cnt.iters);
+    const long long fo = c0 + (long long)(c - 1) * sd;
+#pragma unroll
+    for (int sl = 0; sl < 5; ++sl) out[rot<D>(sl) * P.stride + fo] = F[sl];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      prevR[q] = UR[q];
+      s0[q] = s1[q];
+      s1[q] = s2[q];
+    }
+    q0 = q1;
+    q1 = q2;
+    q2 = q3;
+  }
+  flush_counts(cnt, s);
+  if (HIST) hist.flush(s);
+}
+
+// x-direction sweep: one wavefront per (row, segment of XW faces).  Lane l holds cell
+// cw - 3 + l; slopes are valid on lanes 1..62, traces on 2..61, faces c-1/2 on 3..61.
+template <typename T, int STAGE, bool HIST, int K>
+__global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  DevScalars* __restrict__ s = r.G->s;
+  const double dt = s->dt;
+  if (!(dt > 0.0)) return;
+  const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
+  const GLOBAL T* __restrict__ fstar_all = (const GLOBAL T*)r.G->flux;
+  const long long fds = 5 * P.stride;
+  GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + (STAGE == 1 ? 0 : 3) * fds;
+  const int lane = threadIdx.x & 63;
+  const long long task = r.lb * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lo = STAGE == 1 ? -1 : 0;
+  const int ey = P.n[1] + (STAGE == 1 ? 2 : 0);
+  const int ez = P.n[2] + (STAGE == 1 ? 2 : 0);
+  const int nseg = (P.n[0] + 1 + XW - 1) / XW;
+  if (task >= (long long)nseg * ey * ez) return;  // whole wavefront exits together
+  const int sx = (int)(task % nseg);
+  const long long row = task / nseg;
+  const int j = (int)(row % ey) + lo;
+  const int k = (int)(row / ey) + lo;
+  const int cw = sx * XW;
+  const int c = cw - 3 + lane;  // this lane's cell along x
+  const long long id = cell_index(P, c, j, k);
+  const bool in_alloc = c >= -NG && c < P.n[0] + NG;
+  const T dtodx = T(dt / P.dx[0]);
+  const T igm1 = T(P.inv_gm1);
+
+  Prim<T> me;
+  if (in_alloc)
+    load_prim<T, 0>(u, P.stride, id, P, me);
+  else
+    safe_prim(me);
+  const int lm1 = lane > 0 ? lane - 1 : 0;
+  const int lp1 = lane < 63 ? lane + 1 : 63;
+  const Prim<T> left = shfl_prim(me, lm1);
+  const Prim<T> right = shfl_prim(me, lp1);
+  T sl[5];
+  slope_fast(left, me, right, sl);
+  T slm[5], slp[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    slm[q] = __shfl(sl[q], lm1, 64);
+    slp[q] = __shfl(sl[q], lp1, 64);
+  }
+  T WL[5], WR[5], UL[5], UR[5];
+  trace_fast(left, me, right, slm, sl, slp, dtodx, WL, WR);
+  to_cons(WL, igm1, UL);
+  to_cons(WR, igm1, UR);
+  const bool traced = lane >= 2 && lane <= 61 && c >= -1 && c <= P.n[0];
+  if (STAGE == 2 && traced) {
+    T dT[5];
+    transverse_delta<T, 0>(fstar_all, fds, P.stride, id, (long long)P.N[0],
+                           (long long)P.N[0] * P.N[1], T(0.5 * dt / P.dx[1]),
+                           T(0.5 * dt / P.dx[2]), dT);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      UL[q] += dT[q];
+      UR[q] += dT[q];
+    }
+  }
+  T prevR[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) prevR[q] = __shfl(UR[q], lm1, 64);
+  if (lane >= 3 && lane <= 61 && c >= 0 && c <= P.n[0]) {
+    RiemannCounts cnt{0u, 0u, 0};
+    T F[5];
+    exact_flux_fast<T, K>(prevR, UL, P, F, cnt);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[q * P.stride + id - 1] = F[q];
+    flush_counts(cnt, s);
+    if (HIST) {
+      NewtonHist hist{};
+      hist.add(cnt.iters);
+      hist.flush(s);
+    }
+  }
+}
+
+// The six sweeps of one stage for every grid of a plan (one launch per direction).
+template <typename T, int K, bool HIST>
+void enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
+  const int stride = v.ngrids + 1;
+  auto tab = [&](int pass) { return LaunchTab{v.d_grids, v.d_start + pass * stride, v.ngrids}; };
+  auto nblocks = [&](int pass) { return dim3((unsigned)v.h_start[pass * stride + v.ngrids]); };
+  const dim3 B(kBlock);
+  if (stage == 1) {
+    // a2-a5: F*, G*, H* on the extended transverse range
+    CTU_TIMED(K_SWEEP1_X, hipLaunchKernelGGL((k_sweep_x<T, 1, HIST, K>), nblocks(P_S1_X), B, 0,
+                                             stream, tab(P_S1_X)));
+    CTU_TIMED(K_SWEEP1_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 1, HIST, K>), nblocks(P_S1_Y),
+                                             B, 0, stream, tab(P_S1_Y)));
+    CTU_TIMED(K_SWEEP1_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 1, HIST, K>), nblocks(P_S1_Z),
+                                             B, 0, stream, tab(P_S1_Z)));
+  } else {
+    // a2-a4 re-traced, a6-a7: F^{n+1/2}, G^{n+1/2}, H^{n+1/2} on the real faces
+    CTU_TIMED(K_SWEEP2_X, hipLaunchKernelGGL((k_sweep_x<T, 2, HIST, K>), nblocks(P_S2_X), B, 0,
+                                             stream, tab(P_S2_X)));
+    CTU_TIMED(K_SWEEP2_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 2, HIST, K>), nblocks(P_S2_Y),
+                                             B, 0, stream, tab(P_S2_Y)));
+    CTU_TIMED(K_SWEEP2_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 2, HIST, K>), nblocks(P_S2_Z),
+                                             B, 0, stream, tab(P_S2_Z)));
+  }
+}
+
+}  // namespace ctu

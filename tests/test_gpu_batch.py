@@ -180,3 +180,19 @@ def test_submitted_grid_is_locked(ctu):
     assert b.poll(t)[0] == ctu.TICKET_DONE
     assert g.info().steps == 2
     assert b.poll(t)[0] == ctu.TICKET_UNKNOWN
+
+
+
+def test_batch_mixed_gas_classes(ctu):
+    """Grids of different gamma (each gas class is its own kernel group) and both precisions
+    in one batch, each equal to its solo run."""
+    jobs = [(WL.random_state(14, 11, 9, seed=61, gamma=1.3), 0, 4),
+            (WL.random_state(12, 10, 13, seed=62, gamma=5.0 / 3.0), 1, 5),
+            (WL.random_state(9, 16, 10, seed=63, gamma=1.4, bc=(1,) * 6), 0, 3),
+            (WL.random_state(10, 9, 12, seed=64, gamma=9.0 / 7.0), 1, 4),
+            (WL.random_state(11, 12, 8, seed=65, gamma=5.0 / 3.0), 0, 6)]
+    _announce("mixed gas classes")
+    solo = [_solo(ctu, wl, prec, n) for wl, prec, n in jobs]
+    res = _serve(ctu, ctu.Batch(max_slots=5, graph=True), jobs, run_steps=2)
+    for i, (wl, prec, n) in enumerate(jobs):
+        assert res[i][2] == n and np.array_equal(res[i][0], solo[i][0]), wl.name
