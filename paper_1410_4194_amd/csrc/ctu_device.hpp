@@ -142,6 +142,48 @@ struct RiemannCounts {
 // textbook formulas only by rounding.
 // ======================================================================================
 
+// Reciprocal, quotient and square root for positive normal operands from the hardware
+// estimates (v_rcp_f64, v_rsq_f64) refined by Newton-Raphson steps in fused multiply-adds:
+// within about an ulp of the correctly rounded result, in roughly half the instructions of
+// the IEEE expansions (which also handle zero, denormal and overflowing operands).
+__device__ __forceinline__ double rcp_nr(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return fma(r, fma(-b, r, 1.0), r);
+}
+__device__ __forceinline__ float rcp_nr(float b) {
+  const float r = __builtin_amdgcn_rcpf(b);
+  return fmaf(r, fmaf(-b, r, 1.0f), r);
+}
+template <typename T>
+__device__ __forceinline__ T div_nr(T a, T b) {
+  const T r = rcp_nr(b);
+  const T q = a * r;
+  return fma(r, fma(-b, q, a), q);
+}
+// s = sqrt(x) and rs = 1/sqrt(x) (coupled Newton iteration on g ~ sqrt(x), h ~ 1/(2 sqrt(x))).
+__device__ __forceinline__ void sqrt_rsqrt_nr(double x, double& s, double& rs) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  s = fma(fma(-g, g, x), h, g);
+  rs = 2.0 * h;
+}
+__device__ __forceinline__ void sqrt_rsqrt_nr(float x, float& s, float& rs) {
+  s = sqrtf(x);
+  rs = rcp_nr(s);
+}
+__device__ __forceinline__ double sqrt_nr(double x) {
+  double s, rs;
+  sqrt_rsqrt_nr(x, s, rs);
+  return s;
+}
+
 // Inverse integer root y = r^(-1/m) for r > 0 and integer m >= 2: a float estimate from
 // the hardware log2/exp2 units, then two Newton steps y <- y + y (1 - r y^m) / m in double,
 // which need no division and converge quadratically from ~1e-6 relative error to full
@@ -210,7 +252,7 @@ struct Prim {
 template <typename T>
 __device__ __forceinline__ void make_prim(const T Ur[5], T gamma, T gm1, T p_floor, Prim<T>& c) {
   const T rho = Ur[0];
-  const T ir = T(1) / rho;
+  const T ir = rcp_nr(rho);
   const T u = Ur[1] * ir, v = Ur[2] * ir, w = Ur[3] * ir;
   T p = gm1 * (Ur[4] - T(0.5) * rho * (u * u + v * v + w * w));
   if (!(p >= p_floor)) p = p_floor;
@@ -220,8 +262,7 @@ __device__ __forceinline__ void make_prim(const T Ur[5], T gamma, T gm1, T p_flo
   c.w[3] = w;
   c.w[4] = p;
   c.irho = ir;
-  c.a = tsqrt(gamma * p * ir);
-  c.ia = T(1) / c.a;
+  sqrt_rsqrt_nr(gamma * p * ir, c.a, c.ia);
 }
 
 // PLMC slope step of cell c (App. A.2) with the cell's own rho and a.
@@ -357,8 +398,8 @@ __device__ __forceinline__ void pfun_fast(double p, const SideK& k, const GridPa
     }
     f = P.two_over_gm1 * k.a * (z - 1.0);
   } else {
-    const double ipb = 1.0 / (p + k.B);
-    const double q = sqrt(k.A * ipb);
+    const double ipb = rcp_nr(p + k.B);
+    const double q = sqrt_nr(k.A * ipb);
     f = (p - k.p) * q;
     df = q * (1.0 - 0.5 * (p - k.p) * ipb);
     z = 0.0;
@@ -390,13 +431,13 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
     kl.irhoa = (double)L.irho * (double)L.ia;
     kr.irhoa = (double)R.irho * (double)R.ia;
   } else {
-    kl.a = sqrt(P.gamma * kl.p / kl.rho);
-    kr.a = sqrt(P.gamma * kr.p / kr.rho);
-    kl.irhoa = 1.0 / (kl.rho * kl.a);
-    kr.irhoa = 1.0 / (kr.rho * kr.a);
+    kl.a = sqrt_nr(P.gamma * kl.p * rcp_nr(kl.rho));
+    kr.a = sqrt_nr(P.gamma * kr.p * rcp_nr(kr.rho));
+    kl.irhoa = rcp_nr(kl.rho * kl.a);
+    kr.irhoa = rcp_nr(kr.rho * kr.a);
   }
-  kl.ip = 1.0 / kl.p;
-  kr.ip = 1.0 / kr.p;
+  kl.ip = rcp_nr(kl.p);
+  kr.ip = rcp_nr(kr.p);
   kl.A = P.two_over_gp1 * (double)L.irho;
   kr.A = P.two_over_gp1 * (double)R.irho;
   kl.B = P.gm1_over_gp1 * kl.p;
@@ -404,9 +445,9 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
 
   double pt = 0.5 * (kl.p + kr.p) + 0.125 * (kl.u - kr.u) * (kl.rho + kr.rho) * (kl.a + kr.a);
   pt = pt < 0.0 ? 0.0 : pt;
-  const double gl = sqrt(kl.A / (pt + kl.B));
-  const double gr = sqrt(kr.A / (pt + kr.B));
-  double p = (gl * kl.p + gr * kr.p - (kr.u - kl.u)) / (gl + gr);
+  const double gl = sqrt_nr(kl.A * rcp_nr(pt + kl.B));
+  const double gr = sqrt_nr(kr.A * rcp_nr(pt + kr.B));
+  double p = div_nr(gl * kl.p + gr * kr.p - (kr.u - kl.u), gl + gr);
   p = p < 1.0e-6 ? 1.0e-6 : p;
   const double du = kr.u - kl.u;
   double fl, dfl, fr, dfr, zl, zr;
@@ -415,7 +456,7 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
   for (int it = 0; it < P.newton_max_iter; ++it) {
     pfun_fast<K>(p, kl, P, fl, dfl, zl);
     pfun_fast<K>(p, kr, P, fr, dfr, zr);
-    double pn = p - (fl + fr + du) / (dfl + dfr);
+    double pn = p - div_nr(fl + fr + du, dfl + dfr);
     if (!(pn >= P.p_floor)) pn = P.p_floor;
     // relative change 2|pn - p|/|pn + p| < tol, without the division
     const bool done = 2.0 * fabs(pn - p) < P.newton_tol * fabs(pn + p);
@@ -452,7 +493,7 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
         pres = T(ps);
       } else {
         const T c = T(P.two_over_gp1) * (T(kl.a) + T(0.5) * gm1 * L.w[1]);
-        const T r = c / T(kl.a);
+        const T r = div_nr(c, T(kl.a));
         const T rr_ = (K > 0 || P.fan_int_exp) ? ipow_n<K>(r, P.fan_int_exp)
                                                  : tpow(r, T(P.two_over_gm1));
         rho = L.w[0] * rr_;
@@ -460,14 +501,14 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
         pres = L.w[4] * rr_ * r * r;
       }
     } else {
-      const double sl = kl.u - kl.a * sqrt(P.shock_a * ps * kl.ip + P.shock_b);
+      const double sl = kl.u - kl.a * sqrt_nr(P.shock_a * ps * kl.ip + P.shock_b);
       if (sl >= 0.0) {
         rho = L.w[0];
         u = L.w[1];
         pres = L.w[4];
       } else {
         const double q = ps * kl.ip;
-        rho = T(kl.rho * (q + P.gm1_over_gp1) / (q * P.gm1_over_gp1 + 1.0));
+        rho = T(kl.rho * div_nr(q + P.gm1_over_gp1, q * P.gm1_over_gp1 + 1.0));
         u = T(us);
         pres = T(ps);
       }
@@ -485,7 +526,7 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
         pres = T(ps);
       } else {
         const T c = T(P.two_over_gp1) * (T(kr.a) - T(0.5) * gm1 * R.w[1]);
-        const T r = c / T(kr.a);
+        const T r = div_nr(c, T(kr.a));
         const T rr_ = (K > 0 || P.fan_int_exp) ? ipow_n<K>(r, P.fan_int_exp)
                                                  : tpow(r, T(P.two_over_gm1));
         rho = R.w[0] * rr_;
@@ -493,14 +534,14 @@ __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], co
         pres = R.w[4] * rr_ * r * r;
       }
     } else {
-      const double sr = kr.u + kr.a * sqrt(P.shock_a * ps * kr.ip + P.shock_b);
+      const double sr = kr.u + kr.a * sqrt_nr(P.shock_a * ps * kr.ip + P.shock_b);
       if (sr <= 0.0) {
         rho = R.w[0];
         u = R.w[1];
         pres = R.w[4];
       } else {
         const double q = ps * kr.ip;
-        rho = T(kr.rho * (q + P.gm1_over_gp1) / (q * P.gm1_over_gp1 + 1.0));
+        rho = T(kr.rho * div_nr(q + P.gm1_over_gp1, q * P.gm1_over_gp1 + 1.0));
         u = T(us);
         pres = T(ps);
       }
