@@ -408,15 +408,49 @@ __device__ __forceinline__ void pfun_fast(double p, const SideK& k, const GridPa
 
 // Exact Riemann flux from rotated conserved states (App. B.1), fast form; K as in pfun_fast.
 template <typename T, int K>
+__device__ __forceinline__ void exact_flux_prim(const Prim<T>& L, const Prim<T>& R,
+                                                const GridParams& P, T F[5], RiemannCounts& cnt);
+
+template <typename T, int K>
 __device__ __forceinline__ void exact_flux_fast(const T UL[5], const T UR[5], const GridParams& P,
                                                 T F[5], RiemannCounts& cnt) {
-  const T gm1 = T(P.gm1);
   const T pf = T(P.p_floor);
   Prim<T> L, R;
-  make_prim(UL, T(P.gamma), gm1, pf, L);
-  make_prim(UR, T(P.gamma), gm1, pf, R);
+  make_prim(UL, T(P.gamma), T(P.gm1), pf, L);
+  make_prim(UR, T(P.gamma), T(P.gm1), pf, R);
   // floor hits: make_prim applied the floor when the pressure equals p_floor after the check
   cnt.floors += (L.w[4] == pf) + (R.w[4] == pf);
+  exact_flux_prim<T, K>(L, R, P, F, cnt);
+}
+
+// The same flux from primitive states (rho, u_n, u_t1, u_t2, p): the traced states of the
+// first stage enter the solver without the round trip through conserved variables, which
+// returns them unchanged up to rounding.  The pressure floor applies as in make_prim.
+template <typename T, int K>
+__device__ __forceinline__ void exact_flux_w(const T WL[5], const T WR[5], const GridParams& P,
+                                             T F[5], RiemannCounts& cnt) {
+  const T pf = T(P.p_floor);
+  const T g = T(P.gamma);
+  Prim<T> L, R;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    L.w[q] = WL[q];
+    R.w[q] = WR[q];
+  }
+  cnt.floors += (!(L.w[4] >= pf)) + (!(R.w[4] >= pf));
+  if (!(L.w[4] >= pf)) L.w[4] = pf;
+  if (!(R.w[4] >= pf)) R.w[4] = pf;
+  L.irho = rcp_nr(L.w[0]);
+  R.irho = rcp_nr(R.w[0]);
+  sqrt_rsqrt_nr(g * L.w[4] * L.irho, L.a, L.ia);
+  sqrt_rsqrt_nr(g * R.w[4] * R.irho, R.a, R.ia);
+  exact_flux_prim<T, K>(L, R, P, F, cnt);
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void exact_flux_prim(const Prim<T>& L, const Prim<T>& R,
+                                                const GridParams& P, T F[5], RiemannCounts& cnt) {
+  const T gm1 = T(P.gm1);
 
   SideK kl, kr;
   kl.rho = L.w[0];

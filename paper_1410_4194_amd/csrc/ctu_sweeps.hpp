@@ -164,11 +164,16 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
     slope_fast(q1, q2, q3, s2);
   }
   // warm-up: trace cell f0-1 (window: q0 = f0-2, q1 = f0-1, q2 = f0, q3 = f0+1)
-  T prevR[5];
+  T prevR[5];  // right-face state of the previous cell: primitive in stage 1, conserved in 2
   {
     T WL[5], WR[5];
     trace_fast(q0, q1, q2, s0, s1, s2, dtodx, WL, WR);
-    to_cons(WR, igm1, prevR);
+    if (STAGE == 1) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) prevR[q] = WR[q];
+    } else {
+      to_cons(WR, igm1, prevR);
+    }
     if (STAGE == 2) {
       T dT[5];
       transverse_delta<T, D>(fstar_all, fds, P.stride, c0 + (long long)(f0 - 1) * sd, st1, st2, h1,
@@ -203,9 +208,13 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
     slope_fast(q1, q2, q3, s2);  // slope of c+1
     T WL[5], WR[5], UL[5], UR[5], F[5];
     trace_fast(q0, q1, q2, s0, s1, s2, dtodx, WL, WR);
-    to_cons(WL, igm1, UL);
-    to_cons(WR, igm1, UR);
-    if (STAGE == 2) {
+    if (STAGE == 1) {
+      exact_flux_w<T, K>(prevR, WL, P, F, cnt);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) UR[q] = WR[q];
+    } else {
+      to_cons(WL, igm1, UL);
+      to_cons(WR, igm1, UR);
       T dT[5];
       transverse_delta<T, D>(fstar_all, fds, P.stride, c0 + (long long)c * sd, st1, st2, h1, h2,
                              dT);
@@ -214,8 +223,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
         UL[q] += dT[q];
         UR[q] += dT[q];
       }
+      exact_flux_fast<T, K>(prevR, UL, P, F, cnt);
     }
-    exact_flux_fast<T, K>(prevR, UL, P, F, cnt);
     if (HIST) hist.add(cnt.iters);
     const long long fo = c0 + (long long)(c - 1) * sd;
 #pragma unroll
@@ -282,10 +291,19 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
     slm[q] = __shfl(sl[q], lm1, 64);
     slp[q] = __shfl(sl[q], lp1, 64);
   }
+  // face states: traced primitives in stage 1, corrected conserved states in stage 2
   T WL[5], WR[5], UL[5], UR[5];
   trace_fast(left, me, right, slm, sl, slp, dtodx, WL, WR);
-  to_cons(WL, igm1, UL);
-  to_cons(WR, igm1, UR);
+  if (STAGE == 1) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      UL[q] = WL[q];
+      UR[q] = WR[q];
+    }
+  } else {
+    to_cons(WL, igm1, UL);
+    to_cons(WR, igm1, UR);
+  }
   const bool traced = lane >= 2 && lane <= 61 && c >= -1 && c <= P.n[0];
   if (STAGE == 2 && traced) {
     T dT[5];
@@ -304,7 +322,10 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   if (lane >= 3 && lane <= 61 && c >= 0 && c <= P.n[0]) {
     RiemannCounts cnt{0u, 0u, 0};
     T F[5];
-    exact_flux_fast<T, K>(prevR, UL, P, F, cnt);
+    if (STAGE == 1)
+      exact_flux_w<T, K>(prevR, UL, P, F, cnt);
+    else
+      exact_flux_fast<T, K>(prevR, UL, P, F, cnt);
 #pragma unroll
     for (int q = 0; q < 5; ++q) out[q * P.stride + id - 1] = F[q];
     flush_counts(cnt, s);
