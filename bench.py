@@ -18,7 +18,8 @@ Beside the primary line's value, the same JSON line carries
            to 1.5 cloud-crushing times, FP32 with the FP64 Newton solve) admitted by HBM
            footprint into a continuous batch: p50/p99 time-to-solution and aggregate rate.
 --precision-study runs the 512^3 turbulent cloud for 50 steps in FP64 and FP32 and reports
-their relative L1 distance; --serve-sweep sweeps the serving arrival rate.
+their relative L1 distance (also with the shock started at x = 0.14, where it reaches the
+cloud within the 50 steps); --serve-sweep sweeps the serving arrival rate.
 
 Prints one JSON line.  Per-kernel durations come from HIP events the library records on
 its own stream around every kernel of the timed steps.
@@ -182,13 +183,14 @@ def run_serve(ctu, WL, rate, count, hbm_budget, seed, steps_per_round=4, keep=Fa
     return out
 
 
-def precision_study(ctu, torch, WL, n=512, steps=50):
+def precision_study(ctu, torch, WL, n=512, steps=50, x_shock=0.1):
     """FP32 form vs FP64 on the turbulent cloud: both advanced with the FP64 grid's time step
     (read back every step), so the difference is the precision alone."""
-    wl = WL.turbulent_cloud(n)
+    wl = WL.turbulent_cloud(n, x_shock=x_shock)
     g64 = ctu.Grid.from_workload(wl, prec=ctu.FP64)
     g32 = ctu.Grid.from_workload(wl, prec=ctu.FP32)
-    out = {"workload": f"turbulent_cloud_{n}^3 Mach-10", "steps": steps, "l1_by_step": {}}
+    out = {"workload": f"turbulent_cloud_{n}^3 Mach-10 shock at x={x_shock}", "steps": steps,
+           "l1_by_step": {}}
     for k in range(1, steps + 1):
         dt = g64.compute_dt()
         g64.step(dt)
@@ -393,6 +395,10 @@ def main():
     if args.precision_study:
         log("[bench] precision study: 512^3 turbulent cloud, 50 steps, FP64 and FP32")
         out["precision_study"] = precision_study(ctu, torch, WL)
+        # the same with the shock started 0.01 from the cloud edge, so that it hits the cloud
+        # within the 50 steps and the flow turns three-dimensional
+        log("[bench] precision study, active variant: shock at x = 0.14")
+        out["precision_study_active"] = precision_study(ctu, torch, WL, x_shock=0.14)
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline: oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -77,3 +77,40 @@ def test_turbulent_cloud_512_fp32():
                (int(0.3 * n), n // 2, n // 2), (int(0.3 * n), n // 2 + int(0.15 * n), n // 2),
                (0, 0, 0), (n - 1, n - 1, n - 1)]
     _check(ctu, wl, ctu.FP32, 1e-5, special, seed=32)
+
+
+
+@pytest.mark.timeout(900)
+def test_turbulent_cloud_512_fp64_steps_25_and_50():
+    """The FP64 reference of the precision study: steps 25 and 50 of the 512^3 turbulent
+    cloud (shock started at x = 0.14 so that it reaches the cloud) against the oracle, each
+    from the GPU state saved before that step, on sampled boxes."""
+    from paper_1410_4194_amd import ctu
+    wl = WL.turbulent_cloud(512, x_shock=0.14)
+    cfg = oracle_config(wl)
+    g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    n = 512
+    rng = np.random.default_rng(33)
+    special = [(int(0.14 * n) + 8, n // 2, n // 2), (int(0.15 * n), n // 2, n // 2),
+               (int(0.16 * n), n // 2 + 20, n // 2 - 20), (0, 0, 0)]
+    for k in range(1, 51):
+        dt = g.compute_dt()
+        if k in (25, 50):
+            print(f"[gpu-test] turbulent cloud 512^3 FP64 step {k}", flush=True)
+            U = g.get_state()
+            u = O.alloc_state(cfg)
+            O.real(cfg, u)[...] = U
+            O.bc_fill(cfg, u)
+            g.step(dt)
+            gpu = g.get_state()
+            for lo, hi in _boxes(n, special, rng, count=3):
+                ref, _ = O.update_box(cfg, u, dt, lo, hi)
+                got = gpu[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+                e = rel_l1(got, ref, wl.gamma)
+                assert e.max() <= 1e-12, (k, lo, e)
+            del u, U
+        else:
+            g.step(dt)
+    status, flags, counters = g.check()
+    assert status == ctu.OK, (flags, counters)
+    g.close()
