@@ -49,50 +49,53 @@ TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_shock_cloud_256.json")
 #   Newton iteration 32, final f 12, u* 4, sampling 6, flux 16 -> 128
 #   transverse correction (eq. transverse_evolution) of one cell: 30
 #   update (eq. conserved_update) 45 + CFL bound of the new state 26 -> 71
-FLOPS_PER_UNIT = {"sweep1": 558 + 128, "sweep2": 558 + 30 + 128, "update": 71}
+FLOPS_FACE_STAGE1 = 558 + 128
+FLOPS_FACE_STAGE2 = 558 + 30 + 128
+FLOPS_CELL_UPDATE = 71
+
+# Algorithmic HBM values (elements of the state's type) per unit of work: what the kernel
+# must read and write once, with stencil and neighbour reuse counted once.
+#   sweep1_d (per face): read the 5 conserved fields of a cell, write 5 first-stage fluxes
+#   sweep2_y/z (per face): read 5 fields and one face of each transverse first-stage flux
+#             (10), write the 5 CTU fluxes
+#   sweep2_x_update (per cell): as sweep2 (20) plus one face of each y and z CTU flux (10)
+#             and the new state (5)
+#   bc_fill (per ghost cell): read and write 5 fields
+VALUES_PER_UNIT = {"sweep1": 10, "sweep2": 20, "sweep2_x_update": 35, "bc": 10}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic HBM bytes per unit of work of each kernel class (element size eb): the data the
-# kernel must read and write once, with stencil and neighbour reuse counted once.
-#   sweep1_d: read the 5 conserved fields of a cell, write the 5 first-stage fluxes of a face
-#   sweep2_d: read 5 conserved fields and one face of each transverse first-stage flux (10),
-#             write the 5 CTU fluxes of a face
-#   update:   read u (5) and one face of each CTU flux (15), write u (5)
-#   bc_fill:  read and write the 5 fields of a ghost cell
-BYTES_PER_UNIT = {"sweep1": 10, "sweep2": 20, "update": 25, "bc": 10, "dt": 1}
-
-
-def _algorithmic_bytes(cls, eb):
-    if cls == "dt_final":
-        return 8
-    return BYTES_PER_UNIT[cls.split("_")[0]] * eb
-
-
-def _units(cls, n):
+def _work(cls, n):
+    """(units, flops, HBM values) of one launch of a kernel class on an n grid."""
     nx, ny, nz = n
     d = {"x": 0, "y": 1, "z": 2}
     if cls.startswith("sweep1"):
         e = [nx + 2, ny + 2, nz + 2]
         e[d[cls[-1]]] = n[d[cls[-1]]] + 1
-        return e[0] * e[1] * e[2]
+        u = e[0] * e[1] * e[2]
+        return u, FLOPS_FACE_STAGE1 * u, VALUES_PER_UNIT["sweep1"] * u
+    if cls == "sweep2_x_update":
+        cells = nx * ny * nz
+        faces = (nx + 1) * ny * nz
+        return cells, FLOPS_FACE_STAGE2 * faces + FLOPS_CELL_UPDATE * cells, \
+            VALUES_PER_UNIT["sweep2_x_update"] * cells
     if cls.startswith("sweep2"):
         e = [nx, ny, nz]
         e[d[cls[-1]]] += 1
-        return e[0] * e[1] * e[2]
-    if cls == "update":
-        return nx * ny * nz
-    if cls == "dt_final":
-        return (nx * ny * nz + 255) // 256
+        u = e[0] * e[1] * e[2]
+        return u, FLOPS_FACE_STAGE2 * u, VALUES_PER_UNIT["sweep2"] * u
     if cls.startswith("bc_fill"):
-        a = d[cls[-1]]
         N = [nx + 6, ny + 6, nz + 6]
-        N[a] = 6
-        return N[0] * N[1] * N[2]
-    return 0
+        N[d[cls[-1]]] = 6
+        u = N[0] * N[1] * N[2]
+        return u, 0, VALUES_PER_UNIT["bc"] * u
+    if cls == "dt_final":
+        u = (ny * nz + 3) // 4
+        return u, u, u
+    return 0, 0, 0
 
 
 def run_gpu(wl, prec, steps, warmup, ctu, torch, keep_state=False, newton_hist=False):
@@ -236,23 +239,20 @@ def roofline(prof, n, eb, prec_name):
     # dominant kernel class by total time over the timed steps
     cls, (ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
     avg_s = ms / launches / 1e3
-    units = _units(cls, n)
-    kind = cls.split("_")[0]
+    units, flops, values = _work(cls, n)
     out = {"kernel": cls, "avg_launch_ms": round(ms / launches, 4), "launches": launches,
-           "units_per_launch": units, "traffic": _traffic(cls, prec_name)}
-    if kind in FLOPS_PER_UNIT and kind != "update":
+           "units_per_launch": units, "traffic": _traffic(cls, prec_name),
+           "algorithmic_bytes_per_launch": values * eb}
+    if flops > units:  # the sweeps: FP vector arithmetic bounds them
         peak = FP64_VECTOR_PEAK_TFLOPS if eb == 8 else FP32_VECTOR_PEAK_TFLOPS
-        achieved = FLOPS_PER_UNIT[kind] * units / avg_s / 1e12
+        achieved = flops / avg_s / 1e12
         out.update({"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                    "flops_per_unit": FLOPS_PER_UNIT[kind],
-                    "algorithmic_bytes_per_launch": _algorithmic_bytes(cls, eb) * units})
+                    "flops_per_launch": flops})
     else:
-        bpu = _algorithmic_bytes(cls, eb)
-        achieved = bpu * units / avg_s / 1e9
+        achieved = values * eb / avg_s / 1e9
         out.update({"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "bytes_per_unit": bpu})
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)})
     return out
 
 

@@ -103,84 +103,34 @@ __global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab) {
 
 
 // ---- a8-a9: conservative update and CFL reduction ------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_update(LaunchTab tab) {
-  const BlockRef r = block_ref(tab);
-  const GridParams P = r.G->P;
-  DevScalars* __restrict__ s = r.G->s;
-  const double dt = s->dt;
-  if (!(dt > 0.0)) return;  // a no-op step keeps the previous partials (state unchanged)
-  const long long total = (long long)P.n[0] * P.n[1] * P.n[2];
-  const long long nblocks = (total + kBlock - 1) / kBlock;
-  const long long lb = xcd_local(r.lb, r.nb);
-  if (lb >= nblocks) return;  // whole block idle
-  GLOBAL T* __restrict__ u = (GLOBAL T*)r.G->u;
-  const long long fds = 5 * P.stride;
-  const GLOBAL T* __restrict__ Fx = (const GLOBAL T*)r.G->flux + 3 * fds;
-  const GLOBAL T* __restrict__ Fy = Fx + fds;
-  const GLOBAL T* __restrict__ Fz = Fy + fds;
-  const long long tid = lb * kBlock + threadIdx.x;
-  double bound = INFINITY;
-  if (tid < total) {
-    const int i = (int)(tid % P.n[0]);
-    const int j = (int)((tid / P.n[0]) % P.n[1]);
-    const int k = (int)(tid / ((long long)P.n[0] * P.n[1]));
-    const long long c = cell_index(P, i, j, k);
-    const long long st[3] = {1, (long long)P.N[0], (long long)P.N[0] * P.N[1]};
-    const T dtdx = T(dt / P.dx[0]), dtdy = T(dt / P.dx[1]), dtdz = T(dt / P.dx[2]);
-    T U[5];
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      const long long o = f * P.stride + c;
-      T v = u[o];
-      v = v + dtdx * (Fx[o - st[0]] - Fx[o]);
-      v = v + dtdy * (Fy[o - st[1]] - Fy[o]);
-      v = v + dtdz * (Fz[o - st[2]] - Fz[o]);
-      U[f] = v;
-      u[o] = v;
-    }
-    bool finite = true;
-#pragma unroll
-    for (int f = 0; f < 5; ++f) finite = finite && isfinite((double)U[f]);
-    if (!finite || !(U[0] > T(0))) {
-      atomicOr(&s->flags, finite ? 2u : 1u);
-      atomicAdd(&s->counters[2], 1ull);
-    } else {
-      bound = cell_dt_bound(U, P);
-    }
-  }
-  block_min_store(bound, (GLOBAL double*)r.G->part, lb);
-}
-
+// CFL bound of the current state with the partial layout of the fused update: one wavefront
+// per x-row of real cells, kBlock/64 rows per block.
 template <typename T>
 __global__ __launch_bounds__(256) void k_dt(LaunchTab tab) {
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
-  const long long total = (long long)P.n[0] * P.n[1] * P.n[2];
-  const long long nblocks = (total + kBlock - 1) / kBlock;
-  const long long lb = xcd_local(r.lb, r.nb);
-  if (lb >= nblocks) return;
+  constexpr int kRows = kBlock / 64;
+  const long long nrows = (long long)P.n[1] * P.n[2];
+  if (r.lb * kRows >= nrows) return;  // whole block idle
   const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
-  const long long tid = lb * kBlock + threadIdx.x;
+  const long long row = r.lb * kRows + (threadIdx.x >> 6);
   double bound = INFINITY;
-  if (tid < total) {
-    const int i = (int)(tid % P.n[0]);
-    const int j = (int)((tid / P.n[0]) % P.n[1]);
-    const int k = (int)(tid / ((long long)P.n[0] * P.n[1]));
-    const long long c = cell_index(P, i, j, k);
-    T U[5];
+  if (row < nrows) {
+    const long long base = cell_index(P, 0, (int)(row % P.n[1]), (int)(row / P.n[1]));
+    for (int i = threadIdx.x & 63; i < P.n[0]; i += 64) {
+      T U[5];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) U[f] = u[f * P.stride + c];
-    bound = cell_dt_bound(U, P);
+      for (int f = 0; f < 5; ++f) U[f] = u[f * P.stride + base + i];
+      bound = fmin(bound, cell_dt_bound(U, P));
+    }
   }
-  block_min_store(bound, (GLOBAL double*)r.G->part, lb);
+  block_min_store(bound, (GLOBAL double*)r.G->part, r.lb);
 }
 
 // Minimum of each grid's block partials into its dt_next_bits: block g reduces grid g.
 __global__ __launch_bounds__(1024) void k_dt_final(const GridDesc* __restrict__ grids) {
   const GridDesc& G = grids[blockIdx.x];
-  const long long total = (long long)G.P.n[0] * G.P.n[1] * G.P.n[2];
-  const long long nblocks = (total + kBlock - 1) / kBlock;
+  const long long nblocks = update_blocks(G.P.n);
   const GLOBAL double* __restrict__ part = (const GLOBAL double*)G.part;
   double m = INFINITY;
   for (long long b = threadIdx.x; b < nblocks; b += blockDim.x) m = fmin(m, part[b]);
@@ -285,7 +235,7 @@ __global__ void k_prim_to_cons(const double* __restrict__ packed, T* __restrict_
 const char* kernel_class_name(int k) {
   static const char* names[K_NUM_CLASSES] = {
       "bc_fill_x", "bc_fill_y", "bc_fill_z", "sweep1_x", "sweep1_y", "sweep1_z",
-      "sweep2_x", "sweep2_y", "sweep2_z", "update", "dt_final"};
+      "sweep2_y", "sweep2_z", "sweep2_x_update", "dt_final"};
   return (k >= 0 && k < K_NUM_CLASSES) ? names[k] : "";
 }
 
@@ -359,11 +309,10 @@ long long pass_blocks(const GridParams& P, int pass) {
     case P_S1_X: return cdiv(nseg_x * (n1 + 2) * (n2 + 2), kBlock / 64);
     case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1 + 1, P.seg[1]);
     case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2 + 1, P.seg[2]);
-    case P_S2_X: return cdiv(nseg_x * n1 * n2, kBlock / 64);
     case P_S2_Y: return cdiv(n0 * n2, kBlock) * cdiv(n1 + 1, P.seg[1]);
     case P_S2_Z: return cdiv(n0 * n1, kBlock) * cdiv(n2 + 1, P.seg[2]);
-    case P_UPDATE:
-    case P_DT: return cdiv(n0 * n1 * n2, kBlock);
+    case P_S2_X:
+    case P_DT: return update_blocks(P.n);
   }
   return 0;
 }
@@ -393,13 +342,12 @@ static hipError_t enqueue_step(const PlanView& v, bool device_dt, hipStream_t st
             hipLaunchKernelGGL((k_bc_fill<T, 1>), nblocks(P_BC_Y), B, 0, stream, tab(P_BC_Y)));
   CTU_TIMED(K_BC_Z,
             hipLaunchKernelGGL((k_bc_fill<T, 2>), nblocks(P_BC_Z), B, 0, stream, tab(P_BC_Z)));
-  // stage 1 (a2-a5), then stage 2 (a2-a4 re-traced, a6-a7)
+  // stage 1 (a2-a5), then stage 2 (a2-a4 re-traced, a6-a7) with the update (a8) fused into
+  // its last sweep
   hipError_t e = sweeps<T>(v, 1, stream, prof);
   if (e == hipSuccess) e = sweeps<T>(v, 2, stream, prof);
   if (e != hipSuccess) return e;
-  // a8-a9
-  CTU_TIMED(K_UPDATE,
-            hipLaunchKernelGGL(k_update<T>, nblocks(P_UPDATE), B, 0, stream, tab(P_UPDATE)));
+  // a9: minimum of the CFL partials that the fused update wrote
   CTU_TIMED(K_DT_FINAL,
             hipLaunchKernelGGL(k_dt_final, dim3(v.ngrids), dim3(1024), 0, stream, v.d_grids));
   hipLaunchKernelGGL(k_end_step, gsmall, B, 0, stream, v.d_grids, v.ngrids);

@@ -16,13 +16,21 @@ namespace ctu {
 
 // Passes of one step, in launch order, plus the stand-alone CFL reduction.
 enum Pass {
-  P_BC_X, P_BC_Y, P_BC_Z, P_S1_X, P_S1_Y, P_S1_Z, P_S2_X, P_S2_Y, P_S2_Z, P_UPDATE, P_DT,
+  P_BC_X, P_BC_Y, P_BC_Z, P_S1_X, P_S1_Y, P_S1_Z, P_S2_Y, P_S2_Z, P_S2_X, P_DT,
   P_NUM
 };
 
 constexpr int kBlock = 256;  // threads per block of every pass
 constexpr int kSegDefault = 32;  // target faces per thread in the marching sweeps
-constexpr int XW = 59;       // x-faces per wavefront in the shuffle sweeps
+constexpr int XW = 59;       // x-faces per wavefront in the first-stage x sweep
+constexpr int XU = 58;       // x-cells per chunk of the second-stage x sweep with the update
+
+// The second-stage x sweep carries the update and the CFL bound: one wavefront per x-row of
+// real cells, kBlock/64 rows per block, one CFL partial per block.
+__host__ __device__ inline long long update_blocks(const int n[3]) {
+  const long long rows = (long long)n[1] * n[2];
+  return (rows + kBlock / 64 - 1) / (kBlock / 64);
+}
 
 // Everything a kernel needs about one grid, resident in device memory.
 struct GridDesc {
@@ -45,8 +53,8 @@ long long pass_blocks(const GridParams& P, int pass);
 
 // Per-kernel timing with HIP events recorded on the launch stream, accumulated per class.
 enum KernelClass {
-  K_BC_X, K_BC_Y, K_BC_Z, K_SWEEP1_X, K_SWEEP1_Y, K_SWEEP1_Z, K_SWEEP2_X, K_SWEEP2_Y,
-  K_SWEEP2_Z, K_UPDATE, K_DT_FINAL, K_NUM_CLASSES
+  K_BC_X, K_BC_Y, K_BC_Z, K_SWEEP1_X, K_SWEEP1_Y, K_SWEEP1_Z, K_SWEEP2_Y, K_SWEEP2_Z,
+  K_SWEEP2_X_UPDATE, K_DT_FINAL, K_NUM_CLASSES
 };
 const char* kernel_class_name(int k);
 

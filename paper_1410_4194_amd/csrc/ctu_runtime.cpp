@@ -51,10 +51,10 @@ static_assert(kStartOffset + sizeof(int) * ctu::P_NUM * 2 <= kHeaderBytes, "head
 
 size_t elem_bytes(int prec) { return prec == CTU_FP32 ? 4 : 8; }
 
-// One double per 256-cell update block, for the block-partial CFL reduction.
+// One double per block of the fused update, for the block-partial CFL reduction.
 size_t partial_bytes(const ctu_config& c) {
-  const long long cells = (long long)c.nx * c.ny * c.nz;
-  const long long blocks = (cells + 255) / 256 + 64;
+  const int n[3] = {c.nx, c.ny, c.nz};
+  const long long blocks = ctu::update_blocks(n) + 64;
   return (size_t)((blocks * 8 + 255) / 256 * 256);
 }
 

@@ -86,14 +86,15 @@ __device__ __forceinline__ void flush_counts(const RiemannCounts& cnt, DevScalar
 
 // Newton-iteration histogram of the solves of one wavefront (instrumented sweeps only):
 // each solve's bin is counted over the active lanes with a ballot, so lanes that left the
-// kernel early are simply not counted.
+// kernel early are simply not counted.  The wave counts sit in vector registers, so add and
+// flush must run with the same set of active lanes (or add with all lanes active).
 struct NewtonHist {
   unsigned long long n[8];
-  __device__ void add(int iters) {
+  __device__ void add(int iters, bool counted = true) {
     const int b = iters == 0 ? 7
                   : iters <= 4 ? iters - 1 : (iters <= 8 ? 4 : (iters <= 16 ? 5 : 6));
 #pragma unroll
-    for (int k = 0; k < 8; ++k) n[k] += __popcll(__ballot(b == k));
+    for (int k = 0; k < 8; ++k) n[k] += __popcll(__ballot(counted && b == k));
   }
   // The first active lane adds the wave's counts to the grid's histogram.
   __device__ void flush(DevScalars* s) const {
@@ -337,6 +338,150 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   }
 }
 
+// Second-stage x sweep fused with the conservative update (a8) and the CFL bound (a9).
+// One wavefront owns one x-row of real cells and marches along it in chunks of XU cells:
+// lane l holds cell cw - 3 + l, computes the face flux F(c-1/2) as in the first-stage
+// sweep (re-traced, plus the transverse correction from the y and z first-stage fluxes),
+// takes F(c+1/2) from lane l+1, and updates cells cw..cw+XU-1 (lanes 3..60) with the y and
+// z second-stage fluxes, which the two earlier second-stage sweeps stored.  The new state
+// is written in place, but only after the next chunk has read its stencil (the cells up to
+// three behind it), so every stencil still sees u^n; no other wavefront reads this row.
+template <typename T, bool HIST, int K>
+__global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  DevScalars* __restrict__ s = r.G->s;
+  const double dt = s->dt;
+  if (!(dt > 0.0)) return;  // a no-op step keeps the previous partials (state unchanged)
+  constexpr int kRows = kBlock / 64;
+  const long long nrows = (long long)P.n[1] * P.n[2];
+  if (r.lb * kRows >= nrows) return;  // whole block idle
+  GLOBAL T* __restrict__ u = (GLOBAL T*)r.G->u;
+  const GLOBAL T* __restrict__ fstar_all = (const GLOBAL T*)r.G->flux;
+  const long long fds = 5 * P.stride;
+  GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + 3 * fds;  // F^{n+1/2}_x
+  const GLOBAL T* __restrict__ Gy = (const GLOBAL T*)r.G->flux + 4 * fds;  // G^{n+1/2}
+  const GLOBAL T* __restrict__ Hz = Gy + fds;                              // H^{n+1/2}
+  const int lane = threadIdx.x & 63;
+  const long long row = r.lb * kRows + (threadIdx.x >> 6);
+  double bound = INFINITY;
+  if (row < nrows) {  // wave-uniform
+    const int j = (int)(row % P.n[1]);
+    const int k = (int)(row / P.n[1]);
+    const long long rowbase = cell_index(P, 0, j, k);
+    const long long sty = P.N[0], stz = (long long)P.N[0] * P.N[1];
+    const T dtodx = T(dt / P.dx[0]);
+    const T dtdx = T(dt / P.dx[0]), dtdy = T(dt / P.dx[1]), dtdz = T(dt / P.dx[2]);
+    const T igm1 = T(P.inv_gm1);
+    const T h1 = T(0.5 * dt / P.dx[1]), h2 = T(0.5 * dt / P.dx[2]);
+    const int lm1 = lane > 0 ? lane - 1 : 0;
+    const int lp1 = lane < 63 ? lane + 1 : 63;
+    RiemannCounts cnt{0u, 0u, 0};
+    NewtonHist hist{};
+    unsigned bad = 0;
+    T Udef[5] = {T(0), T(0), T(0), T(0), T(0)};
+    long long def_id = -1;  // cell whose new state waits for the next chunk's loads
+    for (int cw = 0; cw < P.n[0]; cw += XU) {
+      const int c = cw - 3 + lane;
+      const long long id = rowbase + c;
+      const bool in_alloc = c >= -NG && c < P.n[0] + NG;
+      T U0[5];
+      Prim<T> me;
+      if (in_alloc) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) U0[f] = u[f * P.stride + id];
+        make_prim(U0, T(P.gamma), T(P.gm1), T(P.p_floor), me);
+      } else {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) U0[f] = T(0);
+        safe_prim(me);
+      }
+      // this chunk's stencil has been read (make_prim consumed it): the previous chunk's
+      // new states can go out
+      if (def_id >= 0) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) u[f * P.stride + def_id] = Udef[f];
+      }
+      def_id = -1;
+      const Prim<T> left = shfl_prim(me, lm1);
+      const Prim<T> right = shfl_prim(me, lp1);
+      T sl[5];
+      slope_fast(left, me, right, sl);
+      T slm[5], slp[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        slm[q] = __shfl(sl[q], lm1, 64);
+        slp[q] = __shfl(sl[q], lp1, 64);
+      }
+      T WL[5], WR[5], UL[5], UR[5];
+      trace_fast(left, me, right, slm, sl, slp, dtodx, WL, WR);
+      to_cons(WL, igm1, UL);
+      to_cons(WR, igm1, UR);
+      if (lane >= 2 && lane <= 61 && c >= -1 && c <= P.n[0]) {
+        T dT[5];
+        transverse_delta<T, 0>(fstar_all, fds, P.stride, id, sty, stz, h1, h2, dT);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          UL[q] += dT[q];
+          UR[q] += dT[q];
+        }
+      }
+      T prevR[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) prevR[q] = __shfl(UR[q], lm1, 64);
+      T F[5] = {T(0), T(0), T(0), T(0), T(0)};  // flux at face c-1/2
+      int iters = -1;  // Newton iterations of this lane's counted solve
+      if (lane >= 3 && lane <= 61 && c <= P.n[0]) {
+        // lane 61's face is solved again as the next chunk's first face: count it there
+        const bool counted = lane <= 60 || c == P.n[0];
+        RiemannCounts dup{0u, 0u, 0};
+        exact_flux_fast<T, K>(prevR, UL, P, F, counted ? cnt : dup);
+        if (counted) iters = cnt.iters;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) out[q * P.stride + id - 1] = F[q];
+      }
+      // the histogram keeps its wave counts in vector registers: every lane takes the add
+      if (HIST) hist.add(iters, iters >= 0);
+      T Fr[5];  // flux at face c+1/2
+#pragma unroll
+      for (int q = 0; q < 5; ++q) Fr[q] = __shfl(F[q], lp1, 64);
+      if (lane >= 3 && lane <= 60 && c < P.n[0]) {
+        // u^{n+1} = u^n + dt/dx (F_{-1/2} - F_{+1/2}) + dt/dy (...) + dt/dz (...), in this order
+        T Un[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          const long long o = f * P.stride + id;
+          T v = U0[f];
+          v = v + dtdx * (F[f] - Fr[f]);
+          v = v + dtdy * (Gy[o - sty] - Gy[o]);
+          v = v + dtdz * (Hz[o - stz] - Hz[o]);
+          Un[f] = v;
+        }
+        bool finite = true;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) finite = finite && isfinite((double)Un[f]);
+        if (!finite || !(Un[0] > T(0))) {
+          atomicOr(&s->flags, finite ? 2u : 1u);
+          ++bad;
+        } else {
+          bound = fmin(bound, cell_dt_bound(Un, P));
+        }
+#pragma unroll
+        for (int f = 0; f < 5; ++f) Udef[f] = Un[f];
+        def_id = id;
+      }
+    }
+    if (def_id >= 0) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) u[f * P.stride + def_id] = Udef[f];
+    }
+    flush_counts(cnt, s);
+    if (bad) atomicAdd(&s->counters[2], (unsigned long long)bad);
+    if (HIST) hist.flush(s);
+  }
+  block_min_store(bound, (GLOBAL double*)r.G->part, r.lb);
+}
+
 // The six sweeps of one stage for every grid of a plan (one launch per direction).
 template <typename T, int K, bool HIST>
 void enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
@@ -353,13 +498,15 @@ void enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* 
     CTU_TIMED(K_SWEEP1_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 1, HIST, K>), nblocks(P_S1_Z),
                                              B, 0, stream, tab(P_S1_Z)));
   } else {
-    // a2-a4 re-traced, a6-a7: F^{n+1/2}, G^{n+1/2}, H^{n+1/2} on the real faces
-    CTU_TIMED(K_SWEEP2_X, hipLaunchKernelGGL((k_sweep_x<T, 2, HIST, K>), nblocks(P_S2_X), B, 0,
-                                             stream, tab(P_S2_X)));
+    // a2-a4 re-traced, a6-a7: G^{n+1/2}, H^{n+1/2} on the real faces, then F^{n+1/2} with the
+    // update (a8) and the CFL bound of the new state (a9)
     CTU_TIMED(K_SWEEP2_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 2, HIST, K>), nblocks(P_S2_Y),
                                              B, 0, stream, tab(P_S2_Y)));
     CTU_TIMED(K_SWEEP2_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 2, HIST, K>), nblocks(P_S2_Z),
                                              B, 0, stream, tab(P_S2_Z)));
+    CTU_TIMED(K_SWEEP2_X_UPDATE,
+              hipLaunchKernelGGL((k_sweep_x_update<T, HIST, K>), nblocks(P_S2_X), B, 0, stream,
+                                 tab(P_S2_X)));
   }
 }
 
