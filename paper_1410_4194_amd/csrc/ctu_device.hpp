@@ -40,6 +40,7 @@ struct GridParams {
   double inv_root_m;    // (gamma - 1) / (2 gamma)
   double inv_gm1;       // 1 / (gamma - 1)
   int seg[3];           // faces per thread segment of the marching sweeps along y and z
+  int xrows;            // x-rows of real cells per wavefront in the fused x update
 };
 
 // Device scalars of one grid (in the workspace).

@@ -109,19 +109,24 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_dt(LaunchTab tab) {
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
-  constexpr int kRows = kBlock / 64;
-  const long long nrows = (long long)P.n[1] * P.n[2];
-  if (r.lb * kRows >= nrows) return;  // whole block idle
+  constexpr int kWaves = kBlock / 64;
+  const long long ngy = (P.n[1] + P.xrows - 1) / P.xrows;
+  const long long ngroups = ngy * P.n[2];
+  if (r.lb * kWaves >= ngroups) return;  // whole block idle
   const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
-  const long long row = r.lb * kRows + (threadIdx.x >> 6);
+  const long long grp = r.lb * kWaves + (threadIdx.x >> 6);
   double bound = INFINITY;
-  if (row < nrows) {
-    const long long base = cell_index(P, 0, (int)(row % P.n[1]), (int)(row / P.n[1]));
-    for (int i = threadIdx.x & 63; i < P.n[0]; i += 64) {
-      T U[5];
+  if (grp < ngroups) {
+    const int j0 = (int)(grp % ngy) * P.xrows;
+    const int k = (int)(grp / ngy);
+    for (int j = j0; j < min(j0 + P.xrows, P.n[1]); ++j) {
+      const long long base = cell_index(P, 0, j, k);
+      for (int i = threadIdx.x & 63; i < P.n[0]; i += 64) {
+        T U[5];
 #pragma unroll
-      for (int f = 0; f < 5; ++f) U[f] = u[f * P.stride + base + i];
-      bound = fmin(bound, cell_dt_bound(U, P));
+        for (int f = 0; f < 5; ++f) U[f] = u[f * P.stride + base + i];
+        bound = fmin(bound, cell_dt_bound(U, P));
+      }
     }
   }
   block_min_store(bound, (GLOBAL double*)r.G->part, r.lb);
@@ -130,7 +135,7 @@ __global__ __launch_bounds__(256) void k_dt(LaunchTab tab) {
 // Minimum of each grid's block partials into its dt_next_bits: block g reduces grid g.
 __global__ __launch_bounds__(1024) void k_dt_final(const GridDesc* __restrict__ grids) {
   const GridDesc& G = grids[blockIdx.x];
-  const long long nblocks = update_blocks(G.P.n);
+  const long long nblocks = update_blocks(G.P);
   const GLOBAL double* __restrict__ part = (const GLOBAL double*)G.part;
   double m = INFINITY;
   for (long long b = threadIdx.x; b < nblocks; b += blockDim.x) m = fmin(m, part[b]);
@@ -301,18 +306,17 @@ static inline long long cdiv(long long a, long long b) { return (a + b - 1) / b;
 long long pass_blocks(const GridParams& P, int pass) {
   const long long n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const long long N0 = P.N[0], N1 = P.N[1], N2 = P.N[2];
-  const long long nseg_x = cdiv(n0 + 1, XW);
   switch (pass) {
     case P_BC_X: return cdiv(2LL * NG * N1 * N2, kBlock);
     case P_BC_Y: return cdiv(2LL * NG * N0 * N2, kBlock);
     case P_BC_Z: return cdiv(2LL * NG * N0 * N1, kBlock);
-    case P_S1_X: return cdiv(nseg_x * (n1 + 2) * (n2 + 2), kBlock / 64);
+    case P_S1_X: return cdiv(cdiv((n1 + 2) * N0, XW) * (n2 + 2), kBlock / 64);
     case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1 + 1, P.seg[1]);
     case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2 + 1, P.seg[2]);
     case P_S2_Y: return cdiv(n0 * n2, kBlock) * cdiv(n1 + 1, P.seg[1]);
     case P_S2_Z: return cdiv(n0 * n1, kBlock) * cdiv(n2 + 1, P.seg[2]);
     case P_S2_X:
-    case P_DT: return update_blocks(P.n);
+    case P_DT: return update_blocks(P);
   }
   return 0;
 }

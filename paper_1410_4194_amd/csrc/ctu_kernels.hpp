@@ -25,11 +25,35 @@ constexpr int kSegDefault = 32;  // target faces per thread in the marching swee
 constexpr int XW = 59;       // x-faces per wavefront in the first-stage x sweep
 constexpr int XU = 58;       // x-cells per chunk of the second-stage x sweep with the update
 
-// The second-stage x sweep carries the update and the CFL bound: one wavefront per x-row of
-// real cells, kBlock/64 rows per block, one CFL partial per block.
-__host__ __device__ inline long long update_blocks(const int n[3]) {
-  const long long rows = (long long)n[1] * n[2];
-  return (rows + kBlock / 64 - 1) / (kBlock / 64);
+// The second-stage x sweep carries the update and the CFL bound: one wavefront per group of
+// P.xrows x-rows of real cells, kBlock/64 groups per block, one CFL partial per block.
+__host__ __device__ inline long long update_blocks(const GridParams& P) {
+  const long long groups = (long long)((P.n[1] + P.xrows - 1) / P.xrows) * P.n[2];
+  return (groups + kBlock / 64 - 1) / (kBlock / 64);
+}
+
+// Rows per wavefront of the fused x update: the count of whole rows (1..8) that wastes the
+// fewest lanes over the chunks of XU positions that march over them.  Longer marches hide
+// latency worse (measured: two rows per wavefront at 256^3 are 14% slower than one, for 11%
+// fewer idle lanes), so more than one row is taken only when it cuts idle lanes by 20%.
+inline int choose_xrows(int nx, int ny) {
+  const int N0 = nx + 6;
+  auto eff = [&](int R) {
+    const long long last = (long long)(R - 1) * N0 + nx + 2;  // last real-cell position
+    const long long chunks = (last - 3) / XU + 1;
+    const long long groups = (ny + R - 1) / R;
+    // lanes used over lanes issued, rows of the last partial group included
+    return (double)ny * nx / ((double)groups * chunks * 64.0);
+  };
+  int best = 1;
+  double best_eff = eff(1);
+  for (int R = 2; R <= 8 && R <= ny; ++R) {
+    if (eff(R) > best_eff * 1.0001) {
+      best_eff = eff(R);
+      best = R;
+    }
+  }
+  return best_eff >= 1.2 * eff(1) ? best : 1;
 }
 
 // Everything a kernel needs about one grid, resident in device memory.

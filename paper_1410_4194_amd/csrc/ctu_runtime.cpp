@@ -51,10 +51,11 @@ static_assert(kStartOffset + sizeof(int) * ctu::P_NUM * 2 <= kHeaderBytes, "head
 
 size_t elem_bytes(int prec) { return prec == CTU_FP32 ? 4 : 8; }
 
+GridParams make_params(const ctu_config& c);
+
 // One double per block of the fused update, for the block-partial CFL reduction.
 size_t partial_bytes(const ctu_config& c) {
-  const int n[3] = {c.nx, c.ny, c.nz};
-  const long long blocks = ctu::update_blocks(n) + 64;
+  const long long blocks = ctu::update_blocks(make_params(c)) + 64;
   return (size_t)((blocks * 8 + 255) / 256 * 256);
 }
 
@@ -133,6 +134,7 @@ GridParams make_params(const ctu_config& c) {
     nseg = nseg < 1 ? 1 : (nseg > faces ? faces : nseg);
     P.seg[a] = (faces + nseg - 1) / nseg;
   }
+  P.xrows = ctu::choose_xrows(c.nx, c.ny);
   return P;
 }
 

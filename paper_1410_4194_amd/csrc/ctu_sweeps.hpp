@@ -244,39 +244,37 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   if (HIST) hist.flush(s);
 }
 
-// x-direction sweep: one wavefront per (row, segment of XW faces).  Lane l holds cell
-// cw - 3 + l; slopes are valid on lanes 1..62, traces on 2..61, faces c-1/2 on 3..61.
+// First-stage x sweep.  The x-rows of one z-plane (j over the extended range [-1, n_y], each
+// row with its three ghost cells per side) lie back to back in memory, so they are treated
+// as one flattened line of positions p = (j + 1) N_x + (c + 3).  A wavefront covers 64
+// consecutive positions: lane l holds position 59 w - 3 + l, slopes are valid on lanes
+// 1..62, traces on 2..61, and lanes 3..61 solve the face c-1/2 of their cell when
+// 0 <= c <= n_x.  Every stencil of such a face lies in its own row, so short rows share a
+// wavefront instead of leaving most of its lanes idle.
 template <typename T, int STAGE, bool HIST, int K>
 __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
+  static_assert(STAGE == 1, "the second-stage x sweep is fused with the update");
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
   DevScalars* __restrict__ s = r.G->s;
   const double dt = s->dt;
   if (!(dt > 0.0)) return;
   const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
-  const GLOBAL T* __restrict__ fstar_all = (const GLOBAL T*)r.G->flux;
-  const long long fds = 5 * P.stride;
-  GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + (STAGE == 1 ? 0 : 3) * fds;
+  GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux;
   const int lane = threadIdx.x & 63;
   const long long task = r.lb * (kBlock / 64) + (threadIdx.x >> 6);
-  const int lo = STAGE == 1 ? -1 : 0;
-  const int ey = P.n[1] + (STAGE == 1 ? 2 : 0);
-  const int ez = P.n[2] + (STAGE == 1 ? 2 : 0);
-  const int nseg = (P.n[0] + 1 + XW - 1) / XW;
-  if (task >= (long long)nseg * ey * ez) return;  // whole wavefront exits together
-  const int sx = (int)(task % nseg);
-  const long long row = task / nseg;
-  const int j = (int)(row % ey) + lo;
-  const int k = (int)(row / ey) + lo;
-  const int cw = sx * XW;
-  const int c = cw - 3 + lane;  // this lane's cell along x
-  const long long id = cell_index(P, c, j, k);
-  const bool in_alloc = c >= -NG && c < P.n[0] + NG;
+  const long long plen = (long long)(P.n[1] + 2) * P.N[0];  // positions of one plane
+  const long long nw = (plen + XW - 1) / XW;                   // wavefronts per plane
+  if (task >= nw * (P.n[2] + 2)) return;  // whole wavefront exits together
+  const int k = (int)(task / nw) - 1;
+  const long long p = (task % nw) * XW - 3 + lane;
+  const bool in_line = p >= 0 && p < plen;
+  const int c = in_line ? (int)(p % P.N[0]) - NG : -NG - 1;
+  const long long id = cell_index(P, -NG, -1, k) + p;
   const T dtodx = T(dt / P.dx[0]);
-  const T igm1 = T(P.inv_gm1);
 
   Prim<T> me;
-  if (in_alloc)
+  if (in_line)
     load_prim<T, 0>(u, P.stride, id, P, me);
   else
     safe_prim(me);
@@ -292,41 +290,16 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
     slm[q] = __shfl(sl[q], lm1, 64);
     slp[q] = __shfl(sl[q], lp1, 64);
   }
-  // face states: traced primitives in stage 1, corrected conserved states in stage 2
-  T WL[5], WR[5], UL[5], UR[5];
+  // traced primitive face states enter the solver directly
+  T WL[5], WR[5];
   trace_fast(left, me, right, slm, sl, slp, dtodx, WL, WR);
-  if (STAGE == 1) {
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      UL[q] = WL[q];
-      UR[q] = WR[q];
-    }
-  } else {
-    to_cons(WL, igm1, UL);
-    to_cons(WR, igm1, UR);
-  }
-  const bool traced = lane >= 2 && lane <= 61 && c >= -1 && c <= P.n[0];
-  if (STAGE == 2 && traced) {
-    T dT[5];
-    transverse_delta<T, 0>(fstar_all, fds, P.stride, id, (long long)P.N[0],
-                           (long long)P.N[0] * P.N[1], T(0.5 * dt / P.dx[1]),
-                           T(0.5 * dt / P.dx[2]), dT);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      UL[q] += dT[q];
-      UR[q] += dT[q];
-    }
-  }
   T prevR[5];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) prevR[q] = __shfl(UR[q], lm1, 64);
+  for (int q = 0; q < 5; ++q) prevR[q] = __shfl(WR[q], lm1, 64);
   if (lane >= 3 && lane <= 61 && c >= 0 && c <= P.n[0]) {
     RiemannCounts cnt{0u, 0u, 0};
     T F[5];
-    if (STAGE == 1)
-      exact_flux_w<T, K>(prevR, UL, P, F, cnt);
-    else
-      exact_flux_fast<T, K>(prevR, UL, P, F, cnt);
+    exact_flux_w<T, K>(prevR, WL, P, F, cnt);
 #pragma unroll
     for (int q = 0; q < 5; ++q) out[q * P.stride + id - 1] = F[q];
     flush_counts(cnt, s);
@@ -339,13 +312,16 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
 }
 
 // Second-stage x sweep fused with the conservative update (a8) and the CFL bound (a9).
-// One wavefront owns one x-row of real cells and marches along it in chunks of XU cells:
-// lane l holds cell cw - 3 + l, computes the face flux F(c-1/2) as in the first-stage
-// sweep (re-traced, plus the transverse correction from the y and z first-stage fluxes),
-// takes F(c+1/2) from lane l+1, and updates cells cw..cw+XU-1 (lanes 3..60) with the y and
-// z second-stage fluxes, which the two earlier second-stage sweeps stored.  The new state
-// is written in place, but only after the next chunk has read its stencil (the cells up to
-// three behind it), so every stencil still sees u^n; no other wavefront reads this row.
+// One wavefront owns P.xrows consecutive x-rows of real cells of one z-plane; with their
+// ghost cells they lie back to back in memory and are marched as one flattened line of
+// positions p = (row - first row) N_x + (c + 3), in chunks of XU positions: lane l holds
+// position cw - 3 + l, computes the face flux F(c-1/2) as the first-stage sweep does
+// (re-traced, plus the transverse correction from the y and z first-stage fluxes), takes
+// F(c+1/2) from lane l+1, and updates the real cells among positions cw..cw+XU-1 (lanes
+// 3..60) with the y and z second-stage fluxes, which the two earlier second-stage sweeps
+// stored.  The new state is written in place, but only after the next chunk has read its
+// stencil (the cells up to three behind it), so every stencil sees u^n; stencils of real
+// faces stay within their row and no other wavefront reads these rows.
 template <typename T, bool HIST, int K>
 __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
   const BlockRef r = block_ref(tab);
@@ -353,9 +329,10 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
   DevScalars* __restrict__ s = r.G->s;
   const double dt = s->dt;
   if (!(dt > 0.0)) return;  // a no-op step keeps the previous partials (state unchanged)
-  constexpr int kRows = kBlock / 64;
-  const long long nrows = (long long)P.n[1] * P.n[2];
-  if (r.lb * kRows >= nrows) return;  // whole block idle
+  constexpr int kWaves = kBlock / 64;
+  const long long ngy = (P.n[1] + P.xrows - 1) / P.xrows;  // row groups per plane
+  const long long ngroups = ngy * P.n[2];
+  if (r.lb * kWaves >= ngroups) return;  // whole block idle
   GLOBAL T* __restrict__ u = (GLOBAL T*)r.G->u;
   const GLOBAL T* __restrict__ fstar_all = (const GLOBAL T*)r.G->flux;
   const long long fds = 5 * P.stride;
@@ -363,12 +340,13 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
   const GLOBAL T* __restrict__ Gy = (const GLOBAL T*)r.G->flux + 4 * fds;  // G^{n+1/2}
   const GLOBAL T* __restrict__ Hz = Gy + fds;                              // H^{n+1/2}
   const int lane = threadIdx.x & 63;
-  const long long row = r.lb * kRows + (threadIdx.x >> 6);
+  const long long grp = r.lb * kWaves + (threadIdx.x >> 6);
   double bound = INFINITY;
-  if (row < nrows) {  // wave-uniform
-    const int j = (int)(row % P.n[1]);
-    const int k = (int)(row / P.n[1]);
-    const long long rowbase = cell_index(P, 0, j, k);
+  if (grp < ngroups) {  // wave-uniform
+    const int j0 = (int)(grp % ngy) * P.xrows;
+    const int k = (int)(grp / ngy);
+    const int plen = min(P.xrows, P.n[1] - j0) * P.N[0];  // at most 8 rows: fits 32 bits
+    const long long linebase = cell_index(P, -NG, j0, k);  // position 0
     const long long sty = P.N[0], stz = (long long)P.N[0] * P.N[1];
     const T dtodx = T(dt / P.dx[0]);
     const T dtdx = T(dt / P.dx[0]), dtdy = T(dt / P.dx[1]), dtdz = T(dt / P.dx[2]);
@@ -381,13 +359,14 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
     unsigned bad = 0;
     T Udef[5] = {T(0), T(0), T(0), T(0), T(0)};
     long long def_id = -1;  // cell whose new state waits for the next chunk's loads
-    for (int cw = 0; cw < P.n[0]; cw += XU) {
-      const int c = cw - 3 + lane;
-      const long long id = rowbase + c;
-      const bool in_alloc = c >= -NG && c < P.n[0] + NG;
+    for (int cw = NG; cw < plen - NG; cw += XU) {
+      const int p = cw - 3 + lane;
+      const bool in_line = p >= 0 && p < plen;
+      const int c = in_line ? p % P.N[0] - NG : -NG - 1;
+      const long long id = linebase + p;
       T U0[5];
       Prim<T> me;
-      if (in_alloc) {
+      if (in_line) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) U0[f] = u[f * P.stride + id];
         make_prim(U0, T(P.gamma), T(P.gm1), T(P.p_floor), me);
@@ -431,9 +410,9 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
       for (int q = 0; q < 5; ++q) prevR[q] = __shfl(UR[q], lm1, 64);
       T F[5] = {T(0), T(0), T(0), T(0), T(0)};  // flux at face c-1/2
       int iters = -1;  // Newton iterations of this lane's counted solve
-      if (lane >= 3 && lane <= 61 && c <= P.n[0]) {
+      if (lane >= 3 && lane <= 61 && c >= 0 && c <= P.n[0]) {
         // lane 61's face is solved again as the next chunk's first face: count it there
-        const bool counted = lane <= 60 || c == P.n[0];
+        const bool counted = lane <= 60 || cw + XU >= plen - NG;
         RiemannCounts dup{0u, 0u, 0};
         exact_flux_fast<T, K>(prevR, UL, P, F, counted ? cnt : dup);
         if (counted) iters = cnt.iters;
@@ -445,7 +424,7 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
       T Fr[5];  // flux at face c+1/2
 #pragma unroll
       for (int q = 0; q < 5; ++q) Fr[q] = __shfl(F[q], lp1, 64);
-      if (lane >= 3 && lane <= 60 && c < P.n[0]) {
+      if (lane >= 3 && lane <= 60 && c >= 0 && c < P.n[0]) {
         // u^{n+1} = u^n + dt/dx (F_{-1/2} - F_{+1/2}) + dt/dy (...) + dt/dz (...), in this order
         T Un[5];
 #pragma unroll
