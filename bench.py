@@ -236,23 +236,27 @@ def _traffic(cls, prec_name):
 
 
 def roofline(prof, n, eb, prec_name):
-    # dominant kernel class by total time over the timed steps
+    """Roofline of the dominant kernel class (by total time over the timed steps): achieved
+    algorithmic flops and algorithmic bytes per second against the FP vector peak and the HBM
+    peak; `bound` is the resource the kernel comes closer to."""
     cls, (ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
     avg_s = ms / launches / 1e3
     units, flops, values = _work(cls, n)
-    out = {"kernel": cls, "avg_launch_ms": round(ms / launches, 4), "launches": launches,
-           "units_per_launch": units, "traffic": _traffic(cls, prec_name),
-           "algorithmic_bytes_per_launch": values * eb}
-    if flops > units:  # the sweeps: FP vector arithmetic bounds them
-        peak = FP64_VECTOR_PEAK_TFLOPS if eb == 8 else FP32_VECTOR_PEAK_TFLOPS
-        achieved = flops / avg_s / 1e12
-        out.update({"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                    "flops_per_launch": flops})
-    else:
-        achieved = values * eb / avg_s / 1e9
-        out.update({"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)})
+    peak_alu = FP64_VECTOR_PEAK_TFLOPS if eb == 8 else FP32_VECTOR_PEAK_TFLOPS
+    alu = {"achieved": round(flops / avg_s / 1e12, 3), "peak": peak_alu, "unit": "TFLOP/s",
+           "frac": round(flops / avg_s / 1e12 / peak_alu, 4), "flops_per_launch": flops}
+    hbm = {"achieved": round(values * eb / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(values * eb / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+    traffic = _traffic(cls, prec_name)
+    if traffic:
+        hbm["measured_GBps"] = round(traffic / avg_s / 1e9, 1)
+    bound, other = ("alu", "hbm") if alu["frac"] >= hbm["frac"] else ("hbm", "alu")
+    main = alu if bound == "alu" else hbm
+    out = {"bound": bound, "achieved": main["achieved"], "peak": main["peak"],
+           "unit": main["unit"], "frac": main["frac"], "traffic": traffic,
+           "kernel": cls, "avg_launch_ms": round(ms / launches, 4), "launches": launches,
+           "units_per_launch": units, "algorithmic_bytes_per_launch": values * eb,
+           other: alu if other == "alu" else hbm}
     return out
 
 

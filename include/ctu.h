@@ -148,7 +148,10 @@ ctu_status ctu_check(ctu_grid* g, uint32_t* flags, uint64_t counters[4]);
  * face i+1/2 stored at cell i, x fastest): which = 0 first-stage fluxes F*, G*, H*;
  * which = 1 CTU fluxes F^{n+1/2}, G^{n+1/2}, H^{n+1/2}; dir 0/1/2 = x/y/z;
  * h_fields[5] arrays of alloc_cells doubles.  Only values on the ranges the step computes
- * are meaningful.  Syncs. */
+ * are meaningful.  The x CTU flux feeds the update in registers and is stored only while
+ * ctu_debug_keep_fluxes(g, 1) is in effect (which = 1, dir = 0 fails with CTU_EINVAL
+ * otherwise).  Both sync. */
+ctu_status ctu_debug_keep_fluxes(ctu_grid* g, int32_t keep);
 ctu_status ctu_debug_fluxes(ctu_grid* g, int32_t which, int32_t dir, double* const h_fields[5]);
 
 /* ---- Measurement -------------------------------------------------------------------------

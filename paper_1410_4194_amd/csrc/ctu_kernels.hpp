@@ -64,7 +64,10 @@ struct GridDesc {
   DevScalars* s;    // dt, time, CFL bound, error word
   double* part;     // CFL partials, one per update block
   int bc[6];
+  int flags;        // GRID_KEEP_X_FLUXES: also store F^{n+1/2}_x (debug read-back only)
 };
+
+enum { GRID_KEEP_X_FLUXES = 1 };
 
 struct LaunchTab {
   const GridDesc* grids;

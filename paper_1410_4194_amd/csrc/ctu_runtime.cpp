@@ -284,6 +284,7 @@ ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, s
   g->desc.s = g->scalars();
   g->desc.part = g->partials();
   for (int i = 0; i < 6; ++i) g->desc.bc[i] = cfg->bc[i];
+  g->desc.flags = 0;
   if (!build_starts({g->P}, g->h_start)) {
     delete g;
     return fail(CTU_EINVAL, "grid too large for one launch per pass");
@@ -524,9 +525,25 @@ ctu_status ctu_check(ctu_grid* g, uint32_t* flags, uint64_t counters[4]) {
   return CTU_OK;
 }
 
+ctu_status ctu_debug_keep_fluxes(ctu_grid* g, int32_t keep) {
+  if (!g) return fail(CTU_EINVAL, "null grid");
+  if (ctu_status st = not_in_batch(g)) return st;
+  const int flags = keep ? (g->desc.flags | ctu::GRID_KEEP_X_FLUXES)
+                         : (g->desc.flags & ~ctu::GRID_KEEP_X_FLUXES);
+  if (flags == g->desc.flags) return CTU_OK;
+  g->desc.flags = flags;
+  HIP_TRY(hipMemcpyAsync(g->d_desc(), &g->desc, sizeof(g->desc), hipMemcpyHostToDevice,
+                         g->stream),
+          "descriptor upload");
+  HIP_TRY(hipStreamSynchronize(g->stream), "descriptor sync");
+  return CTU_OK;
+}
+
 ctu_status ctu_debug_fluxes(ctu_grid* g, int32_t which, int32_t dir, double* const h_fields[5]) {
   if (!g || !h_fields || which < 0 || which > 1 || dir < 0 || dir > 2)
     return fail(CTU_EINVAL, "bad argument");
+  if (which == 1 && dir == 0 && !(g->desc.flags & ctu::GRID_KEEP_X_FLUXES))
+    return fail(CTU_EINVAL, "x CTU fluxes are stored only after ctu_debug_keep_fluxes(g, 1)");
   const size_t n = (size_t)alloc_cells(g->cfg);
   const size_t eb = elem_bytes(g->cfg.prec);
   const size_t base = (which == 0 ? 0 : 15) + 5 * dir;

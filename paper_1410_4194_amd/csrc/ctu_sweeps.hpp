@@ -337,6 +337,7 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
   const GLOBAL T* __restrict__ fstar_all = (const GLOBAL T*)r.G->flux;
   const long long fds = 5 * P.stride;
   GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + 3 * fds;  // F^{n+1/2}_x
+  const bool keep = (r.G->flags & GRID_KEEP_X_FLUXES) != 0;
   const GLOBAL T* __restrict__ Gy = (const GLOBAL T*)r.G->flux + 4 * fds;  // G^{n+1/2}
   const GLOBAL T* __restrict__ Hz = Gy + fds;                              // H^{n+1/2}
   const int lane = threadIdx.x & 63;
@@ -416,8 +417,10 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
         RiemannCounts dup{0u, 0u, 0};
         exact_flux_fast<T, K>(prevR, UL, P, F, counted ? cnt : dup);
         if (counted) iters = cnt.iters;
+        if (keep) {  // the update consumes F in registers; storing it serves debugging only
 #pragma unroll
-        for (int q = 0; q < 5; ++q) out[q * P.stride + id - 1] = F[q];
+          for (int q = 0; q < 5; ++q) out[q * P.stride + id - 1] = F[q];
+        }
       }
       // the histogram keeps its wave counts in vector registers: every lane takes the add
       if (HIST) hist.add(iters, iters >= 0);

@@ -35,7 +35,7 @@ EXPORTS = [
     "ctu_config_default", "ctu_workspace_bytes", "ctu_grid_create", "ctu_grid_destroy",
     "ctu_grid_info_get", "ctu_set_state", "ctu_set_primitive", "ctu_get_state",
     "ctu_compute_dt", "ctu_step", "ctu_advance", "ctu_totals", "ctu_check",
-    "ctu_debug_fluxes", "ctu_batch_workspace_bytes", "ctu_batch_create", "ctu_batch_submit",
+    "ctu_debug_fluxes", "ctu_debug_keep_fluxes", "ctu_batch_workspace_bytes", "ctu_batch_create", "ctu_batch_submit",
     "ctu_batch_run",
     "ctu_batch_poll", "ctu_batch_destroy", "ctu_last_error", "ctu_profile_enable",
     "ctu_profile_read", "ctu_profile_name", "ctu_newton_histogram",
@@ -84,6 +84,7 @@ def _load() -> C.CDLL:
         "ctu_totals": ([vp, C.POINTER(C.c_double)], st),
         "ctu_check": ([vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)], st),
         "ctu_debug_fluxes": ([vp, C.c_int32, C.c_int32, C.POINTER(vp)], st),
+        "ctu_debug_keep_fluxes": ([vp, C.c_int32], st),
         "ctu_batch_workspace_bytes": ([C.c_int32, C.POINTER(sz)], st),
         "ctu_batch_create": ([C.c_int32, vp, sz, vp, C.c_int32, C.POINTER(vp)], st),
         "ctu_batch_submit": ([vp, vp, C.c_int32, C.c_double, C.POINTER(C.c_uint64)], st),
@@ -213,6 +214,10 @@ class Grid:
         _check(lib.ctu_get_state(self.handle, self._host_ptrs(fields)),
                allow=(ENONPHYS,) if allow_nonphys else ())
         return out
+
+    def debug_keep_fluxes(self, keep: bool = True) -> None:
+        """Also store the x CTU fluxes of each step (for debug_fluxes(1, 0))."""
+        _check(lib.ctu_debug_keep_fluxes(self.handle, 1 if keep else 0))
 
     def debug_fluxes(self, which: int, direction: int) -> np.ndarray:
         """Fluxes of the last step over the allocated box (5, NZ, NY, NX), float64."""

@@ -124,6 +124,9 @@ def test_per_pass_fluxes_fp64(ctu, name, make):
     _, _, fstar, fhalf = O.update_box(cfg, u, dt, (0, 0, 0), (wl.nx, wl.ny, wl.nz), want_fluxes=True)
     _announce(name, "per-pass")
     g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    with pytest.raises(ctu.CtuError):  # not stored unless asked for
+        g.debug_fluxes(1, 0)
+    g.debug_keep_fluxes(True)
     g.step(dt)
     for d in range(3):
         e1, n1 = _flux_err(g.debug_fluxes(0, d), fstar[d])
@@ -131,6 +134,10 @@ def test_per_pass_fluxes_fp64(ctu, name, make):
         assert n1 > 0 and n2 > 0
         assert e1.max() <= TOL64, ("F*", d, e1)
         assert e2.max() <= TOL64, ("F^{n+1/2}", d, e2)
+    # keeping the fluxes changes nothing else
+    g2 = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    g2.step(dt)
+    assert np.array_equal(g2.get_state(), g.get_state())
 
 
 def test_compute_dt_matches_oracle(ctu):
