@@ -55,13 +55,14 @@ FLOPS_CELL_UPDATE = 71
 
 # Algorithmic HBM values (elements of the state's type) per unit of work: what the kernel
 # must read and write once, with stencil and neighbour reuse counted once.
-#   sweep1_d (per face): read the 5 conserved fields of a cell, write 5 first-stage fluxes
-#   sweep2_y/z (per face): read 5 fields and one face of each transverse first-stage flux
-#             (10), write the 5 CTU fluxes
-#   sweep2_x_update (per cell): as sweep2 (20) plus one face of each y and z CTU flux (10)
-#             and the new state (5)
+#   sweep1_d (per face): read the 5 conserved fields of a cell, write the 5 per-cell
+#             differences of the first-stage fluxes
+#   sweep2_y/z (per face): read 5 fields and the two transverse first-stage differences
+#             (10), write the 5 per-cell differences of the CTU fluxes
+#   sweep2_x_update (per cell): read 5 fields, the two transverse first-stage differences
+#             (10) and the y and z CTU differences (10), write the new state (5)
 #   bc_fill (per ghost cell): read and write 5 fields
-VALUES_PER_UNIT = {"sweep1": 10, "sweep2": 20, "sweep2_x_update": 35, "bc": 10}
+VALUES_PER_UNIT = {"sweep1": 10, "sweep2": 20, "sweep2_x_update": 30, "bc": 10}
 
 
 def log(*a):

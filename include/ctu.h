@@ -72,9 +72,9 @@ typedef struct {
   double newton_tol;       /* relative change that stops the Newton loop (1e-6) */
   int32_t newton_max_iter; /* Newton iteration cap (50) */
   double p_floor;          /* pressure floor on every primitive conversion (1e-20) */
-  int32_t march_seg[2];    /* tile shape: target faces per thread of the y and z sweeps, which
+  int32_t march_seg[2];    /* tile shape: target cells per thread of the y and z sweeps, which
                               march along their axis; 0 = the library default (32).  The
-                              n+1 faces of an axis are split into round((n+1)/target) equal
+                              n cells of an axis are split into round(n/target) equal
                               segments.  Changes the launch shape; results change only by
                               rounding (last-bit differences in a segment's first trace). */
 } ctu_config;
@@ -144,13 +144,14 @@ ctu_status ctu_totals(ctu_grid* g, double out[5]);
  * was hit, else CTU_OK.  Syncs. */
 ctu_status ctu_check(ctu_grid* g, uint32_t* flags, uint64_t counters[4]);
 
-/* Debug access to the fluxes of the last step (host double arrays over the allocated box,
- * face i+1/2 stored at cell i, x fastest): which = 0 first-stage fluxes F*, G*, H*;
- * which = 1 CTU fluxes F^{n+1/2}, G^{n+1/2}, H^{n+1/2}; dir 0/1/2 = x/y/z;
- * h_fields[5] arrays of alloc_cells doubles.  Only values on the ranges the step computes
- * are meaningful.  The x CTU flux feeds the update in registers and is stored only while
- * ctu_debug_keep_fluxes(g, 1) is in effect (which = 1, dir = 0 fails with CTU_EINVAL
- * otherwise).  Both sync. */
+/* Debug access to the fluxes of the last step as the step keeps them: per-cell differences
+ * dF(c) = F(c - 1/2) - F(c + 1/2) along the flux's own axis (host double arrays over the
+ * allocated box, x fastest), the only form that the transverse correction and the update
+ * consume.  which = 0: first-stage F*, G*, H*; which = 1: CTU F^{n+1/2}, G^{n+1/2},
+ * H^{n+1/2}; dir 0/1/2 = x/y/z; h_fields[5] arrays of alloc_cells doubles.  Only values on
+ * the cells the step covers are meaningful.  The x CTU difference feeds the update in
+ * registers and is stored only while ctu_debug_keep_fluxes(g, 1) is in effect (which = 1,
+ * dir = 0 fails with CTU_EINVAL otherwise).  Both sync. */
 ctu_status ctu_debug_keep_fluxes(ctu_grid* g, int32_t keep);
 ctu_status ctu_debug_fluxes(ctu_grid* g, int32_t which, int32_t dir, double* const h_fields[5]);
 

@@ -1,8 +1,9 @@
 """Tile-shape autotuner for the marching sweeps.
 
-The y and z sweeps give each thread one column and a segment of faces along the sweep axis;
-each segment pays a short warm-up (the window of primitives and slopes it starts with), so
-long segments waste less work while short segments expose more parallelism.  The best
+The y and z sweeps give each thread one column and a segment of cells along the sweep axis;
+each segment pays a short warm-up (the window of primitives and slopes it starts with, and
+the one face it shares with the next segment), so long segments waste less work while short
+segments expose more parallelism.  The best
 length depends on the axis length, the cross-section (how many columns there are to spread
 over the GPU) and the precision.  This module times candidate lengths on the GPU with the
 library's own per-kernel event timing and stores the winners in a table that

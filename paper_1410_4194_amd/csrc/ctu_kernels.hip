@@ -311,10 +311,10 @@ long long pass_blocks(const GridParams& P, int pass) {
     case P_BC_Y: return cdiv(2LL * NG * N0 * N2, kBlock);
     case P_BC_Z: return cdiv(2LL * NG * N0 * N1, kBlock);
     case P_S1_X: return cdiv(cdiv((n1 + 2) * N0, XW) * (n2 + 2), kBlock / 64);
-    case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1 + 1, P.seg[1]);
-    case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2 + 1, P.seg[2]);
-    case P_S2_Y: return cdiv(n0 * n2, kBlock) * cdiv(n1 + 1, P.seg[1]);
-    case P_S2_Z: return cdiv(n0 * n1, kBlock) * cdiv(n2 + 1, P.seg[2]);
+    case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1, P.seg[1]);
+    case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2, P.seg[2]);
+    case P_S2_Y: return cdiv(n0 * n2, kBlock) * cdiv(n1, P.seg[1]);
+    case P_S2_Z: return cdiv(n0 * n1, kBlock) * cdiv(n2, P.seg[2]);
     case P_S2_X:
     case P_DT: return update_blocks(P);
   }

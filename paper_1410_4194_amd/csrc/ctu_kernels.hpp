@@ -21,8 +21,8 @@ enum Pass {
 };
 
 constexpr int kBlock = 256;  // threads per block of every pass
-constexpr int kSegDefault = 32;  // target faces per thread in the marching sweeps
-constexpr int XW = 59;       // x-faces per wavefront in the first-stage x sweep
+constexpr int kSegDefault = 32;  // target cells per thread segment in the marching sweeps
+constexpr int XW = 58;       // x-cells per wavefront in the first-stage x sweep
 constexpr int XU = 58;       // x-cells per chunk of the second-stage x sweep with the update
 
 // The second-stage x sweep carries the update and the CFL bound: one wavefront per group of

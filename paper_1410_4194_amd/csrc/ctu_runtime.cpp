@@ -125,14 +125,14 @@ GridParams make_params(const ctu_config& c) {
   P.root_m = (std::fabs(m - mr) < 1e-12 && mr >= 2.0 && mr <= 16.0) ? (int)mr : 0;
   P.inv_root_m = (g - 1.0) / (2.0 * g);
   P.inv_gm1 = 1.0 / (g - 1.0);
-  // march segments: round((n+1)/target) equal segments of the n+1 faces of the axis
+  // march segments: round(n/target) equal segments of the n cells of the axis
   P.seg[0] = 0;
   for (int a = 1; a < 3; ++a) {
-    const int faces = P.n[a] + 1;
+    const int cells = P.n[a];
     const int target = c.march_seg[a - 1] > 0 ? c.march_seg[a - 1] : ctu::kSegDefault;
-    int nseg = (int)std::lround((double)faces / target);
-    nseg = nseg < 1 ? 1 : (nseg > faces ? faces : nseg);
-    P.seg[a] = (faces + nseg - 1) / nseg;
+    int nseg = (int)std::lround((double)cells / target);
+    nseg = nseg < 1 ? 1 : (nseg > cells ? cells : nseg);
+    P.seg[a] = (cells + nseg - 1) / nseg;
   }
   P.xrows = ctu::choose_xrows(c.nx, c.ny);
   return P;
@@ -543,7 +543,7 @@ ctu_status ctu_debug_fluxes(ctu_grid* g, int32_t which, int32_t dir, double* con
   if (!g || !h_fields || which < 0 || which > 1 || dir < 0 || dir > 2)
     return fail(CTU_EINVAL, "bad argument");
   if (which == 1 && dir == 0 && !(g->desc.flags & ctu::GRID_KEEP_X_FLUXES))
-    return fail(CTU_EINVAL, "x CTU fluxes are stored only after ctu_debug_keep_fluxes(g, 1)");
+    return fail(CTU_EINVAL, "x CTU differences are stored only after ctu_debug_keep_fluxes(g, 1)");
   const size_t n = (size_t)alloc_cells(g->cfg);
   const size_t eb = elem_bytes(g->cfg.prec);
   const size_t base = (which == 0 ? 0 : 15) + 5 * dir;

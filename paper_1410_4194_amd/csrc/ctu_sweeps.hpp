@@ -46,19 +46,20 @@ __device__ __forceinline__ Prim<T> shfl_prim(const Prim<T>& p, int src) {
   return r;
 }
 
-// Transverse flux difference of a cell (eq. transverse_evolution), rotated to the sweep
-// frame: dT = h1 (F_t1(c - e_t1) - F_t1(c)) + h2 (F_t2(c - e_t2) - F_t2(c)).
+// Transverse correction of a cell (eq. transverse_evolution), rotated to the sweep frame:
+// dT = h1 dF_t1(c) + h2 dF_t2(c), where dF(c) = F(c - 1/2) - F(c + 1/2) is the per-cell
+// difference of the first-stage fluxes that the first-stage sweeps store.
 template <typename T, int D>
-__device__ __forceinline__ void transverse_delta(const GLOBAL T* __restrict__ fstar_all, long long fds,
-                                                 long long stride, long long c, long long st1,
-                                                 long long st2, T h1, T h2, T dT[5]) {
+__device__ __forceinline__ void transverse_delta(const GLOBAL T* __restrict__ dstar_all,
+                                                 long long fds, long long stride, long long c,
+                                                 T h1, T h2, T dT[5]) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const GLOBAL T* F1 = fstar_all + T1 * fds;
-  const GLOBAL T* F2 = fstar_all + T2 * fds;
+  const GLOBAL T* D1 = dstar_all + T1 * fds;
+  const GLOBAL T* D2 = dstar_all + T2 * fds;
 #pragma unroll
   for (int sl = 0; sl < 5; ++sl) {
     const long long o = rot<D>(sl) * stride + c;
-    dT[sl] = h1 * (F1[o - st1] - F1[o]) + h2 * (F2[o - st2] - F2[o]);
+    dT[sl] = h1 * D1[o] + h2 * D2[o];
   }
 }
 
@@ -108,10 +109,14 @@ struct NewtonHist {
 };
 
 // K is the gas class of the exact solver (see pfun_fast).
-// STAGE = 1: first-stage fluxes F*_D on faces c-1/2, c in [0, n_D], transverse range
-//            [-1, n] on both other axes; written at cell c-1.
+// STAGE = 1: first-stage fluxes F*_D on the faces c-1/2, c in [0, n_D], transverse range
+//            [-1, n] on both other axes.
 // STAGE = 2: CTU fluxes F^{n+1/2}_D on the same faces over the real transverse range, from
-//            the re-traced states plus the transverse flux differences of stage 1.
+//            the re-traced states plus the transverse correction of stage 1.
+// Each stores the per-cell difference dF(c) = F(c - 1/2) - F(c + 1/2) of the real cells
+// c in [0, n_D): the consumers (transverse correction, update) need only that, and read it
+// once per cell instead of two faces.  A thread's segment covers the cells [f0, f1) and
+// solves the f1 - f0 + 1 faces around them.
 // Block layout per grid: (plane block of kBlock columns, segment), plane blocks fastest.
 template <typename T, int D, int STAGE, bool HIST, int K>
 __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   const double dt = s->dt;
   if (!(dt > 0.0)) return;
   const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
-  const GLOBAL T* __restrict__ fstar_all = (const GLOBAL T*)r.G->flux;
+  const GLOBAL T* __restrict__ dstar_all = (const GLOBAL T*)r.G->flux;
   const long long fds = 5 * P.stride;
   GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + (STAGE == 1 ? D : 3 + D) * fds;
   constexpr int B = (D == 1) ? 2 : 1;  // the transverse axis other than x
@@ -132,24 +137,23 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   const int nd = P.n[D];
   const long long nbx = ((long long)ea * eb + kBlock - 1) / kBlock;
   const int seg = P.seg[D];
-  const long long nseg = (nd + 1 + seg - 1) / seg;
+  const long long nseg = (nd + seg - 1) / seg;
   if (r.lb >= nbx * nseg) return;
   const long long tid = (r.lb % nbx) * kBlock + threadIdx.x;
   if (tid >= (long long)ea * eb) return;
   const int i = (int)(tid % ea) + lo;
   const int o = (int)(tid / ea) + lo;
   const int f0 = (int)(r.lb / nbx) * seg;
-  const int f1 = min(f0 + seg, nd + 1);
+  const int f1 = min(f0 + seg, nd);
   const long long stx = 1, sty = P.N[0], stz = (long long)P.N[0] * P.N[1];
   const long long sd = D == 1 ? sty : stz;
   const long long c0 = D == 1 ? cell_index(P, i, 0, o) : cell_index(P, i, o, 0);
   const T dtodx = T(dt / P.dx[D]);
   const T igm1 = T(P.inv_gm1);
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const long long st1 = T1 == 0 ? stx : (T1 == 1 ? sty : stz);
-  const long long st2 = T2 == 0 ? stx : (T2 == 1 ? sty : stz);
   const T h1 = T(0.5 * dt / P.dx[T1]);
   const T h2 = T(0.5 * dt / P.dx[T2]);
+  (void)stx;
 
   Prim<T> q0, q1, q2, q3;  // cells c-1, c, c+1, c+2 around the traced cell c
   T s0[5], s1[5], s2[5];   // limited slopes of c-1, c, c+1
@@ -177,8 +181,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
     }
     if (STAGE == 2) {
       T dT[5];
-      transverse_delta<T, D>(fstar_all, fds, P.stride, c0 + (long long)(f0 - 1) * sd, st1, st2, h1,
-                             h2, dT);
+      transverse_delta<T, D>(dstar_all, fds, P.stride, c0 + (long long)(f0 - 1) * sd, h1, h2,
+                             dT);
 #pragma unroll
       for (int q = 0; q < 5; ++q) prevR[q] += dT[q];
     }
@@ -198,10 +202,13 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   for (int sl = 0; sl < 5; ++sl) raw[sl] = u[rot<D>(sl) * P.stride + c0 + (long long)(f0 + 2) * sd];
   RiemannCounts cnt{0u, 0u, 0};
   NewtonHist hist{};
-  for (int c = f0; c < f1; ++c) {
-    // window: q0 = c-1, q1 = c, q2 = c+1, slopes s0 = c-1, s1 = c
+  // flux at face c-3/2, kept in LDS (each thread its own slot): registers would cost the
+  // first-stage sweeps a wave per SIMD
+  __shared__ T prevF[5][kBlock];
+  for (int c = f0; c <= f1; ++c) {
+    // window: q0 = c-1, q1 = c, q2 = c+1, slopes s0 = c-1, s1 = c; face c-1/2
     make_prim(raw, T(P.gamma), T(P.gm1), T(P.p_floor), q3);  // cell c+2
-    if (c + 1 < f1) {
+    if (c + 1 <= f1) {
       const long long nid = c0 + (long long)(c + 3) * sd;
 #pragma unroll
       for (int sl = 0; sl < 5; ++sl) raw[sl] = u[rot<D>(sl) * P.stride + nid];
@@ -209,29 +216,38 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
     slope_fast(q1, q2, q3, s2);  // slope of c+1
     T WL[5], WR[5], UL[5], UR[5], F[5];
     trace_fast(q0, q1, q2, s0, s1, s2, dtodx, WL, WR);
+    // the segment's last face is solved again as the next segment's first: count it there
+    const bool dupface = c == f1 && f1 < nd;
+    RiemannCounts dup{0u, 0u, 0};
     if (STAGE == 1) {
-      exact_flux_w<T, K>(prevR, WL, P, F, cnt);
+      exact_flux_w<T, K>(prevR, WL, P, F, dupface ? dup : cnt);
 #pragma unroll
       for (int q = 0; q < 5; ++q) UR[q] = WR[q];
     } else {
       to_cons(WL, igm1, UL);
       to_cons(WR, igm1, UR);
       T dT[5];
-      transverse_delta<T, D>(fstar_all, fds, P.stride, c0 + (long long)c * sd, st1, st2, h1, h2,
-                             dT);
+      transverse_delta<T, D>(dstar_all, fds, P.stride, c0 + (long long)c * sd, h1, h2, dT);
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
         UL[q] += dT[q];
         UR[q] += dT[q];
       }
-      exact_flux_fast<T, K>(prevR, UL, P, F, cnt);
+      exact_flux_fast<T, K>(prevR, UL, P, F, dupface ? dup : cnt);
     }
-    if (HIST) hist.add(cnt.iters);
-    const long long fo = c0 + (long long)(c - 1) * sd;
+    if (HIST) hist.add(dupface ? dup.iters : cnt.iters, !dupface);
+    // keep the LDS read of the previous flux below the solve (hoisted above it, the five
+    // values would stay live through the solve and cost the first stage a wave per SIMD)
+    asm volatile("" ::: "memory");
+    if (c > f0) {  // cell c-1 now has both faces
+      const long long co = c0 + (long long)(c - 1) * sd;
 #pragma unroll
-    for (int sl = 0; sl < 5; ++sl) out[rot<D>(sl) * P.stride + fo] = F[sl];
+      for (int sl = 0; sl < 5; ++sl)
+        out[rot<D>(sl) * P.stride + co] = prevF[sl][threadIdx.x] - F[sl];
+    }
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
+      prevF[q][threadIdx.x] = F[q];
       prevR[q] = UR[q];
       s0[q] = s1[q];
       s1[q] = s2[q];
@@ -247,10 +263,11 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
 // First-stage x sweep.  The x-rows of one z-plane (j over the extended range [-1, n_y], each
 // row with its three ghost cells per side) lie back to back in memory, so they are treated
 // as one flattened line of positions p = (j + 1) N_x + (c + 3).  A wavefront covers 64
-// consecutive positions: lane l holds position 59 w - 3 + l, slopes are valid on lanes
-// 1..62, traces on 2..61, and lanes 3..61 solve the face c-1/2 of their cell when
-// 0 <= c <= n_x.  Every stencil of such a face lies in its own row, so short rows share a
-// wavefront instead of leaving most of its lanes idle.
+// consecutive positions: lane l holds position XW w - 3 + l, slopes are valid on lanes
+// 1..62, traces on 2..61, lanes 3..61 solve the face c-1/2 of their cell when
+// 0 <= c <= n_x, and lanes 3..60 store the difference dF(c) = F(c-1/2) - F(c+1/2) of their
+// real cell (F(c+1/2) from the next lane).  Every stencil of such a face lies in its own
+// row, so short rows share a wavefront instead of leaving most of its lanes idle.
 template <typename T, int STAGE, bool HIST, int K>
 __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   static_assert(STAGE == 1, "the second-stage x sweep is fused with the update");
@@ -296,18 +313,29 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   T prevR[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) prevR[q] = __shfl(WR[q], lm1, 64);
+  T F[5] = {T(0), T(0), T(0), T(0), T(0)};  // flux at face c-1/2
+  int iters = -1;  // Newton iterations of this lane's counted solve
   if (lane >= 3 && lane <= 61 && c >= 0 && c <= P.n[0]) {
+    // lane 61's face is solved again as the next wavefront's first face: count it there
+    const bool counted = lane <= 60 || task % nw == nw - 1;
     RiemannCounts cnt{0u, 0u, 0};
-    T F[5];
     exact_flux_w<T, K>(prevR, WL, P, F, cnt);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) out[q * P.stride + id - 1] = F[q];
-    flush_counts(cnt, s);
-    if (HIST) {
-      NewtonHist hist{};
-      hist.add(cnt.iters);
-      hist.flush(s);
+    if (counted) {
+      flush_counts(cnt, s);
+      iters = cnt.iters;
     }
+  }
+  T Fr[5];  // flux at face c+1/2
+#pragma unroll
+  for (int q = 0; q < 5; ++q) Fr[q] = __shfl(F[q], lp1, 64);
+  if (lane >= 3 && lane <= 60 && c >= 0 && c < P.n[0]) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[q * P.stride + id] = F[q] - Fr[q];
+  }
+  if (HIST) {  // wave counts sit in vector registers: every lane takes the add and the flush
+    NewtonHist hist{};
+    hist.add(iters, iters >= 0);
+    hist.flush(s);
   }
 }
 
@@ -316,10 +344,10 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
 // ghost cells they lie back to back in memory and are marched as one flattened line of
 // positions p = (row - first row) N_x + (c + 3), in chunks of XU positions: lane l holds
 // position cw - 3 + l, computes the face flux F(c-1/2) as the first-stage sweep does
-// (re-traced, plus the transverse correction from the y and z first-stage fluxes), takes
-// F(c+1/2) from lane l+1, and updates the real cells among positions cw..cw+XU-1 (lanes
-// 3..60) with the y and z second-stage fluxes, which the two earlier second-stage sweeps
-// stored.  The new state is written in place, but only after the next chunk has read its
+// (re-traced, plus the transverse correction from the y and z first-stage flux
+// differences), takes F(c+1/2) from lane l+1, and updates the real cells among positions
+// cw..cw+XU-1 (lanes 3..60) with the y and z second-stage flux differences, which the two
+// earlier second-stage sweeps stored.  The new state is written in place, but only after the next chunk has read its
 // stencil (the cells up to three behind it), so every stencil sees u^n; stencils of real
 // faces stay within their row and no other wavefront reads these rows.
 template <typename T, bool HIST, int K>
@@ -334,12 +362,12 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
   const long long ngroups = ngy * P.n[2];
   if (r.lb * kWaves >= ngroups) return;  // whole block idle
   GLOBAL T* __restrict__ u = (GLOBAL T*)r.G->u;
-  const GLOBAL T* __restrict__ fstar_all = (const GLOBAL T*)r.G->flux;
+  const GLOBAL T* __restrict__ dstar_all = (const GLOBAL T*)r.G->flux;
   const long long fds = 5 * P.stride;
-  GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + 3 * fds;  // F^{n+1/2}_x
+  GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + 3 * fds;  // dF^{n+1/2}_x (debug only)
   const bool keep = (r.G->flags & GRID_KEEP_X_FLUXES) != 0;
-  const GLOBAL T* __restrict__ Gy = (const GLOBAL T*)r.G->flux + 4 * fds;  // G^{n+1/2}
-  const GLOBAL T* __restrict__ Hz = Gy + fds;                              // H^{n+1/2}
+  const GLOBAL T* __restrict__ dG = (const GLOBAL T*)r.G->flux + 4 * fds;  // dG^{n+1/2}
+  const GLOBAL T* __restrict__ dH = dG + fds;                              // dH^{n+1/2}
   const int lane = threadIdx.x & 63;
   const long long grp = r.lb * kWaves + (threadIdx.x >> 6);
   double bound = INFINITY;
@@ -348,7 +376,6 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
     const int k = (int)(grp / ngy);
     const int plen = min(P.xrows, P.n[1] - j0) * P.N[0];  // at most 8 rows: fits 32 bits
     const long long linebase = cell_index(P, -NG, j0, k);  // position 0
-    const long long sty = P.N[0], stz = (long long)P.N[0] * P.N[1];
     const T dtodx = T(dt / P.dx[0]);
     const T dtdx = T(dt / P.dx[0]), dtdy = T(dt / P.dx[1]), dtdz = T(dt / P.dx[2]);
     const T igm1 = T(P.inv_gm1);
@@ -399,7 +426,7 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
       to_cons(WR, igm1, UR);
       if (lane >= 2 && lane <= 61 && c >= -1 && c <= P.n[0]) {
         T dT[5];
-        transverse_delta<T, 0>(fstar_all, fds, P.stride, id, sty, stz, h1, h2, dT);
+        transverse_delta<T, 0>(dstar_all, fds, P.stride, id, h1, h2, dT);
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
           UL[q] += dT[q];
@@ -417,10 +444,6 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
         RiemannCounts dup{0u, 0u, 0};
         exact_flux_fast<T, K>(prevR, UL, P, F, counted ? cnt : dup);
         if (counted) iters = cnt.iters;
-        if (keep) {  // the update consumes F in registers; storing it serves debugging only
-#pragma unroll
-          for (int q = 0; q < 5; ++q) out[q * P.stride + id - 1] = F[q];
-        }
       }
       // the histogram keeps its wave counts in vector registers: every lane takes the add
       if (HIST) hist.add(iters, iters >= 0);
@@ -433,10 +456,12 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
           const long long o = f * P.stride + id;
+          const T dFx = F[f] - Fr[f];
+          if (keep) out[o] = dFx;  // the update consumes it in registers: debugging only
           T v = U0[f];
-          v = v + dtdx * (F[f] - Fr[f]);
-          v = v + dtdy * (Gy[o - sty] - Gy[o]);
-          v = v + dtdz * (Hz[o - stz] - Hz[o]);
+          v = v + dtdx * dFx;
+          v = v + dtdy * dG[o];
+          v = v + dtdz * dH[o];
           Un[f] = v;
         }
         bool finite = true;
