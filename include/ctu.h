@@ -48,7 +48,13 @@ typedef enum {
   CTU_EAGAIN = -6     /* batch has no free slot */
 } ctu_status;
 
-typedef enum { CTU_BC_PERIODIC = 0, CTU_BC_OUTFLOW = 1 } ctu_bc;
+/* Boundary types, Sec. 3.1 (ghost cells and boundary conditions).
+ * Periodic: a ghost copies the real cell one period away.
+ * Outflow (transmissive): every ghost layer copies the edge real cell.
+ * Reflect: a ghost copies its mirror-image real cell across the wall (ghost layer m outside
+ * takes real layer m-1 inside) and negates the momentum normal to the wall; the axis needs
+ * at least 3 real cells so that every mirror image is a real cell. */
+typedef enum { CTU_BC_PERIODIC = 0, CTU_BC_OUTFLOW = 1, CTU_BC_REFLECT = 2 } ctu_bc;
 typedef enum { CTU_FP64 = 0, CTU_FP32 = 1 } ctu_prec;
 
 /* Device error-word bits reported by ctu_check. */
@@ -65,7 +71,8 @@ typedef struct {
   int32_t nx, ny, nz;      /* real cells per axis, each >= 1 */
   double dx, dy, dz;       /* cell widths, > 0 */
   double gamma;            /* ratio of specific heats, > 1 */
-  int32_t bc[6];           /* x-, x+, y-, y+, z-, z+ : ctu_bc; periodic must pair */
+  int32_t bc[6];           /* x-, x+, y-, y+, z-, z+ : ctu_bc; periodic must pair;
+                              reflect needs >= 3 cells on its axis */
   int32_t prec;            /* ctu_prec.  CTU_FP32 stores state, reconstruction and fluxes
                               in float and keeps the Newton star-pressure solve in double */
   double cfl;              /* Courant number C0, 0 < cfl < 0.5 (six-solve CTU limit) */

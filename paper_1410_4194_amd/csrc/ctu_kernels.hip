@@ -88,17 +88,22 @@ __global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab) {
   const int q = layer < NG ? layer - NG : n + (layer - NG);
   const int bc = layer < NG ? r.G->bc[2 * AXIS] : r.G->bc[2 * AXIS + 1];
   int src;
-  if (bc == 0) {
+  if (bc == 0) {          // periodic: one period away
     src = q % n;
     if (src < 0) src += n;
-  } else {
+  } else if (bc == 1) {   // outflow: the edge cell
     src = q < 0 ? 0 : n - 1;
+  } else {                // reflect: the mirror image across the wall (n >= NG is validated)
+    src = q < 0 ? -1 - q : 2 * n - 1 - q;
   }
   const long long d = cell_index(P, AXIS == 0 ? q : i, AXIS == 1 ? q : j, AXIS == 2 ? q : k);
   const long long sidx =
       cell_index(P, AXIS == 0 ? src : i, AXIS == 1 ? src : j, AXIS == 2 ? src : k);
 #pragma unroll
-  for (int f = 0; f < 5; ++f) u[f * P.stride + d] = u[f * P.stride + sidx];
+  for (int f = 0; f < 5; ++f) {
+    const T v = u[f * P.stride + sidx];
+    u[f * P.stride + d] = (bc == 2 && f == 1 + AXIS) ? -v : v;
+  }
 }
 
 

@@ -83,10 +83,14 @@ ctu_status validate(const ctu_config* c) {
       return fail(CTU_EINVAL, "march_seg must lie in [0, 4096]");
   for (int a = 0; a < 3; ++a) {
     int lo = c->bc[2 * a], hi = c->bc[2 * a + 1];
-    if ((lo != CTU_BC_PERIODIC && lo != CTU_BC_OUTFLOW) || (hi != CTU_BC_PERIODIC && hi != CTU_BC_OUTFLOW))
-      return fail(CTU_EINVAL, "unknown boundary type");
+    for (int b : {lo, hi})
+      if (b != CTU_BC_PERIODIC && b != CTU_BC_OUTFLOW && b != CTU_BC_REFLECT)
+        return fail(CTU_EINVAL, "unknown boundary type");
     if ((lo == CTU_BC_PERIODIC) != (hi == CTU_BC_PERIODIC))
       return fail(CTU_EINVAL, "periodic boundaries must pair");
+    const int n = a == 0 ? c->nx : a == 1 ? c->ny : c->nz;
+    if ((lo == CTU_BC_REFLECT || hi == CTU_BC_REFLECT) && n < 3)
+      return fail(CTU_EINVAL, "a reflecting boundary needs >= 3 cells on its axis");
   }
   const long long ncell = (long long)c->nx * c->ny * c->nz;
   if (ncell > (1LL << 31)) return fail(CTU_EINVAL, "grid too large");

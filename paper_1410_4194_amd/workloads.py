@@ -20,6 +20,7 @@ import numpy as np
 BASE_SEED = 14104194
 PERIODIC = 0
 OUTFLOW = 1
+REFLECT = 2
 
 
 @dataclass
@@ -120,6 +121,35 @@ def strong_rarefaction(n: int = 128, ny: int = 1, nz: int = 1) -> Workload:
     """Einfeldt 123 problem (1, -2, 0.4) | (1, 2, 0.4), gamma 1.4, t = 0.15 (Sec. 4.1.3)."""
     return riemann_tube((1.0, -2.0, 0.4), (1.0, 2.0, 0.4), n, ny, nz, 0, 1.4, 0.5, 0.15,
                         name="strong_rarefaction")
+
+
+def blast_waves(n: int = 400, ny: int = 1, nz: int = 1) -> Workload:
+    """Interacting blast waves (Sec. 4.1.5): rho = 1, u = 0, gamma 1.4 on x in [0, 1] with
+    p = 1000 for x < 0.1, p = 100 for x > 0.9 and p = 0.01 between; reflecting walls at both
+    ends of x, periodic across; t = 0.038."""
+    d = 1.0 / n
+    xc = _centres(n, d)
+    p = np.where(xc < 0.1, 1000.0, np.where(xc > 0.9, 100.0, 0.01))
+    W = np.zeros((5, nz, ny, n))
+    W[0] = 1.0
+    W[4] = p.reshape(1, 1, n)
+    bc = (REFLECT, REFLECT, PERIODIC, PERIODIC, PERIODIC, PERIODIC)
+    return Workload(f"blast_waves_{n}", n, ny, nz, d, d, d, 1.4, bc, W, cfl=0.3, t_end=0.038)
+
+
+def implosion(n: int = 400, nz: int = 1) -> Workload:
+    """Implosion (Sec. 4.2.1): the quadrant [0, 0.3]^2 with reflecting walls on all four
+    sides; rho = 0.125, p = 0.14 inside the diamond x + y < 0.15, rho = 1, p = 1 outside, at
+    rest, gamma 1.4; periodic along z (nz copies of the 2D problem); t = 0.045 (early) or
+    2.5 (jet).  The initial state is symmetric under x <-> y, and so is the exact solution."""
+    d = 0.3 / n
+    xc = _centres(n, d)
+    inside = (xc.reshape(1, n) + xc.reshape(n, 1)) < 0.15
+    W = np.zeros((5, nz, n, n))
+    W[0] = np.where(inside, 0.125, 1.0)
+    W[4] = np.where(inside, 0.14, 1.0)
+    bc = (REFLECT, REFLECT, REFLECT, REFLECT, PERIODIC, PERIODIC)
+    return Workload(f"implosion_{n}", n, n, nz, d, d, d, 1.4, bc, W, cfl=0.3, t_end=0.045)
 
 
 # ------------------------------------------------------------------------------------------

@@ -51,7 +51,9 @@ def test_workspace_bytes_and_validation(ctu):
     assert sb32 == 5 * ((14 ** 3 + 63) // 64 * 64) * 4
     bad = [
         dict(nx=0), dict(dx=0.0), dict(gamma=1.0), dict(cfl=0.5), dict(cfl=0.0),
-        dict(bc=(0, 1, 0, 0, 0, 0)), dict(bc=(2, 2, 0, 0, 0, 0)), dict(prec=7),
+        dict(bc=(0, 1, 0, 0, 0, 0)), dict(bc=(3, 3, 0, 0, 0, 0)), dict(prec=7),
+        dict(bc=(2, 0, 0, 0, 0, 0)), dict(nx=2, bc=(2, 2, 0, 0, 0, 0)),
+        dict(nz=1, bc=(0, 0, 0, 0, 1, 2)),
         dict(newton_max_iter=0), dict(newton_tol=0.0), dict(p_floor=0.0),
         dict(march_seg=(-1, 0)), dict(march_seg=(0, 5000)),
     ]
@@ -63,6 +65,8 @@ def test_workspace_bytes_and_validation(ctu):
         with pytest.raises(ctu.CtuError) as ei:
             ctu.workspace_bytes(c)
         assert ei.value.status == ctu.EINVAL
+    ok = ctu.make_config(3, 8, 1, 1, 1, 1, 1.4, (ctu.BC_REFLECT, ctu.BC_OUTFLOW, 2, 2, 0, 0))
+    ctu.workspace_bytes(ok)
 
 
 def test_grid_create_rejects_small_workspace(ctu):

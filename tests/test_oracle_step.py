@@ -21,32 +21,160 @@ def _l1(a, b):
     return float(np.mean(np.abs(a - b)))
 
 
-@pytest.mark.parametrize("bc", [(0,) * 6, (1,) * 6, (1, 1, 0, 0, 0, 0), (0, 0, 1, 1, 0, 0)])
+@pytest.mark.parametrize("bc", [(0,) * 6, (1,) * 6, (1, 1, 0, 0, 0, 0), (0, 0, 1, 1, 0, 0),
+                                (2,) * 6, (2, 2, 0, 0, 1, 1), (1, 2, 2, 1, 0, 0),
+                                (0, 0, 2, 1, 2, 2)])
 def test_bc_fill_matches_numpy_pad(bc):
+    """Ghost fill against numpy.pad: 'wrap' (periodic), 'edge' (outflow) and 'symmetric'
+    (reflecting: mirror image across the wall, edge cell included) followed by a sign flip
+    of the wall-normal velocity in the new ghost layers; x, then y, then z."""
     wl = WL.random_state(7, 5, 4, seed=1, bc=bc)
     cfg = oracle_config(wl)
     u = oracle_state(wl, cfg)
     O.bc_fill(cfg, u)
-    real = wl.W.copy()
-    exp = real
-    modes = {0: "wrap", 1: "edge"}
+    exp = wl.W.copy()
+    modes = {0: "wrap", 1: "edge", 2: "symmetric"}
     for axis in range(3):  # x, then y, then z
         npax = 3 - axis
-        assert bc[2 * axis] == bc[2 * axis + 1] or True
+        lo, hi = bc[2 * axis], bc[2 * axis + 1]
         pad = [(0, 0)] * 4
-        lo_mode, hi_mode = modes[bc[2 * axis]], modes[bc[2 * axis + 1]]
-        if lo_mode == hi_mode:
+        if lo == hi:  # one call, so that 'wrap' sees only real cells
             pad[npax] = (O.NG, O.NG)
-            exp = np.pad(exp, pad, mode=lo_mode)
+            exp = np.pad(exp, pad, mode=modes[lo])
         else:
             pad[npax] = (O.NG, 0)
-            exp = np.pad(exp, pad, mode=lo_mode)
+            exp = np.pad(exp, pad, mode=modes[lo])
             pad[npax] = (0, O.NG)
-            exp = np.pad(exp, pad, mode=hi_mode)
-    # compare primitives: convert the oracle's conserved ghosts back
-    rho = u[0]
-    assert np.array_equal(rho, exp[0])
-    assert np.array_equal(u[1], exp[0] * exp[1])
+            exp = np.pad(exp, pad, mode=modes[hi])
+        for side in (0, 1):
+            if bc[2 * axis + side] == 2:
+                sl = [slice(None)] * 4
+                sl[0] = 1 + axis
+                sl[npax] = slice(0, O.NG) if side == 0 else slice(-O.NG, None)
+                exp[tuple(sl)] *= -1.0
+    # compare conserved values: rho and rho * velocity
+    assert np.array_equal(u[0], exp[0])
+    for q in (1, 2, 3):
+        assert np.array_equal(u[q], exp[0] * exp[q])
+
+
+def test_reflect_needs_three_cells():
+    wl = WL.random_state(7, 2, 4, seed=1, bc=(0, 0, 2, 2, 0, 0))
+    cfg = oracle_config(wl)
+    u = oracle_state(wl, cfg)
+    with pytest.raises(ValueError):
+        O.bc_fill(cfg, u)
+
+
+def _mirror_doubled(W, axis, side):
+    """W extended by its mirror image across the low (side 0) or high (side 1) wall of
+    `axis`, with the velocity normal to that wall negated in the mirrored half."""
+    npax = 2 - axis
+    M = np.flip(W, axis=1 + npax).copy()
+    M[1 + axis] *= -1.0
+    return np.concatenate([M, W] if side == 0 else [W, M], axis=1 + npax)
+
+
+@pytest.mark.parametrize("axis,bc_other", [(0, 0), (1, 1), (2, 0)])
+def test_reflect_equals_mirrored_periodic_box(axis, bc_other):
+    """A box with reflecting walls at both ends of an axis evolves exactly like the first
+    half of a periodic box of twice the length that holds the state and its mirror image
+    (the even extension): every cell of the half sees the same stencil values, because a
+    reflecting ghost is the mirror cell with its normal momentum negated (an exact
+    operation).  One step from the same dt agrees bit for bit."""
+    n = [6, 5, 4]
+    n[axis] = 7
+    bc = [bc_other] * 6
+    bc[2 * axis] = bc[2 * axis + 1] = 2
+    wl = WL.random_state(*n, seed=11 + axis, bc=tuple(bc))
+    cfg = oracle_config(wl)
+    u = oracle_state(wl, cfg)
+    dt = 0.5 * O.compute_dt(cfg, u)
+    O.step(cfg, u, dt)
+
+    W2 = _mirror_doubled(wl.W, axis, 1)
+    n2 = list(n)
+    n2[axis] *= 2
+    bc2 = list(bc)
+    bc2[2 * axis] = bc2[2 * axis + 1] = 0
+    d = [wl.dx, wl.dy, wl.dz]
+    cfg2 = O.Config(*n2, *d, wl.gamma, bc=tuple(bc2), cfl=wl.cfl)
+    u2 = O.state_from_primitive(cfg2, W2)
+    O.step(cfg2, u2, dt)
+    half = [slice(None)] * 4
+    half[3 - axis] = slice(0, n[axis])
+    assert np.array_equal(O.real(cfg, u), O.real(cfg2, u2)[tuple(half)])
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_reflect_one_wall_equals_mirrored_outflow_box(side):
+    """One reflecting wall (the other end outflow): the box is the corresponding half of an
+    outflow box of twice the length holding the mirror-extended state.  Bit for bit."""
+    bc = [0, 0, 1, 1, 1, 1]
+    bc[side] = 2
+    bc[1 - side] = 1
+    wl = WL.random_state(8, 4, 5, seed=21 + side, bc=tuple(bc))
+    cfg = oracle_config(wl)
+    u = oracle_state(wl, cfg)
+    dt = 0.5 * O.compute_dt(cfg, u)
+    O.step(cfg, u, dt)
+    W2 = _mirror_doubled(wl.W, 0, side)
+    bc2 = list(bc)
+    bc2[0] = bc2[1] = 1
+    cfg2 = O.Config(16, 4, 5, wl.dx, wl.dy, wl.dz, wl.gamma, bc=tuple(bc2), cfl=wl.cfl)
+    u2 = O.state_from_primitive(cfg2, W2)
+    O.step(cfg2, u2, dt)
+    got = O.real(cfg2, u2)[..., 8:] if side == 0 else O.real(cfg2, u2)[..., :8]
+    assert np.array_equal(O.real(cfg, u), got)
+
+
+def test_reflect_walls_conserve_mass_and_energy():
+    """A closed box (reflecting on all six faces): no mass or energy crosses a wall, whose
+    two states are mirror images (u* = 0, so the mass and energy fluxes vanish).  Mass and
+    energy totals stay fixed to rounding over several steps; momentum does not (the walls
+    push back)."""
+    wl = WL.random_state(6, 5, 7, seed=5, bc=(2,) * 6)
+    cfg = oracle_config(wl)
+    u = oracle_state(wl, cfg)
+    r0 = O.real(cfg, u).reshape(5, -1)
+    m0, e0 = math.fsum(r0[0]), math.fsum(r0[4])
+    for _ in range(4):
+        O.step(cfg, u, O.compute_dt(cfg, u))
+    r1 = O.real(cfg, u).reshape(5, -1)
+    assert abs(math.fsum(r1[0]) - m0) <= 1e-13 * math.fsum(np.abs(r0[0]))
+    assert abs(math.fsum(r1[4]) - e0) <= 1e-13 * math.fsum(np.abs(r0[4]))
+    assert abs(math.fsum(r1[1]) - math.fsum(r0[1])) > 1e-6
+
+
+def test_implosion_keeps_diagonal_symmetry():
+    """The implosion quadrant (Sec. 4.2.1) is symmetric under x <-> y and so is its exact
+    solution; the unsplit step treats the two axes alike, so the discrete solution stays
+    symmetric to rounding (the paper reports exact symmetry for its ordering).  20 steps
+    at 40^2."""
+    wl = WL.implosion(40)
+    cfg, u, t, n = run_oracle(wl, steps=20)
+    r = O.real(cfg, u)[:, 0]
+    assert np.max(np.abs(r[0] - r[0].T)) <= 1e-12 * np.max(r[0])
+    assert np.max(np.abs(r[4] - r[4].T)) <= 1e-12 * np.max(r[4])
+    assert np.max(np.abs(r[1] - r[2].T)) <= 1e-12 * np.max(np.abs(r[1]))
+    # the flow has moved: the diamond's rarefaction has reached the walls' corner region
+    assert np.max(np.abs(r[1])) > 1e-2
+
+
+def test_blast_waves_stay_physical_and_closed():
+    """Interacting blast waves (Sec. 4.1.5) at 100 cells to t = 0.038: reflecting walls keep
+    mass and energy exactly (to rounding) and the state physical; the two blast fronts
+    have collided (density well above the initial 1)."""
+    wl = WL.blast_waves(100)
+    cfg = oracle_config(wl)
+    u0 = O.real(cfg, oracle_state(wl, cfg))
+    cfg, u, t, n = run_oracle(wl, t_end=wl.t_end)
+    r = O.real(cfg, u)
+    assert abs(t - wl.t_end) < 1e-12
+    assert abs(r[0].sum() - u0[0].sum()) <= 1e-12 * u0[0].sum()
+    assert abs(r[4].sum() - u0[4].sum()) <= 1e-12 * u0[4].sum()
+    assert np.all(r[0] > 0)
+    assert r[0].max() > 3.0
 
 
 def test_dt_closed_form_uniform():
