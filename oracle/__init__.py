@@ -14,9 +14,12 @@ from typing import Optional, Sequence, Tuple
 
 import numpy as np
 
-NG = 3
+NG = 3  # ghost layers of the PPMC configuration (Config.ng in general)
 BC_PERIODIC = 0
 BC_OUTFLOW = 1
+BC_REFLECT = 2
+RIEMANN_EXACT, RIEMANN_ROE = 0, 1
+RECON_PPMC, RECON_PPMP = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.environ.get("CTU_ORACLE_LIB") or os.path.join(_HERE, "libctu_oracle.so")
@@ -28,12 +31,13 @@ class _Config(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("gamma", C.c_double), ("bc", C.c_int * 6), ("cfl", C.c_double),
                 ("newton_tol", C.c_double), ("newton_max_iter", C.c_int),
-                ("p_floor", C.c_double)]
+                ("p_floor", C.c_double), ("riemann", C.c_int), ("h_correction", C.c_int),
+                ("recon", C.c_int)]
 
 
 class _Stats(C.Structure):
     _fields_ = [("solves", C.c_long), ("newton_iters", C.c_long),
-                ("newton_capped", C.c_long), ("p_floored", C.c_long)]
+                ("newton_capped", C.c_long), ("p_floored", C.c_long), ("hlle", C.c_long)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -63,7 +67,13 @@ def _load():
     lib.ref_riemann_wave_speeds.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
     lib.ref_riemann_flux.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_int, C.c_double,
                                      _dp, C.POINTER(_Stats)]
+    lib.ref_ghost_width.argtypes = [C.POINTER(_Config)]
+    lib.ref_ghost_width.restype = C.c_int
+    lib.ref_roe_flux.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, _dp,
+                                 C.POINTER(_Stats)]
+    lib.ref_roe_flux.restype = C.c_int
     lib.ref_bc_fill.argtypes = [C.POINTER(_Config), C.POINTER(_dp)]
+    lib.ref_bc_fill.restype = C.c_int
     lib.ref_compute_dt.argtypes = [C.POINTER(_Config), C.POINTER(_dp)]
     lib.ref_compute_dt.restype = C.c_double
     lib.ref_ctu_update_box.argtypes = [C.POINTER(_Config), C.POINTER(_dp), C.c_double,
@@ -102,6 +112,9 @@ class Config:
     newton_tol: float = 1e-6
     newton_max_iter: int = 50
     p_floor: float = 1e-20
+    riemann: int = 0          # RIEMANN_EXACT or RIEMANN_ROE
+    h_correction: int = 0     # 1: H correction of the second-stage Roe fluxes
+    recon: int = 0            # RECON_PPMC or RECON_PPMP
 
     def _c(self) -> _Config:
         c = _Config()
@@ -114,11 +127,20 @@ class Config:
         c.newton_tol = self.newton_tol
         c.newton_max_iter = self.newton_max_iter
         c.p_floor = self.p_floor
+        c.riemann = self.riemann
+        c.h_correction = self.h_correction
+        c.recon = self.recon
         return c
 
     @property
+    def ng(self) -> int:
+        """Ghost layers per side (3 for PPMC; 4 for PPMP or with the H correction)."""
+        return int(_load().ref_ghost_width(C.byref(self._c())))
+
+    @property
     def alloc_shape(self) -> Tuple[int, int, int]:
-        return (self.nz + 2 * NG, self.ny + 2 * NG, self.nx + 2 * NG)
+        g = self.ng
+        return (self.nz + 2 * g, self.ny + 2 * g, self.nx + 2 * g)
 
 
 @dataclass
@@ -127,10 +149,11 @@ class Stats:
     newton_iters: int = 0
     newton_capped: int = 0
     p_floored: int = 0
+    hlle: int = 0
 
 
 def _stats_out(s: _Stats) -> Stats:
-    return Stats(s.solves, s.newton_iters, s.newton_capped, s.p_floored)
+    return Stats(s.solves, s.newton_iters, s.newton_capped, s.p_floored, s.hlle)
 
 
 # --- pointwise pieces ----------------------------------------------------------------------
@@ -235,6 +258,16 @@ def riemann_flux(UL, UR, gamma: float, tol: float = 1e-6, max_iter: int = 50,
     return F, _stats_out(st)
 
 
+def roe_flux(UL, UR, gamma: float, p_floor: float = 1e-20, eta_h: float = 0.0):
+    """Roe flux with the HLLE failsafe; returns (F, used_hlle, stats)."""
+    lib = _load()
+    ul, ur = _vec(UL, 5), _vec(UR, 5)
+    F = np.zeros(5)
+    st = _Stats()
+    used = lib.ref_roe_flux(_ptr(ul), _ptr(ur), gamma, p_floor, eta_h, _ptr(F), C.byref(st))
+    return F, bool(used), _stats_out(st)
+
+
 # --- whole-grid operations ------------------------------------------------------------------
 
 def _field_ptrs(u: np.ndarray):
@@ -250,7 +283,8 @@ def alloc_state(cfg: Config) -> np.ndarray:
 
 
 def bc_fill(cfg: Config, u: np.ndarray) -> None:
-    _load().ref_bc_fill(C.byref(cfg._c()), _field_ptrs(u))
+    if _load().ref_bc_fill(C.byref(cfg._c()), _field_ptrs(u)) != 0:
+        raise ValueError("a reflecting boundary needs >= 3 cells on its axis")
 
 
 def compute_dt(cfg: Config, u: np.ndarray) -> float:
@@ -299,7 +333,8 @@ def update_box(cfg: Config, u: np.ndarray, dt: float, lo, hi, want_fluxes: bool 
 
 def real(cfg: Config, u: np.ndarray) -> np.ndarray:
     """View of the real cells of an allocated state."""
-    return u[:, NG:NG + cfg.nz, NG:NG + cfg.ny, NG:NG + cfg.nx]
+    g = cfg.ng
+    return u[:, g:g + cfg.nz, g:g + cfg.ny, g:g + cfg.nx]
 
 
 def state_from_primitive(cfg: Config, W: np.ndarray) -> np.ndarray:

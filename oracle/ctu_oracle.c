@@ -16,7 +16,6 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define NG REF_NG
 
 /* ------------------------------------------------------------------------------------ */
 /* Equation of state and variable sets (Sec. 2, eqs. conserved_variables,                */
@@ -424,12 +423,136 @@ void ref_riemann_flux(const double UL[5], const double UR[5], double gamma, doub
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* Roe solver with the HLLE failsafe (Sec. 2.3.2-2.3.3, App. B.2).                          */
+/* ------------------------------------------------------------------------------------ */
+
+/* Flux vector f of eq. x_flux for a state with primitives W (rho, u, v, w, p) and total
+ * energy E. */
+static void euler_flux(const double W[5], double E, double F[5]) {
+  F[0] = W[0] * W[1];
+  F[1] = W[0] * W[1] * W[1] + W[4];
+  F[2] = W[0] * W[1] * W[2];
+  F[3] = W[0] * W[1] * W[3];
+  F[4] = (E + W[4]) * W[1];
+}
+
+/* Pressure of a conserved state, without a floor (for the positivity test). */
+static double raw_pressure(const double U[5], double gamma) {
+  return (gamma - 1.0) * (U[4] - 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / U[0]);
+}
+
+/* Reading: the Roe inputs are the interface states in the conserved form in which they are
+ * kept between the stages; primitives come from the same conversion (with the pressure
+ * floor) as for the exact solver, and F_L, F_R use the stored total energies.  eta_h >= 0
+ * is the H-correction speed (App. C); 0 leaves the eigenvalues as they are.  An
+ * intermediate state counts as failed when its density or pressure is not positive. */
+int ref_roe_flux(const double UL[5], const double UR[5], double gamma, double p_floor,
+                 double eta_h, double F[5], ref_stats* st) {
+  double WL[5], WR[5];
+  int fl = ref_cons_to_prim(UL, gamma, p_floor, WL);
+  int fr = ref_cons_to_prim(UR, gamma, p_floor, WR);
+  if (st) {
+    st->solves += 1;
+    st->p_floored += fl + fr;
+  }
+  double FL[5], FR[5];
+  euler_flux(WL, UL[4], FL);
+  euler_flux(WR, UR[4], FR);
+
+  /* Roe averages; enthalpy H = (E + p) / rho in place of the pressure */
+  double sl = sqrt(WL[0]), sr = sqrt(WR[0]);
+  double HL = (UL[4] + WL[4]) / WL[0], HR = (UR[4] + WR[4]) / WR[0];
+  double ut = (sl * WL[1] + sr * WR[1]) / (sl + sr);
+  double vt = (sl * WL[2] + sr * WR[2]) / (sl + sr);
+  double wt = (sl * WL[3] + sr * WR[3]) / (sl + sr);
+  double Ht = (sl * HL + sr * HR) / (sl + sr);
+  double V2 = ut * ut + vt * vt + wt * wt;
+  double at = sqrt((gamma - 1.0) * (Ht - 0.5 * V2));
+  double lm = ut - at, l0 = ut, lp = ut + at;
+
+  /* supersonic: the upwind state's flux */
+  if (lm >= 0.0) {
+    for (int q = 0; q < 5; ++q) F[q] = FL[q];
+    return 0;
+  }
+  if (lp <= 0.0) {
+    for (int q = 0; q < 5; ++q) F[q] = FR[q];
+    return 0;
+  }
+
+  double dU[5];
+  for (int q = 0; q < 5; ++q) dU[q] = UR[q] - UL[q];
+  /* wave strengths: projections of dU on the left eigenvectors */
+  double gp = gamma - 1.0;
+  double Na = 1.0 / (2.0 * at * at);
+  double xi[5];
+  xi[0] = dU[0] * Na * (0.5 * gp * V2 + ut * at) - dU[1] * Na * (gp * ut + at) -
+          dU[2] * Na * gp * vt - dU[3] * Na * gp * wt + dU[4] * Na * gp;
+  xi[1] = -dU[0] * vt + dU[2];
+  xi[2] = -dU[0] * wt + dU[3];
+  xi[3] = dU[0] * (1.0 - Na * gp * V2) + dU[1] * gp * ut / (at * at) +
+          dU[2] * gp * vt / (at * at) + dU[3] * gp * wt / (at * at) - dU[4] * gp / (at * at);
+  xi[4] = dU[0] * Na * (0.5 * gp * V2 - ut * at) - dU[1] * Na * (gp * ut - at) -
+          dU[2] * Na * gp * vt - dU[3] * Na * gp * wt + dU[4] * Na * gp;
+
+  /* coefficients, with |lambda| raised to eta_h by the H correction */
+  double am = fmax(fabs(lm), eta_h), a0 = fmax(fabs(l0), eta_h), ap = fmax(fabs(lp), eta_h);
+  double C[5] = {xi[0] * am, xi[1] * a0, xi[2] * a0, xi[3] * a0, xi[4] * ap};
+  /* sum of the coefficients times the right eigenvectors ([Q28]: C3 multiplies w~ in s3) */
+  double s[5];
+  s[0] = C[0] + C[3] + C[4];
+  s[1] = C[0] * (ut - at) + C[3] * ut + C[4] * (ut + at);
+  s[2] = C[0] * vt + C[1] + C[3] * vt + C[4] * vt;
+  s[3] = C[0] * wt + C[2] + C[3] * wt + C[4] * wt;
+  s[4] = C[0] * (Ht - ut * at) + C[1] * vt + C[2] * wt + 0.5 * C[3] * V2 + C[4] * (Ht + ut * at);
+
+  /* intermediate states: the left state plus the waves crossed from the left */
+  int failed = 0;
+  double Um[5];
+  Um[0] = UL[0] + xi[0];
+  Um[1] = UL[1] + xi[0] * (ut - at);
+  Um[2] = UL[2] + xi[0] * vt;
+  Um[3] = UL[3] + xi[0] * wt;
+  Um[4] = UL[4] + xi[0] * (Ht - ut * at);
+  if (l0 > lm && (!(Um[0] > 0.0) || !(raw_pressure(Um, gamma) > 0.0))) failed = 1;
+  if (!failed) {
+    Um[0] = Um[0] + xi[3];
+    Um[1] = Um[1] + xi[3] * ut;
+    Um[2] = Um[2] + xi[1] + xi[3] * vt;
+    Um[3] = Um[3] + xi[2] + xi[3] * wt;
+    Um[4] = Um[4] + xi[1] * vt + xi[2] * wt + 0.5 * xi[3] * V2;
+    if (lp > l0 && (!(Um[0] > 0.0) || !(raw_pressure(Um, gamma) > 0.0))) failed = 1;
+  }
+  if (!failed) {
+    for (int q = 0; q < 5; ++q) F[q] = 0.5 * (FL[q] + FR[q] - s[q]);
+    return 0;
+  }
+
+  /* HLLE failsafe: bounding speeds from the Roe eigenvalues and the input acoustic speeds */
+  double aL = sqrt(gamma * WL[4] / WL[0]), aR = sqrt(gamma * WR[4] / WR[0]);
+  double bm = fmin(fmin(lm, WL[1] - aL), 0.0);
+  double bp = fmax(fmax(lp, WR[1] + aR), 0.0);
+  for (int q = 0; q < 5; ++q) {
+    double fl_q = FL[q] - bm * UL[q];
+    double fr_q = FR[q] - bp * UR[q];
+    F[q] = 0.5 * ((fl_q + fr_q) + (fl_q - fr_q) * ((bp + bm) / (bp - bm)));
+  }
+  if (st) st->hlle += 1;
+  return 1;
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Grid helpers.                                                                          */
 /* ------------------------------------------------------------------------------------ */
 
+int ref_ghost_width(const ref_config* c) {
+  return (c->recon == REF_RECON_PPMP || c->h_correction) ? 4 : 3;
+}
+
 static long alloc_index(const ref_config* c, int i, int j, int k) {
-  long NX = c->nx + 2 * NG, NY = c->ny + 2 * NG;
-  return (long)(i + NG) + NX * ((long)(j + NG) + NY * (long)(k + NG));
+  int ng = ref_ghost_width(c);
+  long NX = c->nx + 2 * ng, NY = c->ny + 2 * ng;
+  return (long)(i + ng) + NX * ((long)(j + ng) + NY * (long)(k + ng));
 }
 
 static int wrap_index(int q, int n) {
@@ -437,29 +560,45 @@ static int wrap_index(int q, int n) {
   return r < 0 ? r + n : r;
 }
 
-void ref_bc_fill(const ref_config* c, double* const u[5]) {
+/* Sec. 3.1: periodic and transmissive ghosts copy the matching real cell; a reflecting
+ * ghost does the same with its mirror image across the wall and flips the sign of the
+ * momentum normal to that wall.  The sentence naming the flipped quantity is cut off in
+ * the available text; the wall-normal momentum is the reading taken. */
+int ref_bc_fill(const ref_config* c, double* const u[5]) {
   int n[3] = {c->nx, c->ny, c->nz};
+  const int ng = ref_ghost_width(c);
+  for (int axis = 0; axis < 3; ++axis)
+    if ((c->bc[2 * axis] == REF_BC_REFLECT || c->bc[2 * axis + 1] == REF_BC_REFLECT) &&
+        n[axis] < ng)
+      return -1;
   for (int axis = 0; axis < 3; ++axis) {
-    for (int k = -NG; k < c->nz + NG; ++k)
-      for (int j = -NG; j < c->ny + NG; ++j)
-        for (int i = -NG; i < c->nx + NG; ++i) {
+    for (int k = -ng; k < c->nz + ng; ++k)
+      for (int j = -ng; j < c->ny + ng; ++j)
+        for (int i = -ng; i < c->nx + ng; ++i) {
           int pos[3] = {i, j, k};
           int q = pos[axis];
           if (q >= 0 && q < n[axis]) continue;
           int side = (q < 0) ? 0 : 1;
           int bc = c->bc[2 * axis + side];
           int src;
-          if (bc == REF_BC_PERIODIC)
+          double flip = 1.0; /* sign applied to the wall-normal momentum */
+          if (bc == REF_BC_PERIODIC) {
             src = wrap_index(q, n[axis]);
-          else /* transmissive: zero-gradient copy of the edge cell [Q17] */
+          } else if (bc == REF_BC_OUTFLOW) { /* zero-gradient copy of the edge cell [Q17] */
             src = (q < 0) ? 0 : n[axis] - 1;
+          } else { /* mirror image: ghost -1-m pairs with real m, ghost n+m with n-1-m */
+            src = (q < 0) ? -1 - q : 2 * n[axis] - 1 - q;
+            flip = -1.0;
+          }
           int spos[3] = {i, j, k};
           spos[axis] = src;
           long dst_i = alloc_index(c, i, j, k);
           long src_i = alloc_index(c, spos[0], spos[1], spos[2]);
-          for (int f = 0; f < 5; ++f) u[f][dst_i] = u[f][src_i];
+          for (int f = 0; f < 5; ++f)
+            u[f][dst_i] = (f == 1 + axis) ? flip * u[f][src_i] : u[f][src_i];
         }
   }
+  return 0;
 }
 
 double ref_compute_dt(const ref_config* c, double* const u[5]) {
@@ -507,6 +646,15 @@ static long box_size(const box* b) { return b->n[0] * b->n[1] * b->n[2]; }
  * rotated slot s holds global component rot[d][s]. */
 static const int rot[3][5] = {{0, 1, 2, 3, 4}, {0, 2, 3, 1, 4}, {0, 3, 1, 2, 4}};
 
+/* The interface flux of the configured Riemann solver from rotated conserved states. */
+static void face_flux(const ref_config* c, const double ul[5], const double ur[5],
+                      double eta_h, double F[5], ref_stats* st) {
+  if (c->riemann == REF_RIEMANN_ROE)
+    ref_roe_flux(ul, ur, c->gamma, c->p_floor, eta_h, F, st);
+  else
+    ref_riemann_flux(ul, ur, c->gamma, c->newton_tol, c->newton_max_iter, c->p_floor, F, st);
+}
+
 int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const int lo[3],
                        const int hi[3], double* const out[5], double* const* fstar,
                        double* const* fhalf, ref_stats* st) {
@@ -514,6 +662,8 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
   double dd[3] = {c->dx, c->dy, c->dz};
   for (int a = 0; a < 3; ++a)
     if (lo[a] < 0 || hi[a] > n[a] || lo[a] >= hi[a]) return -1;
+  if (c->riemann != REF_RIEMANN_EXACT && c->riemann != REF_RIEMANN_ROE) return -1;
+  if (c->recon != REF_RECON_PPMC || c->h_correction) return -1;
   double g = c->gamma;
 
   /* Boxes: R = cells to update; X = R grown by one cell (cells whose traced states and
@@ -522,8 +672,8 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
   for (int a = 0; a < 3; ++a) {
     xlo[a] = lo[a] - 1;
     xhi[a] = hi[a] + 1;
-    plo[a] = lo[a] - NG;
-    phi[a] = hi[a] + NG;
+    plo[a] = lo[a] - ref_ghost_width(c);
+    phi[a] = hi[a] + ref_ghost_width(c);
   }
   box R = make_box(lo, hi), X = make_box(xlo, xhi), P = make_box(plo, phi);
 
@@ -595,7 +745,7 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
             ul[q] = Us[d][1][rot[d][q]][xc];
             ur[q] = Us[d][0][rot[d][q]][xn];
           }
-          ref_riemann_flux(ul, ur, g, c->newton_tol, c->newton_max_iter, c->p_floor, fl, st);
+          face_flux(c, ul, ur, 0.0, fl, st);
           for (int q = 0; q < 5; ++q) Fs[d][rot[d][q]][xc] = fl[q];
           if (fstar) {
             long ai = alloc_index(c, i, j, k);
@@ -646,7 +796,7 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
             ul[q] = Uh[0][rot[d][q]];
             ur[q] = Uh[1][rot[d][q]];
           }
-          ref_riemann_flux(ul, ur, g, c->newton_tol, c->newton_max_iter, c->p_floor, fl, st);
+          face_flux(c, ul, ur, 0.0, fl, st);
           long hb = box_index(&H[d], i, j, k);
           for (int q = 0; q < 5; ++q) Fh[d][rot[d][q]][hb] = fl[q];
           if (fhalf) {
@@ -692,7 +842,7 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
 }
 
 int ref_ctu_step(const ref_config* c, double* const u[5], double dt, ref_stats* st) {
-  ref_bc_fill(c, u);
+  if (ref_bc_fill(c, u) != 0) return -1;
   int lo[3] = {0, 0, 0};
   int hi[3] = {c->nx, c->ny, c->nz};
   long nr = (long)c->nx * c->ny * c->nz;

@@ -15,10 +15,10 @@
  * laws, jump conditions, invariants or brute force (see tests/test_oracle_*.py).
  *
  * Layout: conserved state is structure-of-arrays, 5 fields (rho, rho*u, rho*v, rho*w, E),
- * each over the allocated box (nx+6)(ny+6)(nz+6) with x fastest; real cell (i,j,k),
- * 0 <= i < nx, sits at (i+3) + NX*((j+3) + NY*(k+3)), NX = nx+6, NY = ny+6.  Three ghost
- * layers: the PPMC stencil reaches two cells to each side and the CTU transverse
- * correction one more.
+ * each over the allocated box (nx+2g)(ny+2g)(nz+2g) with x fastest, g = ref_ghost_width();
+ * real cell (i,j,k), 0 <= i < nx, sits at (i+g) + NX*((j+g) + NY*(k+g)), NX = nx+2g,
+ * NY = ny+2g.  g = 3 for PPMC: its stencil reaches two cells to each side and the CTU
+ * transverse correction one more.
  */
 #ifndef CTU_ORACLE_H
 #define CTU_ORACLE_H
@@ -27,9 +27,13 @@
 extern "C" {
 #endif
 
-#define REF_NG 3
 #define REF_BC_PERIODIC 0
 #define REF_BC_OUTFLOW 1
+#define REF_BC_REFLECT 2
+#define REF_RIEMANN_EXACT 0 /* exact solver, Newton star pressure (App. B.1) */
+#define REF_RIEMANN_ROE 1   /* Roe solver with the HLLE failsafe (App. B.2) */
+#define REF_RECON_PPMC 0    /* PPM with characteristic limiting and tracing (App. A.3) */
+#define REF_RECON_PPMP 1    /* PPM in the primitive variables, CW84 (App. A.4) */
 
 typedef struct {
   int nx, ny, nz;          /* real cells per axis, >= 1 */
@@ -40,13 +44,22 @@ typedef struct {
   double newton_tol;       /* relative tolerance on the star-pressure change */
   int newton_max_iter;     /* iteration cap of the Newton loop */
   double p_floor;          /* pressure floor applied on every primitive conversion */
+  int riemann;             /* REF_RIEMANN_* */
+  int h_correction;        /* 1: H correction of the second-stage Roe fluxes (App. C) */
+  int recon;               /* REF_RECON_* */
 } ref_config;
+
+/* Ghost layers of the state arrays: 3 for PPMC (stencil of two cells plus one for the
+ * transverse correction), 4 when PPMP (three-cell stencil) or the H correction (which reads
+ * second-stage states one cell beyond the boundary) is used. */
+int ref_ghost_width(const ref_config* c);
 
 typedef struct {
   long solves;             /* Riemann problems solved */
   long newton_iters;       /* Newton iterations summed over all solves */
   long newton_capped;      /* solves that hit newton_max_iter without converging */
   long p_floored;          /* primitive conversions whose pressure was raised to p_floor */
+  long hlle;               /* Roe solves that fell back to the HLLE flux */
 } ref_stats;
 
 /* --- pointwise pieces (exposed for the pin tests) ------------------------------------ */
@@ -95,11 +108,20 @@ void ref_riemann_wave_speeds(const double WL[3], const double WR[3], double psta
 void ref_riemann_flux(const double UL[5], const double UR[5], double gamma, double tol,
                       int max_iter, double p_floor, double F[5], ref_stats* st);
 
+/* Roe flux (App. B.2) from rotated conserved states UL, UR, with the HLLE flux substituted
+ * when an intermediate Roe state has a non-positive density or pressure.  eta_h is the
+ * H-correction speed (App. C; 0 for none).  Returns 1 when HLLE was used, else 0. */
+int ref_roe_flux(const double UL[5], const double UR[5], double gamma, double p_floor,
+                 double eta_h, double F[5], ref_stats* st);
+
 /* --- whole-grid operations ----------------------------------------------------------- */
 
 /* Ghost fill: x faces, then y, then z, each over the full extent of the other two axes
- * (ghosts included), so edge and corner ghosts end up consistent. */
-void ref_bc_fill(const ref_config* c, double* const u[5]);
+ * (ghosts included), so edge and corner ghosts end up consistent.  Periodic ghosts copy the
+ * real cell one period away, outflow ghosts the edge cell, reflecting ghosts their mirror
+ * image across the wall with the wall-normal momentum negated (needs as many cells on the
+ * axis as there are ghost layers; returns -1 without filling otherwise). */
+int ref_bc_fill(const ref_config* c, double* const u[5]);
 
 /* CFL time step over the real cells: C0 * min(dx/(|u|+a), dy/(|v|+a), dz/(|w|+a)). */
 double ref_compute_dt(const ref_config* c, double* const u[5]);

@@ -42,10 +42,21 @@ M=[
  ("fprime rare exponent", "*df = 1.0 / (rho_k * a_k) * pow(p / p_k, -(gamma + 1.0) / (2.0 * gamma));", "*df = 1.0 / (rho_k * a_k) * pow(p / p_k, (gamma + 1.0) / (2.0 * gamma));"),
  ("fan u", "out[1] = c + S;", "out[1] = c;"),
  ("half dt transverse", "double h1 = 0.5 * dt / dd[t1];", "double h1 = dt / dd[t1];"),
+ ("reflect mirror off by one", "src = (q < 0) ? -1 - q : 2 * n[axis] - 1 - q;", "src = (q < 0) ? -q : 2 * n[axis] - 2 - q;"),
+ ("reflect no flip", "flip = -1.0;", "flip = 1.0;"),
+ ("reflect flips wrong component", "u[f][dst_i] = (f == 1 + axis) ? flip", "u[f][dst_i] = (f == 1 + (axis + 1) % 3) ? flip"),
+ ("roe s3 printed", "s[3] = C[0] * wt + C[2] + C[3] * wt + C[4] * wt;", "s[3] = C[0] * wt + C[2] + C[3] * 2.0 + C[4] * wt;"),
+ ("roe xi4 sign", "xi[4] = dU[0] * Na * (0.5 * gp * V2 - ut * at)", "xi[4] = dU[0] * Na * (0.5 * gp * V2 + ut * at)"),
+ ("roe dissipation sign", "F[q] = 0.5 * (FL[q] + FR[q] - s[q]);", "F[q] = 0.5 * (FL[q] + FR[q] + s[q]);"),
+ ("roe never falls back", "if (!failed) {\n    for (int q = 0; q < 5; ++q) F[q] = 0.5", "if (1) {\n    for (int q = 0; q < 5; ++q) F[q] = 0.5"),
+ ("hlle bm without roe speed", "double bm = fmin(fmin(lm, WL[1] - aL), 0.0);", "double bm = fmin(WL[1] - aL, 0.0);"),
+ ("roe plain mean velocity", "double ut = (sl * WL[1] + sr * WR[1]) / (sl + sr);", "double ut = 0.5 * (WL[1] + WR[1]);"),
+ ("eta ignored", "double am = fmax(fabs(lm), eta_h), a0 = fmax(fabs(l0), eta_h)", "double am = fabs(lm), a0 = fmax(fabs(l0), eta_h)"),
  ("own rho for slopes", "  double rho = w0[0];\n  double a = sound_speed(w0, gamma);", "  double rho = wm[0];\n  double a = sound_speed(wm, gamma);"),
 ]
 
-PINS = ["tests/test_oracle_riemann.py", "tests/test_oracle_ppmc.py", "tests/test_oracle_step.py"]
+PINS = ["tests/test_oracle_riemann.py", "tests/test_oracle_roe.py", "tests/test_oracle_ppmc.py",
+        "tests/test_oracle_step.py"]
 
 
 @pytest.mark.slow
