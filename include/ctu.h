@@ -57,6 +57,12 @@ typedef enum {
 typedef enum { CTU_BC_PERIODIC = 0, CTU_BC_OUTFLOW = 1, CTU_BC_REFLECT = 2 } ctu_bc;
 typedef enum { CTU_FP64 = 0, CTU_FP32 = 1 } ctu_prec;
 
+/* Riemann solvers, Sec. 2.3.  Exact: Newton iteration for the star pressure (App. B.1).
+ * Roe: the linearized solver of App. B.2, which substitutes the HLLE flux where an
+ * intermediate state would have a non-positive density or pressure (counted in
+ * ctu_check counters[3]). */
+typedef enum { CTU_RIEMANN_EXACT = 0, CTU_RIEMANN_ROE = 1 } ctu_riemann;
+
 /* Device error-word bits reported by ctu_check. */
 enum {
   CTU_FLAG_NONFINITE = 1u << 0, /* an updated conserved value is NaN or infinite */
@@ -84,6 +90,7 @@ typedef struct {
                               n cells of an axis are split into round(n/target) equal
                               segments.  Changes the launch shape; results change only by
                               rounding (last-bit differences in a segment's first trace). */
+  int32_t riemann;         /* ctu_riemann; both stages use the same solver */
 } ctu_config;
 
 typedef struct ctu_grid ctu_grid;
@@ -146,7 +153,8 @@ ctu_status ctu_advance(ctu_grid* g, int32_t nsteps, double t_end);
 ctu_status ctu_totals(ctu_grid* g, double out[5]);
 
 /* Read and clear the device error word and counters: counters[0] pressure-floor hits,
- * [1] Newton solves that hit the cap, [2] non-physical updated cells, [3] reserved.
+ * [1] Newton solves that hit the cap, [2] non-physical updated cells, [3] Roe solves that
+ * substituted the HLLE flux (informational; sets no flag).
  * Returns CTU_ENONPHYS if non-physical bits are set, CTU_ENOCONV if only the Newton cap
  * was hit, else CTU_OK.  Syncs. */
 ctu_status ctu_check(ctu_grid* g, uint32_t* flags, uint64_t counters[4]);

@@ -41,6 +41,7 @@ struct GridParams {
   double inv_gm1;       // 1 / (gamma - 1)
   int seg[3];           // faces per thread segment of the marching sweeps along y and z
   int xrows;            // x-rows of real cells per wavefront in the fused x update
+  int riemann;          // 0 exact, 1 Roe with the HLLE failsafe
 };
 
 // Device scalars of one grid (in the workspace).
@@ -133,7 +134,8 @@ __device__ __forceinline__ T ppm_IR(T beta, T dw, T w6) {
 struct RiemannCounts {
   unsigned floors;
   unsigned caps;
-  int iters;  // Newton iterations of the last solve, 0 when it hit the cap
+  int iters;      // Newton iterations of the last solve, 0 when it hit the cap
+  unsigned hlle;  // Roe solves that substituted the HLLE flux
 };
 
 // ======================================================================================
@@ -591,6 +593,180 @@ __device__ __forceinline__ void exact_flux_prim(const Prim<T>& L, const Prim<T>&
   F[2] = mu * vt;
   F[3] = mu * wt;
   F[4] = (E + pres) * u;
+}
+
+// ======================================================================================
+// Roe solver with the HLLE failsafe (App. B.2), in rotated components (slot 1 normal).
+// W holds the primitives with the pressure floor applied, U the conserved state whose
+// total energy enters the fluxes; a, irho as in Prim.  eta_h >= 0 is the H-correction
+// floor on |lambda| (App. C; 0 leaves the eigenvalues unchanged).
+// ======================================================================================
+template <typename T>
+__device__ __forceinline__ void roe_core(const Prim<T>& L, const Prim<T>& R, const T UL[5],
+                                         const T UR[5], const GridParams& P, T eta_h, T F[5],
+                                         RiemannCounts& cnt) {
+  const T gm1 = T(P.gm1);
+  T FL[5], FR[5];
+  {
+    const T ml = L.w[0] * L.w[1], mr = R.w[0] * R.w[1];
+    FL[0] = ml;
+    FL[1] = ml * L.w[1] + L.w[4];
+    FL[2] = ml * L.w[2];
+    FL[3] = ml * L.w[3];
+    FL[4] = (UL[4] + L.w[4]) * L.w[1];
+    FR[0] = mr;
+    FR[1] = mr * R.w[1] + R.w[4];
+    FR[2] = mr * R.w[2];
+    FR[3] = mr * R.w[3];
+    FR[4] = (UR[4] + R.w[4]) * R.w[1];
+  }
+  // Roe averages, weights sqrt(rho)
+  T sl, isl, sr, isr;
+  sqrt_rsqrt_nr(L.w[0], sl, isl);
+  sqrt_rsqrt_nr(R.w[0], sr, isr);
+  const T isum = rcp_nr(sl + sr);
+  const T HL = (UL[4] + L.w[4]) * L.irho, HR = (UR[4] + R.w[4]) * R.irho;
+  const T ut = (sl * L.w[1] + sr * R.w[1]) * isum;
+  const T vt = (sl * L.w[2] + sr * R.w[2]) * isum;
+  const T wt = (sl * L.w[3] + sr * R.w[3]) * isum;
+  const T Ht = (sl * HL + sr * HR) * isum;
+  const T V2 = ut * ut + vt * vt + wt * wt;
+  T at, iat;
+  sqrt_rsqrt_nr(gm1 * (Ht - T(0.5) * V2), at, iat);
+  const T lm = ut - at, lp = ut + at;
+  if (lm >= T(0)) {  // supersonic to the right
+#pragma unroll
+    for (int q = 0; q < 5; ++q) F[q] = FL[q];
+    return;
+  }
+  if (lp <= T(0)) {  // supersonic to the left
+#pragma unroll
+    for (int q = 0; q < 5; ++q) F[q] = FR[q];
+    return;
+  }
+  T dU[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) dU[q] = UR[q] - UL[q];
+  const T ia2 = iat * iat;
+  const T Na = T(0.5) * ia2;
+  const T gv = gm1 * (vt * dU[2] + wt * dU[3]);  // shared transverse terms
+  const T gE = gm1 * dU[4];
+  const T xi0 = Na * (dU[0] * (T(0.5) * gm1 * V2 + ut * at) - dU[1] * (gm1 * ut + at) - gv + gE);
+  const T xi1 = dU[2] - dU[0] * vt;
+  const T xi2 = dU[3] - dU[0] * wt;
+  const T xi3 = dU[0] * (T(1) - Na * gm1 * V2) + ia2 * (gm1 * ut * dU[1] + gv - gE);
+  const T xi4 = Na * (dU[0] * (T(0.5) * gm1 * V2 - ut * at) - dU[1] * (gm1 * ut - at) - gv + gE);
+  const T am = fmax(fabs(lm), eta_h), a0 = fmax(fabs(ut), eta_h), ap = fmax(fabs(lp), eta_h);
+  const T C0 = xi0 * am, C1 = xi1 * a0, C2 = xi2 * a0, C3 = xi3 * a0, C4 = xi4 * ap;
+  const T uat = ut * at;
+  // intermediate states: crossing the left acoustic wave, then the contact and shear waves
+  T Um[5];
+  Um[0] = UL[0] + xi0;
+  Um[1] = UL[1] + xi0 * lm;
+  Um[2] = UL[2] + xi0 * vt;
+  Um[3] = UL[3] + xi0 * wt;
+  Um[4] = UL[4] + xi0 * (Ht - uat);
+  // positive pressure <=> 2 E rho - |m|^2 > 0 once rho > 0
+  bool bad = !(Um[0] > T(0)) ||
+             !(T(2) * Um[4] * Um[0] - (Um[1] * Um[1] + Um[2] * Um[2] + Um[3] * Um[3]) > T(0));
+  if (!bad) {
+    Um[0] += xi3;
+    Um[1] += xi3 * ut;
+    Um[2] += xi1 + xi3 * vt;
+    Um[3] += xi2 + xi3 * wt;
+    Um[4] += xi1 * vt + xi2 * wt + T(0.5) * xi3 * V2;
+    bad = !(Um[0] > T(0)) ||
+          !(T(2) * Um[4] * Um[0] - (Um[1] * Um[1] + Um[2] * Um[2] + Um[3] * Um[3]) > T(0));
+  }
+  if (!bad) {
+    const T s0 = C0 + C3 + C4;
+    const T s1 = C0 * lm + C3 * ut + C4 * lp;
+    const T s2 = (C0 + C3 + C4) * vt + C1;
+    const T s3 = (C0 + C3 + C4) * wt + C2;
+    const T s4 = C0 * (Ht - uat) + C1 * vt + C2 * wt + T(0.5) * C3 * V2 + C4 * (Ht + uat);
+    F[0] = T(0.5) * (FL[0] + FR[0] - s0);
+    F[1] = T(0.5) * (FL[1] + FR[1] - s1);
+    F[2] = T(0.5) * (FL[2] + FR[2] - s2);
+    F[3] = T(0.5) * (FL[3] + FR[3] - s3);
+    F[4] = T(0.5) * (FL[4] + FR[4] - s4);
+    return;
+  }
+  // HLLE: bounding speeds from the Roe eigenvalues and the input acoustic speeds
+  cnt.hlle += 1;
+  const T bm = fmin(fmin(lm, L.w[1] - L.a), T(0));
+  const T bp = fmax(fmax(lp, R.w[1] + R.a), T(0));
+  const T ratio = (bp + bm) * rcp_nr(bp - bm);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const T fl = FL[q] - bm * UL[q];
+    const T fr = FR[q] - bp * UR[q];
+    F[q] = T(0.5) * ((fl + fr) + (fl - fr) * ratio);
+  }
+}
+
+// Roe flux from rotated conserved states (second stage).
+template <typename T>
+__device__ __forceinline__ void roe_flux_u(const T UL[5], const T UR[5], const GridParams& P,
+                                           T eta_h, T F[5], RiemannCounts& cnt) {
+  const T pf = T(P.p_floor);
+  Prim<T> L, R;
+  make_prim(UL, T(P.gamma), T(P.gm1), pf, L);
+  make_prim(UR, T(P.gamma), T(P.gm1), pf, R);
+  cnt.floors += (L.w[4] == pf) + (R.w[4] == pf);
+  roe_core(L, R, UL, UR, P, eta_h, F, cnt);
+}
+
+// Roe flux from rotated primitive states (the traced states of the first stage), with the
+// pressure floor as in make_prim and E = p/(g-1) + rho V^2/2.
+template <typename T>
+__device__ __forceinline__ void roe_flux_w(const T WL[5], const T WR[5], const GridParams& P,
+                                           T eta_h, T F[5], RiemannCounts& cnt) {
+  const T pf = T(P.p_floor);
+  const T g = T(P.gamma), igm1 = T(P.inv_gm1);
+  Prim<T> L, R;
+  T UL[5], UR[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    L.w[q] = WL[q];
+    R.w[q] = WR[q];
+  }
+  cnt.floors += (!(L.w[4] >= pf)) + (!(R.w[4] >= pf));
+  if (!(L.w[4] >= pf)) L.w[4] = pf;
+  if (!(R.w[4] >= pf)) R.w[4] = pf;
+  L.irho = rcp_nr(L.w[0]);
+  R.irho = rcp_nr(R.w[0]);
+  sqrt_rsqrt_nr(g * L.w[4] * L.irho, L.a, L.ia);
+  sqrt_rsqrt_nr(g * R.w[4] * R.irho, R.a, R.ia);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    UL[q] = q == 0 ? L.w[0] : L.w[0] * L.w[q];
+    UR[q] = q == 0 ? R.w[0] : R.w[0] * R.w[q];
+  }
+  UL[4] = L.w[4] * igm1 + T(0.5) * L.w[0] * (L.w[1] * L.w[1] + L.w[2] * L.w[2] + L.w[3] * L.w[3]);
+  UR[4] = R.w[4] * igm1 + T(0.5) * R.w[0] * (R.w[1] * R.w[1] + R.w[2] * R.w[2] + R.w[3] * R.w[3]);
+  roe_core(L, R, UL, UR, P, eta_h, F, cnt);
+}
+
+// Solver class of the sweep kernels: the exact solver specialized for its gas class K (0, 3
+// or 5), or the Roe solver (kRoe).
+constexpr int kRoe = 1;
+
+template <typename T, int K>
+__device__ __forceinline__ void face_flux_w(const T WL[5], const T WR[5], const GridParams& P,
+                                            T F[5], RiemannCounts& cnt) {
+  if constexpr (K == kRoe)
+    roe_flux_w<T>(WL, WR, P, T(0), F, cnt);
+  else
+    exact_flux_w<T, K>(WL, WR, P, F, cnt);
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void face_flux_u(const T UL[5], const T UR[5], const GridParams& P,
+                                            T F[5], RiemannCounts& cnt) {
+  if constexpr (K == kRoe)
+    roe_flux_u<T>(UL, UR, P, T(0), F, cnt);
+  else
+    exact_flux_fast<T, K>(UL, UR, P, F, cnt);
 }
 
 }  // namespace ctu

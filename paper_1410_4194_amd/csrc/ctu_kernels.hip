@@ -331,6 +331,7 @@ static hipError_t sweeps(const PlanView& v, int stage, hipStream_t stream, Profi
   switch (v.gclass) {
     case 3: return launch_sweeps<T, 3>(v, stage, stream, prof);
     case 5: return launch_sweeps<T, 5>(v, stage, stream, prof);
+    case kRoe: return launch_sweeps<T, kRoe>(v, stage, stream, prof);
     default: return launch_sweeps<T, 0>(v, stage, stream, prof);
   }
 }

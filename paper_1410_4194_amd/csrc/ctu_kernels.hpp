@@ -112,11 +112,14 @@ struct PlanView {
   int ngrids;
   const int* h_start;  // same layout as d_start
   int prec;            // 0 = double, 1 = float
-  int gclass;          // gas class of the exact solver: 3 (gamma 5/3), 5 (gamma 7/5), 0 other
+  int gclass;          // solver class: exact with gas class 3 (gamma 5/3), 5 (gamma 7/5) or
+                       // 0 (other), or kRoe
 };
 
-// Gas class of a grid: K when 2/(gamma-1) = K and 2 gamma/(gamma-1) = K + 2 for K in {3, 5}.
+// Solver class of a grid: kRoe for the Roe solver; for the exact solver its gas class, K
+// when 2/(gamma-1) = K and 2 gamma/(gamma-1) = K + 2 for K in {3, 5}, else 0.
 inline int gas_class(const GridParams& P) {
+  if (P.riemann == 1) return kRoe;
   return ((P.fan_int_exp == 3 || P.fan_int_exp == 5) && P.root_m == P.fan_int_exp + 2)
              ? P.fan_int_exp
              : 0;
@@ -127,6 +130,8 @@ inline int gas_class(const GridParams& P) {
 template <typename T, int K>
 hipError_t launch_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof);
 template <> hipError_t launch_sweeps<double, 0>(const PlanView&, int, hipStream_t, Profiler*);
+template <> hipError_t launch_sweeps<double, kRoe>(const PlanView&, int, hipStream_t, Profiler*);
+template <> hipError_t launch_sweeps<float, kRoe>(const PlanView&, int, hipStream_t, Profiler*);
 template <> hipError_t launch_sweeps<double, 3>(const PlanView&, int, hipStream_t, Profiler*);
 template <> hipError_t launch_sweeps<double, 5>(const PlanView&, int, hipStream_t, Profiler*);
 template <> hipError_t launch_sweeps<float, 0>(const PlanView&, int, hipStream_t, Profiler*);

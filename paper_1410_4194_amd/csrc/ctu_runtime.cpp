@@ -78,6 +78,8 @@ ctu_status validate(const ctu_config* c) {
   if (c->newton_max_iter < 1) return fail(CTU_EINVAL, "newton_max_iter must be >= 1");
   if (!(c->p_floor > 0.0)) return fail(CTU_EINVAL, "p_floor must be > 0");
   if (c->prec != CTU_FP64 && c->prec != CTU_FP32) return fail(CTU_EINVAL, "unknown precision");
+  if (c->riemann != CTU_RIEMANN_EXACT && c->riemann != CTU_RIEMANN_ROE)
+    return fail(CTU_EINVAL, "unknown Riemann solver");
   for (int a = 0; a < 2; ++a)
     if (c->march_seg[a] < 0 || c->march_seg[a] > 4096)
       return fail(CTU_EINVAL, "march_seg must lie in [0, 4096]");
@@ -129,6 +131,7 @@ GridParams make_params(const ctu_config& c) {
   P.root_m = (std::fabs(m - mr) < 1e-12 && mr >= 2.0 && mr <= 16.0) ? (int)mr : 0;
   P.inv_root_m = (g - 1.0) / (2.0 * g);
   P.inv_gm1 = 1.0 / (g - 1.0);
+  P.riemann = c.riemann;
   // march segments: round(n/target) equal segments of the n cells of the axis
   P.seg[0] = 0;
   for (int a = 1; a < 3; ++a) {
@@ -323,6 +326,8 @@ ctu_status ctu_grid_destroy(ctu_grid* g) {
 ctu_status ctu_profile_enable(ctu_grid* g, int32_t enable) {
   if (!g) return fail(CTU_EINVAL, "null grid");
   if (enable & ~(CTU_PROFILE_TIMING | CTU_PROFILE_NEWTON)) return fail(CTU_EINVAL, "unknown mode");
+  if ((enable & CTU_PROFILE_NEWTON) && g->P.riemann != CTU_RIEMANN_EXACT)
+    return fail(CTU_EINVAL, "the Newton histogram needs the exact solver");
   if (enable) {
     if (!g->prof) g->prof = new ctu::Profiler();
     HIP_TRY(hipStreamSynchronize(g->stream), "profile sync");
@@ -592,7 +597,7 @@ struct ctu_batch {
       return ctu::PlanView{d_desc, d_start, (int)descs.size(), start.data(), prec, gclass};
     }
   };
-  static constexpr int kGroups = 6;  // {FP64, FP32} x gas class {0, 3, 5}
+  static constexpr int kGroups = 8;  // {FP64, FP32} x solver class {0, 3, 5, Roe}
   std::vector<Slot> slots;
   int32_t flags = 0;
   hipStream_t caller = nullptr;  // the caller's stream: batch work is ordered after its work
@@ -629,8 +634,9 @@ size_t batch_bytes(int32_t max_slots) {
 }
 
 int group_of(const ctu_grid* g) {
+  // group index matches kClass = {0, 3, 5, kRoe} within each precision
   const int c = ctu::gas_class(g->P);
-  return (g->cfg.prec == CTU_FP32 ? 3 : 0) + (c == 3 ? 1 : (c == 5 ? 2 : 0));
+  return (g->cfg.prec == CTU_FP32 ? 4 : 0) + (c == 3 ? 1 : c == 5 ? 2 : c == ctu::kRoe ? 3 : 0);
 }
 
 void drop_graph(ctu_batch* b) {
@@ -734,10 +740,10 @@ ctu_status ctu_batch_create(int32_t max_slots, void* d_work, size_t work_bytes, 
   b->flags = flags;
   b->caller = reinterpret_cast<hipStream_t>(hip_stream);
   char* w = reinterpret_cast<char*>(d_work);
-  static const int kClass[3] = {0, 3, 5};
+  static const int kClass[4] = {0, 3, 5, ctu::kRoe};
   for (int p = 0; p < ctu_batch::kGroups; ++p) {
-    b->groups[p].prec = p / 3;
-    b->groups[p].gclass = kClass[p % 3];
+    b->groups[p].prec = p / 4;
+    b->groups[p].gclass = kClass[p % 4];
     b->groups[p].d_desc = reinterpret_cast<ctu::GridDesc*>(w);
     b->groups[p].d_start =
         reinterpret_cast<int*>(w + round256(sizeof(ctu::GridDesc) * (size_t)max_slots));

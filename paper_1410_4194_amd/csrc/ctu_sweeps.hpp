@@ -83,6 +83,7 @@ __device__ __forceinline__ void flush_counts(const RiemannCounts& cnt, DevScalar
     atomicAdd(&s->counters[1], (unsigned long long)cnt.caps);
     atomicOr(&s->flags, 8u);
   }
+  if (cnt.hlle) atomicAdd(&s->counters[3], (unsigned long long)cnt.hlle);
 }
 
 // Newton-iteration histogram of the solves of one wavefront (instrumented sweeps only):
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
     const bool dupface = c == f1 && f1 < nd;
     RiemannCounts dup{0u, 0u, 0};
     if (STAGE == 1) {
-      exact_flux_w<T, K>(prevR, WL, P, F, dupface ? dup : cnt);
+      face_flux_w<T, K>(prevR, WL, P, F, dupface ? dup : cnt);
 #pragma unroll
       for (int q = 0; q < 5; ++q) UR[q] = WR[q];
     } else {
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
         UL[q] += dT[q];
         UR[q] += dT[q];
       }
-      exact_flux_fast<T, K>(prevR, UL, P, F, dupface ? dup : cnt);
+      face_flux_u<T, K>(prevR, UL, P, F, dupface ? dup : cnt);
     }
     if (HIST) hist.add(dupface ? dup.iters : cnt.iters, !dupface);
     // keep the LDS read of the previous flux below the solve (hoisted above it, the five
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
     // lane 61's face is solved again as the next wavefront's first face: count it there
     const bool counted = lane <= 60 || task % nw == nw - 1;
     RiemannCounts cnt{0u, 0u, 0};
-    exact_flux_w<T, K>(prevR, WL, P, F, cnt);
+    face_flux_w<T, K>(prevR, WL, P, F, cnt);
     if (counted) {
       flush_counts(cnt, s);
       iters = cnt.iters;
@@ -442,7 +443,7 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
         // lane 61's face is solved again as the next chunk's first face: count it there
         const bool counted = lane <= 60 || cw + XU >= plen - NG;
         RiemannCounts dup{0u, 0u, 0};
-        exact_flux_fast<T, K>(prevR, UL, P, F, counted ? cnt : dup);
+        face_flux_u<T, K>(prevR, UL, P, F, counted ? cnt : dup);
         if (counted) iters = cnt.iters;
       }
       // the histogram keeps its wave counts in vector registers: every lane takes the add

@@ -24,6 +24,7 @@ LIB_PATH = os.environ.get("CTU_LIBRARY") or os.path.join(_HERE, "libctu.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, ENOCONV, EAGAIN = 0, -1, -2, -3, -4, -5, -6
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
+RIEMANN_EXACT, RIEMANN_ROE = 0, 1
 FP64, FP32 = 0, 1
 FLAG_NONFINITE, FLAG_DENSITY, FLAG_PFLOOR, FLAG_NEWTON_CAP = 1, 2, 4, 8
 TICKET_QUEUED, TICKET_RUNNING, TICKET_DONE, TICKET_FAILED, TICKET_UNKNOWN = 0, 1, 2, 3, -1
@@ -48,7 +49,7 @@ class Config(C.Structure):
                 ("gamma", C.c_double), ("bc", C.c_int32 * 6), ("prec", C.c_int32),
                 ("cfl", C.c_double), ("newton_tol", C.c_double),
                 ("newton_max_iter", C.c_int32), ("p_floor", C.c_double),
-                ("march_seg", C.c_int32 * 2)]
+                ("march_seg", C.c_int32 * 2), ("riemann", C.c_int32)]
 
 
 class GridInfo(C.Structure):
@@ -115,7 +116,8 @@ def _check(status: int, allow=()) -> int:
 
 
 def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64, cfl=0.3,
-                newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20, march_seg=None) -> Config:
+                newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20, march_seg=None,
+                riemann=0) -> Config:
     """Grid configuration.  march_seg: target faces per thread of the y and z sweeps; None
     takes the autotuned table (tiles.json beside this module) when it exists, else the
     library default."""
@@ -135,6 +137,7 @@ def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64,
         from .autotune import lookup
         march_seg = lookup(int(prec), int(ny), int(nz))
     c.march_seg[0], c.march_seg[1] = int(march_seg[0]), int(march_seg[1])
+    c.riemann = int(riemann)
     return c
 
 

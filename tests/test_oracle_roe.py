@@ -203,3 +203,59 @@ def test_supersonic_shortcuts():
     mr = (wl[0], -wl[1], wl[2], wl[3], wl[4])
     F2, used2, _ = O.roe_flux(cons(ml, g), cons(mr, g), g)
     assert _rel(F2, phys_flux(mr, g)) <= 4e-16
+
+
+# --- whole CTU step with the Roe solver ----------------------------------------------------
+
+from tests.common import oracle_config, oracle_state, run_oracle  # noqa: E402
+
+
+def test_roe_step_keeps_uniform_flow():
+    wl = WL.random_state(9, 7, 6, seed=3)
+    wl.W[:] = np.array([1.3, 0.4, -0.2, 0.7, 2.0])[:, None, None, None]
+    cfg = oracle_config(wl, riemann=O.RIEMANN_ROE)
+    u = oracle_state(wl, cfg)
+    before = O.real(cfg, u).copy()
+    O.step(cfg, u, 0.5 * O.compute_dt(cfg, u))
+    assert np.array_equal(O.real(cfg, u), before)
+
+
+def test_roe_step_conserves_on_periodic_grid():
+    wl = WL.random_state(11, 9, 8, seed=4)
+    cfg = oracle_config(wl, riemann=O.RIEMANN_ROE)
+    u = oracle_state(wl, cfg)
+    r0 = O.real(cfg, u).reshape(5, -1).copy()
+    for _ in range(3):
+        O.step(cfg, u, O.compute_dt(cfg, u))
+    r1 = O.real(cfg, u).reshape(5, -1)
+    for f in range(5):
+        assert abs(math.fsum(r1[f]) - math.fsum(r0[f])) <= 1e-13 * math.fsum(np.abs(r0[f]))
+
+
+def test_roe_sod_matches_exact_solution():
+    """Sod to t = 0.2 with the Roe solver: mean density error against the exact solution is
+    as small as with the exact solver (the solvers differ only inside the waves)."""
+    wl = WL.sod(128, 1, 1)
+    cfg = oracle_config(wl, riemann=O.RIEMANN_ROE)
+    cfg, u, t, n = run_oracle(wl, t_end=0.2, cfg=cfg)
+    x = (np.arange(128) + 0.5) / 128
+    ex = O.exact_solution((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4, (x - 0.5) / 0.2)
+    r = O.real(cfg, u)[:, 0, 0, :]
+    assert np.mean(np.abs(r[0] - ex[0])) < 0.004
+
+
+def test_roe_strong_rarefaction_stays_physical():
+    """The 1-2-3 problem to t = 0.15: HLLE keeps density and pressure positive where the
+    linearization alone would not."""
+    wl = WL.strong_rarefaction(128, 1, 1)
+    cfg = oracle_config(wl, riemann=O.RIEMANN_ROE)
+    u = oracle_state(wl, cfg)
+    t, hlle = 0.0, 0
+    while t < 0.15 * (1 - 1e-14):
+        dt = min(O.compute_dt(cfg, u), 0.15 - t)
+        hlle += O.step(cfg, u, dt).hlle
+        t += dt
+    r = O.real(cfg, u)[:, 0, 0, :]
+    p = 0.4 * (r[4] - 0.5 * r[1] ** 2 / r[0])
+    assert np.all(r[0] > 0) and np.all(p > 0)
+    assert hlle > 0
