@@ -67,6 +67,11 @@ def _load():
     lib.ref_riemann_wave_speeds.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
     lib.ref_riemann_flux.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_int, C.c_double,
                                      _dp, C.POINTER(_Stats)]
+    lib.ref_ppmp.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
+    lib.ref_ppmp_flattening.argtypes = [_dp]
+    lib.ref_ppmp_flattening.restype = C.c_double
+    lib.ref_ppmp_steepening.argtypes = [_dp, C.c_double, C.c_double]
+    lib.ref_ppmp_steepening.restype = C.c_double
     lib.ref_ghost_width.argtypes = [C.POINTER(_Config)]
     lib.ref_ghost_width.restype = C.c_int
     lib.ref_roe_flux.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, _dp,
@@ -256,6 +261,24 @@ def riemann_flux(UL, UR, gamma: float, tol: float = 1e-6, max_iter: int = 50,
     lib.ref_riemann_flux(_ptr(ul), _ptr(ur), gamma, tol, max_iter, p_floor, _ptr(F),
                          C.byref(st))
     return F, _stats_out(st)
+
+
+def ppmp(w7x5, dtodx: float, dx: float, gamma: float):
+    """PPMP traced face states of the centre cell of 7 rotated primitive states; returns
+    (WsL, WsR, WL_mono, WR_mono)."""
+    lib = _load()
+    w = _vec(w7x5, 35)
+    L, R, LR = np.zeros(5), np.zeros(5), np.zeros(10)
+    lib.ref_ppmp(_ptr(w), dtodx, dx, gamma, _ptr(L), _ptr(R), _ptr(LR))
+    return L, R, LR[:5].copy(), LR[5:].copy()
+
+
+def ppmp_coefficients(w7x5, gamma: float, dx: float):
+    """(flattening F, steepening eta) of the centre cell of 7 rotated primitive states."""
+    lib = _load()
+    w = _vec(w7x5, 35)
+    return (float(lib.ref_ppmp_flattening(_ptr(w))),
+            float(lib.ref_ppmp_steepening(_ptr(w), gamma, dx)))
 
 
 def roe_flux(UL, UR, gamma: float, p_floor: float = 1e-20, eta_h: float = 0.0):

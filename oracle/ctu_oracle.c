@@ -1,13 +1,17 @@
 /*
- * ctu_oracle.c -- plain serial FP64 oracle for one CTU + PPMC + exact-Riemann step.
+ * ctu_oracle.c -- plain serial FP64 oracle for one CTU step (PPMC or PPMP reconstruction,
+ * exact or Roe/HLLE Riemann solver).
  *
  * TEST INFRASTRUCTURE ONLY (see ctu_oracle.h).  Written from the paper
  * (Schneider & Robertson 2015, arXiv:1410.4194):
  *   - CTU six-solve algorithm: Sec. 2.1, eqs. (simple_conserved_update),
  *     (transverse_evolution), (conserved_update); time step eqs. (calc_dt_1D/3D).
  *   - PPMC reconstruction: App. A.3, which reuses the PLMC slope step of App. A.2.
+ *   - PPMP reconstruction: App. A.4 (CW84 in the primitive variables), with the
+ *     van Leer limiter of App. A.1.
  *   - Exact Riemann solver: App. B.1 (Toro's solver, sampled at x/t = 0).
- *   - Boundary conditions: Sec. 3.1 (periodic and transmissive ghost copies).
+ *   - Roe solver with the HLLE failsafe: Sec. 2.3.2-2.3.3, App. B.2.
+ *   - Boundary conditions: Sec. 3.1 (periodic, transmissive and reflecting ghosts).
  * Readings of garbled or silent passages are marked [Qn] and listed in the design notes.
  */
 #include "ctu_oracle.h"
@@ -220,6 +224,158 @@ void ref_ppmc(const double w[5][5], double dtodx, double gamma, double WsL[5], d
     WsR[2] += D[2];
     WsR[3] += D[3];
   }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* PPMP (App. A.4).                                                                       */
+/* ------------------------------------------------------------------------------------ */
+
+/* Van Leer's monotonized central slope of one primitive variable (eqs. diffs and
+ * vanLeer_limiter of App. A.1), sgn(0) = +1. */
+static double vl_slope(double wm, double w0, double wp) {
+  return mc_limit(w0 - wm, wp - w0, 0.5 * (wp - wm));
+}
+
+/* Shock-flattening coefficient F~ of cell i from its neighbours i-2..i+2 (pressure p[0..4],
+ * normal velocity u[0..4], cell i in slot 2). */
+static double ppmp_flat_tilde(const double p[5], const double u[5]) {
+  double dp = p[3] - p[1];
+  /* not flattened when the relative pressure jump is small or the flow expands */
+  if (fabs(dp) / fmin(p[3], p[1]) < 1.0 / 3.0) return 0.0;
+  if (u[3] - u[1] > 0.0) return 0.0;
+  double S = dp / (p[4] - p[0]);
+  return fmax(0.0, fmin(1.0, 10.0 * (S - 0.75)));
+}
+
+double ref_ppmp_flattening(const double w[7][5]) {
+  double p[7], u[7];
+  for (int s = 0; s < 7; ++s) {
+    p[s] = w[s][4];
+    u[s] = w[s][1];
+  }
+  double Fm = ppmp_flat_tilde(p, u);         /* cell i-1: slots 0..4 */
+  double F0 = ppmp_flat_tilde(p + 1, u + 1); /* cell i */
+  double Fp = ppmp_flat_tilde(p + 2, u + 2); /* cell i+1 */
+  return (p[4] - p[2] < 0.0) ? fmax(F0, Fp) : fmax(F0, Fm);
+}
+
+/* Contact-steepening coefficient eta of cell i (slot 3) from the densities and pressures of
+ * i-2..i+2.  [Q31] The concavity test takes the sign that CW84 uses (second differences of
+ * opposite sign on the two sides of cell i, an inflection); the printed "same concavity"
+ * would never fire inside a smeared contact, against the behaviour the paper reports for
+ * PPMP in its blast-wave test. */
+double ref_ppmp_steepening(const double w[7][5], double gamma, double dx) {
+  double rho[5], pr[5]; /* cells i-2..i+2 */
+  for (int s = 0; s < 5; ++s) {
+    rho[s] = w[s + 1][0];
+    pr[s] = w[s + 1][4];
+  }
+  double drho = fabs(rho[3] - rho[1]) / fmin(rho[3], rho[1]);
+  if (!(drho > 0.01)) return 0.0;
+  double dprs = fabs(pr[3] - pr[1]) / fmin(pr[3], pr[1]);
+  if (!(dprs < 0.1 * gamma * drho)) return 0.0;
+  double dx2 = dx * dx;
+  double d2m = (rho[2] - 2.0 * rho[1] + rho[0]) / (6.0 * dx2); /* delta^2 rho_{i-1} */
+  double d2p = (rho[4] - 2.0 * rho[3] + rho[2]) / (6.0 * dx2); /* delta^2 rho_{i+1} */
+  if (!(d2m * d2p < 0.0)) return 0.0;
+  double eta_t = -(d2p - d2m) * dx2 / (rho[3] - rho[1]);
+  return fmax(0.0, fmin(20.0 * eta_t - 1.0, 1.0));
+}
+
+void ref_ppmp(const double w[7][5], double dtodx, double dx, double gamma, double WsL[5],
+              double WsR[5], double* WLR_out) {
+  const double* wm = w[2];
+  const double* wc = w[3];
+  const double* wp = w[4];
+
+  /* Step 1: parabolic interpolation with van Leer slopes of cells i-1, i, i+1. */
+  double dwm[5], dwc[5], dwp[5], WL[5], WR[5];
+  for (int q = 0; q < 5; ++q) {
+    dwm[q] = vl_slope(w[1][q], wm[q], wc[q]);
+    dwc[q] = vl_slope(wm[q], wc[q], wp[q]);
+    dwp[q] = vl_slope(wc[q], wp[q], w[5][q]);
+    WL[q] = 0.5 * (wc[q] + wm[q]) - (dwc[q] - dwm[q]) / 6.0;
+    WR[q] = 0.5 * (wp[q] + wc[q]) - (dwp[q] - dwc[q]) / 6.0;
+  }
+
+  /* Step 2: contact steepening of the density [Q7: rho_R uses rho_{i+1}]. */
+  double eta = ref_ppmp_steepening(w, gamma, dx);
+  WL[0] = WL[0] * (1.0 - eta) + (wm[0] + 0.5 * dwm[0]) * eta;
+  WR[0] = WR[0] * (1.0 - eta) + (wp[0] - 0.5 * dwp[0]) * eta;
+
+  /* Step 3: shock flattening of every variable. */
+  double F = ref_ppmp_flattening(w);
+  for (int q = 0; q < 5; ++q) {
+    WL[q] = F * wc[q] + (1.0 - F) * WL[q];
+    WR[q] = F * wc[q] + (1.0 - F) * WR[q];
+  }
+
+  /* Step 4: monotonicity [Q7: the third rule sets W_R]. */
+  for (int q = 0; q < 5; ++q) {
+    double c = wc[q];
+    if ((WR[q] - c) * (c - WL[q]) <= 0.0) {
+      WL[q] = c;
+      WR[q] = c;
+    }
+    if ((WR[q] - WL[q]) * (WL[q] - (3.0 * c - 2.0 * WR[q])) < 0.0) WL[q] = 3.0 * c - 2.0 * WR[q];
+    if ((WR[q] - WL[q]) * ((3.0 * c - 2.0 * WL[q]) - WR[q]) < 0.0) WR[q] = 3.0 * c - 2.0 * WL[q];
+  }
+  if (WLR_out) {
+    for (int q = 0; q < 5; ++q) {
+      WLR_out[q] = WL[q];
+      WLR_out[5 + q] = WR[q];
+    }
+  }
+
+  /* Step 5: integration under the parabola along each characteristic. */
+  double a = sound_speed(wc, gamma);
+  double lam[3] = {wc[1] - a, wc[1], wc[1] + a};
+  double al[3], be[3];
+  for (int k = 0; k < 3; ++k) {
+    al[k] = dtodx * fmin(lam[k], 0.0);
+    be[k] = dtodx * fmax(lam[k], 0.0);
+  }
+  double WLk[3][5], WRk[3][5]; /* k = 0 (m), 1 (0), 2 (p) */
+  for (int q = 0; q < 5; ++q) {
+    double dw = WR[q] - WL[q];
+    double w6 = 6.0 * (wc[q] - 0.5 * (WL[q] + WR[q]));
+    for (int k = 0; k < 3; ++k) {
+      WLk[k][q] = WL[q] - 0.5 * al[k] * (dw + w6 * (1.0 + (2.0 / 3.0) * al[k]));
+      WRk[k][q] = WR[q] - 0.5 * be[k] * (dw - w6 * (1.0 - (2.0 / 3.0) * be[k]));
+    }
+  }
+
+  /* Step 6: characteristic tracing (CW84).  Reference states: the fastest wave toward each
+   * face for rho, u, p; the advection wave for the transverse velocities. */
+  const double* mL = WLk[0];
+  const double* oL = WLk[1];
+  const double* pL = WLk[2];
+  const double* mR = WRk[0];
+  const double* oR = WRk[1];
+  const double* pR = WRk[2];
+  double aL = sqrt(gamma * mL[4] / mL[0]);
+  double aR = sqrt(gamma * pR[4] / pR[0]);
+  double CL = mL[0] * aL, CR = pR[0] * aR;
+  /* [Q7] pressure difference (p^m - p^p) and rho^p_R in the printed chi^p_L and chi^m_R */
+  double chipL = -(1.0 / (2.0 * CL)) * ((mL[1] - pL[1]) + (mL[4] - pL[4]) / CL);
+  double chimR = (1.0 / (2.0 * CR)) * ((pR[1] - mR[1]) - (pR[4] - mR[4]) / CR);
+  double chi0L = (mL[4] - oL[4]) / (CL * CL) + 1.0 / mL[0] - 1.0 / oL[0];
+  double chi0R = (pR[4] - oR[4]) / (CR * CR) + 1.0 / pR[0] - 1.0 / oR[0];
+  /* waves moving away from a face leave it unchanged */
+  if (lam[1] > 0.0) chi0L = 0.0;
+  if (lam[2] > 0.0) chipL = 0.0;
+  if (lam[0] < 0.0) chimR = 0.0;
+  if (lam[1] < 0.0) chi0R = 0.0;
+  WsL[0] = 1.0 / (1.0 / mL[0] - chi0L - chipL);
+  WsL[1] = mL[1] + CL * chipL;
+  WsL[2] = oL[2];
+  WsL[3] = oL[3];
+  WsL[4] = mL[4] + CL * CL * chipL;
+  WsR[0] = 1.0 / (1.0 / pR[0] - chimR - chi0R);
+  WsR[1] = pR[1] - CR * chimR;
+  WsR[2] = oR[2];
+  WsR[3] = oR[3];
+  WsR[4] = pR[4] + CR * CR * chimR;
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -663,7 +819,8 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
   for (int a = 0; a < 3; ++a)
     if (lo[a] < 0 || hi[a] > n[a] || lo[a] >= hi[a]) return -1;
   if (c->riemann != REF_RIEMANN_EXACT && c->riemann != REF_RIEMANN_ROE) return -1;
-  if (c->recon != REF_RECON_PPMC || c->h_correction) return -1;
+  if (c->recon != REF_RECON_PPMC && c->recon != REF_RECON_PPMP) return -1;
+  if (c->h_correction) return -1;
   double g = c->gamma;
 
   /* Boxes: R = cells to update; X = R grown by one cell (cells whose traced states and
@@ -710,15 +867,26 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
     for (int k = X.lo[2]; k < X.hi[2]; ++k)
       for (int j = X.lo[1]; j < X.hi[1]; ++j)
         for (int i = X.lo[0]; i < X.hi[0]; ++i) {
-          double w[5][5];
-          for (int s = -2; s <= 2; ++s) {
-            int pos[3] = {i, j, k};
-            pos[d] += s;
-            long pb = box_index(&P, pos[0], pos[1], pos[2]);
-            for (int q = 0; q < 5; ++q) w[s + 2][q] = W[rot[d][q]][pb];
-          }
           double wsl[5], wsr[5], usl[5], usr[5];
-          ref_ppmc(w, dtodx, g, wsl, wsr, NULL);
+          if (c->recon == REF_RECON_PPMP) {
+            double w[7][5];
+            for (int s = -3; s <= 3; ++s) {
+              int pos[3] = {i, j, k};
+              pos[d] += s;
+              long pb = box_index(&P, pos[0], pos[1], pos[2]);
+              for (int q = 0; q < 5; ++q) w[s + 3][q] = W[rot[d][q]][pb];
+            }
+            ref_ppmp(w, dtodx, dd[d], g, wsl, wsr, NULL);
+          } else {
+            double w[5][5];
+            for (int s = -2; s <= 2; ++s) {
+              int pos[3] = {i, j, k};
+              pos[d] += s;
+              long pb = box_index(&P, pos[0], pos[1], pos[2]);
+              for (int q = 0; q < 5; ++q) w[s + 2][q] = W[rot[d][q]][pb];
+            }
+            ref_ppmc(w, dtodx, g, wsl, wsr, NULL);
+          }
           /* Between stages the interface states are kept in conserved form (App. B.1). */
           ref_prim_to_cons(wsl, g, usl);
           ref_prim_to_cons(wsr, g, usr);

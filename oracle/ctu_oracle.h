@@ -87,6 +87,17 @@ void ref_plmc_slope(const double wm[5], const double w0[5], const double wp[5], 
 void ref_ppmc(const double w[5][5], double dtodx, double gamma, double WsL[5], double WsR[5],
               double* WLR_out);
 
+/* PPMP (App. A.4): given rotated primitives of cells c-3..c+3 (w[0]..w[6]), dtodx = dt/dx
+ * and the cell width dx along the sweep, return the traced face states W*_L, W*_R of cell
+ * c.  WLR_out as for ref_ppmc (after steepening, flattening and the monotonicity fixes). */
+void ref_ppmp(const double w[7][5], double dtodx, double dx, double gamma, double WsL[5],
+              double WsR[5], double* WLR_out);
+
+/* The two PPMP coefficients of cell c (slot 3 of w[7][5]): the shock-flattening F_c and the
+ * contact-steepening eta_c, both in [0, 1]. */
+double ref_ppmp_flattening(const double w[7][5]);
+double ref_ppmp_steepening(const double w[7][5], double gamma, double dx);
+
 /* Exact Riemann problem, star region: left (rho, u, p), right (rho, u, p).
  * Returns the Newton iteration count; *capped = 1 if the cap was reached. */
 int ref_riemann_star(const double WL[3], const double WR[3], double gamma, double tol,

@@ -52,11 +52,20 @@ M=[
  ("hlle bm without roe speed", "double bm = fmin(fmin(lm, WL[1] - aL), 0.0);", "double bm = fmin(WL[1] - aL, 0.0);"),
  ("roe plain mean velocity", "double ut = (sl * WL[1] + sr * WR[1]) / (sl + sr);", "double ut = 0.5 * (WL[1] + WR[1]);"),
  ("eta ignored", "double am = fmax(fabs(lm), eta_h), a0 = fmax(fabs(l0), eta_h)", "double am = fabs(lm), a0 = fmax(fabs(l0), eta_h)"),
+ ("ppmp printed concavity", "if (!(d2m * d2p < 0.0)) return 0.0;", "if (!(d2m * d2p > 0.0)) return 0.0;"),
+ ("ppmp printed rho_R steepening", "WR[0] = WR[0] * (1.0 - eta) + (wp[0] - 0.5 * dwp[0]) * eta;", "WR[0] = WR[0] * (1.0 - eta) + (wm[0] - 0.5 * dwp[0]) * eta;"),
+ ("ppmp printed chi^p_L", "((mL[1] - pL[1]) + (mL[4] - pL[4]) / CL)", "((mL[1] - pL[1]) - (mL[4] + pL[4]) / CL)"),
+ ("ppmp printed monotonicity 3", "< 0.0) WR[q] = 3.0 * c - 2.0 * WL[q];", "< 0.0) WL[q] = 3.0 * c - 2.0 * WL[q];"),
+ ("ppmp chi0 zeroing sign", "if (lam[1] > 0.0) chi0L = 0.0;", "if (lam[1] < 0.0) chi0L = 0.0;"),
+ ("ppmp flattening branch swap", "return (p[4] - p[2] < 0.0) ? fmax(F0, Fp) : fmax(F0, Fm);", "return (p[4] - p[2] < 0.0) ? fmax(F0, Fm) : fmax(F0, Fp);"),
+ ("ppmp transverse from reference", "WsL[2] = oL[2];", "WsL[2] = mL[2];"),
+ ("ppmp no expansion test", "if (u[3] - u[1] > 0.0) return 0.0;", "if (0) return 0.0;"),
+ ("ppmp chi^m_R sign", "WsR[1] = pR[1] - CR * chimR;", "WsR[1] = pR[1] + CR * chimR;"),
  ("own rho for slopes", "  double rho = w0[0];\n  double a = sound_speed(w0, gamma);", "  double rho = wm[0];\n  double a = sound_speed(wm, gamma);"),
 ]
 
 PINS = ["tests/test_oracle_riemann.py", "tests/test_oracle_roe.py", "tests/test_oracle_ppmc.py",
-        "tests/test_oracle_step.py"]
+        "tests/test_oracle_ppmp.py", "tests/test_oracle_step.py"]
 
 
 @pytest.mark.slow
