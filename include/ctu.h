@@ -18,12 +18,12 @@
  *   wait for that stream.
  * State layout: structure of arrays.  Field q in {0: rho, 1: rho*u, 2: rho*v, 3: rho*w,
  *   4: E} (total energy per volume, E = p/(gamma-1) + rho V^2/2, Sec. 2) occupies a
- *   contiguous array of the allocated box (nx+6)(ny+6)(nz+6), x fastest: real cell
- *   (i, j, k), 0 <= i < nx, is element (i+3) + NX*((j+3) + NY*(k+3)), NX = nx+6,
- *   NY = ny+6.  Consecutive fields start `field_stride` elements apart
- *   (ctu_grid_info).  Three ghost layers per side: the PPMC stencil needs two, the CTU
- *   transverse correction one more.  Element type is double (CTU_FP64) or float
- *   (CTU_FP32).
+ *   contiguous array of the allocated box (nx+2g)(ny+2g)(nz+2g), x fastest: real cell
+ *   (i, j, k), 0 <= i < nx, is element (i+g) + NX*((j+g) + NY*(k+g)), NX = nx+2g,
+ *   NY = ny+2g.  Consecutive fields start `field_stride` elements apart
+ *   (ctu_grid_info).  g ghost layers per side: g = 3 with PPMC (its stencil needs two, the
+ *   CTU transverse correction one more), g = 4 with PPMP (three-cell stencil).  Element
+ *   type is double (CTU_FP64) or float (CTU_FP32).
  * Host arrays for set/get are the real cells only, packed, x fastest, one array per field.
  * Errors found on the device (non-finite or non-positive density / energy in an updated
  *   state) are reported at the next syncing call of that grid as CTU_ENONPHYS.
@@ -53,7 +53,8 @@ typedef enum {
  * Outflow (transmissive): every ghost layer copies the edge real cell.
  * Reflect: a ghost copies its mirror-image real cell across the wall (ghost layer m outside
  * takes real layer m-1 inside) and negates the momentum normal to the wall; the axis needs
- * at least 3 real cells so that every mirror image is a real cell. */
+ * at least as many real cells as there are ghost layers (3, or 4 with PPMP) so that every
+ * mirror image is a real cell. */
 typedef enum { CTU_BC_PERIODIC = 0, CTU_BC_OUTFLOW = 1, CTU_BC_REFLECT = 2 } ctu_bc;
 typedef enum { CTU_FP64 = 0, CTU_FP32 = 1 } ctu_prec;
 
@@ -62,6 +63,12 @@ typedef enum { CTU_FP64 = 0, CTU_FP32 = 1 } ctu_prec;
  * intermediate state would have a non-positive density or pressure (counted in
  * ctu_check counters[3]). */
 typedef enum { CTU_RIEMANN_EXACT = 0, CTU_RIEMANN_ROE = 1 } ctu_riemann;
+
+/* Interface reconstructions, Sec. 2.2.  PPMC: piecewise parabolic with characteristic
+ * limiting and tracing (App. A.3), three ghost layers.  PPMP: piecewise parabolic in the
+ * primitive variables with contact steepening, shock flattening and CW84 tracing
+ * (App. A.4); its three-cell stencil needs four ghost layers. */
+typedef enum { CTU_RECON_PPMC = 0, CTU_RECON_PPMP = 1 } ctu_recon;
 
 /* Device error-word bits reported by ctu_check. */
 enum {
@@ -78,7 +85,7 @@ typedef struct {
   double dx, dy, dz;       /* cell widths, > 0 */
   double gamma;            /* ratio of specific heats, > 1 */
   int32_t bc[6];           /* x-, x+, y-, y+, z-, z+ : ctu_bc; periodic must pair;
-                              reflect needs >= 3 cells on its axis */
+                              reflect needs >= 3 cells (4 with PPMP) on its axis */
   int32_t prec;            /* ctu_prec.  CTU_FP32 stores state, reconstruction and fluxes
                               in float and keeps the Newton star-pressure solve in double */
   double cfl;              /* Courant number C0, 0 < cfl < 0.5 (six-solve CTU limit) */
@@ -91,17 +98,19 @@ typedef struct {
                               segments.  Changes the launch shape; results change only by
                               rounding (last-bit differences in a segment's first trace). */
   int32_t riemann;         /* ctu_riemann; both stages use the same solver */
+  int32_t recon;           /* ctu_recon */
 } ctu_config;
 
 typedef struct ctu_grid ctu_grid;
 typedef struct ctu_batch ctu_batch;
 
 typedef struct {
-  int64_t alloc_cells;   /* (nx+6)(ny+6)(nz+6) */
+  int64_t alloc_cells;   /* (nx+2g)(ny+2g)(nz+2g) */
   int64_t field_stride;  /* elements between consecutive fields of the state buffer */
   int32_t elem_bytes;    /* 8 (FP64) or 4 (FP32) */
   double t;              /* simulation time accumulated by step/advance (syncs) */
   int64_t steps;         /* steps taken (syncs) */
+  int32_t ghost;         /* g, ghost layers per side */
 } ctu_grid_info;
 
 /* Fill *cfg with the defaults: cfl 0.3, newton_tol 1e-6, newton_max_iter 50,

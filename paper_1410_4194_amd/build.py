@@ -12,11 +12,13 @@ REPO = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libctu.so")
 ARCH = os.environ.get("CTU_OFFLOAD_ARCH", "gfx950")
-# (source, object, extra defines): the sweep kernels are compiled once per storage type and
-# solver class (exact solver per gas class 0, 3, 5; Roe solver 1), in parallel
+# (source, object, extra defines): the sweep kernels are compiled once per storage type,
+# solver class (exact solver per gas class 0, 3, 5; Roe solver 1) and reconstruction (PPMC;
+# PPMP with the general exact solver and with Roe), in parallel
 UNITS = [("ctu_kernels.hip", "ctu_kernels.o", []), ("ctu_runtime.cpp", "ctu_runtime.o", [])] + [
-    ("ctu_sweeps.hip", f"ctu_sweeps_{t[0]}{k}.o", [f"-DCTU_SWEEP_T={t}", f"-DCTU_SWEEP_K={k}"])
-    for t in ("double", "float") for k in (0, 1, 3, 5)]
+    ("ctu_sweeps.hip", f"ctu_sweeps_{t[0]}{k}{'p' if r else ''}.o",
+     [f"-DCTU_SWEEP_T={t}", f"-DCTU_SWEEP_K={k}", f"-DCTU_SWEEP_R={r}"])
+    for t in ("double", "float") for k, r in ((0, 0), (1, 0), (3, 0), (5, 0), (0, 1), (1, 1))]
 
 
 def build(verbose: bool = False, jobs: int = 0) -> str:

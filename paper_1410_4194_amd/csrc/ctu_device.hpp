@@ -13,12 +13,11 @@
 
 namespace ctu {
 
-constexpr int NG = 3;  // ghost layers: PPMC stencil (2) + CTU transverse stencil (1)
-
 // Per-grid constants passed by value to every kernel.
 struct GridParams {
   int n[3];             // real cells per axis
-  int N[3];             // allocated cells per axis (n + 2*NG)
+  int ng;               // ghost layers per side: 3 (PPMC), 4 (PPMP)
+  int N[3];             // allocated cells per axis (n + 2 ng)
   long long stride;     // elements between consecutive fields
   double dx[3];         // cell widths
   double gamma;
@@ -42,6 +41,7 @@ struct GridParams {
   int seg[3];           // faces per thread segment of the marching sweeps along y and z
   int xrows;            // x-rows of real cells per wavefront in the fused x update
   int riemann;          // 0 exact, 1 Roe with the HLLE failsafe
+  int recon;            // 0 PPMC, 1 PPMP
 };
 
 // Device scalars of one grid (in the workspace).
@@ -60,7 +60,8 @@ struct DevScalars {
 };
 
 __device__ __forceinline__ long long cell_index(const GridParams& P, int i, int j, int k) {
-  return (long long)(i + NG) + (long long)P.N[0] * ((long long)(j + NG) + (long long)P.N[1] * (k + NG));
+  const int g = P.ng;
+  return (long long)(i + g) + (long long)P.N[0] * ((long long)(j + g) + (long long)P.N[1] * (k + g));
 }
 
 // ---- type-generic math -----------------------------------------------------------------
@@ -372,6 +373,114 @@ __device__ __forceinline__ void trace_fast(const Prim<T>& m, const Prim<T>& c, c
     WsR[2] += D[2];
     WsR[3] += D[3];
   }
+}
+
+// ---- PPMP (App. A.4) -------------------------------------------------------------------
+// Van Leer's monotonized central slopes of the primitive variables (App. A.1).
+template <typename T>
+__device__ __forceinline__ void slope_vl(const Prim<T>& m, const Prim<T>& c, const Prim<T>& p,
+                                         T dw[5]) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q)
+    dw[q] = mc_limit(c.w[q] - m.w[q], p.w[q] - c.w[q], T(0.5) * (p.w[q] - m.w[q]));
+}
+
+// Per-cell PPMP coefficients along the sweep axis: shock flattening and contact steepening.
+template <typename T>
+struct PpmpCoef {
+  T flat, eta;
+};
+
+// PPMP interface values of cell c from the primitives and van Leer slopes of c-1, c, c+1,
+// density steepening (eta) and flattening (flat), the monotonicity fixes, then the
+// integration under the parabola along each characteristic and the CW84 tracing with the
+// chi corrections.  Readings: steepened rho_R uses rho_{c+1}; the third monotonicity rule
+// sets W_R; chi^p_L takes (p^m - p^p)/C and chi^m_R takes rho^p_R.
+template <typename T>
+__device__ __forceinline__ void trace_ppmp(const Prim<T>& m, const Prim<T>& c, const Prim<T>& p,
+                                           const T dwm[5], const T dwc[5], const T dwp[5],
+                                           PpmpCoef<T> k, T gamma, T dtodx, T WsL[5],
+                                           T WsR[5]) {
+  const T sixth = T(1) / T(6);
+  const T a = c.a;
+  const T lm = c.w[1] - a, l0 = c.w[1], lp = c.w[1] + a;
+  const T am = dtodx * tmin(lm, T(0)), bm = dtodx * tmax(lm, T(0));
+  const T a0 = dtodx * tmin(l0, T(0)), b0 = dtodx * tmax(l0, T(0));
+  const T ap = dtodx * tmin(lp, T(0)), bp = dtodx * tmax(lp, T(0));
+  // time-evolved face values: L_m, L_0, L_p at the left face, R_m, R_0, R_p at the right
+  T Lm[5], L0[5], Lp[5], Rm[5], R0[5], Rp[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const T cq = c.w[q];
+    T wl = T(0.5) * (cq + m.w[q]) - (dwc[q] - dwm[q]) * sixth;
+    T wr = T(0.5) * (p.w[q] + cq) - (dwp[q] - dwc[q]) * sixth;
+    if (q == 0) {
+      wl = wl * (T(1) - k.eta) + (m.w[0] + T(0.5) * dwm[0]) * k.eta;
+      wr = wr * (T(1) - k.eta) + (p.w[0] - T(0.5) * dwp[0]) * k.eta;
+    }
+    wl = k.flat * cq + (T(1) - k.flat) * wl;
+    wr = k.flat * cq + (T(1) - k.flat) * wr;
+    if ((wr - cq) * (cq - wl) <= T(0)) {
+      wl = cq;
+      wr = cq;
+    }
+    if ((wr - wl) * (wl - (T(3) * cq - T(2) * wr)) < T(0)) wl = T(3) * cq - T(2) * wr;
+    if ((wr - wl) * ((T(3) * cq - T(2) * wl) - wr) < T(0)) wr = T(3) * cq - T(2) * wl;
+    const T dw = wr - wl;
+    const T w6 = T(6) * (cq - T(0.5) * (wl + wr));
+    Lm[q] = wl - ppm_IL(am, dw, w6);
+    L0[q] = wl - ppm_IL(a0, dw, w6);
+    Lp[q] = wl - ppm_IL(ap, dw, w6);
+    Rm[q] = wr - ppm_IR(bm, dw, w6);
+    R0[q] = wr - ppm_IR(b0, dw, w6);
+    Rp[q] = wr - ppm_IR(bp, dw, w6);
+  }
+  // reference states: the fastest wave toward each face (rho, u, p); the advection wave for
+  // the transverse velocities
+  T aL, iaL, aR, iaR;
+  const T irL = rcp_nr(Lm[0]), irR = rcp_nr(Rp[0]);
+  sqrt_rsqrt_nr(gamma * Lm[4] * irL, aL, iaL);
+  sqrt_rsqrt_nr(gamma * Rp[4] * irR, aR, iaR);
+  const T CL = Lm[0] * aL, iCL = irL * iaL;
+  const T CR = Rp[0] * aR, iCR = irR * iaR;
+  T chipL = -(T(0.5) * iCL) * ((Lm[1] - Lp[1]) + (Lm[4] - Lp[4]) * iCL);
+  T chimR = (T(0.5) * iCR) * ((Rp[1] - Rm[1]) - (Rp[4] - Rm[4]) * iCR);
+  T chi0L = (Lm[4] - L0[4]) * (iCL * iCL) + irL - rcp_nr(L0[0]);
+  T chi0R = (Rp[4] - R0[4]) * (iCR * iCR) + irR - rcp_nr(R0[0]);
+  if (l0 > T(0)) chi0L = T(0);
+  if (lp > T(0)) chipL = T(0);
+  if (lm < T(0)) chimR = T(0);
+  if (l0 < T(0)) chi0R = T(0);
+  WsL[0] = rcp_nr(irL - chi0L - chipL);
+  WsL[1] = Lm[1] + CL * chipL;
+  WsL[2] = L0[2];
+  WsL[3] = L0[3];
+  WsL[4] = Lm[4] + CL * CL * chipL;
+  WsR[0] = rcp_nr(irR - chimR - chi0R);
+  WsR[1] = Rp[1] - CR * chimR;
+  WsR[2] = R0[2];
+  WsR[3] = R0[3];
+  WsR[4] = Rp[4] + CR * CR * chimR;
+}
+
+// The reconstruction of the sweep kernels: R = 0 PPMC, R = 1 PPMP.
+template <int R, typename T>
+__device__ __forceinline__ void slope_sel(const Prim<T>& m, const Prim<T>& c, const Prim<T>& p,
+                                          T dw[5]) {
+  if constexpr (R == 1)
+    slope_vl(m, c, p, dw);
+  else
+    slope_fast(m, c, p, dw);
+}
+
+template <int R, typename T>
+__device__ __forceinline__ void trace_sel(const Prim<T>& m, const Prim<T>& c, const Prim<T>& p,
+                                          const T dwm[5], const T dwc[5], const T dwp[5],
+                                          PpmpCoef<T> k, T gamma, T dtodx, T WsL[5], T WsR[5]) {
+  if constexpr (R == 1)
+    trace_ppmp(m, c, p, dwm, dwc, dwp, k, gamma, dtodx, WsL, WsR);
+  else
+    trace_fast(m, c, p, dwm, dwc, dwp, dtodx, WsL, WsR);
 }
 
 // Pressure function and derivative at p for one side, given 1/p and the side's constants.

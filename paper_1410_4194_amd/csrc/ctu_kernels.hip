@@ -58,42 +58,43 @@ __global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab) {
   if (!(r.G->s->dt > 0.0)) return;
   GLOBAL T* __restrict__ u = (GLOBAL T*)r.G->u;
   const int n = P.n[AXIS];
+  const int ng = P.ng;  // ghost layers of this grid
   const long long tid = r.lb * blockDim.x + threadIdx.x;
   int i, j, k, layer;
   if (AXIS == 0) {
-    const long long total = 2LL * NG * P.N[1] * P.N[2];
+    const long long total = 2LL * ng * P.N[1] * P.N[2];
     if (tid >= total) return;
-    layer = (int)(tid % (2 * NG));
-    const long long q = tid / (2 * NG);
-    j = (int)(q % P.N[1]) - NG;
-    k = (int)(q / P.N[1]) - NG;
+    layer = (int)(tid % (2 * ng));
+    const long long q = tid / (2 * ng);
+    j = (int)(q % P.N[1]) - ng;
+    k = (int)(q / P.N[1]) - ng;
     i = 0;
   } else if (AXIS == 1) {
-    const long long total = 2LL * NG * P.N[0] * P.N[2];
+    const long long total = 2LL * ng * P.N[0] * P.N[2];
     if (tid >= total) return;
-    i = (int)(tid % P.N[0]) - NG;
+    i = (int)(tid % P.N[0]) - ng;
     const long long q = tid / P.N[0];
-    layer = (int)(q % (2 * NG));
-    k = (int)(q / (2 * NG)) - NG;
+    layer = (int)(q % (2 * ng));
+    k = (int)(q / (2 * ng)) - ng;
     j = 0;
   } else {
-    const long long total = 2LL * NG * P.N[0] * P.N[1];
+    const long long total = 2LL * ng * P.N[0] * P.N[1];
     if (tid >= total) return;
-    i = (int)(tid % P.N[0]) - NG;
+    i = (int)(tid % P.N[0]) - ng;
     const long long q = tid / P.N[0];
-    j = (int)(q % P.N[1]) - NG;
+    j = (int)(q % P.N[1]) - ng;
     layer = (int)(q / P.N[1]);
     k = 0;
   }
-  const int q = layer < NG ? layer - NG : n + (layer - NG);
-  const int bc = layer < NG ? r.G->bc[2 * AXIS] : r.G->bc[2 * AXIS + 1];
+  const int q = layer < ng ? layer - ng : n + (layer - ng);
+  const int bc = layer < ng ? r.G->bc[2 * AXIS] : r.G->bc[2 * AXIS + 1];
   int src;
   if (bc == 0) {          // periodic: one period away
     src = q % n;
     if (src < 0) src += n;
   } else if (bc == 1) {   // outflow: the edge cell
     src = q < 0 ? 0 : n - 1;
-  } else {                // reflect: the mirror image across the wall (n >= NG is validated)
+  } else {                // reflect: the mirror image across the wall (n >= ng is validated)
     src = q < 0 ? -1 - q : 2 * n - 1 - q;
   }
   const long long d = cell_index(P, AXIS == 0 ? q : i, AXIS == 1 ? q : j, AXIS == 2 ? q : k);
@@ -103,6 +104,76 @@ __global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab) {
   for (int f = 0; f < 5; ++f) {
     const T v = u[f * P.stride + sidx];
     u[f * P.stride + d] = (bc == 2 && f == 1 + AXIS) ? -v : v;
+  }
+}
+
+
+// ---- PPMP flattening and steepening coefficients (App. A.4) ----------------------------------
+// For each cell of the box [-1, n]^3 (every cell whose faces the sweeps trace) and each axis
+// d: the shock-flattening coefficient F_d and the contact-steepening coefficient eta_d, from
+// the densities, pressures and normal velocities of the cells within three along d.  Both
+// depend on u^n only, so one pass before the first stage serves both stages.  The steepening
+// test reads an inflection of the density (second differences of opposite sign on the two
+// sides of the cell, as in CW84); the 1/(6 dx^2) of the second differences cancels in
+// eta~ and does not change the sign test, so it is left out.
+template <typename T>
+__device__ __forceinline__ T flat_tilde(const T p[5], const T un[5]) {
+  const T dp = p[3] - p[1];
+  if (tfabs(dp) < tmin(p[3], p[1]) * (T(1) / T(3))) return T(0);  // weak jump
+  if (un[3] - un[1] > T(0)) return T(0);                         // expansion
+  const T S = dp / (p[4] - p[0]);
+  return tmax(T(0), tmin(T(1), T(10) * (S - T(0.75))));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ppmp_coef(LaunchTab tab) {
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  if (!(r.G->s->dt > 0.0)) return;
+  const long long e0 = P.n[0] + 2, e1 = P.n[1] + 2, e2 = P.n[2] + 2;
+  const long long tid = r.lb * blockDim.x + threadIdx.x;
+  if (tid >= e0 * e1 * e2) return;
+  const int i = (int)(tid % e0) - 1;
+  const int j = (int)((tid / e0) % e1) - 1;
+  const int k = (int)(tid / (e0 * e1)) - 1;
+  const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
+  GLOBAL T* __restrict__ coef = (GLOBAL T*)r.G->coef;
+  const long long c = cell_index(P, i, j, k);
+  const T gm1 = T(P.gm1), pf = T(P.p_floor), gamma = T(P.gamma);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const long long sd = d == 0 ? 1 : (d == 1 ? (long long)P.N[0] : (long long)P.N[0] * P.N[1]);
+    T rho[7], p[7], un[7];
+#pragma unroll
+    for (int s = 0; s < 7; ++s) {
+      const long long id = c + (long long)(s - 3) * sd;
+      const T r0 = u[id], m1 = u[P.stride + id], m2 = u[2 * P.stride + id];
+      const T m3 = u[3 * P.stride + id], E = u[4 * P.stride + id];
+      const T ir = rcp_nr(r0);
+      T pr = gm1 * (E - T(0.5) * (m1 * m1 + m2 * m2 + m3 * m3) * ir);
+      if (!(pr >= pf)) pr = pf;
+      rho[s] = r0;
+      p[s] = pr;
+      un[s] = (d == 0 ? m1 : (d == 1 ? m2 : m3)) * ir;
+    }
+    // flattening: the coefficients of cells c-1, c, c+1, then the neighbour on the side the
+    // pressure falls toward
+    const T Fm = flat_tilde(p, un), F0 = flat_tilde(p + 1, un + 1), Fp = flat_tilde(p + 2, un + 2);
+    const T flat = (p[4] - p[2] < T(0)) ? tmax(F0, Fp) : tmax(F0, Fm);
+    // steepening of the density (cells c-2..c+2 in slots 1..5)
+    T eta = T(0);
+    const T dr = tfabs(rho[4] - rho[2]) / tmin(rho[4], rho[2]);
+    const T dpr = tfabs(p[4] - p[2]) / tmin(p[4], p[2]);
+    if (dr > T(0.01) && dpr < T(0.1) * gamma * dr) {
+      const T d2m = rho[3] - T(2) * rho[2] + rho[1];
+      const T d2p = rho[5] - T(2) * rho[4] + rho[3];
+      if (d2m * d2p < T(0)) {
+        const T et = -(d2p - d2m) / (T(6) * (rho[4] - rho[2]));
+        eta = tmax(T(0), tmin(T(20) * et - T(1), T(1)));
+      }
+    }
+    coef[(2 * d) * P.stride + c] = flat;
+    coef[(2 * d + 1) * P.stride + c] = eta;
   }
 }
 
@@ -244,7 +315,7 @@ __global__ void k_prim_to_cons(const double* __restrict__ packed, T* __restrict_
 // ---- per-kernel timing ----------------------------------------------------------------------
 const char* kernel_class_name(int k) {
   static const char* names[K_NUM_CLASSES] = {
-      "bc_fill_x", "bc_fill_y", "bc_fill_z", "sweep1_x", "sweep1_y", "sweep1_z",
+      "bc_fill_x", "bc_fill_y", "bc_fill_z", "ppmp_coef", "sweep1_x", "sweep1_y", "sweep1_z",
       "sweep2_y", "sweep2_z", "sweep2_x_update", "dt_final"};
   return (k >= 0 && k < K_NUM_CLASSES) ? names[k] : "";
 }
@@ -312,9 +383,10 @@ long long pass_blocks(const GridParams& P, int pass) {
   const long long n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const long long N0 = P.N[0], N1 = P.N[1], N2 = P.N[2];
   switch (pass) {
-    case P_BC_X: return cdiv(2LL * NG * N1 * N2, kBlock);
-    case P_BC_Y: return cdiv(2LL * NG * N0 * N2, kBlock);
-    case P_BC_Z: return cdiv(2LL * NG * N0 * N1, kBlock);
+    case P_BC_X: return cdiv(2LL * P.ng * N1 * N2, kBlock);
+    case P_BC_Y: return cdiv(2LL * P.ng * N0 * N2, kBlock);
+    case P_BC_Z: return cdiv(2LL * P.ng * N0 * N1, kBlock);
+    case P_COEF: return P.recon == 1 ? cdiv((n0 + 2) * (n1 + 2) * (n2 + 2), kBlock) : 0;
     case P_S1_X: return cdiv(cdiv((n1 + 2) * N0, XW) * (n2 + 2), kBlock / 64);
     case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1, P.seg[1]);
     case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2, P.seg[2]);
@@ -328,11 +400,14 @@ long long pass_blocks(const GridParams& P, int pass) {
 
 template <typename T>
 static hipError_t sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
+  if (v.recon == 1)
+    return v.gclass == kRoe ? launch_sweeps<T, kRoe, 1>(v, stage, stream, prof)
+                            : launch_sweeps<T, 0, 1>(v, stage, stream, prof);
   switch (v.gclass) {
-    case 3: return launch_sweeps<T, 3>(v, stage, stream, prof);
-    case 5: return launch_sweeps<T, 5>(v, stage, stream, prof);
-    case kRoe: return launch_sweeps<T, kRoe>(v, stage, stream, prof);
-    default: return launch_sweeps<T, 0>(v, stage, stream, prof);
+    case 3: return launch_sweeps<T, 3, 0>(v, stage, stream, prof);
+    case 5: return launch_sweeps<T, 5, 0>(v, stage, stream, prof);
+    case kRoe: return launch_sweeps<T, kRoe, 0>(v, stage, stream, prof);
+    default: return launch_sweeps<T, 0, 0>(v, stage, stream, prof);
   }
 }
 
@@ -352,6 +427,9 @@ static hipError_t enqueue_step(const PlanView& v, bool device_dt, hipStream_t st
             hipLaunchKernelGGL((k_bc_fill<T, 1>), nblocks(P_BC_Y), B, 0, stream, tab(P_BC_Y)));
   CTU_TIMED(K_BC_Z,
             hipLaunchKernelGGL((k_bc_fill<T, 2>), nblocks(P_BC_Z), B, 0, stream, tab(P_BC_Z)));
+  if (v.recon == 1)
+    CTU_TIMED(K_PPMP_COEF, hipLaunchKernelGGL((k_ppmp_coef<T>), nblocks(P_COEF), B, 0, stream,
+                                              tab(P_COEF)));
   // stage 1 (a2-a5), then stage 2 (a2-a4 re-traced, a6-a7) with the update (a8) fused into
   // its last sweep
   hipError_t e = sweeps<T>(v, 1, stream, prof);

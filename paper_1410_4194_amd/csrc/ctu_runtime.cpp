@@ -14,7 +14,6 @@
 
 using ctu::DevScalars;
 using ctu::GridParams;
-using ctu::NG;
 
 namespace {
 
@@ -44,7 +43,6 @@ constexpr size_t kTotalsOutOffset = kPartialOffset + sizeof(double) * 5 * kTotal
 constexpr size_t kDescOffset = 49152;
 constexpr size_t kStartOffset = 53248;
 constexpr size_t kHeaderBytes = 65536;
-constexpr int kFieldsPerGrid = 30;  // fstar 3x5, fhalf 3x5
 static_assert(kTotalsOutOffset + 5 * sizeof(double) <= kDescOffset, "header overlap");
 static_assert(kDescOffset + sizeof(ctu::GridDesc) <= kStartOffset, "descriptor too large");
 static_assert(kStartOffset + sizeof(int) * ctu::P_NUM * 2 <= kHeaderBytes, "header overflow");
@@ -59,9 +57,18 @@ size_t partial_bytes(const ctu_config& c) {
   return (size_t)((blocks * 8 + 255) / 256 * 256);
 }
 
+// Ghost layers: the PPMC stencil reaches two cells and the CTU transverse correction one
+// more; PPMP's flattening reaches three.
+int ghost_layers(const ctu_config& c) { return c.recon == CTU_RECON_PPMP ? 4 : 3; }
+
 long long alloc_cells(const ctu_config& c) {
-  return (long long)(c.nx + 2 * NG) * (c.ny + 2 * NG) * (c.nz + 2 * NG);
+  const int g = ghost_layers(c);
+  return (long long)(c.nx + 2 * g) * (c.ny + 2 * g) * (c.nz + 2 * g);
 }
+
+// Workspace fields: first-stage and CTU flux differences (3 x 5 each); PPMP adds its
+// flattening and steepening coefficients per axis (3 x 2).
+int fields_per_grid(const ctu_config& c) { return 30 + (c.recon == CTU_RECON_PPMP ? 6 : 0); }
 
 long long field_stride(const ctu_config& c) {
   long long n = alloc_cells(c);
@@ -80,6 +87,8 @@ ctu_status validate(const ctu_config* c) {
   if (c->prec != CTU_FP64 && c->prec != CTU_FP32) return fail(CTU_EINVAL, "unknown precision");
   if (c->riemann != CTU_RIEMANN_EXACT && c->riemann != CTU_RIEMANN_ROE)
     return fail(CTU_EINVAL, "unknown Riemann solver");
+  if (c->recon != CTU_RECON_PPMC && c->recon != CTU_RECON_PPMP)
+    return fail(CTU_EINVAL, "unknown reconstruction");
   for (int a = 0; a < 2; ++a)
     if (c->march_seg[a] < 0 || c->march_seg[a] > 4096)
       return fail(CTU_EINVAL, "march_seg must lie in [0, 4096]");
@@ -91,8 +100,9 @@ ctu_status validate(const ctu_config* c) {
     if ((lo == CTU_BC_PERIODIC) != (hi == CTU_BC_PERIODIC))
       return fail(CTU_EINVAL, "periodic boundaries must pair");
     const int n = a == 0 ? c->nx : a == 1 ? c->ny : c->nz;
-    if ((lo == CTU_BC_REFLECT || hi == CTU_BC_REFLECT) && n < 3)
-      return fail(CTU_EINVAL, "a reflecting boundary needs >= 3 cells on its axis");
+    if ((lo == CTU_BC_REFLECT || hi == CTU_BC_REFLECT) && n < ghost_layers(*c))
+      return fail(CTU_EINVAL, "a reflecting boundary needs as many cells on its axis as there "
+                              "are ghost layers");
   }
   const long long ncell = (long long)c->nx * c->ny * c->nz;
   if (ncell > (1LL << 31)) return fail(CTU_EINVAL, "grid too large");
@@ -104,7 +114,8 @@ GridParams make_params(const ctu_config& c) {
   P.n[0] = c.nx;
   P.n[1] = c.ny;
   P.n[2] = c.nz;
-  for (int a = 0; a < 3; ++a) P.N[a] = P.n[a] + 2 * NG;
+  P.ng = ghost_layers(c);
+  for (int a = 0; a < 3; ++a) P.N[a] = P.n[a] + 2 * P.ng;
   P.stride = field_stride(c);
   P.dx[0] = c.dx;
   P.dx[1] = c.dy;
@@ -132,6 +143,7 @@ GridParams make_params(const ctu_config& c) {
   P.inv_root_m = (g - 1.0) / (2.0 * g);
   P.inv_gm1 = 1.0 / (g - 1.0);
   P.riemann = c.riemann;
+  P.recon = c.recon;
   // march segments: round(n/target) equal segments of the n cells of the axis
   P.seg[0] = 0;
   for (int a = 1; a < 3; ++a) {
@@ -183,14 +195,14 @@ struct ctu_grid {
   double* totals_out() const { return reinterpret_cast<double*>(d_work + kTotalsOutOffset); }
   char* fields() const { return d_work + kHeaderBytes; }
   double* partials() const {
-    return reinterpret_cast<double*>(d_work + kHeaderBytes + (size_t)kFieldsPerGrid * fbytes());
+    return reinterpret_cast<double*>(d_work + kHeaderBytes + (size_t)fields_per_grid(cfg) * fbytes());
   }
   size_t fbytes() const { return (size_t)P.stride * elem_bytes(cfg.prec); }
   ctu::GridDesc* d_desc() const { return reinterpret_cast<ctu::GridDesc*>(d_work + kDescOffset); }
   int* d_start() const { return reinterpret_cast<int*>(d_work + kStartOffset); }
   ctu::PlanView plan() const {
     return ctu::PlanView{d_desc(), d_start(), 1, h_start.data(), cfg.prec == CTU_FP32 ? 1 : 0,
-                         ctu::gas_class(P)};
+                         ctu::gas_class(P), P.recon};
   }
 };
 
@@ -260,7 +272,7 @@ ctu_status ctu_workspace_bytes(const ctu_config* cfg, size_t* state_bytes, size_
   const long long stride = field_stride(*cfg);
   if (state_bytes) *state_bytes = (size_t)5 * stride * eb;
   if (work_bytes)
-    *work_bytes = kHeaderBytes + (size_t)kFieldsPerGrid * stride * eb + partial_bytes(*cfg);
+    *work_bytes = kHeaderBytes + (size_t)fields_per_grid(*cfg) * stride * eb + partial_bytes(*cfg);
   return CTU_OK;
 }
 
@@ -290,6 +302,7 @@ ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, s
   g->desc.flux = g->fields();
   g->desc.s = g->scalars();
   g->desc.part = g->partials();
+  g->desc.coef = cfg->recon == CTU_RECON_PPMP ? g->fields() + 30 * g->fbytes() : nullptr;
   for (int i = 0; i < 6; ++i) g->desc.bc[i] = cfg->bc[i];
   g->desc.flags = 0;
   if (!build_starts({g->P}, g->h_start)) {
@@ -384,6 +397,7 @@ ctu_status ctu_grid_info_get(ctu_grid* g, ctu_grid_info* info) {
   info->elem_bytes = (int32_t)elem_bytes(g->cfg.prec);
   info->t = s.t;
   info->steps = s.steps;
+  info->ghost = g->P.ng;
   return CTU_OK;
 }
 
@@ -589,15 +603,17 @@ struct ctu_batch {
   struct Group {
     int prec = 0;
     int gclass = 0;
+    int recon = 0;
     std::vector<ctu::GridDesc> descs;
     std::vector<int> start;
     ctu::GridDesc* d_desc = nullptr;
     int* d_start = nullptr;
     ctu::PlanView view() const {
-      return ctu::PlanView{d_desc, d_start, (int)descs.size(), start.data(), prec, gclass};
+      return ctu::PlanView{d_desc, d_start, (int)descs.size(), start.data(), prec, gclass, recon};
     }
   };
-  static constexpr int kGroups = 8;  // {FP64, FP32} x solver class {0, 3, 5, Roe}
+  // {FP64, FP32} x {PPMC with solver class 0, 3, 5, Roe; PPMP with 0, Roe}
+  static constexpr int kGroups = 12;
   std::vector<Slot> slots;
   int32_t flags = 0;
   hipStream_t caller = nullptr;  // the caller's stream: batch work is ordered after its work
@@ -633,10 +649,12 @@ size_t batch_bytes(int32_t max_slots) {
          round256(sizeof(DevScalars) * (size_t)max_slots);
 }
 
+// Batch group of a grid; within each precision the groups follow kClass and kRecon below.
 int group_of(const ctu_grid* g) {
-  // group index matches kClass = {0, 3, 5, kRoe} within each precision
   const int c = ctu::gas_class(g->P);
-  return (g->cfg.prec == CTU_FP32 ? 4 : 0) + (c == 3 ? 1 : c == 5 ? 2 : c == ctu::kRoe ? 3 : 0);
+  const int k = g->P.recon == 1 ? (c == ctu::kRoe ? 5 : 4)
+                                : (c == 3 ? 1 : c == 5 ? 2 : c == ctu::kRoe ? 3 : 0);
+  return (g->cfg.prec == CTU_FP32 ? 6 : 0) + k;
 }
 
 void drop_graph(ctu_batch* b) {
@@ -740,10 +758,12 @@ ctu_status ctu_batch_create(int32_t max_slots, void* d_work, size_t work_bytes, 
   b->flags = flags;
   b->caller = reinterpret_cast<hipStream_t>(hip_stream);
   char* w = reinterpret_cast<char*>(d_work);
-  static const int kClass[4] = {0, 3, 5, ctu::kRoe};
+  static const int kClass[6] = {0, 3, 5, ctu::kRoe, 0, ctu::kRoe};
+  static const int kRecon[6] = {0, 0, 0, 0, 1, 1};
   for (int p = 0; p < ctu_batch::kGroups; ++p) {
-    b->groups[p].prec = p / 4;
-    b->groups[p].gclass = kClass[p % 4];
+    b->groups[p].prec = p / 6;
+    b->groups[p].gclass = kClass[p % 6];
+    b->groups[p].recon = kRecon[p % 6];
     b->groups[p].d_desc = reinterpret_cast<ctu::GridDesc*>(w);
     b->groups[p].d_start =
         reinterpret_cast<int*>(w + round256(sizeof(ctu::GridDesc) * (size_t)max_slots));

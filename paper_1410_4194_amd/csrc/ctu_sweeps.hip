@@ -1,26 +1,28 @@
-// ctu_sweeps.hip -- instantiates the sweep kernels for one storage type and solver class.
-// The build compiles this file once per (CTU_SWEEP_T, CTU_SWEEP_K) pair, in parallel: double
-// and float, each with the exact solver for K = 0 (any gamma), 3 (gamma = 5/3) and
-// 5 (gamma = 7/5), and with the Roe solver (K = kRoe = 1).
+// ctu_sweeps.hip -- instantiates the sweep kernels for one storage type, solver class and
+// reconstruction.  The build compiles this file once per (CTU_SWEEP_T, CTU_SWEEP_K,
+// CTU_SWEEP_R) triple, in parallel: double and float; PPMC (R = 0) with the exact solver for
+// K = 0 (any gamma), 3 (gamma = 5/3) and 5 (gamma = 7/5) and with the Roe solver
+// (K = kRoe = 1); PPMP (R = 1) with the exact solver for any gamma and with Roe.
 #include "ctu_sweeps.hpp"
 
-#if !defined(CTU_SWEEP_T) || !defined(CTU_SWEEP_K)
-#error "compile with -DCTU_SWEEP_T=<double|float> -DCTU_SWEEP_K=<0|1|3|5>"
+#if !defined(CTU_SWEEP_T) || !defined(CTU_SWEEP_K) || !defined(CTU_SWEEP_R)
+#error "compile with -DCTU_SWEEP_T=<double|float> -DCTU_SWEEP_K=<0|1|3|5> -DCTU_SWEEP_R=<0|1>"
 #endif
 
 namespace ctu {
 
 template <>
-hipError_t launch_sweeps<CTU_SWEEP_T, CTU_SWEEP_K>(const PlanView& v, int stage, hipStream_t stream,
-                                                   Profiler* prof) {
+hipError_t launch_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, CTU_SWEEP_R>(const PlanView& v, int stage,
+                                                                hipStream_t stream,
+                                                                Profiler* prof) {
   // the Newton histogram exists for the exact solver only
   if constexpr (CTU_SWEEP_K != kRoe) {
     if (prof && prof->hist) {
-      enqueue_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, true>(v, stage, stream, prof);
+      enqueue_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, true, CTU_SWEEP_R>(v, stage, stream, prof);
       return hipGetLastError();
     }
   }
-  enqueue_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, false>(v, stage, stream, prof);
+  enqueue_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, false, CTU_SWEEP_R>(v, stage, stream, prof);
   return hipGetLastError();
 }
 

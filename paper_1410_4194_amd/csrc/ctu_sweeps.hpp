@@ -86,6 +86,19 @@ __device__ __forceinline__ void flush_counts(const RiemannCounts& cnt, DevScalar
   if (cnt.hlle) atomicAdd(&s->counters[3], (unsigned long long)cnt.hlle);
 }
 
+// PPMP coefficients of a cell along axis D (zero, unused, for PPMC).
+template <int R, int D, typename T>
+__device__ __forceinline__ PpmpCoef<T> load_coef(const GridDesc* G, long long stride,
+                                                  long long id) {
+  PpmpCoef<T> k{T(0), T(0)};
+  if constexpr (R == 1) {
+    const GLOBAL T* __restrict__ cf = (const GLOBAL T*)G->coef;
+    k.flat = cf[(2 * D) * stride + id];
+    k.eta = cf[(2 * D + 1) * stride + id];
+  }
+  return k;
+}
+
 // Newton-iteration histogram of the solves of one wavefront (instrumented sweeps only):
 // each solve's bin is counted over the active lanes with a ballot, so lanes that left the
 // kernel early are simply not counted.  The wave counts sit in vector registers, so add and
@@ -119,7 +132,7 @@ struct NewtonHist {
 // once per cell instead of two faces.  A thread's segment covers the cells [f0, f1) and
 // solves the f1 - f0 + 1 faces around them.
 // Block layout per grid: (plane block of kBlock columns, segment), plane blocks fastest.
-template <typename T, int D, int STAGE, bool HIST, int K>
+template <typename T, int D, int STAGE, bool HIST, int K, int R>
 __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   static_assert(D == 1 || D == 2, "marching sweeps run along y or z");
   const BlockRef r = block_ref(tab);
@@ -165,15 +178,17 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
     load_prim<T, D>(u, P.stride, c0 + (long long)(f0 - 1) * sd, P, q1);
     load_prim<T, D>(u, P.stride, c0 + (long long)(f0)*sd, P, q2);
     load_prim<T, D>(u, P.stride, c0 + (long long)(f0 + 1) * sd, P, q3);
-    slope_fast(qm, q0, q1, s0);
-    slope_fast(q0, q1, q2, s1);
-    slope_fast(q1, q2, q3, s2);
+    slope_sel<R>(qm, q0, q1, s0);
+    slope_sel<R>(q0, q1, q2, s1);
+    slope_sel<R>(q1, q2, q3, s2);
   }
   // warm-up: trace cell f0-1 (window: q0 = f0-2, q1 = f0-1, q2 = f0, q3 = f0+1)
   T prevR[5];  // right-face state of the previous cell: primitive in stage 1, conserved in 2
   {
     T WL[5], WR[5];
-    trace_fast(q0, q1, q2, s0, s1, s2, dtodx, WL, WR);
+    trace_sel<R>(q0, q1, q2, s0, s1, s2,
+                 load_coef<R, D, T>(r.G, P.stride, c0 + (long long)(f0 - 1) * sd),
+                 T(P.gamma), dtodx, WL, WR);
     if (STAGE == 1) {
 #pragma unroll
       for (int q = 0; q < 5; ++q) prevR[q] = WR[q];
@@ -214,9 +229,10 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
 #pragma unroll
       for (int sl = 0; sl < 5; ++sl) raw[sl] = u[rot<D>(sl) * P.stride + nid];
     }
-    slope_fast(q1, q2, q3, s2);  // slope of c+1
+    slope_sel<R>(q1, q2, q3, s2);  // slope of c+1
     T WL[5], WR[5], UL[5], UR[5], F[5];
-    trace_fast(q0, q1, q2, s0, s1, s2, dtodx, WL, WR);
+    trace_sel<R>(q0, q1, q2, s0, s1, s2, load_coef<R, D, T>(r.G, P.stride, c0 + (long long)c * sd),
+                 T(P.gamma), dtodx, WL, WR);
     // the segment's last face is solved again as the next segment's first: count it there
     const bool dupface = c == f1 && f1 < nd;
     RiemannCounts dup{0u, 0u, 0};
@@ -269,7 +285,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
 // 0 <= c <= n_x, and lanes 3..60 store the difference dF(c) = F(c-1/2) - F(c+1/2) of their
 // real cell (F(c+1/2) from the next lane).  Every stencil of such a face lies in its own
 // row, so short rows share a wavefront instead of leaving most of its lanes idle.
-template <typename T, int STAGE, bool HIST, int K>
+template <typename T, int STAGE, bool HIST, int K, int R>
 __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   static_assert(STAGE == 1, "the second-stage x sweep is fused with the update");
   const BlockRef r = block_ref(tab);
@@ -287,8 +303,8 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   const int k = (int)(task / nw) - 1;
   const long long p = (task % nw) * XW - 3 + lane;
   const bool in_line = p >= 0 && p < plen;
-  const int c = in_line ? (int)(p % P.N[0]) - NG : -NG - 1;
-  const long long id = cell_index(P, -NG, -1, k) + p;
+  const int c = in_line ? (int)(p % P.N[0]) - P.ng : -P.ng - 1;
+  const long long id = cell_index(P, -P.ng, -1, k) + p;
   const T dtodx = T(dt / P.dx[0]);
 
   Prim<T> me;
@@ -301,7 +317,7 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   const Prim<T> left = shfl_prim(me, lm1);
   const Prim<T> right = shfl_prim(me, lp1);
   T sl[5];
-  slope_fast(left, me, right, sl);
+  slope_sel<R>(left, me, right, sl);
   T slm[5], slp[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
@@ -310,7 +326,9 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   }
   // traced primitive face states enter the solver directly
   T WL[5], WR[5];
-  trace_fast(left, me, right, slm, sl, slp, dtodx, WL, WR);
+  PpmpCoef<T> kc{T(0), T(0)};
+  if (R == 1 && in_line && c >= -1 && c <= P.n[0]) kc = load_coef<R, 0, T>(r.G, P.stride, id);
+  trace_sel<R>(left, me, right, slm, sl, slp, kc, T(P.gamma), dtodx, WL, WR);
   T prevR[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) prevR[q] = __shfl(WR[q], lm1, 64);
@@ -351,7 +369,7 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
 // earlier second-stage sweeps stored.  The new state is written in place, but only after the next chunk has read its
 // stencil (the cells up to three behind it), so every stencil sees u^n; stencils of real
 // faces stay within their row and no other wavefront reads these rows.
-template <typename T, bool HIST, int K>
+template <typename T, bool HIST, int K, int R>
 __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
@@ -376,7 +394,8 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
     const int j0 = (int)(grp % ngy) * P.xrows;
     const int k = (int)(grp / ngy);
     const int plen = min(P.xrows, P.n[1] - j0) * P.N[0];  // at most 8 rows: fits 32 bits
-    const long long linebase = cell_index(P, -NG, j0, k);  // position 0
+    const int ng = P.ng;
+    const long long linebase = cell_index(P, -ng, j0, k);  // position 0
     const T dtodx = T(dt / P.dx[0]);
     const T dtdx = T(dt / P.dx[0]), dtdy = T(dt / P.dx[1]), dtdz = T(dt / P.dx[2]);
     const T igm1 = T(P.inv_gm1);
@@ -388,10 +407,10 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
     unsigned bad = 0;
     T Udef[5] = {T(0), T(0), T(0), T(0), T(0)};
     long long def_id = -1;  // cell whose new state waits for the next chunk's loads
-    for (int cw = NG; cw < plen - NG; cw += XU) {
+    for (int cw = ng; cw < plen - ng; cw += XU) {
       const int p = cw - 3 + lane;
       const bool in_line = p >= 0 && p < plen;
-      const int c = in_line ? p % P.N[0] - NG : -NG - 1;
+      const int c = in_line ? p % P.N[0] - ng : -ng - 1;
       const long long id = linebase + p;
       T U0[5];
       Prim<T> me;
@@ -414,7 +433,7 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
       const Prim<T> left = shfl_prim(me, lm1);
       const Prim<T> right = shfl_prim(me, lp1);
       T sl[5];
-      slope_fast(left, me, right, sl);
+      slope_sel<R>(left, me, right, sl);
       T slm[5], slp[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
@@ -422,7 +441,9 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
         slp[q] = __shfl(sl[q], lp1, 64);
       }
       T WL[5], WR[5], UL[5], UR[5];
-      trace_fast(left, me, right, slm, sl, slp, dtodx, WL, WR);
+      PpmpCoef<T> kc{T(0), T(0)};
+      if (R == 1 && in_line && c >= -1 && c <= P.n[0]) kc = load_coef<R, 0, T>(r.G, P.stride, id);
+      trace_sel<R>(left, me, right, slm, sl, slp, kc, T(P.gamma), dtodx, WL, WR);
       to_cons(WL, igm1, UL);
       to_cons(WR, igm1, UR);
       if (lane >= 2 && lane <= 61 && c >= -1 && c <= P.n[0]) {
@@ -441,7 +462,7 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
       int iters = -1;  // Newton iterations of this lane's counted solve
       if (lane >= 3 && lane <= 61 && c >= 0 && c <= P.n[0]) {
         // lane 61's face is solved again as the next chunk's first face: count it there
-        const bool counted = lane <= 60 || cw + XU >= plen - NG;
+        const bool counted = lane <= 60 || cw + XU >= plen - ng;
         RiemannCounts dup{0u, 0u, 0};
         face_flux_u<T, K>(prevR, UL, P, F, counted ? cnt : dup);
         if (counted) iters = cnt.iters;
@@ -491,7 +512,7 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
 }
 
 // The six sweeps of one stage for every grid of a plan (one launch per direction).
-template <typename T, int K, bool HIST>
+template <typename T, int K, bool HIST, int R>
 void enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
   const int stride = v.ngrids + 1;
   auto tab = [&](int pass) { return LaunchTab{v.d_grids, v.d_start + pass * stride, v.ngrids}; };
@@ -499,21 +520,21 @@ void enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* 
   const dim3 B(kBlock);
   if (stage == 1) {
     // a2-a5: F*, G*, H* on the extended transverse range
-    CTU_TIMED(K_SWEEP1_X, hipLaunchKernelGGL((k_sweep_x<T, 1, HIST, K>), nblocks(P_S1_X), B, 0,
+    CTU_TIMED(K_SWEEP1_X, hipLaunchKernelGGL((k_sweep_x<T, 1, HIST, K, R>), nblocks(P_S1_X), B, 0,
                                              stream, tab(P_S1_X)));
-    CTU_TIMED(K_SWEEP1_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 1, HIST, K>), nblocks(P_S1_Y),
+    CTU_TIMED(K_SWEEP1_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 1, HIST, K, R>), nblocks(P_S1_Y),
                                              B, 0, stream, tab(P_S1_Y)));
-    CTU_TIMED(K_SWEEP1_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 1, HIST, K>), nblocks(P_S1_Z),
+    CTU_TIMED(K_SWEEP1_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 1, HIST, K, R>), nblocks(P_S1_Z),
                                              B, 0, stream, tab(P_S1_Z)));
   } else {
     // a2-a4 re-traced, a6-a7: G^{n+1/2}, H^{n+1/2} on the real faces, then F^{n+1/2} with the
     // update (a8) and the CFL bound of the new state (a9)
-    CTU_TIMED(K_SWEEP2_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 2, HIST, K>), nblocks(P_S2_Y),
+    CTU_TIMED(K_SWEEP2_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 2, HIST, K, R>), nblocks(P_S2_Y),
                                              B, 0, stream, tab(P_S2_Y)));
-    CTU_TIMED(K_SWEEP2_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 2, HIST, K>), nblocks(P_S2_Z),
+    CTU_TIMED(K_SWEEP2_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 2, HIST, K, R>), nblocks(P_S2_Z),
                                              B, 0, stream, tab(P_S2_Z)));
     CTU_TIMED(K_SWEEP2_X_UPDATE,
-              hipLaunchKernelGGL((k_sweep_x_update<T, HIST, K>), nblocks(P_S2_X), B, 0, stream,
+              hipLaunchKernelGGL((k_sweep_x_update<T, HIST, K, R>), nblocks(P_S2_X), B, 0, stream,
                                  tab(P_S2_X)));
   }
 }

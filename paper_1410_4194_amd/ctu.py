@@ -25,6 +25,7 @@ LIB_PATH = os.environ.get("CTU_LIBRARY") or os.path.join(_HERE, "libctu.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, ENOCONV, EAGAIN = 0, -1, -2, -3, -4, -5, -6
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
 RIEMANN_EXACT, RIEMANN_ROE = 0, 1
+RECON_PPMC, RECON_PPMP = 0, 1
 FP64, FP32 = 0, 1
 FLAG_NONFINITE, FLAG_DENSITY, FLAG_PFLOOR, FLAG_NEWTON_CAP = 1, 2, 4, 8
 TICKET_QUEUED, TICKET_RUNNING, TICKET_DONE, TICKET_FAILED, TICKET_UNKNOWN = 0, 1, 2, 3, -1
@@ -49,12 +50,13 @@ class Config(C.Structure):
                 ("gamma", C.c_double), ("bc", C.c_int32 * 6), ("prec", C.c_int32),
                 ("cfl", C.c_double), ("newton_tol", C.c_double),
                 ("newton_max_iter", C.c_int32), ("p_floor", C.c_double),
-                ("march_seg", C.c_int32 * 2), ("riemann", C.c_int32)]
+                ("march_seg", C.c_int32 * 2), ("riemann", C.c_int32), ("recon", C.c_int32)]
 
 
 class GridInfo(C.Structure):
     _fields_ = [("alloc_cells", C.c_int64), ("field_stride", C.c_int64),
-                ("elem_bytes", C.c_int32), ("t", C.c_double), ("steps", C.c_int64)]
+                ("elem_bytes", C.c_int32), ("t", C.c_double), ("steps", C.c_int64),
+                ("ghost", C.c_int32)]
 
 
 class CtuError(RuntimeError):
@@ -117,7 +119,7 @@ def _check(status: int, allow=()) -> int:
 
 def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64, cfl=0.3,
                 newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20, march_seg=None,
-                riemann=0) -> Config:
+                riemann=0, recon=0) -> Config:
     """Grid configuration.  march_seg: target faces per thread of the y and z sweeps; None
     takes the autotuned table (tiles.json beside this module) when it exists, else the
     library default."""
@@ -138,6 +140,7 @@ def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64,
         march_seg = lookup(int(prec), int(ny), int(nz))
     c.march_seg[0], c.march_seg[1] = int(march_seg[0]), int(march_seg[1])
     c.riemann = int(riemann)
+    c.recon = int(recon)
     return c
 
 
@@ -225,7 +228,8 @@ class Grid:
     def debug_fluxes(self, which: int, direction: int) -> np.ndarray:
         """Fluxes of the last step over the allocated box (5, NZ, NY, NX), float64."""
         nx, ny, nz = self.n
-        out = np.empty((5, nz + 6, ny + 6, nx + 6), dtype=np.float64)
+        g2 = 2 * self.info().ghost
+        out = np.empty((5, nz + g2, ny + g2, nx + g2), dtype=np.float64)
         _check(lib.ctu_debug_fluxes(self.handle, which, direction,
                                     self._host_ptrs([out[f] for f in range(5)])))
         return out

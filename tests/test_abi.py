@@ -67,6 +67,17 @@ def test_workspace_bytes_and_validation(ctu):
         assert ei.value.status == ctu.EINVAL
     ok = ctu.make_config(3, 8, 1, 1, 1, 1, 1.4, (ctu.BC_REFLECT, ctu.BC_OUTFLOW, 2, 2, 0, 0))
     ctu.workspace_bytes(ok)
+    # PPMP: four ghost layers, six coefficient fields more, reflect needs four cells
+    pp = ctu.make_config(8, 8, 8, 1, 1, 1, 1.4, recon=ctu.RECON_PPMP)
+    sbp, wbp = ctu.workspace_bytes(pp)
+    assert sbp == 5 * ((16 ** 3 + 63) // 64 * 64) * 8
+    assert wbp >= 36 * ((16 ** 3 + 63) // 64 * 64) * 8
+    with pytest.raises(ctu.CtuError):
+        ctu.workspace_bytes(ctu.make_config(3, 8, 8, 1, 1, 1, 1.4, (2, 2, 0, 0, 0, 0),
+                                            recon=ctu.RECON_PPMP))
+    for bad_kw in (dict(recon=2), dict(riemann=2)):
+        with pytest.raises(ctu.CtuError):
+            ctu.workspace_bytes(ctu.make_config(8, 8, 8, 1, 1, 1, 1.4, **bad_kw))
 
 
 def test_grid_create_rejects_small_workspace(ctu):
