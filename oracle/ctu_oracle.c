@@ -702,7 +702,7 @@ int ref_roe_flux(const double UL[5], const double UR[5], double gamma, double p_
 /* ------------------------------------------------------------------------------------ */
 
 int ref_ghost_width(const ref_config* c) {
-  return (c->recon == REF_RECON_PPMP || c->h_correction) ? 4 : 3;
+  return (c->recon == REF_RECON_PPMP ? 4 : 3) + (c->h_correction ? 1 : 0);
 }
 
 static long alloc_index(const ref_config* c, int i, int j, int k) {
@@ -802,6 +802,37 @@ static long box_size(const box* b) { return b->n[0] * b->n[1] * b->n[2]; }
  * rotated slot s holds global component rot[d][s]. */
 static const int rot[3][5] = {{0, 1, 2, 3, 4}, {0, 2, 3, 1, 4}, {0, 3, 1, 2, 4}};
 
+/* Second-stage input states of the d-face between cell cl and its neighbour cl + e_d
+ * (eq. transverse_evolution): the traced conserved states U*_L (right face state of cl) and
+ * U*_R (left face state of the neighbour), each corrected with half the first-stage flux
+ * differences of its own cell along the two other axes, in the cyclic order of Sec. 2.1.
+ * Us and Fs live on the box X (cell-centred labels; face c+1/2 at cell c). */
+static void ctu_face_states(const ref_config* c, int d, const int cl[3], double dt, const box* X,
+                            double* const Us[3][2][5], double* const Fs[3][5],
+                            double Uh[2][5]) {
+  double dd[3] = {c->dx, c->dy, c->dz};
+  int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  double h1 = 0.5 * dt / dd[t1];
+  double h2 = 0.5 * dt / dd[t2];
+  int cr[3] = {cl[0], cl[1], cl[2]};
+  cr[d] += 1;
+  for (int side = 0; side < 2; ++side) {
+    const int* cc = side == 0 ? cl : cr;
+    long xc = box_index(X, cc[0], cc[1], cc[2]);
+    int m1[3] = {cc[0], cc[1], cc[2]};
+    int m2[3] = {cc[0], cc[1], cc[2]};
+    m1[t1] -= 1;
+    m2[t2] -= 1;
+    long x1 = box_index(X, m1[0], m1[1], m1[2]); /* face c - 1/2 along t1 */
+    long x2 = box_index(X, m2[0], m2[1], m2[2]); /* face c - 1/2 along t2 */
+    for (int f = 0; f < 5; ++f) {
+      double ustar = side == 0 ? Us[d][1][f][xc] : Us[d][0][f][xc];
+      Uh[side][f] = ustar + h1 * (Fs[t1][f][x1] - Fs[t1][f][xc]) +
+                    h2 * (Fs[t2][f][x2] - Fs[t2][f][xc]);
+    }
+  }
+}
+
 /* The interface flux of the configured Riemann solver from rotated conserved states. */
 static void face_flux(const ref_config* c, const double ul[5], const double ur[5],
                       double eta_h, double F[5], ref_stats* st) {
@@ -820,15 +851,18 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
     if (lo[a] < 0 || hi[a] > n[a] || lo[a] >= hi[a]) return -1;
   if (c->riemann != REF_RIEMANN_EXACT && c->riemann != REF_RIEMANN_ROE) return -1;
   if (c->recon != REF_RECON_PPMC && c->recon != REF_RECON_PPMP) return -1;
-  if (c->h_correction) return -1;
+  /* App. C: the H correction belongs to the Roe solver */
+  if (c->h_correction && c->riemann != REF_RIEMANN_ROE) return -1;
   double g = c->gamma;
+  const int ext = c->h_correction ? 1 : 0;
 
   /* Boxes: R = cells to update; X = R grown by one cell (cells whose traced states and
-   * first-stage fluxes the transverse correction reads); P = R grown by three (stencil). */
+   * first-stage fluxes the transverse correction reads), by two with the H correction (whose
+   * eta^H reads second-stage states one cell beyond R); P = the stencil of X's cells. */
   int xlo[3], xhi[3], plo[3], phi[3];
   for (int a = 0; a < 3; ++a) {
-    xlo[a] = lo[a] - 1;
-    xhi[a] = hi[a] + 1;
+    xlo[a] = lo[a] - 1 - ext;
+    xhi[a] = hi[a] + 1 + ext;
     plo[a] = lo[a] - ref_ghost_width(c);
     phi[a] = hi[a] + ref_ghost_width(c);
   }
@@ -933,10 +967,38 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
     H[d] = make_box(hlo, hi);
     for (int f = 0; f < 5; ++f) Fh[d][f] = (double*)malloc(sizeof(double) * box_size(&H[d]));
   }
+
+  /* App. C: eta at every d-face whose second-stage states the H stencil of R's faces reads
+   * (the faces of R's cells along d, over R grown by one cell across d), from those states:
+   * eta = |(u_R + a_R) - (u_L + a_L)| / 2 with the normal velocity u.  Stored on E[d], face
+   * c+1/2 at cell c. */
+  double* eta[3] = {NULL, NULL, NULL};
+  box E[3];
+  if (ext) {
+    for (int d = 0; d < 3; ++d) {
+      int elo[3], ehi[3];
+      for (int a = 0; a < 3; ++a) {
+        elo[a] = lo[a] - 1;
+        ehi[a] = a == d ? hi[a] : hi[a] + 1;
+      }
+      E[d] = make_box(elo, ehi);
+      eta[d] = (double*)malloc(sizeof(double) * box_size(&E[d]));
+      for (int k = E[d].lo[2]; k < E[d].hi[2]; ++k)
+        for (int j = E[d].lo[1]; j < E[d].hi[1]; ++j)
+          for (int i = E[d].lo[0]; i < E[d].hi[0]; ++i) {
+            int cl[3] = {i, j, k};
+            double Uh[2][5], w[2][5];
+            ctu_face_states(c, d, cl, dt, &X, Us, Fs, Uh);
+            for (int side = 0; side < 2; ++side) ref_cons_to_prim(Uh[side], g, c->p_floor, w[side]);
+            double sL = w[0][1 + d] + sqrt(g * w[0][4] / w[0][0]);
+            double sR = w[1][1 + d] + sqrt(g * w[1][4] / w[1][0]);
+            eta[d][box_index(&E[d], i, j, k)] = 0.5 * fabs(sR - sL);
+          }
+    }
+  }
+
   for (int d = 0; d < 3; ++d) {
-    int t1 = (d + 1) % 3, t2 = (d + 2) % 3; /* cyclic permutation of Sec. 2.1 step 3 */
-    double h1 = 0.5 * dt / dd[t1];
-    double h2 = 0.5 * dt / dd[t2];
+    int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
     for (int k = H[d].lo[2]; k < H[d].hi[2]; ++k)
       for (int j = H[d].lo[1]; j < H[d].hi[1]; ++j)
         for (int i = H[d].lo[0]; i < H[d].hi[0]; ++i) {
@@ -944,19 +1006,21 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
           int cr[3] = {i, j, k};
           cr[d] += 1;
           double Uh[2][5];
-          for (int side = 0; side < 2; ++side) {
-            const int* cc = side == 0 ? cl : cr;
-            long xc = box_index(&X, cc[0], cc[1], cc[2]);
-            int m1[3] = {cc[0], cc[1], cc[2]};
-            int m2[3] = {cc[0], cc[1], cc[2]};
-            m1[t1] -= 1;
-            m2[t2] -= 1;
-            long x1 = box_index(&X, m1[0], m1[1], m1[2]); /* face c - 1/2 along t1 */
-            long x2 = box_index(&X, m2[0], m2[1], m2[2]); /* face c - 1/2 along t2 */
-            for (int f = 0; f < 5; ++f) {
-              double ustar = side == 0 ? Us[d][1][f][xc] : Us[d][0][f][xc];
-              Uh[side][f] = ustar + h1 * (Fs[t1][f][x1] - Fs[t1][f][xc]) +
-                            h2 * (Fs[t2][f][x2] - Fs[t2][f][xc]);
+          ctu_face_states(c, d, cl, dt, &X, Us, Fs, Uh);
+          /* eta^H: this face and the transverse faces on both sides of its two cells (the
+           * nine-point stencil of App. C, [Q28]) */
+          double eta_h = 0.0;
+          if (ext) {
+            eta_h = eta[d][box_index(&E[d], i, j, k)];
+            for (int side = 0; side < 2; ++side) {
+              const int* cc = side == 0 ? cl : cr;
+              for (int tt = 0; tt < 2; ++tt) {
+                int t = tt == 0 ? t1 : t2;
+                int m[3] = {cc[0], cc[1], cc[2]};
+                m[t] -= 1; /* face cc - 1/2 along t */
+                eta_h = fmax(eta_h, eta[t][box_index(&E[t], m[0], m[1], m[2])]);
+                eta_h = fmax(eta_h, eta[t][box_index(&E[t], cc[0], cc[1], cc[2])]);
+              }
             }
           }
           double ul[5], ur[5], fl[5];
@@ -964,7 +1028,7 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
             ul[q] = Uh[0][rot[d][q]];
             ur[q] = Uh[1][rot[d][q]];
           }
-          face_flux(c, ul, ur, 0.0, fl, st);
+          face_flux(c, ul, ur, eta_h, fl, st);
           long hb = box_index(&H[d], i, j, k);
           for (int q = 0; q < 5; ++q) Fh[d][rot[d][q]][hb] = fl[q];
           if (fhalf) {
@@ -973,6 +1037,7 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
           }
         }
   }
+  for (int d = 0; d < 3; ++d) free(eta[d]);
 
   /* Step 5: conservative update, eq. (conserved_update), terms added left to right. */
   double dtd[3] = {dt / dd[0], dt / dd[1], dt / dd[2]};

@@ -1,0 +1,153 @@
+"""Pins of the oracle's H correction (App. C) of the second-stage Roe fluxes.
+
+What fixes the answer, independently of the oracle's own code:
+* stationary contacts in a state made of flat plateaus: every PPMC trace returns the cell
+  value itself and the first-stage fluxes are exact (no transverse correction), so each
+  second-stage Roe flux has a closed form: mass flux -(rho_R - rho_L) eta^H / 2, momentum
+  flux p, energy flux 0, with eta^H the largest eta = |a_R - a_L| / 2 of the face and of the
+  transverse faces around its two cells (the nine-point stencil).  A density step across x
+  next to a contact across y puts the transverse part of the stencil to work; the one-step
+  density field is computed here from that rule alone;
+* without the correction the same state is stationary bit for bit;
+* where every eta stays below every |lambda| (weak waves on a flow moving in all three
+  directions) the correction is inactive and the step equals the plain Roe step bit for bit;
+* uniform flow, conservation, the ghost width.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1410_4194_amd import workloads as WL
+from tests.common import oracle_config, oracle_state
+
+G = 1.4
+
+
+def _contacts_workload():
+    """8 x 8 x 4: density 1 below the y-contact (rows 0..3), 0.125 above; doubled for x >= 4;
+    p = 1, at rest; outflow in x and y, periodic in z."""
+    nx, ny, nz = 8, 8, 4
+    base = np.where(np.arange(ny) < 4, 1.0, 0.125)[:, None] * np.where(np.arange(nx) >= 4, 2.0, 1.0)[None, :]
+    W = np.zeros((5, nz, ny, nx))
+    W[0] = base[None]
+    W[4] = 1.0
+    d = 1.0 / 8
+    return WL.Workload("contacts_8x8x4", nx, ny, nz, d, d, d, G, (1, 1, 1, 1, 0, 0), W)
+
+
+def _expected_density(rho2d, dt, dx):
+    """One step of the stationary-contact field under the H-corrected Roe fluxes, from the
+    closed form above.  rho2d: (ny, nx); x and y ghosts copy the edge cells."""
+    r = np.pad(rho2d, 1, mode="edge")  # ghost ring
+    a = np.sqrt(G * 1.0 / r)
+    # eta of x-faces between r[:, i] and r[:, i+1] and of y-faces between r[j] and r[j+1]
+    eta_x = 0.5 * np.abs(a[:, 1:] - a[:, :-1])  # (ny+2, nx+1)
+    eta_y = 0.5 * np.abs(a[1:, :] - a[:-1, :])  # (ny+1, nx+2)
+    ny, nx = rho2d.shape
+    Fx = np.zeros((ny, nx + 1))
+    for j in range(ny):
+        for f in range(nx + 1):           # face between cells f-1 and f (real indices)
+            jj, il, ir = j + 1, f, f + 1  # padded indices of the two cells
+            eh = eta_x[jj, f]
+            for ic in (il, ir):           # y-faces below and above each cell
+                eh = max(eh, eta_y[jj - 1, ic], eta_y[jj, ic])
+            Fx[j, f] = -0.5 * (r[jj, ir] - r[jj, il]) * eh
+    Fy = np.zeros((ny + 1, nx))
+    for f in range(ny + 1):
+        for i in range(nx):
+            ii, jl, jr = i + 1, f, f + 1
+            eh = eta_y[f, ii]
+            for jc in (jl, jr):
+                eh = max(eh, eta_x[jc, ii - 1], eta_x[jc, ii])
+            Fy[f, i] = -0.5 * (r[jr, ii] - r[jl, ii]) * eh
+    lam = dt / dx
+    return rho2d + lam * (Fx[:, :-1] - Fx[:, 1:]) + lam * (Fy[:-1, :] - Fy[1:, :])
+
+
+def test_ghost_width():
+    wl = WL.random_state(6, 6, 6, seed=1)
+    assert oracle_config(wl, riemann=1, h_correction=1).ng == 4
+    assert oracle_config(wl, riemann=1, h_correction=1, recon=O.RECON_PPMP).ng == 5
+
+
+def test_h_correction_needs_roe():
+    wl = WL.random_state(6, 6, 6, seed=1)
+    cfg = oracle_config(wl, riemann=0, h_correction=1)
+    u = oracle_state(wl, cfg)
+    with pytest.raises(ValueError):
+        O.step(cfg, u, 0.01)
+
+
+def test_stationary_contacts_closed_form():
+    wl = _contacts_workload()
+    dt = 0.1 * wl.dx
+    cfg = oracle_config(wl, riemann=1, h_correction=1)
+    u = oracle_state(wl, cfg)
+    O.step(cfg, u, dt)
+    r = O.real(cfg, u)
+    exp = _expected_density(wl.W[0, 0], dt, wl.dx)
+    for k in range(wl.nz):
+        assert np.allclose(r[0, k], exp, rtol=0, atol=1e-15), np.abs(r[0, k] - exp).max()
+    # the transverse part of the stencil mattered: rows next to the y-contact differ from
+    # what the x-face eta alone would give
+    assert abs(exp[3, 3] - exp[1, 3]) > 1e-3
+    # momentum and energy fluxes are the plain ones: momenta stay 0, energy unchanged
+    assert np.all(r[1:4] == 0.0)
+    assert np.array_equal(r[4], O.real(cfg, oracle_state(wl, cfg))[4])
+
+
+def test_without_correction_contacts_are_stationary():
+    wl = _contacts_workload()
+    cfg = oracle_config(wl, riemann=1)
+    u = oracle_state(wl, cfg)
+    before = O.real(cfg, u).copy()
+    O.step(cfg, u, 0.1 * wl.dx)
+    assert np.array_equal(O.real(cfg, u), before)
+
+
+def test_inactive_where_eta_is_below_every_eigenvalue():
+    """Weak sound waves on a flow moving at half the sound speed along every axis: eta is
+    O(amplitude) while every |lambda| >= a/2, so the corrected step equals the plain one."""
+    n = 10
+    wl = WL.random_state(n, n, n, seed=7, rough=False, mach=1.0)
+    a0 = math.sqrt(G)
+    z, y, x = np.meshgrid(*(np.arange(n) / n,) * 3, indexing="ij")
+    eps = 1e-4 * np.sin(2 * np.pi * (x + 2 * y + z))
+    wl.W[0] = 1.0 + eps
+    wl.W[1] = wl.W[2] = wl.W[3] = 0.5 * a0
+    wl.W[4] = 1.0 + G * eps
+    c0 = oracle_config(wl, riemann=1)
+    c1 = oracle_config(wl, riemann=1, h_correction=1)
+    u0, u1 = oracle_state(wl, c0), oracle_state(wl, c1)
+    dt = 0.8 * O.compute_dt(c0, u0)
+    O.step(c0, u0, dt)
+    O.step(c1, u1, dt)
+    assert np.array_equal(O.real(c0, u0), O.real(c1, u1))
+
+
+def test_active_on_rough_states_and_conservative():
+    wl = WL.random_state(9, 8, 7, seed=8)
+    c0 = oracle_config(wl, riemann=1)
+    c1 = oracle_config(wl, riemann=1, h_correction=1)
+    u0, u1 = oracle_state(wl, c0), oracle_state(wl, c1)
+    r_start = O.real(c1, u1).reshape(5, -1).copy()
+    dt = O.compute_dt(c0, u0)
+    O.step(c0, u0, dt)
+    O.step(c1, u1, dt)
+    assert not np.array_equal(O.real(c0, u0), O.real(c1, u1))
+    r1 = O.real(c1, u1).reshape(5, -1)
+    for f in range(5):
+        assert abs(math.fsum(r1[f]) - math.fsum(r_start[f])) <= 1e-13 * math.fsum(np.abs(r_start[f]))
+
+
+@pytest.mark.parametrize("recon", [0, 1], ids=["ppmc", "ppmp"])
+def test_uniform_flow_is_exact(recon):
+    wl = WL.random_state(9, 7, 6, seed=3)
+    wl.W[:] = np.array([1.3, 0.4, -0.2, 0.7, 2.0])[:, None, None, None]
+    cfg = oracle_config(wl, riemann=1, h_correction=1, recon=recon)
+    u = oracle_state(wl, cfg)
+    before = O.real(cfg, u).copy()
+    O.step(cfg, u, 0.5 * O.compute_dt(cfg, u))
+    assert np.array_equal(O.real(cfg, u), before)

@@ -61,11 +61,13 @@ M=[
  ("ppmp transverse from reference", "WsL[2] = oL[2];", "WsL[2] = mL[2];"),
  ("ppmp no expansion test", "if (u[3] - u[1] > 0.0) return 0.0;", "if (0) return 0.0;"),
  ("ppmp chi^m_R sign", "WsR[1] = pR[1] - CR * chimR;", "WsR[1] = pR[1] + CR * chimR;"),
+ ("hcorr own face only", "eta_h = fmax(eta_h, eta[t][box_index(&E[t], m[0], m[1], m[2])]);\n                eta_h = fmax(eta_h, eta[t][box_index(&E[t], cc[0], cc[1], cc[2])]);", "(void)m;"),
+ ("hcorr eta without half", "eta[d][box_index(&E[d], i, j, k)] = 0.5 * fabs(sR - sL);", "eta[d][box_index(&E[d], i, j, k)] = fabs(sR - sL);"),
  ("own rho for slopes", "  double rho = w0[0];\n  double a = sound_speed(w0, gamma);", "  double rho = wm[0];\n  double a = sound_speed(wm, gamma);"),
 ]
 
 PINS = ["tests/test_oracle_riemann.py", "tests/test_oracle_roe.py", "tests/test_oracle_ppmc.py",
-        "tests/test_oracle_ppmp.py", "tests/test_oracle_step.py"]
+        "tests/test_oracle_ppmp.py", "tests/test_oracle_hcorr.py", "tests/test_oracle_step.py"]
 
 
 @pytest.mark.slow
