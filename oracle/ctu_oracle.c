@@ -597,16 +597,20 @@ static double raw_pressure(const double U[5], double gamma) {
   return (gamma - 1.0) * (U[4] - 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / U[0]);
 }
 
-/* Reading: the Roe inputs are the interface states in the conserved form in which they are
- * kept between the stages; primitives come from the same conversion (with the pressure
- * floor) as for the exact solver, and F_L, F_R use the stored total energies.  eta_h >= 0
- * is the H-correction speed (App. C); 0 leaves the eigenvalues as they are.  An
- * intermediate state counts as failed when its density or pressure is not positive. */
-int ref_roe_flux(const double UL[5], const double UR[5], double gamma, double p_floor,
+/* App. B.2 starts the Roe solver from the primitive input states: the interface states,
+ * kept in conserved form between the stages, are converted with the pressure floor as for
+ * the exact solver, and the conserved states, fluxes and enthalpies used below are those of
+ * these primitives (so a floored pressure also sets the total energy, and the Roe-averaged
+ * sound speed stays real).  eta_h >= 0 is the H-correction speed (App. C); 0 leaves the
+ * eigenvalues as they are.  An intermediate state counts as failed when its density or
+ * pressure is not positive. */
+int ref_roe_flux(const double Uin_L[5], const double Uin_R[5], double gamma, double p_floor,
                  double eta_h, double F[5], ref_stats* st) {
-  double WL[5], WR[5];
-  int fl = ref_cons_to_prim(UL, gamma, p_floor, WL);
-  int fr = ref_cons_to_prim(UR, gamma, p_floor, WR);
+  double WL[5], WR[5], UL[5], UR[5];
+  int fl = ref_cons_to_prim(Uin_L, gamma, p_floor, WL);
+  int fr = ref_cons_to_prim(Uin_R, gamma, p_floor, WR);
+  ref_prim_to_cons(WL, gamma, UL);
+  ref_prim_to_cons(WR, gamma, UR);
   if (st) {
     st->solves += 1;
     st->p_floored += fl + fr;
@@ -623,7 +627,15 @@ int ref_roe_flux(const double UL[5], const double UR[5], double gamma, double p_
   double wt = (sl * WL[3] + sr * WR[3]) / (sl + sr);
   double Ht = (sl * HL + sr * HR) / (sl + sr);
   double V2 = ut * ut + vt * vt + wt * wt;
-  double at = sqrt((gamma - 1.0) * (Ht - 0.5 * V2));
+  /* a~^2 = (gamma-1)(H~ - V~^2/2), evaluated through the equal form
+   * (gamma-1)[w_L h_L + w_R h_R + w_L w_R |V_L - V_R|^2 / 2] with h = gamma p/((gamma-1) rho)
+   * and the weights w = sqrt(rho)/(sqrt(rho_L) + sqrt(rho_R)): the printed difference cancels
+   * catastrophically when p/rho << V^2 (the cold inflow of Noh's problem) */
+  double wl_ = sl / (sl + sr), wr_ = sr / (sl + sr);
+  double hL = gamma * WL[4] / ((gamma - 1.0) * WL[0]), hR = gamma * WR[4] / ((gamma - 1.0) * WR[0]);
+  double dV2 = (WR[1] - WL[1]) * (WR[1] - WL[1]) + (WR[2] - WL[2]) * (WR[2] - WL[2]) +
+               (WR[3] - WL[3]) * (WR[3] - WL[3]);
+  double at = sqrt((gamma - 1.0) * (wl_ * hL + wr_ * hR + 0.5 * wl_ * wr_ * dV2));
   double lm = ut - at, l0 = ut, lp = ut + at;
 
   /* supersonic: the upwind state's flux */

@@ -119,7 +119,8 @@ void ref_riemann_wave_speeds(const double WL[3], const double WR[3], double psta
 void ref_riemann_flux(const double UL[5], const double UR[5], double gamma, double tol,
                       int max_iter, double p_floor, double F[5], ref_stats* st);
 
-/* Roe flux (App. B.2) from rotated conserved states UL, UR, with the HLLE flux substituted
+/* Roe flux (App. B.2) from rotated conserved states UL, UR (taken through their primitive
+ * form with the pressure floor, as the solver starts from primitives), with the HLLE flux substituted
  * when an intermediate Roe state has a non-positive density or pressure.  eta_h is the
  * H-correction speed (App. C; 0 for none).  Returns 1 when HLLE was used, else 0. */
 int ref_roe_flux(const double UL[5], const double UR[5], double gamma, double p_floor,
