@@ -22,8 +22,8 @@
  *   (i, j, k), 0 <= i < nx, is element (i+g) + NX*((j+g) + NY*(k+g)), NX = nx+2g,
  *   NY = ny+2g.  Consecutive fields start `field_stride` elements apart
  *   (ctu_grid_info).  g ghost layers per side: g = 3 with PPMC (its stencil needs two, the
- *   CTU transverse correction one more), g = 4 with PPMP (three-cell stencil).  Element
- *   type is double (CTU_FP64) or float (CTU_FP32).
+ *   CTU transverse correction one more), g = 4 with PPMP (three-cell stencil), one more
+ *   with the H correction.  Element type is double (CTU_FP64) or float (CTU_FP32).
  * Host arrays for set/get are the real cells only, packed, x fastest, one array per field.
  * Errors found on the device (non-finite or non-positive density / energy in an updated
  *   state) are reported at the next syncing call of that grid as CTU_ENONPHYS.
@@ -53,8 +53,8 @@ typedef enum {
  * Outflow (transmissive): every ghost layer copies the edge real cell.
  * Reflect: a ghost copies its mirror-image real cell across the wall (ghost layer m outside
  * takes real layer m-1 inside) and negates the momentum normal to the wall; the axis needs
- * at least as many real cells as there are ghost layers (3, or 4 with PPMP) so that every
- * mirror image is a real cell. */
+ * at least as many real cells as there are ghost layers (3 with PPMC, 4 with PPMP, one
+ * more with the H correction) so that every mirror image is a real cell. */
 typedef enum { CTU_BC_PERIODIC = 0, CTU_BC_OUTFLOW = 1, CTU_BC_REFLECT = 2 } ctu_bc;
 typedef enum { CTU_FP64 = 0, CTU_FP32 = 1 } ctu_prec;
 
@@ -85,7 +85,8 @@ typedef struct {
   double dx, dy, dz;       /* cell widths, > 0 */
   double gamma;            /* ratio of specific heats, > 1 */
   int32_t bc[6];           /* x-, x+, y-, y+, z-, z+ : ctu_bc; periodic must pair;
-                              reflect needs >= 3 cells (4 with PPMP) on its axis */
+                              reflect needs as many cells on its axis as there are
+                              ghost layers */
   int32_t prec;            /* ctu_prec.  CTU_FP32 stores state, reconstruction and fluxes
                               in float and keeps the Newton star-pressure solve in double */
   double cfl;              /* Courant number C0, 0 < cfl < 0.5 (six-solve CTU limit) */
@@ -99,6 +100,11 @@ typedef struct {
                               rounding (last-bit differences in a segment's first trace). */
   int32_t riemann;         /* ctu_riemann; both stages use the same solver */
   int32_t recon;           /* ctu_recon */
+  int32_t h_correction;    /* 1: H correction of the second-stage Roe fluxes (App. C): |lambda|
+                              is floored at the largest eta = |(u+a)_R - (u+a)_L|/2 of the
+                              face and of the transverse faces around its two cells, taken
+                              from the second-stage states; needs CTU_RIEMANN_ROE and one
+                              ghost layer more */
 } ctu_config;
 
 typedef struct ctu_grid ctu_grid;

@@ -16,7 +16,7 @@ namespace ctu {
 // Per-grid constants passed by value to every kernel.
 struct GridParams {
   int n[3];             // real cells per axis
-  int ng;               // ghost layers per side: 3 (PPMC), 4 (PPMP)
+  int ng;               // ghost layers per side: 3 (PPMC), 4 (PPMP), plus ext
   int N[3];             // allocated cells per axis (n + 2 ng)
   long long stride;     // elements between consecutive fields
   double dx[3];         // cell widths
@@ -42,6 +42,8 @@ struct GridParams {
   int xrows;            // x-rows of real cells per wavefront in the fused x update
   int riemann;          // 0 exact, 1 Roe with the HLLE failsafe
   int recon;            // 0 PPMC, 1 PPMP
+  int ext;              // 1 with the H correction: the first stage covers one more cell
+                        // along its axis, whose second-stage states the eta pass needs
 };
 
 // Device scalars of one grid (in the workspace).
@@ -706,8 +708,8 @@ __device__ __forceinline__ void exact_flux_prim(const Prim<T>& L, const Prim<T>&
 
 // ======================================================================================
 // Roe solver with the HLLE failsafe (App. B.2), in rotated components (slot 1 normal).
-// W holds the primitives with the pressure floor applied, U the conserved state whose
-// total energy enters the fluxes; a, irho as in Prim.  eta_h >= 0 is the H-correction
+// W holds the primitives with the pressure floor applied, U the conserved state built from
+// them; a, irho as in Prim.  eta_h >= 0 is the H-correction
 // floor on |lambda| (App. C; 0 leaves the eigenvalues unchanged).
 // ======================================================================================
 template <typename T>
@@ -740,8 +742,14 @@ __device__ __forceinline__ void roe_core(const Prim<T>& L, const Prim<T>& R, con
   const T wt = (sl * L.w[3] + sr * R.w[3]) * isum;
   const T Ht = (sl * HL + sr * HR) * isum;
   const T V2 = ut * ut + vt * vt + wt * wt;
+  // a~^2 = (g-1)(H~ - V~^2/2) through the equal form (g-1)[w_L h_L + w_R h_R +
+  // w_L w_R |V_L - V_R|^2 / 2], h = a^2/(g-1): no cancellation when p/rho << V^2
+  const T wl = sl * isum, wr = sr * isum;
+  const T dv0 = R.w[1] - L.w[1], dv1 = R.w[2] - L.w[2], dv2 = R.w[3] - L.w[3];
   T at, iat;
-  sqrt_rsqrt_nr(gm1 * (Ht - T(0.5) * V2), at, iat);
+  sqrt_rsqrt_nr(wl * (L.a * L.a) + wr * (R.a * R.a) +
+                    T(0.5) * gm1 * wl * wr * (dv0 * dv0 + dv1 * dv1 + dv2 * dv2),
+                at, iat);
   const T lm = ut - at, lp = ut + at;
   if (lm >= T(0)) {  // supersonic to the right
 #pragma unroll
@@ -813,15 +821,27 @@ __device__ __forceinline__ void roe_core(const Prim<T>& L, const Prim<T>& R, con
   }
 }
 
-// Roe flux from rotated conserved states (second stage).
+// Roe flux from rotated conserved states (second stage).  The solver starts from the
+// primitive states (App. B.2): the conserved states it uses are rebuilt from them, so a
+// floored pressure also sets the total energy.
 template <typename T>
-__device__ __forceinline__ void roe_flux_u(const T UL[5], const T UR[5], const GridParams& P,
+__device__ __forceinline__ void roe_flux_u(const T Uin_L[5], const T Uin_R[5], const GridParams& P,
                                            T eta_h, T F[5], RiemannCounts& cnt) {
-  const T pf = T(P.p_floor);
+  const T pf = T(P.p_floor), igm1 = T(P.inv_gm1);
   Prim<T> L, R;
-  make_prim(UL, T(P.gamma), T(P.gm1), pf, L);
-  make_prim(UR, T(P.gamma), T(P.gm1), pf, R);
+  make_prim(Uin_L, T(P.gamma), T(P.gm1), pf, L);
+  make_prim(Uin_R, T(P.gamma), T(P.gm1), pf, R);
   cnt.floors += (L.w[4] == pf) + (R.w[4] == pf);
+  T UL[5], UR[5];
+  UL[0] = L.w[0];
+  UR[0] = R.w[0];
+#pragma unroll
+  for (int q = 1; q < 4; ++q) {
+    UL[q] = L.w[0] * L.w[q];
+    UR[q] = R.w[0] * R.w[q];
+  }
+  UL[4] = L.w[4] * igm1 + T(0.5) * L.w[0] * (L.w[1] * L.w[1] + L.w[2] * L.w[2] + L.w[3] * L.w[3]);
+  UR[4] = R.w[4] * igm1 + T(0.5) * R.w[0] * (R.w[1] * R.w[1] + R.w[2] * R.w[2] + R.w[3] * R.w[3]);
   roe_core(L, R, UL, UR, P, eta_h, F, cnt);
 }
 
@@ -857,22 +877,27 @@ __device__ __forceinline__ void roe_flux_w(const T WL[5], const T WR[5], const G
 }
 
 // Solver class of the sweep kernels: the exact solver specialized for its gas class K (0, 3
-// or 5), or the Roe solver (kRoe).
+// or 5), the Roe solver (kRoe), or the Roe solver with the H correction of its second-stage
+// fluxes (kRoeH).
 constexpr int kRoe = 1;
+constexpr int kRoeH = 2;
 
 template <typename T, int K>
 __device__ __forceinline__ void face_flux_w(const T WL[5], const T WR[5], const GridParams& P,
                                             T F[5], RiemannCounts& cnt) {
-  if constexpr (K == kRoe)
+  if constexpr (K == kRoe || K == kRoeH)  // the first stage is not H-corrected
     roe_flux_w<T>(WL, WR, P, T(0), F, cnt);
   else
     exact_flux_w<T, K>(WL, WR, P, F, cnt);
 }
 
+// eta_h: the H-correction floor (kRoeH only).
 template <typename T, int K>
 __device__ __forceinline__ void face_flux_u(const T UL[5], const T UR[5], const GridParams& P,
-                                            T F[5], RiemannCounts& cnt) {
-  if constexpr (K == kRoe)
+                                            T F[5], RiemannCounts& cnt, T eta_h = T(0)) {
+  if constexpr (K == kRoeH)
+    roe_flux_u<T>(UL, UR, P, eta_h, F, cnt);
+  else if constexpr (K == kRoe)
     roe_flux_u<T>(UL, UR, P, T(0), F, cnt);
   else
     exact_flux_fast<T, K>(UL, UR, P, F, cnt);

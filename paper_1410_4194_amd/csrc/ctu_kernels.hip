@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab) {
 
 
 // ---- PPMP flattening and steepening coefficients (App. A.4) ----------------------------------
-// For each cell of the box [-1, n]^3 (every cell whose faces the sweeps trace) and each axis
+// For each cell of the box [-1 - ext, n + ext]^3 (every cell the sweeps trace) and each axis
 // d: the shock-flattening coefficient F_d and the contact-steepening coefficient eta_d, from
 // the densities, pressures and normal velocities of the cells within three along d.  Both
 // depend on u^n only, so one pass before the first stage serves both stages.  The steepening
@@ -130,12 +130,13 @@ __global__ __launch_bounds__(256) void k_ppmp_coef(LaunchTab tab) {
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
   if (!(r.G->s->dt > 0.0)) return;
-  const long long e0 = P.n[0] + 2, e1 = P.n[1] + 2, e2 = P.n[2] + 2;
+  const int lo = -1 - P.ext;  // the first stage traces one more cell with the H correction
+  const long long e0 = P.n[0] - 2 * lo, e1 = P.n[1] - 2 * lo, e2 = P.n[2] - 2 * lo;
   const long long tid = r.lb * blockDim.x + threadIdx.x;
   if (tid >= e0 * e1 * e2) return;
-  const int i = (int)(tid % e0) - 1;
-  const int j = (int)((tid / e0) % e1) - 1;
-  const int k = (int)(tid / (e0 * e1)) - 1;
+  const int i = (int)(tid % e0) + lo;
+  const int j = (int)((tid / e0) % e1) + lo;
+  const int k = (int)(tid / (e0 * e1)) + lo;
   const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
   GLOBAL T* __restrict__ coef = (GLOBAL T*)r.G->coef;
   const long long c = cell_index(P, i, j, k);
@@ -316,7 +317,7 @@ __global__ void k_prim_to_cons(const double* __restrict__ packed, T* __restrict_
 const char* kernel_class_name(int k) {
   static const char* names[K_NUM_CLASSES] = {
       "bc_fill_x", "bc_fill_y", "bc_fill_z", "ppmp_coef", "sweep1_x", "sweep1_y", "sweep1_z",
-      "sweep2_y", "sweep2_z", "sweep2_x_update", "dt_final"};
+      "hcorr_eta", "sweep2_y", "sweep2_z", "sweep2_x_update", "dt_final"};
   return (k >= 0 && k < K_NUM_CLASSES) ? names[k] : "";
 }
 
@@ -386,10 +387,16 @@ long long pass_blocks(const GridParams& P, int pass) {
     case P_BC_X: return cdiv(2LL * P.ng * N1 * N2, kBlock);
     case P_BC_Y: return cdiv(2LL * P.ng * N0 * N2, kBlock);
     case P_BC_Z: return cdiv(2LL * P.ng * N0 * N1, kBlock);
-    case P_COEF: return P.recon == 1 ? cdiv((n0 + 2) * (n1 + 2) * (n2 + 2), kBlock) : 0;
+    case P_COEF: {
+      const long long e = 2 + 2 * P.ext;  // cells [-1 - ext, n + ext] per axis
+      return P.recon == 1 ? cdiv((n0 + e) * (n1 + e) * (n2 + e), kBlock) : 0;
+    }
     case P_S1_X: return cdiv(cdiv((n1 + 2) * N0, XW) * (n2 + 2), kBlock / 64);
-    case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1, P.seg[1]);
-    case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2, P.seg[2]);
+    case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1 + 2 * P.ext, P.seg[1]);
+    case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2 + 2 * P.ext, P.seg[2]);
+    case P_ETA_X: return P.ext ? cdiv((n0 + 1) * (n1 + 2) * (n2 + 2), kBlock) : 0;
+    case P_ETA_Y: return P.ext ? cdiv((n0 + 2) * (n1 + 1) * (n2 + 2), kBlock) : 0;
+    case P_ETA_Z: return P.ext ? cdiv((n0 + 2) * (n1 + 2) * (n2 + 1), kBlock) : 0;
     case P_S2_Y: return cdiv(n0 * n2, kBlock) * cdiv(n1, P.seg[1]);
     case P_S2_Z: return cdiv(n0 * n1, kBlock) * cdiv(n2, P.seg[2]);
     case P_S2_X:
@@ -401,12 +408,14 @@ long long pass_blocks(const GridParams& P, int pass) {
 template <typename T>
 static hipError_t sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
   if (v.recon == 1)
-    return v.gclass == kRoe ? launch_sweeps<T, kRoe, 1>(v, stage, stream, prof)
-                            : launch_sweeps<T, 0, 1>(v, stage, stream, prof);
+    return v.gclass == kRoeH  ? launch_sweeps<T, kRoeH, 1>(v, stage, stream, prof)
+           : v.gclass == kRoe ? launch_sweeps<T, kRoe, 1>(v, stage, stream, prof)
+                              : launch_sweeps<T, 0, 1>(v, stage, stream, prof);
   switch (v.gclass) {
     case 3: return launch_sweeps<T, 3, 0>(v, stage, stream, prof);
     case 5: return launch_sweeps<T, 5, 0>(v, stage, stream, prof);
     case kRoe: return launch_sweeps<T, kRoe, 0>(v, stage, stream, prof);
+    case kRoeH: return launch_sweeps<T, kRoeH, 0>(v, stage, stream, prof);
     default: return launch_sweeps<T, 0, 0>(v, stage, stream, prof);
   }
 }

@@ -16,8 +16,8 @@ namespace ctu {
 
 // Passes of one step, in launch order, plus the stand-alone CFL reduction.
 enum Pass {
-  P_BC_X, P_BC_Y, P_BC_Z, P_COEF, P_S1_X, P_S1_Y, P_S1_Z, P_S2_Y, P_S2_Z, P_S2_X, P_DT,
-  P_NUM
+  P_BC_X, P_BC_Y, P_BC_Z, P_COEF, P_S1_X, P_S1_Y, P_S1_Z, P_ETA_X, P_ETA_Y, P_ETA_Z, P_S2_Y,
+  P_S2_Z, P_S2_X, P_DT, P_NUM
 };
 
 constexpr int kBlock = 256;  // threads per block of every pass
@@ -64,6 +64,8 @@ struct GridDesc {
   DevScalars* s;    // dt, time, CFL bound, error word
   double* part;     // CFL partials, one per update block
   void* coef;       // PPMP only: flattening and steepening coefficients, 2 fields per axis (T)
+  void* eta;        // H correction only: eta of the faces, 1 field per axis (T), face c-1/2
+                    // at cell c
   int bc[6];
   int flags;        // GRID_KEEP_X_FLUXES: also store F^{n+1/2}_x (debug read-back only)
 };
@@ -81,8 +83,8 @@ long long pass_blocks(const GridParams& P, int pass);
 
 // Per-kernel timing with HIP events recorded on the launch stream, accumulated per class.
 enum KernelClass {
-  K_BC_X, K_BC_Y, K_BC_Z, K_PPMP_COEF, K_SWEEP1_X, K_SWEEP1_Y, K_SWEEP1_Z, K_SWEEP2_Y,
-  K_SWEEP2_Z, K_SWEEP2_X_UPDATE, K_DT_FINAL, K_NUM_CLASSES
+  K_BC_X, K_BC_Y, K_BC_Z, K_PPMP_COEF, K_SWEEP1_X, K_SWEEP1_Y, K_SWEEP1_Z, K_HCORR_ETA,
+  K_SWEEP2_Y, K_SWEEP2_Z, K_SWEEP2_X_UPDATE, K_DT_FINAL, K_NUM_CLASSES
 };
 const char* kernel_class_name(int k);
 
@@ -114,14 +116,14 @@ struct PlanView {
   const int* h_start;  // same layout as d_start
   int prec;            // 0 = double, 1 = float
   int gclass;          // solver class: exact with gas class 3 (gamma 5/3), 5 (gamma 7/5) or
-                       // 0 (other), or kRoe
+                       // 0 (other), kRoe, or kRoeH
   int recon;           // 0 PPMC, 1 PPMP (which takes gas class 0 for the exact solver)
 };
 
 // Solver class of a grid: kRoe for the Roe solver; for the exact solver its gas class, K
 // when 2/(gamma-1) = K and 2 gamma/(gamma-1) = K + 2 for K in {3, 5}, else 0.
 inline int gas_class(const GridParams& P) {
-  if (P.riemann == 1) return kRoe;
+  if (P.riemann == 1) return P.ext ? kRoeH : kRoe;
   if (P.recon == 1) return 0;  // PPMP is compiled for the general exact solver only
   return ((P.fan_int_exp == 3 || P.fan_int_exp == 5) && P.root_m == P.fan_int_exp + 2)
              ? P.fan_int_exp
@@ -141,12 +143,16 @@ CTU_DECLARE_SWEEPS(double, 5, 0)
 CTU_DECLARE_SWEEPS(double, kRoe, 0)
 CTU_DECLARE_SWEEPS(double, 0, 1)
 CTU_DECLARE_SWEEPS(double, kRoe, 1)
+CTU_DECLARE_SWEEPS(double, kRoeH, 0)
+CTU_DECLARE_SWEEPS(double, kRoeH, 1)
 CTU_DECLARE_SWEEPS(float, 0, 0)
 CTU_DECLARE_SWEEPS(float, 3, 0)
 CTU_DECLARE_SWEEPS(float, 5, 0)
 CTU_DECLARE_SWEEPS(float, kRoe, 0)
 CTU_DECLARE_SWEEPS(float, 0, 1)
 CTU_DECLARE_SWEEPS(float, kRoe, 1)
+CTU_DECLARE_SWEEPS(float, kRoeH, 0)
+CTU_DECLARE_SWEEPS(float, kRoeH, 1)
 #undef CTU_DECLARE_SWEEPS
 
 // Brackets one launch with profiler events when timing is on.

@@ -59,7 +59,10 @@ size_t partial_bytes(const ctu_config& c) {
 
 // Ghost layers: the PPMC stencil reaches two cells and the CTU transverse correction one
 // more; PPMP's flattening reaches three.
-int ghost_layers(const ctu_config& c) { return c.recon == CTU_RECON_PPMP ? 4 : 3; }
+// The H correction reads second-stage states one cell beyond the real box: one more.
+int ghost_layers(const ctu_config& c) {
+  return (c.recon == CTU_RECON_PPMP ? 4 : 3) + (c.h_correction ? 1 : 0);
+}
 
 long long alloc_cells(const ctu_config& c) {
   const int g = ghost_layers(c);
@@ -67,8 +70,10 @@ long long alloc_cells(const ctu_config& c) {
 }
 
 // Workspace fields: first-stage and CTU flux differences (3 x 5 each); PPMP adds its
-// flattening and steepening coefficients per axis (3 x 2).
-int fields_per_grid(const ctu_config& c) { return 30 + (c.recon == CTU_RECON_PPMP ? 6 : 0); }
+// flattening and steepening coefficients per axis (3 x 2), the H correction its face eta
+// per axis (3).
+int coef_fields(const ctu_config& c) { return c.recon == CTU_RECON_PPMP ? 6 : 0; }
+int fields_per_grid(const ctu_config& c) { return 30 + coef_fields(c) + (c.h_correction ? 3 : 0); }
 
 long long field_stride(const ctu_config& c) {
   long long n = alloc_cells(c);
@@ -89,6 +94,10 @@ ctu_status validate(const ctu_config* c) {
     return fail(CTU_EINVAL, "unknown Riemann solver");
   if (c->recon != CTU_RECON_PPMC && c->recon != CTU_RECON_PPMP)
     return fail(CTU_EINVAL, "unknown reconstruction");
+  if (c->h_correction != 0 && c->h_correction != 1)
+    return fail(CTU_EINVAL, "h_correction must be 0 or 1");
+  if (c->h_correction && c->riemann != CTU_RIEMANN_ROE)
+    return fail(CTU_EINVAL, "the H correction needs the Roe solver");
   for (int a = 0; a < 2; ++a)
     if (c->march_seg[a] < 0 || c->march_seg[a] > 4096)
       return fail(CTU_EINVAL, "march_seg must lie in [0, 4096]");
@@ -144,6 +153,7 @@ GridParams make_params(const ctu_config& c) {
   P.inv_gm1 = 1.0 / (g - 1.0);
   P.riemann = c.riemann;
   P.recon = c.recon;
+  P.ext = c.h_correction ? 1 : 0;
   // march segments: round(n/target) equal segments of the n cells of the axis
   P.seg[0] = 0;
   for (int a = 1; a < 3; ++a) {
@@ -303,6 +313,7 @@ ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, s
   g->desc.s = g->scalars();
   g->desc.part = g->partials();
   g->desc.coef = cfg->recon == CTU_RECON_PPMP ? g->fields() + 30 * g->fbytes() : nullptr;
+  g->desc.eta = cfg->h_correction ? g->fields() + (30 + coef_fields(*cfg)) * g->fbytes() : nullptr;
   for (int i = 0; i < 6; ++i) g->desc.bc[i] = cfg->bc[i];
   g->desc.flags = 0;
   if (!build_starts({g->P}, g->h_start)) {
@@ -612,8 +623,8 @@ struct ctu_batch {
       return ctu::PlanView{d_desc, d_start, (int)descs.size(), start.data(), prec, gclass, recon};
     }
   };
-  // {FP64, FP32} x {PPMC with solver class 0, 3, 5, Roe; PPMP with 0, Roe}
-  static constexpr int kGroups = 12;
+  // {FP64, FP32} x {PPMC with solver class 0, 3, 5, Roe, RoeH; PPMP with 0, Roe, RoeH}
+  static constexpr int kGroups = 16;
   std::vector<Slot> slots;
   int32_t flags = 0;
   hipStream_t caller = nullptr;  // the caller's stream: batch work is ordered after its work
@@ -652,9 +663,10 @@ size_t batch_bytes(int32_t max_slots) {
 // Batch group of a grid; within each precision the groups follow kClass and kRecon below.
 int group_of(const ctu_grid* g) {
   const int c = ctu::gas_class(g->P);
-  const int k = g->P.recon == 1 ? (c == ctu::kRoe ? 5 : 4)
-                                : (c == 3 ? 1 : c == 5 ? 2 : c == ctu::kRoe ? 3 : 0);
-  return (g->cfg.prec == CTU_FP32 ? 6 : 0) + k;
+  const int k = g->P.recon == 1
+                    ? (c == ctu::kRoeH ? 7 : c == ctu::kRoe ? 6 : 5)
+                    : (c == 3 ? 1 : c == 5 ? 2 : c == ctu::kRoe ? 3 : c == ctu::kRoeH ? 4 : 0);
+  return (g->cfg.prec == CTU_FP32 ? 8 : 0) + k;
 }
 
 void drop_graph(ctu_batch* b) {
@@ -758,12 +770,12 @@ ctu_status ctu_batch_create(int32_t max_slots, void* d_work, size_t work_bytes, 
   b->flags = flags;
   b->caller = reinterpret_cast<hipStream_t>(hip_stream);
   char* w = reinterpret_cast<char*>(d_work);
-  static const int kClass[6] = {0, 3, 5, ctu::kRoe, 0, ctu::kRoe};
-  static const int kRecon[6] = {0, 0, 0, 0, 1, 1};
+  static const int kClass[8] = {0, 3, 5, ctu::kRoe, ctu::kRoeH, 0, ctu::kRoe, ctu::kRoeH};
+  static const int kRecon[8] = {0, 0, 0, 0, 0, 1, 1, 1};
   for (int p = 0; p < ctu_batch::kGroups; ++p) {
-    b->groups[p].prec = p / 6;
-    b->groups[p].gclass = kClass[p % 6];
-    b->groups[p].recon = kRecon[p % 6];
+    b->groups[p].prec = p / 8;
+    b->groups[p].gclass = kClass[p % 8];
+    b->groups[p].recon = kRecon[p % 8];
     b->groups[p].d_desc = reinterpret_cast<ctu::GridDesc*>(w);
     b->groups[p].d_start =
         reinterpret_cast<int*>(w + round256(sizeof(ctu::GridDesc) * (size_t)max_slots));

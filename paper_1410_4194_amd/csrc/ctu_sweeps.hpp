@@ -122,6 +122,76 @@ struct NewtonHist {
   }
 };
 
+// H correction (App. C): eta^H of the D-face between cells cm and cp = cm + e_D, the largest
+// eta of the face itself and of the faces on both sides of cm and cp along the other two
+// axes (the nine-point stencil).  eta holds one field per axis, face c-1/2 at cell c.
+template <int D, typename T>
+__device__ __forceinline__ T eta_h_at(const GLOBAL T* __restrict__ eta, const GridParams& P,
+                                      long long cm, long long cp) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const long long st[3] = {1, P.N[0], (long long)P.N[0] * P.N[1]};
+  const GLOBAL T* __restrict__ e1 = eta + T1 * P.stride;
+  const GLOBAL T* __restrict__ e2 = eta + T2 * P.stride;
+  T e = eta[D * P.stride + cp];
+  e = tmax(e, tmax(tmax(e1[cm], e1[cm + st[T1]]), tmax(e1[cp], e1[cp + st[T1]])));
+  e = tmax(e, tmax(tmax(e2[cm], e2[cm + st[T2]]), tmax(e2[cp], e2[cp + st[T2]])));
+  return e;
+}
+
+// H correction: eta = |(u_R + a_R) - (u_L + a_L)| / 2 on the D-faces c-1/2 of the real cells
+// (c in [0, n_D]) over the transverse range [-1, n], from the second-stage input states
+// (re-traced states of cells c-1 and c plus their transverse corrections), the states the
+// second-stage solve of that face sees.  One thread per face; the stencil (cells c-3..c+2
+// along D) is read directly.
+template <typename T, int D, int R>
+__global__ __launch_bounds__(256) void k_eta(LaunchTab tab) {
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  const double dt = r.G->s->dt;
+  if (!(dt > 0.0)) return;
+  const long long ex = P.n[0] + (D == 0 ? 1 : 2), ey = P.n[1] + (D == 1 ? 1 : 2);
+  const long long ez = P.n[2] + (D == 2 ? 1 : 2);
+  const long long tid = r.lb * blockDim.x + threadIdx.x;
+  if (tid >= ex * ey * ez) return;
+  const int i = (int)(tid % ex) - (D == 0 ? 0 : 1);
+  const int j = (int)((tid / ex) % ey) - (D == 1 ? 0 : 1);
+  const int k = (int)(tid / (ex * ey)) - (D == 2 ? 0 : 1);
+  const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
+  const GLOBAL T* __restrict__ dstar_all = (const GLOBAL T*)r.G->flux;
+  GLOBAL T* __restrict__ eta = (GLOBAL T*)r.G->eta;
+  const long long fds = 5 * P.stride;
+  const long long sd = D == 0 ? 1 : (D == 1 ? (long long)P.N[0] : (long long)P.N[0] * P.N[1]);
+  const long long c = cell_index(P, i, j, k);  // the cell on the + side of the face
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const T dtodx = T(dt / P.dx[D]);
+  const T h1 = T(0.5 * dt / P.dx[T1]), h2 = T(0.5 * dt / P.dx[T2]);
+  const T igm1 = T(P.inv_gm1), g = T(P.gamma);
+  Prim<T> q[6];  // cells c-3 .. c+2
+#pragma unroll
+  for (int s = 0; s < 6; ++s) load_prim<T, D>(u, P.stride, c + (long long)(s - 3) * sd, P, q[s]);
+  T sl[4][5];  // slopes of cells c-2 .. c+1
+#pragma unroll
+  for (int s = 0; s < 4; ++s) slope_sel<R>(q[s], q[s + 1], q[s + 2], sl[s]);
+  T WL[5], WR[5], Wx[5], UL[5], UR[5], dT[5];
+  // right face of cell c-1, left face of cell c
+  trace_sel<R>(q[1], q[2], q[3], sl[0], sl[1], sl[2], load_coef<R, D, T>(r.G, P.stride, c - sd),
+               g, dtodx, Wx, WL);
+  to_cons(WL, igm1, UL);
+  transverse_delta<T, D>(dstar_all, fds, P.stride, c - sd, h1, h2, dT);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) UL[f] += dT[f];
+  trace_sel<R>(q[2], q[3], q[4], sl[1], sl[2], sl[3], load_coef<R, D, T>(r.G, P.stride, c), g,
+               dtodx, WR, Wx);
+  to_cons(WR, igm1, UR);
+  transverse_delta<T, D>(dstar_all, fds, P.stride, c, h1, h2, dT);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) UR[f] += dT[f];
+  Prim<T> L, Rp;
+  make_prim(UL, g, T(P.gm1), T(P.p_floor), L);
+  make_prim(UR, g, T(P.gm1), T(P.p_floor), Rp);
+  eta[D * P.stride + c] = T(0.5) * tfabs((Rp.w[1] + Rp.a) - (L.w[1] + L.a));
+}
+
 // K is the gas class of the exact solver (see pfun_fast).
 // STAGE = 1: first-stage fluxes F*_D on the faces c-1/2, c in [0, n_D], transverse range
 //            [-1, n] on both other axes.
@@ -148,16 +218,19 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   const int lo = STAGE == 1 ? -1 : 0;
   const int ea = P.n[0] + (STAGE == 1 ? 2 : 0);
   const int eb = P.n[B] + (STAGE == 1 ? 2 : 0);
-  const int nd = P.n[D];
+  // cells along D: the real ones, one more on each side in the first stage with the H
+  // correction (its eta pass needs second-stage states one cell beyond the real box)
+  const int dlo = STAGE == 1 ? -P.ext : 0;
+  const int nd = P.n[D] - dlo;  // end of the range
   const long long nbx = ((long long)ea * eb + kBlock - 1) / kBlock;
   const int seg = P.seg[D];
-  const long long nseg = (nd + seg - 1) / seg;
+  const long long nseg = (nd - dlo + seg - 1) / seg;
   if (r.lb >= nbx * nseg) return;
   const long long tid = (r.lb % nbx) * kBlock + threadIdx.x;
   if (tid >= (long long)ea * eb) return;
   const int i = (int)(tid % ea) + lo;
   const int o = (int)(tid / ea) + lo;
-  const int f0 = (int)(r.lb / nbx) * seg;
+  const int f0 = dlo + (int)(r.lb / nbx) * seg;
   const int f1 = min(f0 + seg, nd);
   const long long stx = 1, sty = P.N[0], stz = (long long)P.N[0] * P.N[1];
   const long long sd = D == 1 ? sty : stz;
@@ -250,7 +323,11 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
         UL[q] += dT[q];
         UR[q] += dT[q];
       }
-      face_flux_u<T, K>(prevR, UL, P, F, dupface ? dup : cnt);
+      T eta_h = T(0);
+      if constexpr (K == kRoeH)
+        eta_h = eta_h_at<D>((const GLOBAL T*)r.G->eta, P, c0 + (long long)(c - 1) * sd,
+                            c0 + (long long)c * sd);
+      face_flux_u<T, K>(prevR, UL, P, F, dupface ? dup : cnt, eta_h);
     }
     if (HIST) hist.add(dupface ? dup.iters : cnt.iters, !dupface);
     // keep the LDS read of the previous flux below the solve (hoisted above it, the five
@@ -327,14 +404,16 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   // traced primitive face states enter the solver directly
   T WL[5], WR[5];
   PpmpCoef<T> kc{T(0), T(0)};
-  if (R == 1 && in_line && c >= -1 && c <= P.n[0]) kc = load_coef<R, 0, T>(r.G, P.stride, id);
+  if (R == 1 && in_line && c >= -1 - P.ext && c <= P.n[0] + P.ext)
+    kc = load_coef<R, 0, T>(r.G, P.stride, id);
   trace_sel<R>(left, me, right, slm, sl, slp, kc, T(P.gamma), dtodx, WL, WR);
   T prevR[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) prevR[q] = __shfl(WR[q], lm1, 64);
   T F[5] = {T(0), T(0), T(0), T(0), T(0)};  // flux at face c-1/2
   int iters = -1;  // Newton iterations of this lane's counted solve
-  if (lane >= 3 && lane <= 61 && c >= 0 && c <= P.n[0]) {
+  const int e = P.ext;  // one more cell on each side with the H correction
+  if (lane >= 3 && lane <= 61 && c >= -e && c <= P.n[0] + e) {
     // lane 61's face is solved again as the next wavefront's first face: count it there
     const bool counted = lane <= 60 || task % nw == nw - 1;
     RiemannCounts cnt{0u, 0u, 0};
@@ -347,7 +426,7 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   T Fr[5];  // flux at face c+1/2
 #pragma unroll
   for (int q = 0; q < 5; ++q) Fr[q] = __shfl(F[q], lp1, 64);
-  if (lane >= 3 && lane <= 60 && c >= 0 && c < P.n[0]) {
+  if (lane >= 3 && lane <= 60 && c >= -e && c < P.n[0] + e) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) out[q * P.stride + id] = F[q] - Fr[q];
   }
@@ -464,7 +543,9 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
         // lane 61's face is solved again as the next chunk's first face: count it there
         const bool counted = lane <= 60 || cw + XU >= plen - ng;
         RiemannCounts dup{0u, 0u, 0};
-        face_flux_u<T, K>(prevR, UL, P, F, counted ? cnt : dup);
+        T eta_h = T(0);
+        if constexpr (K == kRoeH) eta_h = eta_h_at<0>((const GLOBAL T*)r.G->eta, P, id - 1, id);
+        face_flux_u<T, K>(prevR, UL, P, F, counted ? cnt : dup, eta_h);
         if (counted) iters = cnt.iters;
       }
       // the histogram keeps its wave counts in vector registers: every lane takes the add
@@ -527,6 +608,15 @@ void enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* 
     CTU_TIMED(K_SWEEP1_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 1, HIST, K, R>), nblocks(P_S1_Z),
                                              B, 0, stream, tab(P_S1_Z)));
   } else {
+    if constexpr (K == kRoeH) {
+      // eta of every face the H stencils of the second stage read
+      CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_eta<T, 0, R>), nblocks(P_ETA_X), B, 0, stream,
+                                                tab(P_ETA_X)));
+      CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_eta<T, 1, R>), nblocks(P_ETA_Y), B, 0, stream,
+                                                tab(P_ETA_Y)));
+      CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_eta<T, 2, R>), nblocks(P_ETA_Z), B, 0, stream,
+                                                tab(P_ETA_Z)));
+    }
     // a2-a4 re-traced, a6-a7: G^{n+1/2}, H^{n+1/2} on the real faces, then F^{n+1/2} with the
     // update (a8) and the CFL bound of the new state (a9)
     CTU_TIMED(K_SWEEP2_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 2, HIST, K, R>), nblocks(P_S2_Y),

@@ -50,7 +50,8 @@ class Config(C.Structure):
                 ("gamma", C.c_double), ("bc", C.c_int32 * 6), ("prec", C.c_int32),
                 ("cfl", C.c_double), ("newton_tol", C.c_double),
                 ("newton_max_iter", C.c_int32), ("p_floor", C.c_double),
-                ("march_seg", C.c_int32 * 2), ("riemann", C.c_int32), ("recon", C.c_int32)]
+                ("march_seg", C.c_int32 * 2), ("riemann", C.c_int32), ("recon", C.c_int32),
+                ("h_correction", C.c_int32)]
 
 
 class GridInfo(C.Structure):
@@ -119,7 +120,7 @@ def _check(status: int, allow=()) -> int:
 
 def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64, cfl=0.3,
                 newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20, march_seg=None,
-                riemann=0, recon=0) -> Config:
+                riemann=0, recon=0, h_correction=0) -> Config:
     """Grid configuration.  march_seg: target faces per thread of the y and z sweeps; None
     takes the autotuned table (tiles.json beside this module) when it exists, else the
     library default."""
@@ -141,6 +142,7 @@ def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64,
     c.march_seg[0], c.march_seg[1] = int(march_seg[0]), int(march_seg[1])
     c.riemann = int(riemann)
     c.recon = int(recon)
+    c.h_correction = int(h_correction)
     return c
 
 

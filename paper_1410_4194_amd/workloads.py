@@ -152,6 +152,27 @@ def implosion(n: int = 400, nz: int = 1) -> Workload:
     return Workload(f"implosion_{n}", n, n, nz, d, d, d, 1.4, bc, W, cfl=0.3, t_end=0.045)
 
 
+def noh(n: int = 64, p0: float = 1e-6) -> Workload:
+    """Noh's strong shock in 3D (Sec. 4.3.1): the octant [0, 1]^3 at rho = 1 moving at unit
+    speed toward the origin, gamma 5/3, reflecting walls at x = 0, y = 0, z = 0.  The paper
+    starts from zero pressure and sets the outer faces from the analytic solution; here the
+    pressure is p0 (the pressure floor keeps the solver defined) and the outer faces are
+    outflow, which leaves the solution inside r < 1 - t untouched.  Analytic: shock at
+    r = t/3, density 64 behind it, (1 + t/r)^2 ahead of it."""
+    d = 1.0 / n
+    xc = _centres(n, d)
+    z, y, x = np.meshgrid(xc, xc, xc, indexing="ij")
+    r = np.sqrt(x * x + y * y + z * z)
+    W = np.zeros((5, n, n, n))
+    W[0] = 1.0
+    W[1] = -x / r
+    W[2] = -y / r
+    W[3] = -z / r
+    W[4] = p0
+    bc = (REFLECT, OUTFLOW, REFLECT, OUTFLOW, REFLECT, OUTFLOW)
+    return Workload(f"noh_{n}^3", n, n, n, d, d, d, 5.0 / 3.0, bc, W, cfl=0.3, t_end=0.6)
+
+
 # ------------------------------------------------------------------------------------------
 # Shock-cloud problems (Sec. 5)
 # ------------------------------------------------------------------------------------------

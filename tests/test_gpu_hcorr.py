@@ -1,0 +1,126 @@
+"""GPU parity for the H correction of the second-stage Roe fluxes (App. C): the extended first
+stage, the eta pass over the second-stage states, and the nine-point eta^H inside the
+second-stage sweeps, with PPMC and PPMP.
+
+One step from the same state and dt against the oracle configured the same way (FP64 <=
+1e-12, FP32 <= 1e-5 relative L1); the stationary-contact pattern whose one-step density the
+oracle pins in closed form; the 3D Noh problem (Sec. 4.3.1) against its analytic solution.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle as O
+from paper_1410_4194_amd import workloads as WL
+from tests.common import oracle_config, oracle_state, rel_l1, run_oracle
+from tests.test_oracle_hcorr import _contacts_workload, _expected_density
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctu():
+    from paper_1410_4194_amd import ctu as _ctu
+    return _ctu
+
+
+def _announce(*parts):
+    print("[gpu-test]", *parts, flush=True)
+    sys.stdout.flush()
+
+
+def _step_both(ctu, wl, prec, cfg, u, recon, dt=None):
+    dt = O.compute_dt(cfg, u) if dt is None else dt
+    _announce(wl.name, "roe-h recon", recon, "prec", prec, "cells", wl.cells, "dt", dt)
+    g = ctu.Grid(ctu.make_config(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.gamma, wl.bc,
+                                 prec, wl.cfl, riemann=1, recon=recon, h_correction=1))
+    assert g.info().ghost == (4 if recon == 0 else 5)
+    g.set_state(O.real(cfg, u))
+    g.step(dt)
+    gpu = g.get_state()
+    ref = u.copy()
+    st = O.step(cfg, ref, dt)
+    status, flags, counters = g.check()
+    assert status == ctu.OK, (flags, counters)
+    return gpu, O.real(cfg, ref), counters, st
+
+
+CASES = [
+    ("rough_periodic_37x11x9", lambda: WL.random_state(37, 11, 9, seed=71, spacing=(1.0, 0.5, 0.4))),
+    ("rough_outflow_mach3_20x17x13",
+     lambda: WL.random_state(20, 17, 13, seed=72, bc=(1,) * 6, mach=3.0)),
+    ("smooth_supersonic_24x20x18", lambda: WL.random_state(24, 20, 18, seed=73, rough=False, mach=3.0)),
+    ("rough_reflect_19x12x10", lambda: WL.random_state(19, 12, 10, seed=74, bc=(2,) * 6)),
+    ("sod_128x16x16", lambda: WL.sod(128, 16, 16)),
+    ("strong_rarefaction_128x2x2", lambda: WL.strong_rarefaction(128, 2, 2)),
+    ("shock_cloud_48", lambda: WL.shock_cloud(48, steps=1)),
+    ("kh_33x27x19", lambda: WL.kelvin_helmholtz(33, 27, 19)),
+    ("implosion_64", lambda: WL.implosion(64)),
+    ("noh_24", lambda: WL.noh(24)),
+    ("one_cell_axes_64x1x1", lambda: WL.random_state(64, 1, 1, seed=75)),
+    ("single_cell", lambda: WL.random_state(1, 1, 1, seed=76)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("recon", [0, 1], ids=["ppmc", "ppmp"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_one_step_hcorr(ctu, name, make, recon, prec):
+    wl = make()
+    if recon == 1 and name == "rough_outflow_mach3_20x17x13":
+        pytest.skip("PPMP traces this state to non-physical values (outside the method)")
+    cfg = oracle_config(wl, riemann=1, h_correction=1, recon=recon)
+    u = oracle_state(wl, cfg)
+    gpu, ref, counters, st = _step_both(ctu, wl, prec, cfg, u, recon)
+    err = rel_l1(gpu, ref, wl.gamma)
+    assert err.max() <= (TOL64 if prec == 0 else TOL32), (name, err)
+    # (HLLE counts are not compared: the oracle's first stage also solves a ring of
+    # transverse faces beyond what the second stage reads)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_stationary_contacts_closed_form(ctu, prec):
+    wl = _contacts_workload()
+    dt = 0.1 * wl.dx
+    cfg = oracle_config(wl, riemann=1, h_correction=1)
+    u = oracle_state(wl, cfg)
+    gpu, ref, counters, st = _step_both(ctu, wl, prec, cfg, u, 0, dt=dt)
+    exp = _expected_density(wl.W[0, 0], dt, wl.dx)
+    tol = 1e-15 if prec == 0 else 1e-6
+    for k in range(wl.nz):
+        assert np.allclose(gpu[0, k].astype(np.float64), exp, rtol=0, atol=tol)
+
+
+def test_one_step_hcorr_evolved_noh(ctu):
+    """From the Noh state the oracle has evolved for 25 steps (shock off the walls)."""
+    wl = WL.noh(20)
+    cfg = oracle_config(wl, riemann=1, h_correction=1)
+    cfg, u, t, n = run_oracle(wl, steps=25, cfg=cfg)
+    gpu, ref, counters, st = _step_both(ctu, wl, 0, cfg, u, 0)
+    err = rel_l1(gpu, ref, wl.gamma)
+    assert err.max() <= TOL64, err
+
+
+def test_noh_3d_analytic(ctu):
+    """Noh 96^3 with Roe + H correction to t = 0.6: the pre-shock density follows
+    (1 + t/r)^2 and the shocked gas reaches the analytic 64 (averaged over the shell between
+    the wall-heated core and the shock)."""
+    wl = WL.noh(96)
+    g = ctu.Grid.from_workload(wl, prec=ctu.FP64, riemann=1, h_correction=1)
+    _announce("noh 96^3 to t=0.6")
+    g.advance(100000, t_end=wl.t_end)
+    status, flags, counters = g.check()
+    assert status == ctu.OK, (flags, counters)
+    rho = g.get_state()[0]
+    xc = (np.arange(96) + 0.5) / 96
+    z, y, x = np.meshgrid(xc, xc, xc, indexing="ij")
+    r = np.sqrt(x * x + y * y + z * z)
+    t = wl.t_end
+    pre = (r > 0.28) & (r < 0.38)
+    assert np.abs(rho[pre] / (1.0 + t / r[pre]) ** 2 - 1.0).mean() < 0.02
+    post = (r > 0.08) & (r < 0.17)
+    assert abs(rho[post].mean() / 64.0 - 1.0) < 0.15, rho[post].mean()
