@@ -69,8 +69,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _work(cls, n):
-    """(units, flops, HBM values) of one launch of a kernel class on an n grid."""
+def _work(cls, n, ng=3):
+    """(units, flops, HBM values) of one launch of a kernel class on an n grid with ng ghost
+    layers (flops: exact-solver path only)."""
     nx, ny, nz = n
     d = {"x": 0, "y": 1, "z": 2}
     if cls.startswith("sweep1"):
@@ -89,18 +90,26 @@ def _work(cls, n):
         u = e[0] * e[1] * e[2]
         return u, FLOPS_FACE_STAGE2 * u, VALUES_PER_UNIT["sweep2"] * u
     if cls.startswith("bc_fill"):
-        N = [nx + 6, ny + 6, nz + 6]
-        N[d[cls[-1]]] = 6
+        N = [nx + 2 * ng, ny + 2 * ng, nz + 2 * ng]
+        N[d[cls[-1]]] = 2 * ng
         u = N[0] * N[1] * N[2]
         return u, 0, VALUES_PER_UNIT["bc"] * u
+    if cls == "ppmp_coef":  # per cell: read 5 fields, write 6 coefficients
+        u = (nx + 2) * (ny + 2) * (nz + 2)
+        return u, 0, 11 * u
+    if cls == "hcorr_eta":  # per face: 5 fields + 10 differences read, eta written; the
+        # class times one launch per axis, so one launch carries a third of the faces
+        u = ((nx + 1) * (ny + 2) * (nz + 2) + (nx + 2) * (ny + 1) * (nz + 2) +
+             (nx + 2) * (ny + 2) * (nz + 1)) // 3
+        return u, 0, 16 * u
     if cls == "dt_final":
         u = (ny * nz + 3) // 4
         return u, u, u
     return 0, 0, 0
 
 
-def run_gpu(wl, prec, steps, warmup, ctu, torch, keep_state=False, newton_hist=False):
-    g = ctu.Grid.from_workload(wl, prec=prec)
+def run_gpu(wl, prec, steps, warmup, ctu, torch, keep_state=False, newton_hist=False, **method):
+    g = ctu.Grid.from_workload(wl, prec=prec, **method)
     g.advance(warmup)
     torch.cuda.synchronize()
     g.profile_enable(True)
@@ -236,13 +245,22 @@ def _traffic(cls, prec_name):
     return round(k["fetch_kib"] * t["fetch_scale"] * 1024 + k["write_kib"] * t["write_scale"] * 1024)
 
 
-def roofline(prof, n, eb, prec_name):
+def roofline(prof, n, eb, prec_name, ng=3, exact=True):
     """Roofline of the dominant kernel class (by total time over the timed steps): achieved
     algorithmic flops and algorithmic bytes per second against the FP vector peak and the HBM
-    peak; `bound` is the resource the kernel comes closer to."""
-    cls, (ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
+    peak; `bound` is the resource the kernel comes closer to.  The flop counts hold for the
+    exact-solver PPMC path only; other methods report the HBM side alone."""
+    cls, (ms, launches) = max(((k, v) for k, v in prof.items() if v[1] > 0),
+                              key=lambda kv: kv[1][0])
     avg_s = ms / launches / 1e3
-    units, flops, values = _work(cls, n)
+    units, flops, values = _work(cls, n, ng)
+    if not exact:
+        hbm_frac = values * eb / avg_s / 1e9 / HBM_PEAK_GBS
+        return {"bound": "hbm", "achieved": round(values * eb / avg_s / 1e9, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm_frac, 4),
+                "traffic": None, "kernel": cls, "avg_launch_ms": round(ms / launches, 4),
+                "launches": launches, "units_per_launch": units,
+                "algorithmic_bytes_per_launch": values * eb, "flops": None}
     peak_alu = FP64_VECTOR_PEAK_TFLOPS if eb == 8 else FP32_VECTOR_PEAK_TFLOPS
     alu = {"achieved": round(flops / avg_s / 1e12, 3), "peak": peak_alu, "unit": "TFLOP/s",
            "frac": round(flops / avg_s / 1e12 / peak_alu, 4), "flops_per_launch": flops}
@@ -295,6 +313,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-methods", action="store_true",
+                    help="skip the Roe, Roe+H and PPMP legs on the same workload")
+    ap.add_argument("--method-steps", type=int, default=20)
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-load", type=float, default=0.5,
@@ -341,7 +362,8 @@ def main():
     v64 = cells * args.steps / r64["seconds"]
     log(f"[bench] FP64 {v64:.4g} cell-updates/s, {1e3 * r64['seconds'] / args.steps:.3f} ms/step")
     for k, (ms, la) in sorted(r64["profile"].items(), key=lambda kv: -kv[1][0]):
-        log(f"[bench]   {k:12s} {ms / max(la, 1):8.4f} ms/launch  x{la}")
+        if la:
+            log(f"[bench]   {k:12s} {ms / max(la, 1):8.4f} ms/launch  x{la}")
 
     out = {
         "metric": METRIC, "value": round(v64, 1), "unit": "cell-updates/s", "n_gpus": 1,
@@ -353,7 +375,8 @@ def main():
                    "newton_caps": r64["counters"][1], "status": r64["status"],
                    "newton_iterations_per_solve": r64.get("newton_hist")},
         "roofline": roofline(r64["profile"], n, 8, "fp64"),
-        "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in r64["profile"].items()},
+        "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in r64["profile"].items()
+                       if v[1] > 0},
     }
     if not args.no_fp32:
         log(f"[bench] FP32 form: warmup {args.warmup}, timed {args.steps} steps")
@@ -368,6 +391,29 @@ def main():
                        "rel_l1_vs_fp64": [float(f"{e:.3e}") for e in l1],
                        "t_minus_t_fp64": r32["t"] - r64["t"],
                        "roofline": roofline(r32["profile"], n, 4, "fp32")}
+    if not args.no_methods:
+        # the other reconstruction and Riemann solvers of the paper on the same workload
+        methods = [("ppmc_roe", dict(riemann=1)), ("ppmc_roe_hcorr", dict(riemann=1, h_correction=1)),
+                   ("ppmp_exact", dict(recon=1)), ("ppmp_roe", dict(recon=1, riemann=1)),
+                   ("ppmp_roe_hcorr", dict(recon=1, riemann=1, h_correction=1))]
+        out["methods"] = {}
+        for mname, kw in methods:
+            ng = (4 if kw.get("recon") else 3) + kw.get("h_correction", 0)
+            for pname, prec, eb in (("fp64", ctu.FP64, 8), ("fp32", ctu.FP32, 4)):
+                log(f"[bench] method {mname} {pname}: warmup {args.warmup}, timed {args.method_steps} steps")
+                rm = run_gpu(wl, prec, args.method_steps, args.warmup, ctu, torch, **kw)
+                vm = cells * args.method_steps / rm["seconds"]
+                log(f"[bench]   {vm:.4g} cell-updates/s, status {rm['status']}, "
+                    f"HLLE substitutions {rm['counters'][3]}")
+                out["methods"][f"{mname}_{pname}"] = {
+                    "value": round(vm, 1), "unit": "cell-updates/s", "steps": args.method_steps,
+                    "ms_per_step": round(1e3 * rm["seconds"] / args.method_steps, 4),
+                    "vs_ppmc_exact": round(vm / (v64 if prec == ctu.FP64 else
+                                                 out.get("fp32", {}).get("value", v64)), 3),
+                    "status": rm["status"], "hlle_substitutions": rm["counters"][3],
+                    "roofline": roofline(rm["profile"], n, eb, pname, ng=ng, exact=False),
+                    "kernels_ms": {k: round(v[0] / max(v[1], 1), 4)
+                                   for k, v in rm["profile"].items() if v[1] > 0}}
     if not args.no_batched:
         for name, prec in (("fp64", ctu.FP64), ("fp32", ctu.FP32)):
             log(f"[bench] batched Kelvin-Helmholtz, 64 grids, {name}")
