@@ -405,19 +405,21 @@ long long pass_blocks(const GridParams& P, int pass) {
   return 0;
 }
 
+template <typename T, int R>
+static hipError_t sweeps_r(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
+  switch (v.gclass) {
+    case 3: return launch_sweeps<T, 3, R>(v, stage, stream, prof);
+    case 5: return launch_sweeps<T, 5, R>(v, stage, stream, prof);
+    case kRoe: return launch_sweeps<T, kRoe, R>(v, stage, stream, prof);
+    case kRoeH: return launch_sweeps<T, kRoeH, R>(v, stage, stream, prof);
+    default: return launch_sweeps<T, 0, R>(v, stage, stream, prof);
+  }
+}
+
 template <typename T>
 static hipError_t sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
-  if (v.recon == 1)
-    return v.gclass == kRoeH  ? launch_sweeps<T, kRoeH, 1>(v, stage, stream, prof)
-           : v.gclass == kRoe ? launch_sweeps<T, kRoe, 1>(v, stage, stream, prof)
-                              : launch_sweeps<T, 0, 1>(v, stage, stream, prof);
-  switch (v.gclass) {
-    case 3: return launch_sweeps<T, 3, 0>(v, stage, stream, prof);
-    case 5: return launch_sweeps<T, 5, 0>(v, stage, stream, prof);
-    case kRoe: return launch_sweeps<T, kRoe, 0>(v, stage, stream, prof);
-    case kRoeH: return launch_sweeps<T, kRoeH, 0>(v, stage, stream, prof);
-    default: return launch_sweeps<T, 0, 0>(v, stage, stream, prof);
-  }
+  return v.recon == 1 ? sweeps_r<T, 1>(v, stage, stream, prof)
+                      : sweeps_r<T, 0>(v, stage, stream, prof);
 }
 
 template <typename T>

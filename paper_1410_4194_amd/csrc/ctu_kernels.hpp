@@ -117,14 +117,13 @@ struct PlanView {
   int prec;            // 0 = double, 1 = float
   int gclass;          // solver class: exact with gas class 3 (gamma 5/3), 5 (gamma 7/5) or
                        // 0 (other), kRoe, or kRoeH
-  int recon;           // 0 PPMC, 1 PPMP (which takes gas class 0 for the exact solver)
+  int recon;           // 0 PPMC, 1 PPMP
 };
 
 // Solver class of a grid: kRoe for the Roe solver; for the exact solver its gas class, K
 // when 2/(gamma-1) = K and 2 gamma/(gamma-1) = K + 2 for K in {3, 5}, else 0.
 inline int gas_class(const GridParams& P) {
   if (P.riemann == 1) return P.ext ? kRoeH : kRoe;
-  if (P.recon == 1) return 0;  // PPMP is compiled for the general exact solver only
   return ((P.fan_int_exp == 3 || P.fan_int_exp == 5) && P.root_m == P.fan_int_exp + 2)
              ? P.fan_int_exp
              : 0;
@@ -142,6 +141,8 @@ CTU_DECLARE_SWEEPS(double, 3, 0)
 CTU_DECLARE_SWEEPS(double, 5, 0)
 CTU_DECLARE_SWEEPS(double, kRoe, 0)
 CTU_DECLARE_SWEEPS(double, 0, 1)
+CTU_DECLARE_SWEEPS(double, 3, 1)
+CTU_DECLARE_SWEEPS(double, 5, 1)
 CTU_DECLARE_SWEEPS(double, kRoe, 1)
 CTU_DECLARE_SWEEPS(double, kRoeH, 0)
 CTU_DECLARE_SWEEPS(double, kRoeH, 1)
@@ -150,6 +151,8 @@ CTU_DECLARE_SWEEPS(float, 3, 0)
 CTU_DECLARE_SWEEPS(float, 5, 0)
 CTU_DECLARE_SWEEPS(float, kRoe, 0)
 CTU_DECLARE_SWEEPS(float, 0, 1)
+CTU_DECLARE_SWEEPS(float, 3, 1)
+CTU_DECLARE_SWEEPS(float, 5, 1)
 CTU_DECLARE_SWEEPS(float, kRoe, 1)
 CTU_DECLARE_SWEEPS(float, kRoeH, 0)
 CTU_DECLARE_SWEEPS(float, kRoeH, 1)

@@ -623,8 +623,8 @@ struct ctu_batch {
       return ctu::PlanView{d_desc, d_start, (int)descs.size(), start.data(), prec, gclass, recon};
     }
   };
-  // {FP64, FP32} x {PPMC with solver class 0, 3, 5, Roe, RoeH; PPMP with 0, Roe, RoeH}
-  static constexpr int kGroups = 16;
+  // {FP64, FP32} x {PPMC, PPMP} x solver class {0, 3, 5, Roe, RoeH}
+  static constexpr int kGroups = 20;
   std::vector<Slot> slots;
   int32_t flags = 0;
   hipStream_t caller = nullptr;  // the caller's stream: batch work is ordered after its work
@@ -663,10 +663,8 @@ size_t batch_bytes(int32_t max_slots) {
 // Batch group of a grid; within each precision the groups follow kClass and kRecon below.
 int group_of(const ctu_grid* g) {
   const int c = ctu::gas_class(g->P);
-  const int k = g->P.recon == 1
-                    ? (c == ctu::kRoeH ? 7 : c == ctu::kRoe ? 6 : 5)
-                    : (c == 3 ? 1 : c == 5 ? 2 : c == ctu::kRoe ? 3 : c == ctu::kRoeH ? 4 : 0);
-  return (g->cfg.prec == CTU_FP32 ? 8 : 0) + k;
+  const int k = c == 3 ? 1 : c == 5 ? 2 : c == ctu::kRoe ? 3 : c == ctu::kRoeH ? 4 : 0;
+  return (g->cfg.prec == CTU_FP32 ? 10 : 0) + 5 * g->P.recon + k;
 }
 
 void drop_graph(ctu_batch* b) {
@@ -770,12 +768,11 @@ ctu_status ctu_batch_create(int32_t max_slots, void* d_work, size_t work_bytes, 
   b->flags = flags;
   b->caller = reinterpret_cast<hipStream_t>(hip_stream);
   char* w = reinterpret_cast<char*>(d_work);
-  static const int kClass[8] = {0, 3, 5, ctu::kRoe, ctu::kRoeH, 0, ctu::kRoe, ctu::kRoeH};
-  static const int kRecon[8] = {0, 0, 0, 0, 0, 1, 1, 1};
+  static const int kClass[5] = {0, 3, 5, ctu::kRoe, ctu::kRoeH};
   for (int p = 0; p < ctu_batch::kGroups; ++p) {
-    b->groups[p].prec = p / 8;
-    b->groups[p].gclass = kClass[p % 8];
-    b->groups[p].recon = kRecon[p % 8];
+    b->groups[p].prec = p / 10;
+    b->groups[p].recon = (p % 10) / 5;
+    b->groups[p].gclass = kClass[p % 5];
     b->groups[p].d_desc = reinterpret_cast<ctu::GridDesc*>(w);
     b->groups[p].d_start =
         reinterpret_cast<int*>(w + round256(sizeof(ctu::GridDesc) * (size_t)max_slots));

@@ -1,12 +1,12 @@
 // ctu_sweeps.hip -- instantiates the sweep kernels for one storage type, solver class and
 // reconstruction.  The build compiles this file once per (CTU_SWEEP_T, CTU_SWEEP_K,
-// CTU_SWEEP_R) triple, in parallel: double and float; PPMC (R = 0) with the exact solver for
-// K = 0 (any gamma), 3 (gamma = 5/3) and 5 (gamma = 7/5) and with the Roe solver
-// (K = kRoe = 1); PPMP (R = 1) with the exact solver for any gamma and with Roe.
+// CTU_SWEEP_R) triple, in parallel: double and float; the exact solver for K = 0 (any
+// gamma), 3 (gamma = 5/3) and 5 (gamma = 7/5), the Roe solver (K = kRoe = 1) and Roe with the
+// H correction (K = kRoeH = 2); PPMC (R = 0) and PPMP (R = 1).
 #include "ctu_sweeps.hpp"
 
 #if !defined(CTU_SWEEP_T) || !defined(CTU_SWEEP_K) || !defined(CTU_SWEEP_R)
-#error "compile with -DCTU_SWEEP_T=<double|float> -DCTU_SWEEP_K=<0|1|3|5> -DCTU_SWEEP_R=<0|1>"
+#error "compile with -DCTU_SWEEP_T=<double|float> -DCTU_SWEEP_K=<0|1|2|3|5> -DCTU_SWEEP_R=<0|1>"
 #endif
 
 namespace ctu {
