@@ -121,7 +121,9 @@ def _check(status: int, allow=()) -> int:
 def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64, cfl=0.3,
                 newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20, march_seg=None,
                 riemann=0, recon=0, h_correction=0) -> Config:
-    """Grid configuration.  march_seg: target faces per thread of the y and z sweeps; None
+    """Grid configuration.  riemann: RIEMANN_EXACT or RIEMANN_ROE (with the HLLE failsafe);
+    recon: RECON_PPMC or RECON_PPMP; h_correction: 1 for the H correction of the
+    second-stage Roe fluxes.  march_seg: target cells per thread of the y and z sweeps; None
     takes the autotuned table (tiles.json beside this module) when it exists, else the
     library default."""
     c = Config()
