@@ -65,6 +65,12 @@ FLOPS_CELL_UPDATE = 71
 VALUES_PER_UNIT = {"sweep1": 10, "sweep2": 20, "sweep2_x_update": 30, "bc": 10}
 
 
+# the paper's other reconstruction and Riemann solvers, timed on the same workload
+METHODS = [("ppmc_roe", dict(riemann=1)), ("ppmc_roe_hcorr", dict(riemann=1, h_correction=1)),
+           ("ppmp_exact", dict(recon=1)), ("ppmp_roe", dict(recon=1, riemann=1)),
+           ("ppmp_roe_hcorr", dict(recon=1, riemann=1, h_correction=1))]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -279,28 +285,41 @@ def roofline(prof, n, eb, prec_name, ng=3, exact=True):
     return out
 
 
-def cpu_baseline(wl, seconds_target=15.0):
-    import numpy as np
+def cpu_baseline(wl, seconds_target=15.0, methods=(), method_seconds=3.0):
+    """The serial FP64 oracle on a bounded sample of the same workload: one CTU step of a 64^3
+    box around the shock front and the cloud's upwind edge, repeated for about
+    `seconds_target`; then the same box with each of `methods` ((name, config keywords)),
+    about `method_seconds` each."""
     import oracle as O
 
-    cfg = O.Config(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.gamma, bc=wl.bc, cfl=wl.cfl)
-    u = O.state_from_primitive(cfg, wl.W)
-    O.bc_fill(cfg, u)
-    dt = O.compute_dt(cfg, u)
-    # bounded sample: a 64^3 box around the shock front and the cloud's upwind edge
-    lo = (0, 96, 96)
-    hi = (64, 160, 160)
-    cells = 64 ** 3
-    t_total, reps = 0.0, 0
-    while t_total < seconds_target and reps < 60:
-        t0 = time.perf_counter()
-        O.update_box(cfg, u, dt, lo, hi)
-        t_total += time.perf_counter() - t0
-        reps += 1
-    return {"value": round(cells * reps / t_total, 1), "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{reps} x one CTU step of the 64^3 box [0,64)x[96,160)x[96,160) of the "
-                      f"256^3 shock-cloud initial state, serial FP64 C oracle, {t_total:.1f} s"}
+    lo, hi, cells = (0, 96, 96), (64, 160, 160), 64 ** 3
+
+    def rate(seconds, **kw):
+        cfg = O.Config(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.gamma, bc=wl.bc, cfl=wl.cfl,
+                       **kw)
+        u = O.state_from_primitive(cfg, wl.W)
+        O.bc_fill(cfg, u)
+        dt = O.compute_dt(cfg, u)
+        t_total, reps = 0.0, 0
+        while t_total < seconds and reps < 60:
+            t0 = time.perf_counter()
+            O.update_box(cfg, u, dt, lo, hi)
+            t_total += time.perf_counter() - t0
+            reps += 1
+        del u
+        return cells * reps / t_total, reps, t_total
+
+    v, reps, t_total = rate(seconds_target)
+    out = {"value": round(v, 1), "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+           "sample": f"{reps} x one CTU step of the 64^3 box [0,64)x[96,160)x[96,160) of the "
+                     f"256^3 shock-cloud initial state, serial FP64 C oracle, {t_total:.1f} s"}
+    if methods:
+        out["methods"] = {}
+        for name, kw in methods:
+            vm, rm, tm = rate(method_seconds, **kw)
+            log(f"[bench]   oracle {name}: {vm:.4g} cell-updates/s ({rm} steps of the box)")
+            out["methods"][name] = {"value": round(vm, 1), "steps": rm, "seconds": round(tm, 1)}
+    return out
 
 
 def main():
@@ -393,11 +412,8 @@ def main():
                        "roofline": roofline(r32["profile"], n, 4, "fp32")}
     if not args.no_methods:
         # the other reconstruction and Riemann solvers of the paper on the same workload
-        methods = [("ppmc_roe", dict(riemann=1)), ("ppmc_roe_hcorr", dict(riemann=1, h_correction=1)),
-                   ("ppmp_exact", dict(recon=1)), ("ppmp_roe", dict(recon=1, riemann=1)),
-                   ("ppmp_roe_hcorr", dict(recon=1, riemann=1, h_correction=1))]
         out["methods"] = {}
-        for mname, kw in methods:
+        for mname, kw in METHODS:
             ng = (4 if kw.get("recon") else 3) + kw.get("h_correction", 0)
             for pname, prec, eb in (("fp64", ctu.FP64, 8), ("fp32", ctu.FP32, 4)):
                 log(f"[bench] method {mname} {pname}: warmup {args.warmup}, timed {args.method_steps} steps")
@@ -452,7 +468,7 @@ def main():
         out["precision_study_active"] = precision_study(ctu, torch, WL, x_shock=0.14)
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline: oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline(wl, methods=() if args.no_methods else METHODS)
     print(json.dumps(out), flush=True)
 
 
