@@ -430,6 +430,25 @@ def main():
                     "roofline": roofline(rm["profile"], n, eb, pname, ng=ng, exact=False),
                     "kernels_ms": {k: round(v[0] / max(v[1], 1), 4)
                                    for k, v in rm["profile"].items() if v[1] > 0}}
+    if not args.no_methods:
+        # the primary step on states with structure everywhere: equal face states (which skip
+        # the Newton solve) are the common case in the shock-cloud's ambient gas, rarer here
+        out["workloads"] = {}
+        for wname, wmake in (("turbulent_cloud_256^3", lambda: WL.turbulent_cloud(args.n)),
+                             ("kelvin_helmholtz_256^3", lambda: WL.kelvin_helmholtz(args.n, args.n, args.n))):
+            wl2 = wmake()
+            log(f"[bench] workload {wname} fp64: warmup {args.warmup}, timed {args.method_steps} steps")
+            rw = run_gpu(wl2, ctu.FP64, args.method_steps, args.warmup, ctu, torch, newton_hist=True)
+            vw = wl2.cells * args.method_steps / rw["seconds"]
+            h = rw.get("newton_hist") or {}
+            log(f"[bench]   {vw:.4g} cell-updates/s; Newton iterations per solve {h}")
+            out["workloads"][wname] = {
+                "value": round(vw, 1), "unit": "cell-updates/s", "steps": args.method_steps,
+                "ms_per_step": round(1e3 * rw["seconds"] / args.method_steps, 4),
+                "newton_iterations_per_solve": h,
+                "kernels_ms": {k: round(v[0] / max(v[1], 1), 4)
+                               for k, v in rw["profile"].items() if v[1] > 0}}
+            del wl2
     if not args.no_batched:
         for name, prec in (("fp64", ctu.FP64), ("fp32", ctu.FP32)):
             log(f"[bench] batched Kelvin-Helmholtz, 64 grids, {name}")

@@ -190,9 +190,10 @@ ctu_status ctu_debug_fluxes(ctu_grid* g, int32_t which, int32_t dir, double* con
  *   CTU_PROFILE_TIMING: every kernel a step launches is bracketed by HIP events recorded on
  *     the grid's stream, and elapsed times accumulate per kernel class.
  *   CTU_PROFILE_NEWTON: the sweeps run instrumented copies that count, for every exact
- *     Riemann solve (App. B.1), the Newton iterations it took, in 8 bins: 1, 2, 3, 4, 5-8,
- *     9-16, more than 16, and the cap (newton_max_iter reached).  The copies are slower;
- *     time with CTU_PROFILE_TIMING alone.
+ *     Riemann solve (App. B.1), the Newton iterations it took, in 8 bins: 0 or 1 (equal
+ *     face states have the constant state as their exact solution and take none), 2, 3, 4,
+ *     5-8, 9-16, more than 16, and the cap (newton_max_iter reached).  The copies are
+ *     slower; time with CTU_PROFILE_TIMING alone.
  * ctu_profile_read fills up to max_classes entries of ms[] (total milliseconds) and
  *   launches[] (launch counts) in the order of ctu_profile_name(i), and sets *count to the
  *   number of classes (syncs).  ctu_profile_name returns "" past the last class.

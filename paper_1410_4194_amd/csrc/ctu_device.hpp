@@ -134,10 +134,14 @@ __device__ __forceinline__ T ppm_IR(T beta, T dw, T w6) {
 }
 
 // ---- exact Riemann solver (App. B.1) -----------------------------------------------------
+// Newton iterations recorded for a solve that hit the iteration cap.
+constexpr int kItersCapped = 1 << 30;
+
 struct RiemannCounts {
   unsigned floors;
   unsigned caps;
-  int iters;      // Newton iterations of the last solve, 0 when it hit the cap
+  int iters;      // Newton iterations of the last solve (0 for equal states, kItersCapped
+                  // when it hit the cap)
   unsigned hlle;  // Roe solves that substituted the HLLE flux
 };
 
@@ -566,6 +570,23 @@ __device__ __forceinline__ void exact_flux_prim(const Prim<T>& L, const Prim<T>&
                                                 const GridParams& P, T F[5], RiemannCounts& cnt) {
   const T gm1 = T(P.gm1);
 
+  // Equal states: the exact solution is that state at every x/t, so the flux is the state's
+  // physical flux (the Newton solve would return the same up to rounding).  Uniform regions
+  // trace to equal face states, so whole wavefronts there skip the solve.
+  if (L.w[0] == R.w[0] && L.w[1] == R.w[1] && L.w[2] == R.w[2] && L.w[3] == R.w[3] &&
+      L.w[4] == R.w[4]) {
+    const T rho = L.w[0], u = L.w[1], pres = L.w[4];
+    const T mu = rho * u;
+    const T E = pres * T(P.inv_gm1) + T(0.5) * rho * (u * u + L.w[2] * L.w[2] + L.w[3] * L.w[3]);
+    F[0] = mu;
+    F[1] = mu * u + pres;
+    F[2] = mu * L.w[2];
+    F[3] = mu * L.w[3];
+    F[4] = (E + pres) * u;
+    cnt.iters = 0;
+    return;
+  }
+
   SideK kl, kr;
   kl.rho = L.w[0];
   kl.u = L.w[1];
@@ -617,7 +638,7 @@ __device__ __forceinline__ void exact_flux_prim(const Prim<T>& L, const Prim<T>&
     }
   }
   cnt.caps += conv ? 0u : 1u;
-  if (!conv) cnt.iters = 0;
+  if (!conv) cnt.iters = kItersCapped;
   // u* from f_L, f_R at the final star pressure; when the last step did not move p the
   // values just computed are already those.
   if (!same) {

@@ -106,8 +106,8 @@ __device__ __forceinline__ PpmpCoef<T> load_coef(const GridDesc* G, long long st
 struct NewtonHist {
   unsigned long long n[8];
   __device__ void add(int iters, bool counted = true) {
-    const int b = iters == 0 ? 7
-                  : iters <= 4 ? iters - 1 : (iters <= 8 ? 4 : (iters <= 16 ? 5 : 6));
+    const int b = iters >= kItersCapped ? 7
+                  : iters <= 1 ? 0 : (iters <= 4 ? iters - 1 : (iters <= 8 ? 4 : (iters <= 16 ? 5 : 6)));
 #pragma unroll
     for (int k = 0; k < 8; ++k) n[k] += __popcll(__ballot(counted && b == k));
   }

@@ -31,7 +31,7 @@ FLAG_NONFINITE, FLAG_DENSITY, FLAG_PFLOOR, FLAG_NEWTON_CAP = 1, 2, 4, 8
 TICKET_QUEUED, TICKET_RUNNING, TICKET_DONE, TICKET_FAILED, TICKET_UNKNOWN = 0, 1, 2, 3, -1
 BATCH_GRAPH = 1
 PROFILE_TIMING, PROFILE_NEWTON = 1, 2
-NEWTON_BINS = ("1", "2", "3", "4", "5-8", "9-16", ">16", "cap")
+NEWTON_BINS = ("0-1", "2", "3", "4", "5-8", "9-16", ">16", "cap")
 
 EXPORTS = [
     "ctu_config_default", "ctu_workspace_bytes", "ctu_grid_create", "ctu_grid_destroy",
