@@ -100,9 +100,9 @@ def _work(cls, n, ng=3):
         N[d[cls[-1]]] = 2 * ng
         u = N[0] * N[1] * N[2]
         return u, 0, VALUES_PER_UNIT["bc"] * u
-    if cls == "ppmp_coef":  # per cell: read 5 fields, write 6 coefficients
+    if cls == "ppmp_coef":  # one launch per axis; per cell: read 5 fields, write 2
         u = (nx + 2) * (ny + 2) * (nz + 2)
-        return u, 0, 11 * u
+        return u, 0, 7 * u
     if cls == "hcorr_eta":  # per face: 5 fields + 10 differences read, eta written; the
         # class times one launch per axis, so one launch carries a third of the faces
         u = ((nx + 1) * (ny + 2) * (nz + 2) + (nx + 2) * (ny + 1) * (nz + 2) +

@@ -752,6 +752,13 @@ __device__ __forceinline__ void roe_core(const Prim<T>& L, const Prim<T>& R, con
     FR[3] = mr * R.w[3];
     FR[4] = (UR[4] + R.w[4]) * R.w[1];
   }
+  // equal states: dU = 0, so every wave strength vanishes and the flux is F_L
+  if (L.w[0] == R.w[0] && L.w[1] == R.w[1] && L.w[2] == R.w[2] && L.w[3] == R.w[3] &&
+      L.w[4] == R.w[4]) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) F[q] = FL[q];
+    return;
+  }
   // Roe averages, weights sqrt(rho)
   T sl, isl, sr, isr;
   sqrt_rsqrt_nr(L.w[0], sl, isl);

@@ -112,69 +112,140 @@ __global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab) {
 // For each cell of the box [-1 - ext, n + ext]^3 (every cell the sweeps trace) and each axis
 // d: the shock-flattening coefficient F_d and the contact-steepening coefficient eta_d, from
 // the densities, pressures and normal velocities of the cells within three along d.  Both
-// depend on u^n only, so one pass before the first stage serves both stages.  The steepening
-// test reads an inflection of the density (second differences of opposite sign on the two
-// sides of the cell, as in CW84); the 1/(6 dx^2) of the second differences cancels in
+// depend on u^n only, so one pass per axis before the first stage serves both stages.  The
+// steepening test reads an inflection of the density (second differences of opposite sign on
+// the two sides of the cell, as in CW84); the 1/(6 dx^2) of the second differences cancels in
 // eta~ and does not change the sign test, so it is left out.
 template <typename T>
-__device__ __forceinline__ T flat_tilde(const T p[5], const T un[5]) {
-  const T dp = p[3] - p[1];
-  if (tfabs(dp) < tmin(p[3], p[1]) * (T(1) / T(3))) return T(0);  // weak jump
-  if (un[3] - un[1] > T(0)) return T(0);                         // expansion
-  const T S = dp / (p[4] - p[0]);
+__device__ __forceinline__ T flat_tilde(T pm, T pmm, T pp, T ppp, T um, T up) {
+  const T dp = pp - pm;  // p_{i+1} - p_{i-1}
+  if (tfabs(dp) < tmin(pp, pm) * (T(1) / T(3))) return T(0);  // weak jump
+  if (up - um > T(0)) return T(0);                               // expansion
+  const T S = dp / (ppp - pmm);  // over p_{i+2} - p_{i-2}
   return tmax(T(0), tmin(T(1), T(10) * (S - T(0.75))));
 }
 
+// Steepening coefficient of cell i from rho_{i-2..i+2} and p_{i-1}, p_{i+1}.
 template <typename T>
-__global__ __launch_bounds__(256) void k_ppmp_coef(LaunchTab tab) {
+__device__ __forceinline__ T steep_eta(T rmm, T rm, T r0, T rp, T rpp, T pm, T pp, T gamma) {
+  const T dr = tfabs(rp - rm) / tmin(rp, rm);
+  const T dpr = tfabs(pp - pm) / tmin(pp, pm);
+  if (!(dr > T(0.01) && dpr < T(0.1) * gamma * dr)) return T(0);
+  const T d2m = r0 - T(2) * rm + rmm;
+  const T d2p = rpp - T(2) * rp + r0;
+  if (!(d2m * d2p < T(0))) return T(0);
+  const T et = -(d2p - d2m) / (T(6) * (rp - rm));
+  return tmax(T(0), tmin(T(20) * et - T(1), T(1)));
+}
+
+// Density, pressure (floored) and the velocity along axis d of one cell.
+template <typename T, int DIR>
+__device__ __forceinline__ void coef_prim(const GLOBAL T* __restrict__ u, long long stride,
+                                          long long id, T gm1, T pf, T& rho, T& p, T& un) {
+  const T r0 = u[id], m1 = u[stride + id], m2 = u[2 * stride + id];
+  const T m3 = u[3 * stride + id], E = u[4 * stride + id];
+  const T ir = rcp_nr(r0);
+  T pr = gm1 * (E - T(0.5) * (m1 * m1 + m2 * m2 + m3 * m3) * ir);
+  if (!(pr >= pf)) pr = pf;
+  rho = r0;
+  p = pr;
+  un = (DIR == 0 ? m1 : (DIR == 1 ? m2 : m3)) * ir;
+}
+
+// Coefficients of the centre cell of a seven-cell window (cells c-3..c+3).
+template <typename T>
+__device__ __forceinline__ void ppmp_coefs(const T r[7], const T p[7], const T un[7], T gamma,
+                                           T& flat, T& eta) {
+  const T Fm = flat_tilde(p[1], p[0], p[3], p[4], un[1], un[3]);  // cell c-1
+  const T F0 = flat_tilde(p[2], p[1], p[4], p[5], un[2], un[4]);  // cell c
+  const T Fp = flat_tilde(p[3], p[2], p[5], p[6], un[3], un[5]);  // cell c+1
+  flat = (p[4] - p[2] < T(0)) ? tmax(F0, Fp) : tmax(F0, Fm);
+  eta = steep_eta(r[1], r[2], r[3], r[4], r[5], p[2], p[4], gamma);
+}
+
+// Axis x: the rows of one z-plane (over [-1 - ext, n_y + ext]) lie back to back and are
+// treated as one flattened line; lane l holds position XW w - 3 + l and reads its neighbours
+// within three by lane shuffles; lanes 3..60 store their cell's coefficients.  The stencil of
+// every cell that needs coefficients lies in its own row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ppmp_coef_x(LaunchTab tab) {
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
   if (!(r.G->s->dt > 0.0)) return;
-  const int lo = -1 - P.ext;  // the first stage traces one more cell with the H correction
-  const long long e0 = P.n[0] - 2 * lo, e1 = P.n[1] - 2 * lo, e2 = P.n[2] - 2 * lo;
-  const long long tid = r.lb * blockDim.x + threadIdx.x;
-  if (tid >= e0 * e1 * e2) return;
-  const int i = (int)(tid % e0) + lo;
-  const int j = (int)((tid / e0) % e1) + lo;
-  const int k = (int)(tid / (e0 * e1)) + lo;
+  const int e = 1 + P.ext;  // cells [-e, n + e - 1] per axis
+  const int lane = threadIdx.x & 63;
+  const long long task = r.lb * (kBlock / 64) + (threadIdx.x >> 6);
+  const long long plen = (long long)(P.n[1] + 2 * e) * P.N[0];
+  const long long nw = (plen + XW - 1) / XW;
+  if (task >= nw * (P.n[2] + 2 * e)) return;  // whole wavefront exits together
+  const int k = (int)(task / nw) - e;
+  const long long pos = (task % nw) * XW - 3 + lane;
+  const bool in_line = pos >= 0 && pos < plen;
+  const int c = in_line ? (int)(pos % P.N[0]) - P.ng : -P.ng - 1;
+  const long long id = cell_index(P, -P.ng, -e, k) + pos;
   const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
-  GLOBAL T* __restrict__ coef = (GLOBAL T*)r.G->coef;
-  const long long c = cell_index(P, i, j, k);
+  T rho = T(1), p = T(1), un = T(0);
+  if (in_line) coef_prim<T, 0>(u, P.stride, id, T(P.gm1), T(P.p_floor), rho, p, un);
+  T rw[7], pw[7], uw[7];
+#pragma unroll
+  for (int s = 0; s < 7; ++s) {
+    const int src = min(max(lane + s - 3, 0), 63);
+    rw[s] = __shfl(rho, src, 64);
+    pw[s] = __shfl(p, src, 64);
+    uw[s] = __shfl(un, src, 64);
+  }
+  if (lane >= 3 && lane <= 60 && in_line && c >= -e && c < P.n[0] + e) {
+    T flat, eta;
+    ppmp_coefs(rw, pw, uw, T(P.gamma), flat, eta);
+    GLOBAL T* __restrict__ coef = (GLOBAL T*)r.G->coef;
+    coef[id] = flat;
+    coef[P.stride + id] = eta;
+  }
+}
+
+// Axes y and z: each thread marches one column along D over a segment of kCoefSeg cells with a
+// seven-cell window, reading each cell once.  Block layout per grid: (plane block, segment).
+constexpr int kCoefSeg = 32;
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_ppmp_coef_march(LaunchTab tab) {
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  if (!(r.G->s->dt > 0.0)) return;
+  constexpr int B = (D == 1) ? 2 : 1;  // the transverse axis other than x
+  const int e = 1 + P.ext;
+  const int ea = P.n[0] + 2 * e, eb = P.n[B] + 2 * e, nd = P.n[D] + 2 * e;
+  const long long nbx = ((long long)ea * eb + kBlock - 1) / kBlock;
+  const long long nseg = (nd + kCoefSeg - 1) / kCoefSeg;
+  if (r.lb >= nbx * nseg) return;
+  const long long tid = (r.lb % nbx) * kBlock + threadIdx.x;
+  if (tid >= (long long)ea * eb) return;
+  const int i = (int)(tid % ea) - e;
+  const int o = (int)(tid / ea) - e;
+  const int f0 = (int)(r.lb / nbx) * kCoefSeg - e;
+  const int f1 = min(f0 + kCoefSeg, nd - e);
+  const long long sd = D == 1 ? (long long)P.N[0] : (long long)P.N[0] * P.N[1];
+  const long long c0 = D == 1 ? cell_index(P, i, 0, o) : cell_index(P, i, o, 0);
+  const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
+  GLOBAL T* __restrict__ coef = (GLOBAL T*)r.G->coef + 2 * D * P.stride;
   const T gm1 = T(P.gm1), pf = T(P.p_floor), gamma = T(P.gamma);
+  T rw[7], pw[7], uw[7];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const long long sd = d == 0 ? 1 : (d == 1 ? (long long)P.N[0] : (long long)P.N[0] * P.N[1]);
-    T rho[7], p[7], un[7];
+  for (int s = 1; s < 7; ++s)  // cells f0-3 .. f0+2 into slots 0..5 (shifted below)
+    coef_prim<T, D>(u, P.stride, c0 + (long long)(f0 + s - 4) * sd, gm1, pf, rw[s], pw[s], uw[s]);
+  for (int c = f0; c < f1; ++c) {
 #pragma unroll
-    for (int s = 0; s < 7; ++s) {
-      const long long id = c + (long long)(s - 3) * sd;
-      const T r0 = u[id], m1 = u[P.stride + id], m2 = u[2 * P.stride + id];
-      const T m3 = u[3 * P.stride + id], E = u[4 * P.stride + id];
-      const T ir = rcp_nr(r0);
-      T pr = gm1 * (E - T(0.5) * (m1 * m1 + m2 * m2 + m3 * m3) * ir);
-      if (!(pr >= pf)) pr = pf;
-      rho[s] = r0;
-      p[s] = pr;
-      un[s] = (d == 0 ? m1 : (d == 1 ? m2 : m3)) * ir;
+    for (int s = 0; s < 6; ++s) {
+      rw[s] = rw[s + 1];
+      pw[s] = pw[s + 1];
+      uw[s] = uw[s + 1];
     }
-    // flattening: the coefficients of cells c-1, c, c+1, then the neighbour on the side the
-    // pressure falls toward
-    const T Fm = flat_tilde(p, un), F0 = flat_tilde(p + 1, un + 1), Fp = flat_tilde(p + 2, un + 2);
-    const T flat = (p[4] - p[2] < T(0)) ? tmax(F0, Fp) : tmax(F0, Fm);
-    // steepening of the density (cells c-2..c+2 in slots 1..5)
-    T eta = T(0);
-    const T dr = tfabs(rho[4] - rho[2]) / tmin(rho[4], rho[2]);
-    const T dpr = tfabs(p[4] - p[2]) / tmin(p[4], p[2]);
-    if (dr > T(0.01) && dpr < T(0.1) * gamma * dr) {
-      const T d2m = rho[3] - T(2) * rho[2] + rho[1];
-      const T d2p = rho[5] - T(2) * rho[4] + rho[3];
-      if (d2m * d2p < T(0)) {
-        const T et = -(d2p - d2m) / (T(6) * (rho[4] - rho[2]));
-        eta = tmax(T(0), tmin(T(20) * et - T(1), T(1)));
-      }
-    }
-    coef[(2 * d) * P.stride + c] = flat;
-    coef[(2 * d + 1) * P.stride + c] = eta;
+    coef_prim<T, D>(u, P.stride, c0 + (long long)(c + 3) * sd, gm1, pf, rw[6], pw[6], uw[6]);
+    T flat, eta;
+    ppmp_coefs(rw, pw, uw, gamma, flat, eta);
+    const long long id = c0 + (long long)c * sd;
+    coef[id] = flat;
+    coef[P.stride + id] = eta;
   }
 }
 
@@ -387,9 +458,17 @@ long long pass_blocks(const GridParams& P, int pass) {
     case P_BC_X: return cdiv(2LL * P.ng * N1 * N2, kBlock);
     case P_BC_Y: return cdiv(2LL * P.ng * N0 * N2, kBlock);
     case P_BC_Z: return cdiv(2LL * P.ng * N0 * N1, kBlock);
-    case P_COEF: {
+    case P_COEF_X: {
       const long long e = 2 + 2 * P.ext;  // cells [-1 - ext, n + ext] per axis
-      return P.recon == 1 ? cdiv((n0 + e) * (n1 + e) * (n2 + e), kBlock) : 0;
+      return P.recon == 1 ? cdiv(cdiv((n1 + e) * N0, XW) * (n2 + e), kBlock / 64) : 0;
+    }
+    case P_COEF_Y: {
+      const long long e = 2 + 2 * P.ext;
+      return P.recon == 1 ? cdiv((n0 + e) * (n2 + e), kBlock) * cdiv(n1 + e, kCoefSeg) : 0;
+    }
+    case P_COEF_Z: {
+      const long long e = 2 + 2 * P.ext;
+      return P.recon == 1 ? cdiv((n0 + e) * (n1 + e), kBlock) * cdiv(n2 + e, kCoefSeg) : 0;
     }
     case P_S1_X: return cdiv(cdiv((n1 + 2) * N0, XW) * (n2 + 2), kBlock / 64);
     case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1 + 2 * P.ext, P.seg[1]);
@@ -438,9 +517,14 @@ static hipError_t enqueue_step(const PlanView& v, bool device_dt, hipStream_t st
             hipLaunchKernelGGL((k_bc_fill<T, 1>), nblocks(P_BC_Y), B, 0, stream, tab(P_BC_Y)));
   CTU_TIMED(K_BC_Z,
             hipLaunchKernelGGL((k_bc_fill<T, 2>), nblocks(P_BC_Z), B, 0, stream, tab(P_BC_Z)));
-  if (v.recon == 1)
-    CTU_TIMED(K_PPMP_COEF, hipLaunchKernelGGL((k_ppmp_coef<T>), nblocks(P_COEF), B, 0, stream,
-                                              tab(P_COEF)));
+  if (v.recon == 1) {
+    CTU_TIMED(K_PPMP_COEF, hipLaunchKernelGGL((k_ppmp_coef_x<T>), nblocks(P_COEF_X), B, 0, stream,
+                                              tab(P_COEF_X)));
+    CTU_TIMED(K_PPMP_COEF, hipLaunchKernelGGL((k_ppmp_coef_march<T, 1>), nblocks(P_COEF_Y), B, 0,
+                                              stream, tab(P_COEF_Y)));
+    CTU_TIMED(K_PPMP_COEF, hipLaunchKernelGGL((k_ppmp_coef_march<T, 2>), nblocks(P_COEF_Z), B, 0,
+                                              stream, tab(P_COEF_Z)));
+  }
   // stage 1 (a2-a5), then stage 2 (a2-a4 re-traced, a6-a7) with the update (a8) fused into
   // its last sweep
   hipError_t e = sweeps<T>(v, 1, stream, prof);
