@@ -138,60 +138,6 @@ __device__ __forceinline__ T eta_h_at(const GLOBAL T* __restrict__ eta, const Gr
   return e;
 }
 
-// H correction: eta = |(u_R + a_R) - (u_L + a_L)| / 2 on the D-faces c-1/2 of the real cells
-// (c in [0, n_D]) over the transverse range [-1, n], from the second-stage input states
-// (re-traced states of cells c-1 and c plus their transverse corrections), the states the
-// second-stage solve of that face sees.  One thread per face; the stencil (cells c-3..c+2
-// along D) is read directly.
-template <typename T, int D, int R>
-__global__ __launch_bounds__(256) void k_eta(LaunchTab tab) {
-  const BlockRef r = block_ref(tab);
-  const GridParams P = r.G->P;
-  const double dt = r.G->s->dt;
-  if (!(dt > 0.0)) return;
-  const long long ex = P.n[0] + (D == 0 ? 1 : 2), ey = P.n[1] + (D == 1 ? 1 : 2);
-  const long long ez = P.n[2] + (D == 2 ? 1 : 2);
-  const long long tid = r.lb * blockDim.x + threadIdx.x;
-  if (tid >= ex * ey * ez) return;
-  const int i = (int)(tid % ex) - (D == 0 ? 0 : 1);
-  const int j = (int)((tid / ex) % ey) - (D == 1 ? 0 : 1);
-  const int k = (int)(tid / (ex * ey)) - (D == 2 ? 0 : 1);
-  const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
-  const GLOBAL T* __restrict__ dstar_all = (const GLOBAL T*)r.G->flux;
-  GLOBAL T* __restrict__ eta = (GLOBAL T*)r.G->eta;
-  const long long fds = 5 * P.stride;
-  const long long sd = D == 0 ? 1 : (D == 1 ? (long long)P.N[0] : (long long)P.N[0] * P.N[1]);
-  const long long c = cell_index(P, i, j, k);  // the cell on the + side of the face
-  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const T dtodx = T(dt / P.dx[D]);
-  const T h1 = T(0.5 * dt / P.dx[T1]), h2 = T(0.5 * dt / P.dx[T2]);
-  const T igm1 = T(P.inv_gm1), g = T(P.gamma);
-  Prim<T> q[6];  // cells c-3 .. c+2
-#pragma unroll
-  for (int s = 0; s < 6; ++s) load_prim<T, D>(u, P.stride, c + (long long)(s - 3) * sd, P, q[s]);
-  T sl[4][5];  // slopes of cells c-2 .. c+1
-#pragma unroll
-  for (int s = 0; s < 4; ++s) slope_sel<R>(q[s], q[s + 1], q[s + 2], sl[s]);
-  T WL[5], WR[5], Wx[5], UL[5], UR[5], dT[5];
-  // right face of cell c-1, left face of cell c
-  trace_sel<R>(q[1], q[2], q[3], sl[0], sl[1], sl[2], load_coef<R, D, T>(r.G, P.stride, c - sd),
-               g, dtodx, Wx, WL);
-  to_cons(WL, igm1, UL);
-  transverse_delta<T, D>(dstar_all, fds, P.stride, c - sd, h1, h2, dT);
-#pragma unroll
-  for (int f = 0; f < 5; ++f) UL[f] += dT[f];
-  trace_sel<R>(q[2], q[3], q[4], sl[1], sl[2], sl[3], load_coef<R, D, T>(r.G, P.stride, c), g,
-               dtodx, WR, Wx);
-  to_cons(WR, igm1, UR);
-  transverse_delta<T, D>(dstar_all, fds, P.stride, c, h1, h2, dT);
-#pragma unroll
-  for (int f = 0; f < 5; ++f) UR[f] += dT[f];
-  Prim<T> L, Rp;
-  make_prim(UL, g, T(P.gm1), T(P.p_floor), L);
-  make_prim(UR, g, T(P.gm1), T(P.p_floor), Rp);
-  eta[D * P.stride + c] = T(0.5) * tfabs((Rp.w[1] + Rp.a) - (L.w[1] + L.a));
-}
-
 // K is the gas class of the exact solver (see pfun_fast).
 // STAGE = 1: first-stage fluxes F*_D on the faces c-1/2, c in [0, n_D], transverse range
 //            [-1, n] on both other axes.
@@ -205,6 +151,10 @@ __global__ __launch_bounds__(256) void k_eta(LaunchTab tab) {
 template <typename T, int D, int STAGE, bool HIST, int K, int R>
 __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   static_assert(D == 1 || D == 2, "marching sweeps run along y or z");
+  // STAGE 3 (H correction): the second-stage states of the faces over the first stage's
+  // transverse range, reduced to eta = |(u+a)_R - (u+a)_L|/2 instead of solved
+  constexpr bool ETA = STAGE == 3;
+  constexpr bool S2 = STAGE >= 2;  // second-stage states (re-traced + transverse correction)
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
   DevScalars* __restrict__ s = r.G->s;
@@ -215,9 +165,10 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   const long long fds = 5 * P.stride;
   GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + (STAGE == 1 ? D : 3 + D) * fds;
   constexpr int B = (D == 1) ? 2 : 1;  // the transverse axis other than x
-  const int lo = STAGE == 1 ? -1 : 0;
-  const int ea = P.n[0] + (STAGE == 1 ? 2 : 0);
-  const int eb = P.n[B] + (STAGE == 1 ? 2 : 0);
+  constexpr bool EXT_T = STAGE != 2;   // transverse range [-1, n]
+  const int lo = EXT_T ? -1 : 0;
+  const int ea = P.n[0] + (EXT_T ? 2 : 0);
+  const int eb = P.n[B] + (EXT_T ? 2 : 0);
   // cells along D: the real ones, one more on each side in the first stage with the H
   // correction (its eta pass needs second-stage states one cell beyond the real box)
   const int dlo = STAGE == 1 ? -P.ext : 0;
@@ -268,7 +219,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
     } else {
       to_cons(WR, igm1, prevR);
     }
-    if (STAGE == 2) {
+    if (S2) {
       T dT[5];
       transverse_delta<T, D>(dstar_all, fds, P.stride, c0 + (long long)(f0 - 1) * sd, h1, h2,
                              dT);
@@ -324,16 +275,27 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
         UR[q] += dT[q];
       }
       T eta_h = T(0);
-      if constexpr (K == kRoeH)
+      if constexpr (K == kRoeH && !ETA)  // (the eta pass writes these)
         eta_h = eta_h_at<D>((const GLOBAL T*)r.G->eta, P, c0 + (long long)(c - 1) * sd,
                             c0 + (long long)c * sd);
-      face_flux_u<T, K>(prevR, UL, P, F, dupface ? dup : cnt, eta_h);
+      if constexpr (ETA) {
+        // the face is written by the segment that owns it (not the duplicate)
+        if (!dupface) {
+          Prim<T> Lq, Rq;
+          make_prim(prevR, T(P.gamma), T(P.gm1), T(P.p_floor), Lq);
+          make_prim(UL, T(P.gamma), T(P.gm1), T(P.p_floor), Rq);
+          GLOBAL T* __restrict__ eta = (GLOBAL T*)r.G->eta + D * P.stride;
+          eta[c0 + (long long)c * sd] = T(0.5) * tfabs((Rq.w[1] + Rq.a) - (Lq.w[1] + Lq.a));
+        }
+      } else {
+        face_flux_u<T, K>(prevR, UL, P, F, dupface ? dup : cnt, eta_h);
+      }
     }
     if (HIST) hist.add(dupface ? dup.iters : cnt.iters, !dupface);
     // keep the LDS read of the previous flux below the solve (hoisted above it, the five
     // values would stay live through the solve and cost the first stage a wave per SIMD)
     asm volatile("" ::: "memory");
-    if (c > f0) {  // cell c-1 now has both faces
+    if (!ETA && c > f0) {  // cell c-1 now has both faces
       const long long co = c0 + (long long)(c - 1) * sd;
 #pragma unroll
       for (int sl = 0; sl < 5; ++sl)
@@ -341,7 +303,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
     }
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      prevF[q][threadIdx.x] = F[q];
+      if (!ETA) prevF[q][threadIdx.x] = F[q];
       prevR[q] = UR[q];
       s0[q] = s1[q];
       s1[q] = s2[q];
@@ -352,6 +314,76 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   }
   flush_counts(cnt, s);
   if (HIST) hist.flush(s);
+}
+
+// H correction along x: eta of the x-faces of the real cells (c in [0, n_x]) over rows and
+// planes [-1, n], from the second-stage states (re-traced, plus the transverse correction),
+// on the flattened plane lines of the first-stage x sweep; lanes 3..60 write the face of
+// their own cell, so every face is written once.
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_eta_x(LaunchTab tab) {
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  const double dt = r.G->s->dt;
+  if (!(dt > 0.0)) return;
+  const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
+  const GLOBAL T* __restrict__ dstar_all = (const GLOBAL T*)r.G->flux;
+  const long long fds = 5 * P.stride;
+  const int lane = threadIdx.x & 63;
+  const long long task = r.lb * (kBlock / 64) + (threadIdx.x >> 6);
+  const long long plen = (long long)(P.n[1] + 2) * P.N[0];
+  const long long nw = (plen + XW - 1) / XW;
+  if (task >= nw * (P.n[2] + 2)) return;  // whole wavefront exits together
+  const int k = (int)(task / nw) - 1;
+  const long long p = (task % nw) * XW - 3 + lane;
+  const bool in_line = p >= 0 && p < plen;
+  const int c = in_line ? (int)(p % P.N[0]) - P.ng : -P.ng - 1;
+  const long long id = cell_index(P, -P.ng, -1, k) + p;
+  const T dtodx = T(dt / P.dx[0]);
+  const T h1 = T(0.5 * dt / P.dx[1]), h2 = T(0.5 * dt / P.dx[2]);
+  const T igm1 = T(P.inv_gm1), g = T(P.gamma);
+  Prim<T> me;
+  if (in_line)
+    load_prim<T, 0>(u, P.stride, id, P, me);
+  else
+    safe_prim(me);
+  const int lm1 = lane > 0 ? lane - 1 : 0;
+  const int lp1 = lane < 63 ? lane + 1 : 63;
+  const Prim<T> left = shfl_prim(me, lm1);
+  const Prim<T> right = shfl_prim(me, lp1);
+  T sl[5];
+  slope_sel<R>(left, me, right, sl);
+  T slm[5], slp[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    slm[q] = __shfl(sl[q], lm1, 64);
+    slp[q] = __shfl(sl[q], lp1, 64);
+  }
+  T WL[5], WR[5], UL[5], UR[5];
+  PpmpCoef<T> kc{T(0), T(0)};
+  if (R == 1 && in_line && c >= -1 && c <= P.n[0]) kc = load_coef<R, 0, T>(r.G, P.stride, id);
+  trace_sel<R>(left, me, right, slm, sl, slp, kc, g, dtodx, WL, WR);
+  to_cons(WL, igm1, UL);
+  to_cons(WR, igm1, UR);
+  if (lane >= 2 && lane <= 61 && in_line && c >= -1 && c <= P.n[0]) {
+    T dT[5];
+    transverse_delta<T, 0>(dstar_all, fds, P.stride, id, h1, h2, dT);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      UL[q] += dT[q];
+      UR[q] += dT[q];
+    }
+  }
+  T prevR[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) prevR[q] = __shfl(UR[q], lm1, 64);
+  if (lane >= 3 && lane <= 60 && in_line && c >= 0 && c <= P.n[0]) {
+    Prim<T> Lq, Rq;
+    make_prim(prevR, g, T(P.gm1), T(P.p_floor), Lq);
+    make_prim(UL, g, T(P.gm1), T(P.p_floor), Rq);
+    GLOBAL T* __restrict__ eta = (GLOBAL T*)r.G->eta;
+    eta[id] = T(0.5) * tfabs((Rq.w[1] + Rq.a) - (Lq.w[1] + Lq.a));
+  }
 }
 
 // First-stage x sweep.  The x-rows of one z-plane (j over the extended range [-1, n_y], each
@@ -610,12 +642,12 @@ void enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* 
   } else {
     if constexpr (K == kRoeH) {
       // eta of every face the H stencils of the second stage read
-      CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_eta<T, 0, R>), nblocks(P_ETA_X), B, 0, stream,
+      CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_eta_x<T, R>), nblocks(P_ETA_X), B, 0, stream,
                                                 tab(P_ETA_X)));
-      CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_eta<T, 1, R>), nblocks(P_ETA_Y), B, 0, stream,
-                                                tab(P_ETA_Y)));
-      CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_eta<T, 2, R>), nblocks(P_ETA_Z), B, 0, stream,
-                                                tab(P_ETA_Z)));
+      CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_sweep_march<T, 1, 3, false, K, R>),
+                                                nblocks(P_ETA_Y), B, 0, stream, tab(P_ETA_Y)));
+      CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_sweep_march<T, 2, 3, false, K, R>),
+                                                nblocks(P_ETA_Z), B, 0, stream, tab(P_ETA_Z)));
     }
     // a2-a4 re-traced, a6-a7: G^{n+1/2}, H^{n+1/2} on the real faces, then F^{n+1/2} with the
     // update (a8) and the CFL bound of the new state (a9)
