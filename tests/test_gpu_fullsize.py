@@ -29,13 +29,13 @@ def _boxes(n, special, rng, count=6, size=8):
     return boxes
 
 
-def _check(ctu, wl, prec, tol, special, seed):
-    print(f"[gpu-test] full size {wl.name} prec {prec}", flush=True)
-    cfg = oracle_config(wl)
+def _check(ctu, wl, prec, tol, special, seed, **method):
+    print(f"[gpu-test] full size {wl.name} prec {prec} {method}", flush=True)
+    cfg = oracle_config(wl, **method)
     u = O.state_from_primitive(cfg, wl.W)
     O.bc_fill(cfg, u)
     dt = O.compute_dt(cfg, u)
-    g = ctu.Grid.from_workload(wl, prec=prec)
+    g = ctu.Grid.from_workload(wl, prec=prec, **method)
     dt_gpu = g.compute_dt()
     assert dt_gpu == pytest.approx(dt, rel=1e-14 if prec == ctu.FP64 else 1e-6)
     g.step(dt)
@@ -56,15 +56,30 @@ def _check(ctu, wl, prec, tol, special, seed):
     print(f"[gpu-test]   max relative L1 over {len(errs)} boxes: {max(errs):.3e}", flush=True)
 
 
-def test_shock_cloud_256_fp64(ctu=None):
-    from paper_1410_4194_amd import ctu
-    wl = WL.shock_cloud(256)
-    n = 256
+def _shock_cloud_special(n):
     shock_x = int(0.1 * n)
     cloud_edge = int((0.3 - 0.1) * n)
-    special = [(shock_x, n // 2, n // 2), (shock_x, 3, 3), (cloud_edge, n // 2, n // 2),
-               (int(0.3 * n), n // 2 + int(0.1 * n), n // 2), (0, 0, 0), (n - 1, n - 1, n - 1)]
-    _check(ctu, wl, ctu.FP64, 1e-12, special, seed=31)
+    return [(shock_x, n // 2, n // 2), (shock_x, 3, 3), (cloud_edge, n // 2, n // 2),
+            (int(0.3 * n), n // 2 + int(0.1 * n), n // 2), (0, 0, 0), (n - 1, n - 1, n - 1)]
+
+
+def test_shock_cloud_256_fp64(ctu=None):
+    from paper_1410_4194_amd import ctu
+    _check(ctu, WL.shock_cloud(256), ctu.FP64, 1e-12, _shock_cloud_special(256), seed=31)
+
+
+# the paper's other reconstruction and Riemann solvers, as the benchmark times them
+METHODS = [("ppmc_roe", dict(riemann=1)), ("ppmc_roe_hcorr", dict(riemann=1, h_correction=1)),
+           ("ppmp_exact", dict(recon=1)), ("ppmp_roe", dict(recon=1, riemann=1)),
+           ("ppmp_roe_hcorr", dict(recon=1, riemann=1, h_correction=1))]
+
+
+@pytest.mark.parametrize("name,method", METHODS, ids=[m[0] for m in METHODS])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_shock_cloud_256_methods(name, method, prec):
+    from paper_1410_4194_amd import ctu
+    _check(ctu, WL.shock_cloud(256), prec, 1e-12 if prec == 0 else 1e-5,
+           _shock_cloud_special(256), seed=33, **method)
 
 
 @pytest.mark.timeout(600)

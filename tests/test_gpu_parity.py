@@ -329,3 +329,24 @@ def test_near_vacuum_rarefaction(ctu):
     assert np.isfinite(ref).all()
     err = rel_l1(gpu, ref, wl.gamma)
     assert err.max() <= TOL64, err
+
+METHODS = [("ppmc_exact", {}), ("ppmc_roe", dict(riemann=1)),
+           ("ppmc_roe_hcorr", dict(riemann=1, h_correction=1)), ("ppmp_exact", dict(recon=1)),
+           ("ppmp_roe_hcorr", dict(recon=1, riemann=1, h_correction=1))]
+
+
+@pytest.mark.parametrize("name,kw", METHODS, ids=[m[0] for m in METHODS])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_uniform_flow_is_unchanged_bitwise(ctu, name, kw, prec):
+    """A uniform moving state is an exact steady solution: every face has equal states (the
+    solvers' constant-state path), every flux difference is exactly zero, and ten steps leave
+    the state bit for bit as it was, for every method and boundary type."""
+    wl = WL.random_state(23, 17, 12, seed=90, bc=(1, 1, 0, 0, 1, 1))
+    wl.W[:] = np.array([1.3, 0.4, -0.2, 0.7, 2.0])[:, None, None, None]
+    _announce("uniform flow", name, "prec", prec)
+    g = ctu.Grid.from_workload(wl, prec=prec, **kw)
+    before = g.get_state()
+    g.advance(10)
+    assert np.array_equal(g.get_state(), before)
+    status, flags, counters = g.check()
+    assert status == ctu.OK
