@@ -173,6 +173,28 @@ def noh(n: int = 64, p0: float = 1e-6) -> Workload:
     return Workload(f"noh_{n}^3", n, n, n, d, d, d, 5.0 / 3.0, bc, W, cfl=0.3, t_end=0.6)
 
 
+def shock_duct(nx: int = 96, ny: int = 16, nz: int = 1, mach: float = 6.0,
+               amp: float = 1e-3) -> Workload:
+    """A plane shock aligned with the grid running down a duct (the carbuncle setting of
+    Sec. 4.3.1 and App. C): gas at rest (rho = 1, p = 1/gamma, gamma 1.4) ahead of a Mach
+    `mach` shock that starts at x = 0.5, the Rankine-Hugoniot state behind it, cell width
+    1/ny, walls across y, outflow along x, periodic along z.  One cell ahead of the shock on
+    the duct's centre line has its density raised by the fraction `amp`: a scheme prone to
+    the carbuncle grows that seed into cross-flow, a dissipative one carries it as a small
+    contact."""
+    g = 1.4
+    d = 1.0 / ny
+    rho2, u2, p2, _ = normal_shock(mach, 1.0, 1.0 / g, g)
+    post = (_centres(nx, d) < 0.5).reshape(1, 1, nx)
+    W = np.zeros((5, nz, ny, nx))
+    W[0] = np.where(post, rho2, 1.0)
+    W[1] = np.where(post, u2, 0.0)
+    W[4] = np.where(post, p2, 1.0 / g)
+    W[0, :, ny // 2, int(0.8 * ny)] *= 1.0 + amp
+    bc = (OUTFLOW, OUTFLOW, REFLECT, REFLECT, PERIODIC, PERIODIC)
+    return Workload(f"shock_duct_{nx}x{ny}x{nz}", nx, ny, nz, d, d, d, g, bc, W, cfl=0.3)
+
+
 # ------------------------------------------------------------------------------------------
 # Shock-cloud problems (Sec. 5)
 # ------------------------------------------------------------------------------------------
