@@ -129,7 +129,10 @@ ctu_status ctu_workspace_bytes(const ctu_config* cfg, size_t* state_bytes, size_
 
 /* Create a grid over caller-owned device buffers d_state (>= state_bytes) and d_work
  * (>= work_bytes, 256-byte aligned), bound to hip_stream (hipStream_t, NULL = default).
- * Validates cfg (CTU_EINVAL) and sizes (CTU_ENOMEM); launches nothing. */
+ * Validates cfg (CTU_EINVAL) and sizes (CTU_ENOMEM); launches nothing.  A grid of more
+ * than 2^31 real cells, or one whose largest pass would exceed 2^32 - 1 work-items in one
+ * dispatch, is refused with CTU_EINVAL (memory runs out first on one MI355X: 1024^3 takes
+ * 153 GB in FP32 and 306 GB in FP64). */
 ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, size_t work_bytes,
                            void* hip_stream, ctu_grid** out);
 ctu_status ctu_grid_destroy(ctu_grid* g);

@@ -179,7 +179,8 @@ bool build_starts(const std::vector<GridParams>& Ps, std::vector<int>& start) {
     for (int g = 0; g < n; ++g) {
       start[(size_t)p * (n + 1) + g] = (int)off;
       off += (ctu::pass_blocks(Ps[g], p) + 7) / 8 * 8;
-      if (off > 0x7fffff00LL) return false;
+      // a dispatch holds at most 2^32 - 1 work-items along x
+      if (off * ctu::kBlock > 0xffffffffLL) return false;
     }
     start[(size_t)p * (n + 1) + n] = (int)off;
   }

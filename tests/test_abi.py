@@ -89,6 +89,23 @@ def test_grid_create_rejects_small_workspace(ctu):
     assert b"workspace" in ctu.lib.ctu_last_error()
 
 
+def test_grid_size_limits(ctu):
+    """More than 2^31 real cells is refused by validation; a grid whose x pass would need
+    more than 2^32 - 1 work-items in one dispatch (a 5e8-cell line: every cell is a lane of
+    its own row) is refused when the grid is created, before any device work."""
+    with pytest.raises(ctu.CtuError) as ei:
+        ctu.workspace_bytes(ctu.make_config(2048, 1024, 1025, 1, 1, 1, 1.4))
+    assert ei.value.status == ctu.EINVAL
+    ctu.workspace_bytes(ctu.make_config(2048, 1024, 1024, 1, 1, 1, 1.4))
+    cfg = ctu.make_config(500_000_000, 1, 1, 1, 1, 1, 1.4)
+    sb, wb = ctu.workspace_bytes(cfg)
+    h = C.c_void_p()
+    st = ctu.lib.ctu_grid_create(C.byref(cfg), C.c_void_p(256), C.c_void_p(512), C.c_size_t(wb),
+                                 None, C.byref(h))
+    assert st == ctu.EINVAL and h.value is None
+    assert b"one launch per pass" in ctu.lib.ctu_last_error()
+
+
 def test_product_path_requires_gpu(ctu):
     import torch
     if torch.cuda.is_available():
