@@ -285,6 +285,38 @@ def roofline(prof, n, eb, prec_name, ng=3, exact=True):
     return out
 
 
+def bandwidth_probe(torch, gib=2, reps=5):
+    """What plain streaming kernels reach on this GPU's HBM (torch's own kernels, nothing of
+    the method): a read-only sum, a copy (1 read : 1 write) and an add of two arrays into a
+    third (2 : 1), each over `gib` GiB per array, the best of `reps` launches timed with HIP
+    events.  Context for the roofline fraction, which stays against the published peak."""
+    n = (gib << 30) // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
+    b = torch.empty_like(a).uniform_()
+    c = torch.empty_like(a)
+
+    def best(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        return round(nbytes / min(times) / 1e9, 1)
+
+    nb = n * 8
+    out = {"read_GBps": best(lambda: a.sum(), nb), "copy_GBps": best(lambda: c.copy_(a), 2 * nb),
+           "add_GBps": best(lambda: torch.add(a, b, out=c), 3 * nb), "bytes_per_array": nb}
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, seconds_target=15.0, methods=(), method_seconds=3.0):
     """The serial FP64 oracle on a bounded sample of the same workload: one CTU step of a 64^3
     box around the shock front and the cloud's upwind edge, repeated for about
@@ -397,6 +429,9 @@ def main():
         "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in r64["profile"].items()
                        if v[1] > 0},
     }
+    bw = bandwidth_probe(torch)
+    log(f"[bench] plain streaming kernels on this GPU (GB/s): {bw}")
+    out["roofline"]["achievable"] = bw
     if not args.no_fp32:
         log(f"[bench] FP32 form: warmup {args.warmup}, timed {args.steps} steps")
         r32 = run_gpu(wl, ctu.FP32, args.steps, args.warmup, ctu, torch, keep_state=True)

@@ -534,6 +534,15 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
         for (int f = 0; f < 5; ++f) U0[f] = T(0);
         safe_prim(me);
       }
+      // the y and z second-stage differences of the cell this lane updates, loaded now so
+      // that their latency hides behind the trace and the Riemann solve
+      const bool upd = lane >= 3 && lane <= 60 && c >= 0 && c < P.n[0];
+      T dGc[5], dHc[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        dGc[f] = upd ? dG[f * P.stride + id] : T(0);
+        dHc[f] = upd ? dH[f * P.stride + id] : T(0);
+      }
       // this chunk's stencil has been read (make_prim consumed it): the previous chunk's
       // new states can go out
       if (def_id >= 0) {
@@ -585,18 +594,17 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
       T Fr[5];  // flux at face c+1/2
 #pragma unroll
       for (int q = 0; q < 5; ++q) Fr[q] = __shfl(F[q], lp1, 64);
-      if (lane >= 3 && lane <= 60 && c >= 0 && c < P.n[0]) {
+      if (upd) {
         // u^{n+1} = u^n + dt/dx (F_{-1/2} - F_{+1/2}) + dt/dy (...) + dt/dz (...), in this order
         T Un[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-          const long long o = f * P.stride + id;
           const T dFx = F[f] - Fr[f];
-          if (keep) out[o] = dFx;  // the update consumes it in registers: debugging only
+          if (keep) out[f * P.stride + id] = dFx;  // consumed in registers: debugging only
           T v = U0[f];
           v = v + dtdx * dFx;
-          v = v + dtdy * dG[o];
-          v = v + dtdz * dH[o];
+          v = v + dtdy * dGc[f];
+          v = v + dtdz * dHc[f];
           Un[f] = v;
         }
         bool finite = true;
