@@ -104,9 +104,9 @@ def _work(cls, n, ng=3):
         u = (nx + 2) * (ny + 2) * (nz + 2)
         return u, 0, 7 * u
     if cls == "hcorr_eta":  # per face: 5 fields + 10 differences read, eta written; the
-        # class times one launch per axis, so one launch carries a third of the faces
-        u = ((nx + 1) * (ny + 2) * (nz + 2) + (nx + 2) * (ny + 1) * (nz + 2) +
-             (nx + 2) * (ny + 2) * (nz + 1)) // 3
+        # class times the x and z passes (the y sweep computes eta along y itself), so one
+        # launch carries half of their faces
+        u = ((nx + 1) * (ny + 2) * (nz + 2) + (nx + 2) * (ny + 2) * (nz + 1)) // 2
         return u, 0, 16 * u
     if cls == "dt_final":
         u = (ny * nz + 3) // 4

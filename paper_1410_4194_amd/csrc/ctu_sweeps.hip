@@ -16,7 +16,7 @@ hipError_t launch_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, CTU_SWEEP_R>(const PlanView& 
                                                                 hipStream_t stream,
                                                                 Profiler* prof) {
   // the Newton histogram exists for the exact solver only
-  if constexpr (CTU_SWEEP_K != kRoe) {
+  if constexpr (CTU_SWEEP_K != kRoe && CTU_SWEEP_K != kRoeH) {
     if (prof && prof->hist) {
       enqueue_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, true, CTU_SWEEP_R>(v, stage, stream, prof);
       return hipGetLastError();

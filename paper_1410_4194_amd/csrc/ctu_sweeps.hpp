@@ -138,6 +138,20 @@ __device__ __forceinline__ T eta_h_at(const GLOBAL T* __restrict__ eta, const Gr
   return e;
 }
 
+// The same with the face's own eta given (computed by the caller from the face's states).
+template <int D, typename T>
+__device__ __forceinline__ T eta_h_own(const GLOBAL T* __restrict__ eta, const GridParams& P,
+                                       long long cm, long long cp, T own) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const long long st[3] = {1, P.N[0], (long long)P.N[0] * P.N[1]};
+  const GLOBAL T* __restrict__ e1 = eta + T1 * P.stride;
+  const GLOBAL T* __restrict__ e2 = eta + T2 * P.stride;
+  T e = own;
+  e = tmax(e, tmax(tmax(e1[cm], e1[cm + st[T1]]), tmax(e1[cp], e1[cp + st[T1]])));
+  e = tmax(e, tmax(tmax(e2[cm], e2[cm + st[T2]]), tmax(e2[cp], e2[cp + st[T2]])));
+  return e;
+}
+
 // K is the gas class of the exact solver (see pfun_fast).
 // STAGE = 1: first-stage fluxes F*_D on the faces c-1/2, c in [0, n_D], transverse range
 //            [-1, n] on both other axes.
@@ -155,6 +169,11 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   // transverse range, reduced to eta = |(u+a)_R - (u+a)_L|/2 instead of solved
   constexpr bool ETA = STAGE == 3;
   constexpr bool S2 = STAGE >= 2;  // second-stage states (re-traced + transverse correction)
+  // With the H correction the second-stage y sweep takes the eta pass along y over: it runs
+  // over the first stage's transverse range, stores eta of every face it sees (the z and x
+  // sweeps after it read them) and solves only the faces of real columns, whose eta^H takes
+  // the face's own eta from registers.  The eta passes along x and z run before it.
+  constexpr bool FUSE_ETA = STAGE == 2 && D == 1 && K == kRoeH;
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
   DevScalars* __restrict__ s = r.G->s;
@@ -165,7 +184,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   const long long fds = 5 * P.stride;
   GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux + (STAGE == 1 ? D : 3 + D) * fds;
   constexpr int B = (D == 1) ? 2 : 1;  // the transverse axis other than x
-  constexpr bool EXT_T = STAGE != 2;   // transverse range [-1, n]
+  constexpr bool EXT_T = STAGE != 2 || FUSE_ETA;  // transverse range [-1, n]
   const int lo = EXT_T ? -1 : 0;
   const int ea = P.n[0] + (EXT_T ? 2 : 0);
   const int eb = P.n[B] + (EXT_T ? 2 : 0);
@@ -183,6 +202,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
   const int o = (int)(tid / ea) + lo;
   const int f0 = dlo + (int)(r.lb / nbx) * seg;
   const int f1 = min(f0 + seg, nd);
+  // a column outside the real box along x or the other transverse axis: eta only
+  const bool ring = FUSE_ETA && (i < 0 || i >= P.n[0] || o < 0 || o >= P.n[B]);
   const long long stx = 1, sty = P.N[0], stz = (long long)P.N[0] * P.N[1];
   const long long sd = D == 1 ? sty : stz;
   const long long c0 = D == 1 ? cell_index(P, i, 0, o) : cell_index(P, i, o, 0);
@@ -275,27 +296,31 @@ __global__ __launch_bounds__(256, 2) void k_sweep_march(LaunchTab tab) {
         UR[q] += dT[q];
       }
       T eta_h = T(0);
-      if constexpr (K == kRoeH && !ETA)  // (the eta pass writes these)
+      if constexpr (ETA || FUSE_ETA) {
+        Prim<T> Lq, Rq;
+        make_prim(prevR, T(P.gamma), T(P.gm1), T(P.p_floor), Lq);
+        make_prim(UL, T(P.gamma), T(P.gm1), T(P.p_floor), Rq);
+        const T e = T(0.5) * tfabs((Rq.w[1] + Rq.a) - (Lq.w[1] + Lq.a));
+        // the face is written by the segment that owns it (not the duplicate)
+        if (!dupface) ((GLOBAL T*)r.G->eta + D * P.stride)[c0 + (long long)c * sd] = e;
+        if constexpr (FUSE_ETA) {
+          if (!ring)
+            eta_h = eta_h_own<D>((const GLOBAL T*)r.G->eta, P, c0 + (long long)(c - 1) * sd,
+                                 c0 + (long long)c * sd, e);
+        }
+      } else if constexpr (K == kRoeH) {  // (the eta passes wrote these)
         eta_h = eta_h_at<D>((const GLOBAL T*)r.G->eta, P, c0 + (long long)(c - 1) * sd,
                             c0 + (long long)c * sd);
-      if constexpr (ETA) {
-        // the face is written by the segment that owns it (not the duplicate)
-        if (!dupface) {
-          Prim<T> Lq, Rq;
-          make_prim(prevR, T(P.gamma), T(P.gm1), T(P.p_floor), Lq);
-          make_prim(UL, T(P.gamma), T(P.gm1), T(P.p_floor), Rq);
-          GLOBAL T* __restrict__ eta = (GLOBAL T*)r.G->eta + D * P.stride;
-          eta[c0 + (long long)c * sd] = T(0.5) * tfabs((Rq.w[1] + Rq.a) - (Lq.w[1] + Lq.a));
-        }
-      } else {
-        face_flux_u<T, K>(prevR, UL, P, F, dupface ? dup : cnt, eta_h);
+      }
+      if constexpr (!ETA) {
+        if (!ring) face_flux_u<T, K>(prevR, UL, P, F, dupface ? dup : cnt, eta_h);
       }
     }
     if (HIST) hist.add(dupface ? dup.iters : cnt.iters, !dupface);
     // keep the LDS read of the previous flux below the solve (hoisted above it, the five
     // values would stay live through the solve and cost the first stage a wave per SIMD)
     asm volatile("" ::: "memory");
-    if (!ETA && c > f0) {  // cell c-1 now has both faces
+    if (!ETA && !ring && c > f0) {  // cell c-1 now has both faces
       const long long co = c0 + (long long)(c - 1) * sd;
 #pragma unroll
       for (int sl = 0; sl < 5; ++sl)
@@ -650,10 +675,9 @@ void enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* 
   } else {
     if constexpr (K == kRoeH) {
       // eta of every face the H stencils of the second stage read
+      // (along y the second-stage y sweep computes them itself)
       CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_eta_x<T, R>), nblocks(P_ETA_X), B, 0, stream,
                                                 tab(P_ETA_X)));
-      CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_sweep_march<T, 1, 3, false, K, R>),
-                                                nblocks(P_ETA_Y), B, 0, stream, tab(P_ETA_Y)));
       CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_sweep_march<T, 2, 3, false, K, R>),
                                                 nblocks(P_ETA_Z), B, 0, stream, tab(P_ETA_Z)));
     }

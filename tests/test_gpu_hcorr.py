@@ -1,6 +1,7 @@
 """GPU parity for the H correction of the second-stage Roe fluxes (App. C): the extended first
-stage, the eta pass over the second-stage states, and the nine-point eta^H inside the
-second-stage sweeps, with PPMC and PPMP.
+stage, eta of the second-stage states (passes along x and z; along y inside the second-stage
+y sweep, which covers the first stage's transverse range for it), and the nine-point eta^H
+inside the second-stage sweeps, with PPMC and PPMP.
 
 One step from the same state and dt against the oracle configured the same way (FP64 <=
 1e-12, FP32 <= 1e-5 relative L1); the stationary-contact pattern whose one-step density the
