@@ -197,6 +197,33 @@ def test_determinism_bitwise(ctu):
     assert np.array_equal(out[0], out[1])
 
 
+def test_invalid_step_arguments_change_nothing(ctu):
+    """ctu_step with dt <= 0, NaN or infinite dt, and ctu_advance with a negative step count
+    or a NaN end time are refused with CTU_EINVAL before any device work; the state, time and
+    step count stay as they were, and a valid step afterwards still matches the oracle."""
+    wl = WL.random_state(12, 10, 9, seed=61)
+    g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    before = g.get_state()
+    for dt in (0.0, -1e-3, float("nan"), float("inf")):
+        with pytest.raises(ctu.CtuError) as ei:
+            g.step(dt)
+        assert ei.value.status == ctu.EINVAL, dt
+    for nsteps, t_end in ((-1, float("inf")), (3, float("nan"))):
+        with pytest.raises(ctu.CtuError) as ei:
+            g.advance(nsteps, t_end=t_end)
+        assert ei.value.status == ctu.EINVAL
+    g.advance(0)
+    assert np.array_equal(g.get_state(), before)
+    info = g.info()
+    assert info.steps == 0 and info.t == 0.0
+    cfg = oracle_config(wl)
+    u = oracle_state(wl, cfg)
+    dt = O.compute_dt(cfg, u)
+    g.step(dt)
+    O.step(cfg, u, dt)
+    assert rel_l1(g.get_state(), O.real(cfg, u), wl.gamma).max() <= TOL64
+
+
 def test_advance_equals_host_loop(ctu):
     """Device-side dt (ctu_advance) gives bitwise the same steps as compute_dt + step."""
     wl = WL.sod(64, 4, 4)
