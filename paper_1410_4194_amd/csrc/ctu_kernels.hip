@@ -474,7 +474,6 @@ long long pass_blocks(const GridParams& P, int pass) {
     case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1 + 2 * P.ext, P.seg[1]);
     case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2 + 2 * P.ext, P.seg[2]);
     case P_ETA_X: return P.ext ? cdiv(cdiv((n1 + 2) * N0, XW) * (n2 + 2), kBlock / 64) : 0;
-    case P_ETA_Y: return 0;  // the second-stage y sweep computes eta along y
     case P_S2_Y:  // with the H correction over the first stage's transverse range (eta)
       return P.ext ? cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1, P.seg[1])
                    : cdiv(n0 * n2, kBlock) * cdiv(n1, P.seg[1]);

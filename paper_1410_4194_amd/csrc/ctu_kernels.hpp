@@ -17,7 +17,7 @@ namespace ctu {
 // Passes of one step, in launch order, plus the stand-alone CFL reduction.
 enum Pass {
   P_BC_X, P_BC_Y, P_BC_Z, P_COEF_X, P_COEF_Y, P_COEF_Z, P_S1_X, P_S1_Y, P_S1_Z, P_ETA_X,
-  P_ETA_Y, P_ETA_Z, P_S2_Y, P_S2_Z, P_S2_X, P_DT, P_NUM
+  P_ETA_Z, P_S2_Y, P_S2_Z, P_S2_X, P_DT, P_NUM
 };
 
 constexpr int kBlock = 256;  // threads per block of every pass
