@@ -16,10 +16,12 @@ Beside the primary line's value, the same JSON line carries
   serve:   Poisson-arriving shock-cloud requests (edges {64, 96, 128, 192}, density contrast
            log-uniform in [10, 1000], Mach uniform in [1.5, 10], radius in [0.08, 0.15], run
            to 1.5 cloud-crushing times, FP32 with the FP64 Newton solve) admitted by HBM
-           footprint into a continuous batch: p50/p99 time-to-solution and aggregate rate.
+           footprint into a continuous batch (arrival order, or --serve-policy sjf: least
+           estimated work first): p50/p99 time-to-solution and aggregate rate.
 --precision-study runs the 512^3 turbulent cloud for 50 steps in FP64 and FP32 and reports
 their relative L1 distance (also with the shock started at x = 0.14, where it reaches the
-cloud within the 50 steps); --serve-sweep sweeps the serving arrival rate.
+cloud within the 50 steps); --serve-sweep sweeps the serving arrival rate under both
+admission policies.
 
 Prints one JSON line.  Per-kernel durations come from HIP events the library records on
 its own stream around every kernel of the timed steps.
@@ -190,15 +192,18 @@ def run_batched(ctu, torch, WL, prec, steps, warmup, count=64, compare_solo_step
     return out
 
 
-def run_serve(ctu, WL, rate, count, hbm_budget, seed, steps_per_round=4, keep=False):
+def run_serve(ctu, WL, rate, count, hbm_budget, seed, steps_per_round=4, keep=False,
+              policy="fifo"):
     from paper_1410_4194_amd import serve as S
     reqs = WL.shock_cloud_requests(count, rate=rate, seed=seed)
-    requests = [S.Request(q["rid"], q["arrival"], WL.request_workload(q), q["t_end"], ctu.FP32)
+    requests = [S.Request(q["rid"], q["arrival"], WL.request_workload(q), q["t_end"], ctu.FP32,
+                          cost=WL.estimated_steps(q) * q["n"] ** 3)
                 for q in reqs]
     stats = S.serve(requests, hbm_budget=hbm_budget, max_slots=64,
-                    steps_per_round=steps_per_round, graph=True, keep_states=keep)
+                    steps_per_round=steps_per_round, graph=True, keep_states=keep, policy=policy)
     out = stats.summary()
-    out.update({"rate_per_s": rate, "hbm_budget_gb": round(hbm_budget / 1e9, 2)})
+    out.update({"rate_per_s": rate, "hbm_budget_gb": round(hbm_budget / 1e9, 2),
+                "policy": policy})
     return out
 
 
@@ -372,8 +377,11 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="arrival rate as a fraction of the estimated capacity")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-policy", choices=("fifo", "sjf"), default="fifo",
+                    help="admission policy of the default serving run")
     ap.add_argument("--serve-sweep", action="store_true",
-                    help="also sweep the arrival rate over 0.25, 0.5, 1, 2, 4 x capacity")
+                    help="also sweep the arrival rate over 0.25, 0.5, 1, 2, 4 x capacity, "
+                         "with both admission policies")
     ap.add_argument("--precision-study", action="store_true",
                     help="512^3 turbulent cloud, 50 steps, FP32 vs FP64 relative L1")
     ap.add_argument("--source-hash", action="store_true",
@@ -499,12 +507,15 @@ def main():
         mean_work = float(np.mean([WL.estimated_steps(q) * q["n"] ** 3 for q in probe]))
         capacity = cap_rate / mean_work
         budget = int(args.serve_budget_gb * 1e9)
-        loads = [args.serve_load] + ([0.25, 0.5, 1.0, 2.0, 4.0] if args.serve_sweep else [])
-        for i, load in enumerate(loads):
+        runs = [(args.serve_load, args.serve_policy)]
+        if args.serve_sweep:
+            runs += [(ld, pol) for ld in (0.25, 0.5, 1.0, 2.0, 4.0) for pol in ("fifo", "sjf")]
+        for i, (load, policy) in enumerate(runs):
             rate = load * capacity
-            log(f"[bench] serving: {args.serve_requests} requests at {rate:.3f}/s "
+            log(f"[bench] serving ({policy}): {args.serve_requests} requests at {rate:.3f}/s "
                 f"({load} x estimated capacity {capacity:.3f}/s)")
-            rs = run_serve(ctu, WL, rate, args.serve_requests, budget, WL.BASE_SEED + 5)
+            rs = run_serve(ctu, WL, rate, args.serve_requests, budget, WL.BASE_SEED + 5,
+                           policy=policy)
             rs["load"] = load
             rs["capacity_estimate_per_s"] = round(capacity, 4)
             log(f"[bench]   p50 {rs['p50_s']} s, p99 {rs['p99_s']} s, "

@@ -9,12 +9,17 @@ its solution is downloaded and its memory released, which may admit the next req
 Requests that arrive while others run join the running set at the next round, so their
 work overlaps on the device.
 
+Two admission policies: "fifo" admits in arrival order and stops at the first arrived
+request that does not fit (no request overtakes an earlier one); "sjf" admits, among the
+requests that have arrived, the one with the least estimated work (``Request.cost``, the
+caller's estimate, e.g. cells x estimated steps) that fits, so small requests do not wait
+behind a large one for memory.
+
 Time-to-solution of a request is measured from its arrival to its solution on the host.
 All arithmetic runs in the library's kernels; this module only schedules.
 """
 from __future__ import annotations
 
-import collections
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional
@@ -32,6 +37,7 @@ class Request:
     t_end: float
     prec: int = ctu.FP32
     max_steps: int = 1 << 30
+    cost: float = 0.0          # estimated work (any unit), for the "sjf" admission policy
 
 
 @dataclass
@@ -83,9 +89,34 @@ def footprint(req: Request) -> int:
     return sb + wb
 
 
+POLICIES = ("fifo", "sjf")
+
+
+def next_admission(pending: List[Request], now: float, free_bytes: int, free_slots: int,
+                   need: Callable[[Request], int], policy: str = "fifo") -> Optional[int]:
+    """Index into `pending` (sorted by arrival) of the request to admit next, or None.
+    fifo: the earliest arrival, if it fits; sjf: the least `cost` among the arrived requests
+    that fit (ties by arrival)."""
+    if free_slots <= 0:
+        return None
+    if policy == "fifo":
+        if pending and pending[0].arrival <= now and need(pending[0]) <= free_bytes:
+            return 0
+        return None
+    if policy != "sjf":
+        raise ValueError(f"unknown admission policy {policy!r}")
+    best = None
+    for i, r in enumerate(pending):
+        if r.arrival > now:
+            break
+        if need(r) <= free_bytes and (best is None or r.cost < pending[best].cost):
+            best = i
+    return best
+
+
 def serve(requests: List[Request], hbm_budget: int, max_slots: int = 64,
           steps_per_round: int = 4, graph: bool = True, keep_states: bool = False,
-          clock: Callable[[], float] = time.perf_counter) -> ServeStats:
+          clock: Callable[[], float] = time.perf_counter, policy: str = "fifo") -> ServeStats:
     """Run the request loop until every request is answered.
 
     Each round enqueues `steps_per_round` steps of the running grids first; while the GPU
@@ -94,9 +125,12 @@ def serve(requests: List[Request], hbm_budget: int, max_slots: int = 64,
     poll (a single read-back for all slots) finds the grids that are done."""
     import torch
 
-    pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+    if policy not in POLICIES:
+        raise ValueError(f"unknown admission policy {policy!r}")
+    pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+    need_of = {r.rid: footprint(r) for r in pending}
     for r in pending:
-        if footprint(r) > hbm_budget:
+        if need_of[r.rid] > hbm_budget:
             raise ValueError(f"request {r.rid} needs more than the HBM budget")
     io_stream = torch.cuda.Stream()
     batch = ctu.Batch(max_slots, graph=graph)
@@ -123,19 +157,21 @@ def serve(requests: List[Request], hbm_budget: int, max_slots: int = 64,
                 g.close()
                 resident -= need
             retire = []
-            # ... and admit arrivals in order while memory and slots allow
+            # ... and admit arrivals (by the policy) while memory and slots allow
             now = clock() - t0
-            while pending and pending[0].arrival <= now:
-                req = pending[0]
-                need = footprint(req)
-                if resident + need > hbm_budget or len(active) >= max_slots:
+            while True:
+                i = next_admission(pending, now, hbm_budget - resident, max_slots - len(active),
+                                   lambda r: need_of[r.rid], policy)
+                if i is None:
                     break
+                req = pending[i]
+                need = need_of[req.rid]
                 g = ctu.Grid.from_workload(req.workload, prec=req.prec, stream=io_stream)
                 ticket = batch.submit(g, req.max_steps, req.t_end)
                 if ticket is None:
                     g.close()
                     break
-                pending.popleft()
+                del pending[i]
                 resident += need
                 active[ticket] = (req, g, clock() - t0, need)
                 now = clock() - t0

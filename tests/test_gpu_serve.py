@@ -1,7 +1,8 @@
 """Serving loop on the GPU: Poisson-arriving shock-cloud requests of different sizes, admitted
-by HBM footprint into a continuous batch.  Every answer must equal the same request solved
-alone (bitwise: each grid's arithmetic does not depend on what shares the batch), the HBM
-budget must hold at all times, and requests must actually overlap."""
+by HBM footprint into a continuous batch, in arrival order or least estimated work first.
+Every answer must equal the same request solved alone (bitwise: each grid's arithmetic does
+not depend on what shares the batch), the HBM budget must hold at all times, and requests
+must actually overlap."""
 import sys
 
 import numpy as np
@@ -17,17 +18,20 @@ def _announce(*parts):
     sys.stdout.flush()
 
 
+@pytest.mark.parametrize("policy", ["fifo", "sjf"])
 @pytest.mark.parametrize("prec", [1, 0], ids=["fp32", "fp64"])
-def test_served_answers_equal_solo(prec):
+def test_served_answers_equal_solo(prec, policy):
     from paper_1410_4194_amd import ctu, serve as S
     reqs = WL.shock_cloud_requests(10, rate=200.0, sizes=(16, 24, 32), t_cc_factor=0.05)
-    requests = [S.Request(q["rid"], q["arrival"], WL.request_workload(q), q["t_end"], prec)
+    requests = [S.Request(q["rid"], q["arrival"], WL.request_workload(q), q["t_end"], prec,
+                          cost=WL.estimated_steps(q) * q["n"] ** 3)
                 for q in reqs]
     foot = [S.footprint(r) for r in requests]
     budget = int(2.5 * max(foot))  # admission is limited by memory, not only by slots
-    _announce("serve", len(requests), "requests, budget", budget, "bytes, prec", prec)
+    _announce("serve", len(requests), "requests, budget", budget, "bytes, prec", prec,
+              "policy", policy)
     stats = S.serve(requests, hbm_budget=budget, max_slots=6, steps_per_round=2,
-                    keep_states=True)
+                    keep_states=True, policy=policy)
     assert len(stats.results) == len(requests)
     assert stats.max_resident_bytes <= budget
     assert stats.max_concurrent >= 2
