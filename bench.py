@@ -376,8 +376,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="arrival rate as a fraction of the estimated capacity")
-    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
-    ap.add_argument("--serve-policy", choices=("fifo", "sjf"), default="fifo",
+    ap.add_argument("--serve-budget-gb", type=float, default=2.0,
+                    help="HBM budget of the serving loop (2 GB: admission binds from about "
+                         "the estimated capacity up; the largest request needs 1.1 GB)")
+    ap.add_argument("--serve-policy", choices=("fifo", "sjf"), default="sjf",
                     help="admission policy of the default serving run")
     ap.add_argument("--serve-sweep", action="store_true",
                     help="also sweep the arrival rate over 0.25, 0.5, 1, 2, 4 x capacity, "
