@@ -87,11 +87,4 @@ __device__ __forceinline__ double cell_dt_bound(const T U[5], const GridParams& 
   return fmin(tx, fmin(ty, tz));
 }
 
-// Workgroups are dealt to the 8 XCDs round robin; within a grid's block range (which starts
-// at a multiple of 8) this gives each XCD a contiguous run of logical blocks.
-__device__ __forceinline__ long long xcd_local(long long lb, long long nb) {
-  const long long per = nb / 8;
-  return (lb % 8) * per + lb / 8;
-}
-
 }  // namespace ctu
