@@ -46,6 +46,23 @@ __device__ __forceinline__ BlockRef block_ref(const LaunchTab& tab) {
   return r;
 }
 
+// Index of this wavefront within its block as a wave-uniform value, so that the arithmetic
+// that derives a wavefront's task from it runs on the scalar unit, not the vector ALU.
+__device__ __forceinline__ int wave_in_block() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+// (base + lane) mod n for base + lane >= 0, with base wave-uniform, lane in [0, 64) and
+// n >= 1: one scalar remainder, then no vector division when a row is at least a wavefront
+// long.  (The value for base + lane < 0 is unspecified; callers mask those lanes.)
+__device__ __forceinline__ int wave_row_pos(long long base, int lane, int n) {
+  const long long bm = base % n;
+  const int b = (int)(bm < 0 ? bm + n : bm);
+  const int q = b + lane;
+  if (n >= 64) return q >= n ? q - n : q;
+  return q % n;
+}
+
 // ---- reductions --------------------------------------------------------------------------
 __device__ __forceinline__ double wave_min(double v) {
 #pragma unroll

@@ -174,14 +174,15 @@ __global__ __launch_bounds__(256) void k_ppmp_coef_x(LaunchTab tab) {
   if (!(r.G->s->dt > 0.0)) return;
   const int e = 1 + P.ext;  // cells [-e, n + e - 1] per axis
   const int lane = threadIdx.x & 63;
-  const long long task = r.lb * (kBlock / 64) + (threadIdx.x >> 6);
+  const long long task = r.lb * (kBlock / 64) + wave_in_block();
   const long long plen = (long long)(P.n[1] + 2 * e) * P.N[0];
   const long long nw = (plen + XW - 1) / XW;
   if (task >= nw * (P.n[2] + 2 * e)) return;  // whole wavefront exits together
   const int k = (int)(task / nw) - e;
-  const long long pos = (task % nw) * XW - 3 + lane;
+  const long long pos0 = (task % nw) * XW - 3;  // position of lane 0
+  const long long pos = pos0 + lane;
   const bool in_line = pos >= 0 && pos < plen;
-  const int c = in_line ? (int)(pos % P.N[0]) - P.ng : -P.ng - 1;
+  const int c = in_line ? wave_row_pos(pos0, lane, P.N[0]) - P.ng : -P.ng - 1;
   const long long id = cell_index(P, -P.ng, -e, k) + pos;
   const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
   T rho = T(1), p = T(1), un = T(0);
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(256) void k_dt(LaunchTab tab) {
   const long long ngroups = ngy * P.n[2];
   if (r.lb * kWaves >= ngroups) return;  // whole block idle
   const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
-  const long long grp = r.lb * kWaves + (threadIdx.x >> 6);
+  const long long grp = r.lb * kWaves + wave_in_block();
   double bound = INFINITY;
   if (grp < ngroups) {
     const int j0 = (int)(grp % ngy) * P.xrows;

@@ -355,14 +355,15 @@ __global__ __launch_bounds__(256) void k_eta_x(LaunchTab tab) {
   const GLOBAL T* __restrict__ dstar_all = (const GLOBAL T*)r.G->flux;
   const long long fds = 5 * P.stride;
   const int lane = threadIdx.x & 63;
-  const long long task = r.lb * (kBlock / 64) + (threadIdx.x >> 6);
+  const long long task = r.lb * (kBlock / 64) + wave_in_block();
   const long long plen = (long long)(P.n[1] + 2) * P.N[0];
   const long long nw = (plen + XW - 1) / XW;
   if (task >= nw * (P.n[2] + 2)) return;  // whole wavefront exits together
   const int k = (int)(task / nw) - 1;
-  const long long p = (task % nw) * XW - 3 + lane;
+  const long long p0 = (task % nw) * XW - 3;  // position of lane 0
+  const long long p = p0 + lane;
   const bool in_line = p >= 0 && p < plen;
-  const int c = in_line ? (int)(p % P.N[0]) - P.ng : -P.ng - 1;
+  const int c = in_line ? wave_row_pos(p0, lane, P.N[0]) - P.ng : -P.ng - 1;
   const long long id = cell_index(P, -P.ng, -1, k) + p;
   const T dtodx = T(dt / P.dx[0]);
   const T h1 = T(0.5 * dt / P.dx[1]), h2 = T(0.5 * dt / P.dx[2]);
@@ -430,14 +431,15 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
   GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux;
   const int lane = threadIdx.x & 63;
-  const long long task = r.lb * (kBlock / 64) + (threadIdx.x >> 6);
+  const long long task = r.lb * (kBlock / 64) + wave_in_block();
   const long long plen = (long long)(P.n[1] + 2) * P.N[0];  // positions of one plane
   const long long nw = (plen + XW - 1) / XW;                   // wavefronts per plane
   if (task >= nw * (P.n[2] + 2)) return;  // whole wavefront exits together
   const int k = (int)(task / nw) - 1;
-  const long long p = (task % nw) * XW - 3 + lane;
+  const long long p0 = (task % nw) * XW - 3;  // position of lane 0
+  const long long p = p0 + lane;
   const bool in_line = p >= 0 && p < plen;
-  const int c = in_line ? (int)(p % P.N[0]) - P.ng : -P.ng - 1;
+  const int c = in_line ? wave_row_pos(p0, lane, P.N[0]) - P.ng : -P.ng - 1;
   const long long id = cell_index(P, -P.ng, -1, k) + p;
   const T dtodx = T(dt / P.dx[0]);
 
@@ -524,7 +526,7 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
   const GLOBAL T* __restrict__ dG = (const GLOBAL T*)r.G->flux + 4 * fds;  // dG^{n+1/2}
   const GLOBAL T* __restrict__ dH = dG + fds;                              // dH^{n+1/2}
   const int lane = threadIdx.x & 63;
-  const long long grp = r.lb * kWaves + (threadIdx.x >> 6);
+  const long long grp = r.lb * kWaves + wave_in_block();
   double bound = INFINITY;
   if (grp < ngroups) {  // wave-uniform
     const int j0 = (int)(grp % ngy) * P.xrows;
@@ -546,7 +548,7 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
     for (int cw = ng; cw < plen - ng; cw += XU) {
       const int p = cw - 3 + lane;
       const bool in_line = p >= 0 && p < plen;
-      const int c = in_line ? p % P.N[0] - ng : -ng - 1;
+      const int c = in_line ? wave_row_pos(cw - 3, lane, P.N[0]) - ng : -ng - 1;
       const long long id = linebase + p;
       T U0[5];
       Prim<T> me;
