@@ -191,3 +191,33 @@ def test_noh_carbuncle_near_axes(ctu):
     assert sd[1][0] < 0.5 * sd[0][0], sd
     assert sd[1][1] < 0.5 * sd[0][1], sd
     assert abs(sd[1][2] - sd[0][2]) < 0.005, sd
+
+
+@pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
+def test_batch_mixing_hcorr_with_other_methods(ctu, graph):
+    """A batch holding Roe + H grids (PPMC and PPMP, both precisions, one of them with one-cell
+    z extent) beside plain Roe and exact grids: every grid advances exactly as it does alone
+    (the eta passes and the widened y sweep run over the launch tables of all H grids)."""
+    wls = [WL.kelvin_helmholtz(24, 20, 16), WL.random_state(18, 14, 12, seed=81),
+           WL.shock_duct(48, 8), WL.sod(40, 6, 6), WL.random_state(20, 9, 7, seed=82, mach=2.0),
+           WL.kelvin_helmholtz(16, 16, 16)]
+    kinds = [dict(prec=ctu.FP64, riemann=1, h_correction=1),
+             dict(prec=ctu.FP32, riemann=1, h_correction=1),
+             dict(prec=ctu.FP64, riemann=1, h_correction=1),
+             dict(prec=ctu.FP64, riemann=1, recon=1, h_correction=1),
+             dict(prec=ctu.FP64, riemann=1), dict(prec=ctu.FP32)]
+    _announce("batch roe-h + others graph", graph)
+    solo = []
+    for wl, kw in zip(wls, kinds):
+        g = ctu.Grid.from_workload(wl, **kw)
+        g.advance(6)
+        solo.append(g.get_state())
+    grids = [ctu.Grid.from_workload(wl, **kw) for wl, kw in zip(wls, kinds)]
+    b = ctu.Batch(max_slots=8, graph=graph)
+    tickets = [b.submit(g, 6) for g in grids]
+    b.run(6)
+    for tk in tickets:
+        assert b.poll(tk)[0] == ctu.TICKET_DONE
+    for g, ref in zip(grids, solo):
+        assert np.array_equal(g.get_state(), ref)
+    b.close()
