@@ -1,9 +1,12 @@
 /*
  * ctu.h -- C ABI of the MI355X (gfx950) CTU library: one unsplit Corner Transport Upwind
- * timestep of the 3D Euler equations on a static Cartesian mesh, with PPMC reconstruction
- * and characteristic tracing, exact-Riemann interface fluxes and the CFL time-step
- * reduction (Schneider & Robertson, "Cholla", arXiv:1410.4194: Sec. 2.1 and Appendices
- * A.3 and B.1).
+ * timestep of the 3D Euler equations on a static Cartesian mesh (Schneider & Robertson,
+ * "Cholla", arXiv:1410.4194): PPMC or PPMP reconstruction with half-step tracing (Sec. 2.2,
+ * App. A.3, A.4), interface fluxes from the exact Riemann solver or the Roe solver with the
+ * HLLE fallback and the optional H correction (Sec. 2.3, App. B.1, B.2, C), the CTU
+ * transverse corrections and conservative update (Sec. 2.1), the CFL time step, and
+ * periodic, outflow or reflecting boundaries (Sec. 3.1); one grid at a time or batches of
+ * independent grids.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
