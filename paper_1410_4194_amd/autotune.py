@@ -12,8 +12,12 @@ library's own per-kernel event timing and stores the winners in a table that
     python -m paper_1410_4194_amd.autotune --out tiles.json [--sizes 32 48 64 ...]
 
 The table maps precision -> axis length -> best target length for the y sweep and for the
-z sweep (measured on cubic grids of that edge).  The tile shape changes results only by
-rounding: a segment's first trace is a separately compiled copy of the same formulas.
+z sweep, measured on cubic grids of that edge holding the shock-cloud initial state (a
+Mach-10 shock and a dense cloud in uniform gas, the state the bench and the serving requests
+run; ``--workload kh`` tunes on the Kelvin-Helmholtz shear layer instead, which is smooth
+everywhere and favours slightly longer segments at 256).  The tile shape changes results
+only by rounding: a segment's first trace is a separately compiled copy of the same
+formulas.
 """
 from __future__ import annotations
 
@@ -43,14 +47,21 @@ def _time_candidate(ctu, wl, prec, seg, steps):
     return y / steps, z / steps
 
 
-def tune(sizes=DEFAULT_SIZES, precs=None, candidates=CANDIDATES, steps=8, log=print):
+WORKLOADS = ("shock_cloud", "kh")
+
+
+def tune(sizes=DEFAULT_SIZES, precs=None, candidates=CANDIDATES, steps=8, log=print,
+         workload="shock_cloud"):
     from . import ctu, workloads as WL
+    if workload not in WORKLOADS:
+        raise ValueError(f"unknown workload {workload!r}")
     precs = precs if precs is not None else (ctu.FP64, ctu.FP32)
-    table = {"candidates": list(candidates), "steps": steps, "fp64": {}, "fp32": {}}
+    table = {"candidates": list(candidates), "steps": steps, "workload": workload,
+             "fp64": {}, "fp32": {}}
     for prec in precs:
         name = "fp64" if prec == ctu.FP64 else "fp32"
         for n in sizes:
-            wl = WL.kelvin_helmholtz(n, n, n)
+            wl = WL.shock_cloud(n) if workload == "shock_cloud" else WL.kelvin_helmholtz(n, n, n)
             times = {}
             for seg in candidates:
                 if seg > n + 1:
@@ -96,9 +107,10 @@ def main():
     ap.add_argument("--out", default=TABLE_PATH)
     ap.add_argument("--sizes", type=int, nargs="*", default=list(DEFAULT_SIZES))
     ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--workload", choices=WORKLOADS, default="shock_cloud")
     args = ap.parse_args()
     t0 = time.perf_counter()
-    table = tune(args.sizes, steps=args.steps,
+    table = tune(args.sizes, steps=args.steps, workload=args.workload,
                  log=lambda *a: print(*a, file=sys.stderr, flush=True))
     table["seconds"] = round(time.perf_counter() - t0, 1)
     with open(args.out, "w") as fh:
