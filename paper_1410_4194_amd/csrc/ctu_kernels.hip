@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void k_ppmp_coef_x(LaunchTab tab) {
 
 // Axes y and z: each thread marches one column along D over a segment of kCoefSeg cells with a
 // seven-cell window, reading each cell once.  Block layout per grid: (plane block, segment).
-constexpr int kCoefSeg = 32;
+constexpr int kCoefSeg = 8;
 
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_ppmp_coef_march(LaunchTab tab) {
