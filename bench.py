@@ -192,7 +192,7 @@ def run_batched(ctu, torch, WL, prec, steps, warmup, count=64, compare_solo_step
     return out
 
 
-def run_serve(ctu, WL, rate, count, hbm_budget, seed, steps_per_round=4, keep=False,
+def run_serve(ctu, WL, rate, count, hbm_budget, seed, steps_per_round=8, keep=False,
               policy="fifo"):
     from paper_1410_4194_amd import serve as S
     reqs = WL.shock_cloud_requests(count, rate=rate, seed=seed)

@@ -115,7 +115,7 @@ def next_admission(pending: List[Request], now: float, free_bytes: int, free_slo
 
 
 def serve(requests: List[Request], hbm_budget: int, max_slots: int = 64,
-          steps_per_round: int = 4, graph: bool = True, keep_states: bool = False,
+          steps_per_round: int = 8, graph: bool = True, keep_states: bool = False,
           clock: Callable[[], float] = time.perf_counter, policy: str = "fifo") -> ServeStats:
     """Run the request loop until every request is answered.
 
