@@ -1,9 +1,11 @@
-"""CPU oracle for the CTU + PPMC + exact-Riemann step (TEST INFRASTRUCTURE ONLY).
+"""CPU oracle for the CTU step (TEST INFRASTRUCTURE ONLY): PPMC or PPMP reconstruction, the
+exact or the Roe/HLLE Riemann solver, the optional H correction.
 
 Thin ctypes wrapper over ``libctu_oracle.so`` (plain serial FP64 C, see ctu_oracle.c).
 Only the tests, the smoke check and the benchmark's CPU-baseline leg import this package;
 the GPU library never does.  Arrays are numpy float64; a conserved state is a (5, NZ, NY, NX)
-array over the allocated box (three ghost layers per side), fields (rho, mx, my, mz, E).
+array over the allocated box (``Config.ng`` ghost layers per side: 3 with PPMC, 4 with PPMP,
+one more with the H correction), fields (rho, mx, my, mz, E).
 """
 from __future__ import annotations
 

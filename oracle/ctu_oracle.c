@@ -1,6 +1,6 @@
 /*
  * ctu_oracle.c -- plain serial FP64 oracle for one CTU step (PPMC or PPMP reconstruction,
- * exact or Roe/HLLE Riemann solver).
+ * exact or Roe/HLLE Riemann solver, optional H correction).
  *
  * TEST INFRASTRUCTURE ONLY (see ctu_oracle.h).  Written from the paper
  * (Schneider & Robertson 2015, arXiv:1410.4194):
@@ -11,6 +11,7 @@
  *     van Leer limiter of App. A.1.
  *   - Exact Riemann solver: App. B.1 (Toro's solver, sampled at x/t = 0).
  *   - Roe solver with the HLLE failsafe: Sec. 2.3.2-2.3.3, App. B.2.
+ *   - H correction of the second-stage Roe fluxes: App. C.
  *   - Boundary conditions: Sec. 3.1 (periodic, transmissive and reflecting ghosts).
  * Readings of garbled or silent passages are marked [Qn] and listed in the design notes.
  */
