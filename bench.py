@@ -16,8 +16,15 @@ Beside the primary line's value, the same JSON line carries
   serve:   Poisson-arriving shock-cloud requests (edges {64, 96, 128, 192}, density contrast
            log-uniform in [10, 1000], Mach uniform in [1.5, 10], radius in [0.08, 0.15], run
            to 1.5 cloud-crushing times, FP32 with the FP64 Newton solve) admitted by HBM
-           footprint into a continuous batch (arrival order, or --serve-policy sjf: least
-           estimated work first): p50/p99 time-to-solution and aggregate rate.
+           footprint (2 GB budget) into a continuous batch, least estimated work first
+           (--serve-policy fifo: arrival order): p50/p99 time-to-solution and aggregate rate;
+  methods: the same 256^3 workload with PPMC + Roe/HLLE, PPMC + Roe with the H correction,
+           PPMP + exact, PPMP + Roe/HLLE and PPMP + Roe with the H correction, both
+           precisions (--no-methods skips them and the next leg);
+  workloads: the primary step on the 256^3 turbulent cloud and Kelvin-Helmholtz layer;
+  cpu_baseline: the serial FP64 oracle on a bounded sample of the same state;
+  roofline: the dominant kernel against the HBM and FP vector peaks, with its measured
+           traffic (committed counters) and what plain streaming kernels reach here.
 --precision-study runs the 512^3 turbulent cloud for 50 steps in FP64 and FP32 and reports
 their relative L1 distance (also with the shock started at x = 0.14, where it reaches the
 cloud within the 50 steps); --serve-sweep sweeps the serving arrival rate under both
