@@ -414,12 +414,13 @@ __global__ __launch_bounds__(256) void k_eta_x(LaunchTab tab) {
 
 // First-stage x sweep.  The x-rows of one z-plane (j over the extended range [-1, n_y], each
 // row with its three ghost cells per side) lie back to back in memory, so they are treated
-// as one flattened line of positions p = (j + 1) N_x + (c + 3).  A wavefront covers 64
+// as one flattened line of positions p = (j + 1) N_x + (c + 3).  A chunk covers 64
 // consecutive positions: lane l holds position XW w - 3 + l, slopes are valid on lanes
 // 1..62, traces on 2..61, lanes 3..61 solve the face c-1/2 of their cell when
 // 0 <= c <= n_x, and lanes 3..60 store the difference dF(c) = F(c-1/2) - F(c+1/2) of their
 // real cell (F(c+1/2) from the next lane).  Every stencil of such a face lies in its own
-// row, so short rows share a wavefront instead of leaving most of its lanes idle.
+// row, so short rows share a chunk instead of leaving most of its lanes idle.  A wavefront
+// takes kXChunks consecutive chunks, paying its set-up once for them.
 template <typename T, int STAGE, bool HIST, int K, int R>
 __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   static_assert(STAGE == 1, "the second-stage x sweep is fused with the update");
@@ -431,69 +432,72 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
   GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux;
   const int lane = threadIdx.x & 63;
-  const long long task = r.lb * (kBlock / 64) + wave_in_block();
+  const long long task0 = (r.lb * (kBlock / 64) + wave_in_block()) * kXChunks;
   const long long plen = (long long)(P.n[1] + 2) * P.N[0];  // positions of one plane
-  const long long nw = (plen + XW - 1) / XW;                   // wavefronts per plane
-  if (task >= nw * (P.n[2] + 2)) return;  // whole wavefront exits together
-  const int k = (int)(task / nw) - 1;
-  const long long p0 = (task % nw) * XW - 3;  // position of lane 0
-  const long long p = p0 + lane;
-  const bool in_line = p >= 0 && p < plen;
-  const int c = in_line ? wave_row_pos(p0, lane, P.N[0]) - P.ng : -P.ng - 1;
-  const long long id = cell_index(P, -P.ng, -1, k) + p;
+  const long long nw = (plen + XW - 1) / XW;                   // chunks per plane
+  const long long ntask = nw * (P.n[2] + 2);
+  if (task0 >= ntask) return;  // whole wavefront exits together
   const T dtodx = T(dt / P.dx[0]);
-
-  Prim<T> me;
-  if (in_line)
-    load_prim<T, 0>(u, P.stride, id, P, me);
-  else
-    safe_prim(me);
   const int lm1 = lane > 0 ? lane - 1 : 0;
   const int lp1 = lane < 63 ? lane + 1 : 63;
-  const Prim<T> left = shfl_prim(me, lm1);
-  const Prim<T> right = shfl_prim(me, lp1);
-  T sl[5];
-  slope_sel<R>(left, me, right, sl);
-  T slm[5], slp[5];
-#pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    slm[q] = __shfl(sl[q], lm1, 64);
-    slp[q] = __shfl(sl[q], lp1, 64);
-  }
-  // traced primitive face states enter the solver directly
-  T WL[5], WR[5];
-  PpmpCoef<T> kc{T(0), T(0)};
-  if (R == 1 && in_line && c >= -1 - P.ext && c <= P.n[0] + P.ext)
-    kc = load_coef<R, 0, T>(r.G, P.stride, id);
-  trace_sel<R>(left, me, right, slm, sl, slp, kc, T(P.gamma), dtodx, WL, WR);
-  T prevR[5];
-#pragma unroll
-  for (int q = 0; q < 5; ++q) prevR[q] = __shfl(WR[q], lm1, 64);
-  T F[5] = {T(0), T(0), T(0), T(0), T(0)};  // flux at face c-1/2
-  int iters = -1;  // Newton iterations of this lane's counted solve
   const int e = P.ext;  // one more cell on each side with the H correction
-  if (lane >= 3 && lane <= 61 && c >= -e && c <= P.n[0] + e) {
-    // lane 61's face is solved again as the next wavefront's first face: count it there
-    const bool counted = lane <= 60 || task % nw == nw - 1;
-    RiemannCounts cnt{0u, 0u, 0};
-    face_flux_w<T, K>(prevR, WL, P, F, cnt);
-    if (counted) {
-      flush_counts(cnt, s);
-      iters = cnt.iters;
+  NewtonHist hist{};
+  for (int qc = 0; qc < kXChunks; ++qc) {
+    const long long task = task0 + qc;
+    if (task >= ntask) break;  // wave-uniform
+    const int k = (int)(task / nw) - 1;
+    const long long p0 = (task % nw) * XW - 3;  // position of lane 0
+    const long long p = p0 + lane;
+    const bool in_line = p >= 0 && p < plen;
+    const int c = in_line ? wave_row_pos(p0, lane, P.N[0]) - P.ng : -P.ng - 1;
+    const long long id = cell_index(P, -P.ng, -1, k) + p;
+
+    Prim<T> me;
+    if (in_line)
+      load_prim<T, 0>(u, P.stride, id, P, me);
+    else
+      safe_prim(me);
+    const Prim<T> left = shfl_prim(me, lm1);
+    const Prim<T> right = shfl_prim(me, lp1);
+    T sl[5];
+    slope_sel<R>(left, me, right, sl);
+    T slm[5], slp[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      slm[q] = __shfl(sl[q], lm1, 64);
+      slp[q] = __shfl(sl[q], lp1, 64);
     }
-  }
-  T Fr[5];  // flux at face c+1/2
+    // traced primitive face states enter the solver directly
+    T WL[5], WR[5];
+    PpmpCoef<T> kc{T(0), T(0)};
+    if (R == 1 && in_line && c >= -1 - P.ext && c <= P.n[0] + P.ext)
+      kc = load_coef<R, 0, T>(r.G, P.stride, id);
+    trace_sel<R>(left, me, right, slm, sl, slp, kc, T(P.gamma), dtodx, WL, WR);
+    T prevR[5];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) Fr[q] = __shfl(F[q], lp1, 64);
-  if (lane >= 3 && lane <= 60 && c >= -e && c < P.n[0] + e) {
+    for (int q = 0; q < 5; ++q) prevR[q] = __shfl(WR[q], lm1, 64);
+    T F[5] = {T(0), T(0), T(0), T(0), T(0)};  // flux at face c-1/2
+    int iters = -1;  // Newton iterations of this lane's counted solve
+    if (lane >= 3 && lane <= 61 && c >= -e && c <= P.n[0] + e) {
+      // lane 61's face is solved again as the next chunk's first face: count it there
+      const bool counted = lane <= 60 || task % nw == nw - 1;
+      RiemannCounts cnt{0u, 0u, 0};
+      face_flux_w<T, K>(prevR, WL, P, F, cnt);
+      if (counted) {
+        flush_counts(cnt, s);
+        iters = cnt.iters;
+      }
+    }
+    T Fr[5];  // flux at face c+1/2
 #pragma unroll
-    for (int q = 0; q < 5; ++q) out[q * P.stride + id] = F[q] - Fr[q];
+    for (int q = 0; q < 5; ++q) Fr[q] = __shfl(F[q], lp1, 64);
+    if (lane >= 3 && lane <= 60 && c >= -e && c < P.n[0] + e) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) out[q * P.stride + id] = F[q] - Fr[q];
+    }
+    if (HIST) hist.add(iters, iters >= 0);  // every lane takes the add
   }
-  if (HIST) {  // wave counts sit in vector registers: every lane takes the add and the flush
-    NewtonHist hist{};
-    hist.add(iters, iters >= 0);
-    hist.flush(s);
-  }
+  if (HIST) hist.flush(s);
 }
 
 // Second-stage x sweep fused with the conservative update (a8) and the CFL bound (a9).
