@@ -1,7 +1,9 @@
 """CPU oracle for the CTU step (TEST INFRASTRUCTURE ONLY): PPMC or PPMP reconstruction, the
 exact or the Roe/HLLE Riemann solver, the optional H correction.
 
-Thin ctypes wrapper over ``libctu_oracle.so`` (plain serial FP64 C, see ctu_oracle.c).
+Thin ctypes wrapper over ``libctu_oracle.so`` (plain serial FP64 C, see ctu_oracle.c), or,
+after ``set_threads(n)``, over the OpenMP build of the same source (``libctu_oracle_omp.so``,
+bit-identical results).
 Only the tests, the smoke check and the benchmark's CPU-baseline leg import this package;
 the GPU library never does.  Arrays are numpy float64; a conserved state is a (5, NZ, NY, NX)
 array over the allocated box (``Config.ng`` ghost layers per side: 3 with PPMC, 4 with PPMP,
@@ -25,7 +27,10 @@ RECON_PPMC, RECON_PPMP = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.environ.get("CTU_ORACLE_LIB") or os.path.join(_HERE, "libctu_oracle.so")
+# the OpenMP build of the same source (z-planes shared among threads, bit-identical results)
+_LIBPATH_OMP = None if os.environ.get("CTU_ORACLE_LIB") else os.path.join(_HERE, "libctu_oracle_omp.so")
 _lib = None
+_libs = {}
 
 
 class _Config(C.Structure):
@@ -47,12 +52,37 @@ _dp = C.POINTER(C.c_double)
 
 def _load():
     global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIBPATH):
+    if _lib is None:
+        _lib = _open(_LIBPATH)
+    return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads of the whole-grid operations (step, update_box): 1 selects the serial build,
+    n > 1 the OpenMP build with n threads.  Returns the count in effect (1 when only the
+    serial library is available, e.g. a library given by CTU_ORACLE_LIB)."""
+    global _lib
+    if n <= 1 or _LIBPATH_OMP is None:
+        _lib = _open(_LIBPATH)
+        return 1
+    _lib = _open(_LIBPATH_OMP)
+    return int(_lib.ref_threads(int(n)))
+
+
+def threads() -> int:
+    """Threads the whole-grid operations currently use."""
+    return int(_load().ref_threads(0))
+
+
+def _open(path):
+    if path in _libs:
+        return _libs[path]
+    if not os.path.exists(path):
         from . import build as _b  # noqa: F401  (build on first use)
         _b.build()
-    lib = C.CDLL(_LIBPATH)
+    lib = C.CDLL(path)
+    lib.ref_threads.argtypes = [C.c_int]
+    lib.ref_threads.restype = C.c_int
     lib.ref_cons_to_prim.argtypes = [_dp, C.c_double, C.c_double, _dp]
     lib.ref_cons_to_prim.restype = C.c_int
     lib.ref_prim_to_cons.argtypes = [_dp, C.c_double, _dp]
@@ -90,7 +120,7 @@ def _load():
     lib.ref_ctu_step.argtypes = [C.POINTER(_Config), C.POINTER(_dp), C.c_double,
                                  C.POINTER(_Stats)]
     lib.ref_ctu_step.restype = C.c_int
-    _lib = lib
+    _libs[path] = lib
     return lib
 
 

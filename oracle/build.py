@@ -1,7 +1,9 @@
-"""Build the CPU oracle shared library (test infrastructure only).
+"""Build the CPU oracle shared libraries (test infrastructure only).
 
-Plain serial C, double precision, -O2 with FMA contraction off so that every operation is
-rounded as written.  Usage: ``python oracle/build.py``.
+Plain C, double precision, -O2 with FMA contraction off so that every operation is rounded
+as written.  The same source is built twice: serial (``libctu_oracle.so``) and with OpenMP
+over z-planes (``libctu_oracle_omp.so``); the two give bit-identical results.
+Usage: ``python oracle/build.py``.
 """
 import os
 import subprocess
@@ -10,15 +12,17 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ctu_oracle.c")
 LIB = os.path.join(HERE, "libctu_oracle.so")
+LIB_OMP = os.path.join(HERE, "libctu_oracle_omp.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-Wall", "-Wextra",
-           "-fPIC", "-shared", SRC, "-o", LIB + ".tmp", "-lm"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    for lib, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-Wall",
+               "-Wextra", "-fPIC", "-shared", *extra, SRC, "-o", lib + ".tmp", "-lm"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(lib + ".tmp", lib)
     return LIB
 
 

@@ -14,12 +14,20 @@
  *   - H correction of the second-stage Roe fluxes: App. C.
  *   - Boundary conditions: Sec. 3.1 (periodic, transmissive and reflecting ghosts).
  * Readings of garbled or silent passages are marked [Qn] and listed in the design notes.
+ *
+ * The same source builds twice: plain serial, and with OpenMP, where the loops over the
+ * z-planes of ref_ctu_update_box are shared among threads.  Every cell's result is computed
+ * by the same operations in either build (the planes are independent; only integer counters
+ * are summed across threads), so the two builds agree bit for bit.
  */
 #include "ctu_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 
 /* ------------------------------------------------------------------------------------ */
@@ -789,6 +797,32 @@ double ref_compute_dt(const ref_config* c, double* const u[5]) {
   return c->cfl * best;
 }
 
+/* Threads of the OpenMP build (n > 0 sets the count); the serial build always has one. */
+int ref_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
+/* Adds one thread's counters to the caller's (integer sums: the order does not matter). */
+static void stats_merge(ref_stats* st, const ref_stats* t) {
+  if (!st) return;
+#ifdef _OPENMP
+#pragma omp critical(ref_stats_merge)
+#endif
+  {
+    st->solves += t->solves;
+    st->newton_iters += t->newton_iters;
+    st->newton_capped += t->newton_capped;
+    st->p_floored += t->p_floored;
+    st->hlle += t->hlle;
+  }
+}
+
 /* A box of cells [lo, hi) in real-cell coordinates with its own compact storage. */
 typedef struct {
   int lo[3], hi[3];
@@ -885,16 +919,26 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
   long nP = box_size(&P);
   double* W[5];
   for (int f = 0; f < 5; ++f) W[f] = (double*)malloc(sizeof(double) * nP);
-  for (int k = P.lo[2]; k < P.hi[2]; ++k)
-    for (int j = P.lo[1]; j < P.hi[1]; ++j)
-      for (int i = P.lo[0]; i < P.hi[0]; ++i) {
-        double U[5], w[5];
-        long id = alloc_index(c, i, j, k);
-        for (int f = 0; f < 5; ++f) U[f] = u[f][id];
-        if (ref_cons_to_prim(U, g, c->p_floor, w) && st) st->p_floored += 1;
-        long pb = box_index(&P, i, j, k);
-        for (int f = 0; f < 5; ++f) W[f][pb] = w[f];
-      }
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+  {
+    ref_stats ts = {0, 0, 0, 0, 0};
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+    for (int k = P.lo[2]; k < P.hi[2]; ++k)
+      for (int j = P.lo[1]; j < P.hi[1]; ++j)
+        for (int i = P.lo[0]; i < P.hi[0]; ++i) {
+          double U[5], w[5];
+          long id = alloc_index(c, i, j, k);
+          for (int f = 0; f < 5; ++f) U[f] = u[f][id];
+          if (ref_cons_to_prim(U, g, c->p_floor, w)) ts.p_floored += 1;
+          long pb = box_index(&P, i, j, k);
+          for (int f = 0; f < 5; ++f) W[f][pb] = w[f];
+        }
+    stats_merge(st, &ts);
+  }
 
   /* Per direction: conserved traced states of every cell of X (cell-centred labels:
    * Us[d][0] = U*_L at the cell's left face, Us[d][1] = U*_R at its right face), and
@@ -911,6 +955,9 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
   for (int d = 0; d < 3; ++d) {
     double dtodx = dt / dd[d];
     /* Step 1 of Sec. 2.1: reconstruction and half-step characteristic tracing. */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int k = X.lo[2]; k < X.hi[2]; ++k)
       for (int j = X.lo[1]; j < X.hi[1]; ++j)
         for (int i = X.lo[0]; i < X.hi[0]; ++i) {
@@ -946,27 +993,37 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
     /* Step 2: first Riemann solve at each d-face between cells of X.  [Q30] the right
      * face state W*_R of cell c is the left input U*_L of face c+1/2, and W*_L of cell
      * c+1 is its right input U*_R. */
-    for (int k = X.lo[2]; k < X.hi[2]; ++k)
-      for (int j = X.lo[1]; j < X.hi[1]; ++j)
-        for (int i = X.lo[0]; i < X.hi[0]; ++i) {
-          int pos[3] = {i, j, k};
-          if (pos[d] + 1 >= X.hi[d]) continue;
-          int nb[3] = {i, j, k};
-          nb[d] += 1;
-          long xc = box_index(&X, i, j, k);
-          long xn = box_index(&X, nb[0], nb[1], nb[2]);
-          double ul[5], ur[5], fl[5];
-          for (int q = 0; q < 5; ++q) {
-            ul[q] = Us[d][1][rot[d][q]][xc];
-            ur[q] = Us[d][0][rot[d][q]][xn];
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+      ref_stats ts = {0, 0, 0, 0, 0};
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+      for (int k = X.lo[2]; k < X.hi[2]; ++k)
+        for (int j = X.lo[1]; j < X.hi[1]; ++j)
+          for (int i = X.lo[0]; i < X.hi[0]; ++i) {
+            int pos[3] = {i, j, k};
+            if (pos[d] + 1 >= X.hi[d]) continue;
+            int nb[3] = {i, j, k};
+            nb[d] += 1;
+            long xc = box_index(&X, i, j, k);
+            long xn = box_index(&X, nb[0], nb[1], nb[2]);
+            double ul[5], ur[5], fl[5];
+            for (int q = 0; q < 5; ++q) {
+              ul[q] = Us[d][1][rot[d][q]][xc];
+              ur[q] = Us[d][0][rot[d][q]][xn];
+            }
+            face_flux(c, ul, ur, 0.0, fl, &ts);
+            for (int q = 0; q < 5; ++q) Fs[d][rot[d][q]][xc] = fl[q];
+            if (fstar) {
+              long ai = alloc_index(c, i, j, k);
+              for (int q = 0; q < 5; ++q) fstar[d * 5 + rot[d][q]][ai] = fl[q];
+            }
           }
-          face_flux(c, ul, ur, 0.0, fl, st);
-          for (int q = 0; q < 5; ++q) Fs[d][rot[d][q]][xc] = fl[q];
-          if (fstar) {
-            long ai = alloc_index(c, i, j, k);
-            for (int q = 0; q < 5; ++q) fstar[d * 5 + rot[d][q]][ai] = fl[q];
-          }
-        }
+      stats_merge(st, &ts);
+    }
   }
 
   /* Steps 3-4: transverse correction (eq. transverse_evolution) and the second Riemann
@@ -996,6 +1053,9 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
       }
       E[d] = make_box(elo, ehi);
       eta[d] = (double*)malloc(sizeof(double) * box_size(&E[d]));
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
       for (int k = E[d].lo[2]; k < E[d].hi[2]; ++k)
         for (int j = E[d].lo[1]; j < E[d].hi[1]; ++j)
           for (int i = E[d].lo[0]; i < E[d].hi[0]; ++i) {
@@ -1012,48 +1072,61 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
 
   for (int d = 0; d < 3; ++d) {
     int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
-    for (int k = H[d].lo[2]; k < H[d].hi[2]; ++k)
-      for (int j = H[d].lo[1]; j < H[d].hi[1]; ++j)
-        for (int i = H[d].lo[0]; i < H[d].hi[0]; ++i) {
-          int cl[3] = {i, j, k};
-          int cr[3] = {i, j, k};
-          cr[d] += 1;
-          double Uh[2][5];
-          ctu_face_states(c, d, cl, dt, &X, Us, Fs, Uh);
-          /* eta^H: this face and the transverse faces on both sides of its two cells (the
-           * nine-point stencil of App. C, [Q28]) */
-          double eta_h = 0.0;
-          if (ext) {
-            eta_h = eta[d][box_index(&E[d], i, j, k)];
-            for (int side = 0; side < 2; ++side) {
-              const int* cc = side == 0 ? cl : cr;
-              for (int tt = 0; tt < 2; ++tt) {
-                int t = tt == 0 ? t1 : t2;
-                int m[3] = {cc[0], cc[1], cc[2]};
-                m[t] -= 1; /* face cc - 1/2 along t */
-                eta_h = fmax(eta_h, eta[t][box_index(&E[t], m[0], m[1], m[2])]);
-                eta_h = fmax(eta_h, eta[t][box_index(&E[t], cc[0], cc[1], cc[2])]);
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+      ref_stats ts = {0, 0, 0, 0, 0};
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+      for (int k = H[d].lo[2]; k < H[d].hi[2]; ++k)
+        for (int j = H[d].lo[1]; j < H[d].hi[1]; ++j)
+          for (int i = H[d].lo[0]; i < H[d].hi[0]; ++i) {
+            int cl[3] = {i, j, k};
+            int cr[3] = {i, j, k};
+            cr[d] += 1;
+            double Uh[2][5];
+            ctu_face_states(c, d, cl, dt, &X, Us, Fs, Uh);
+            /* eta^H: this face and the transverse faces on both sides of its two cells (the
+             * nine-point stencil of App. C, [Q28]) */
+            double eta_h = 0.0;
+            if (ext) {
+              eta_h = eta[d][box_index(&E[d], i, j, k)];
+              for (int side = 0; side < 2; ++side) {
+                const int* cc = side == 0 ? cl : cr;
+                for (int tt = 0; tt < 2; ++tt) {
+                  int t = tt == 0 ? t1 : t2;
+                  int m[3] = {cc[0], cc[1], cc[2]};
+                  m[t] -= 1; /* face cc - 1/2 along t */
+                  eta_h = fmax(eta_h, eta[t][box_index(&E[t], m[0], m[1], m[2])]);
+                  eta_h = fmax(eta_h, eta[t][box_index(&E[t], cc[0], cc[1], cc[2])]);
+                }
               }
             }
+            double ul[5], ur[5], fl[5];
+            for (int q = 0; q < 5; ++q) {
+              ul[q] = Uh[0][rot[d][q]];
+              ur[q] = Uh[1][rot[d][q]];
+            }
+            face_flux(c, ul, ur, eta_h, fl, &ts);
+            long hb = box_index(&H[d], i, j, k);
+            for (int q = 0; q < 5; ++q) Fh[d][rot[d][q]][hb] = fl[q];
+            if (fhalf) {
+              long ai = alloc_index(c, i, j, k);
+              for (int q = 0; q < 5; ++q) fhalf[d * 5 + rot[d][q]][ai] = fl[q];
+            }
           }
-          double ul[5], ur[5], fl[5];
-          for (int q = 0; q < 5; ++q) {
-            ul[q] = Uh[0][rot[d][q]];
-            ur[q] = Uh[1][rot[d][q]];
-          }
-          face_flux(c, ul, ur, eta_h, fl, st);
-          long hb = box_index(&H[d], i, j, k);
-          for (int q = 0; q < 5; ++q) Fh[d][rot[d][q]][hb] = fl[q];
-          if (fhalf) {
-            long ai = alloc_index(c, i, j, k);
-            for (int q = 0; q < 5; ++q) fhalf[d * 5 + rot[d][q]][ai] = fl[q];
-          }
-        }
+      stats_merge(st, &ts);
+    }
   }
   for (int d = 0; d < 3; ++d) free(eta[d]);
 
   /* Step 5: conservative update, eq. (conserved_update), terms added left to right. */
   double dtd[3] = {dt / dd[0], dt / dd[1], dt / dd[2]};
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
   for (int k = R.lo[2]; k < R.hi[2]; ++k)
     for (int j = R.lo[1]; j < R.hi[1]; ++j)
       for (int i = R.lo[0]; i < R.hi[0]; ++i) {

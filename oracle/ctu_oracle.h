@@ -152,6 +152,11 @@ int ref_ctu_update_box(const ref_config* c, double* const u[5], double dt, const
 /* One full CTU step in place: ghost fill, then u^{n+1} on every real cell. */
 int ref_ctu_step(const ref_config* c, double* const u[5], double dt, ref_stats* st);
 
+/* Threads used by ref_ctu_update_box (and so ref_ctu_step): the OpenMP build of this source
+ * shares the z-planes of every loop among them (n > 0 sets the count; returns the count in
+ * effect); the serial build ignores n and returns 1.  Both builds give identical results. */
+int ref_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,11 +1,16 @@
-"""Full-size parity: one step of the benchmark workloads on the GPU, checked on sampled boxes
-that the oracle computes independently from the same seeded input.
+"""Full-size parity: steps of the benchmark workloads on the GPU, checked against the oracle.
 
-256^3 FP64 shock-cloud (the benchmark workload) and 512^3 FP32 turbulent cloud.  Both sides
-use the oracle's dt, so the GPU runs the same kernels and launch shapes as the benchmark.
-Sampled boxes cover the shock front, the cloud edge, the domain corners (outflow ghosts) and
-random interior points.
+* The whole 256^3 shock-cloud grid, every cell, one step from an evolved state (the shock
+  started at x = 0.17 has run into the cloud after 90 GPU steps), in FP64 and in the FP32
+  form; the oracle runs its OpenMP build for this.
+* Sampled boxes of one step from the initial states of the 256^3 shock-cloud with every
+  method, of the 512^3 turbulent cloud (FP32), and of its FP64 steps 25 and 50.
+
+Both sides use the same dt, so the GPU runs the same kernels and launch shapes as the
+benchmark.  Every comparison checks the relative L1 norm and every cell against its own
+scale (tests.common.assert_parity).
 """
+import os
 import sys
 
 import numpy as np
@@ -15,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 import oracle as O
 from paper_1410_4194_amd import workloads as WL
-from tests.common import oracle_config, rel_l1
+from tests.common import ELEM32, ELEM64, TOL32, TOL64, assert_parity, oracle_config
 
 
 def _boxes(n, special, rng, count=6, size=8):
@@ -46,14 +51,11 @@ def _check(ctu, wl, prec, tol, special, seed, **method):
     del g
     rng = np.random.default_rng(seed)
     n = wl.nx
-    errs = []
+    tol_elem = ELEM64 if prec == ctu.FP64 else ELEM32
     for lo, hi in _boxes(n, special, rng):
         ref, _ = O.update_box(cfg, u, dt, lo, hi)
         got = gpu[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
-        e = rel_l1(got, ref, wl.gamma)
-        errs.append(e.max())
-        assert e.max() <= tol, (lo, hi, e)
-    print(f"[gpu-test]   max relative L1 over {len(errs)} boxes: {max(errs):.3e}", flush=True)
+        assert_parity(got, ref, wl.gamma, tol, tol_elem, what=(wl.name, prec, lo, hi))
 
 
 def _shock_cloud_special(n):
@@ -61,6 +63,56 @@ def _shock_cloud_special(n):
     cloud_edge = int((0.3 - 0.1) * n)
     return [(shock_x, n // 2, n // 2), (shock_x, 3, 3), (cloud_edge, n // 2, n // 2),
             (int(0.3 * n), n // 2 + int(0.1 * n), n // 2), (0, 0, 0), (n - 1, n - 1, n - 1)]
+
+
+def _oracle_threads():
+    """The OpenMP oracle on this host's share of cores (at most 16)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return O.set_threads(max(1, min(16, n)))
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_shock_cloud_256_full_grid_evolved(prec):
+    """Every cell of the 256^3 shock-cloud after one step from an evolved state: the GPU runs
+    90 steps (its own CFL time steps) with the shock started at x = 0.17, so that it has
+    entered the cloud (edge at x = 0.2) and compressed it; its state is downloaded and one more GPU step is
+    compared with the oracle's step of that same state (FP64 arithmetic on the float state
+    in the FP32 form), cell by cell over the whole grid."""
+    from paper_1410_4194_amd import ctu
+    wl = WL.shock_cloud(256, x_shock=0.17)
+    cfg = oracle_config(wl)
+    print(f"[gpu-test] full grid 256^3 shock-cloud (x_shock 0.17) prec {prec}: 90 GPU steps",
+          flush=True)
+    g = ctu.Grid.from_workload(wl, prec=prec)
+    g.advance(90)
+    U = g.get_state()
+    dt = g.compute_dt()
+    g.step(dt)
+    status, flags, counters = g.check()
+    assert status == ctu.OK, (flags, counters)
+    gpu = g.get_state()
+    g.close()
+    del g
+    # the shock has entered the cloud: cloud gas compressed above its initial density 10
+    rho = U[0].astype(np.float64)
+    assert rho[:, :, 50:70].max() > 14.0, rho[:, :, 50:70].max()
+    threads = _oracle_threads()
+    try:
+        print(f"[gpu-test]   oracle step of the whole grid on {threads} threads", flush=True)
+        u = O.alloc_state(cfg)
+        O.real(cfg, u)[...] = U
+        del U
+        O.step(cfg, u, dt)
+    finally:
+        O.set_threads(1)
+    if prec == ctu.FP64:
+        assert_parity(gpu, O.real(cfg, u), wl.gamma, TOL64, ELEM64, what="256^3 full grid fp64")
+    else:
+        assert_parity(gpu, O.real(cfg, u), wl.gamma, TOL32, ELEM32, what="256^3 full grid fp32")
 
 
 def test_shock_cloud_256_fp64(ctu=None):
@@ -121,8 +173,7 @@ def test_turbulent_cloud_512_fp64_steps_25_and_50():
             for lo, hi in _boxes(n, special, rng, count=3):
                 ref, _ = O.update_box(cfg, u, dt, lo, hi)
                 got = gpu[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
-                e = rel_l1(got, ref, wl.gamma)
-                assert e.max() <= 1e-12, (k, lo, e)
+                assert_parity(got, ref, wl.gamma, TOL64, ELEM64, what=("step", k, lo))
             del u, U
         else:
             g.step(dt)

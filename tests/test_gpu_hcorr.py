@@ -4,7 +4,7 @@ y sweep, which covers the first stage's transverse range for it), and the nine-p
 inside the second-stage sweeps, with PPMC and PPMP.
 
 One step from the same state and dt against the oracle configured the same way (FP64 <=
-1e-12, FP32 <= 1e-5 relative L1); the stationary-contact pattern whose one-step density the
+1e-12, FP32 <= 1e-5 relative L1, and per cell 1e-10 / 1e-4 of the cell's own scale); the stationary-contact pattern whose one-step density the
 oracle pins in closed form; the 3D Noh problem (Sec. 4.3.1) against its analytic solution;
 a grid-aligned duct shock, 300 steps against the oracle and, at twice the resolution, the
 carbuncle that grows without the correction and not with it; the scatter of Noh's shocked
@@ -19,11 +19,13 @@ pytestmark = pytest.mark.gpu
 
 import oracle as O
 from paper_1410_4194_amd import workloads as WL
-from tests.common import oracle_config, oracle_state, rel_l1, run_oracle
+from tests.common import (ELEM64, TOL64, assert_parity, oracle_config, oracle_state,
+                          parity_bounds, run_oracle)
 from tests.test_oracle_hcorr import _contacts_workload, _expected_density
 
-TOL64 = 1e-12
-TOL32 = 1e-5
+# per-cell bound of multi-step FP64 runs, where rounding differences between the two
+# implementations grow at discontinuities over the steps
+MULTI64 = 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -76,12 +78,14 @@ CASES = [
 def test_one_step_hcorr(ctu, name, make, recon, prec):
     wl = make()
     if recon == 1 and name == "rough_outflow_mach3_20x17x13":
-        pytest.skip("PPMP traces this state to non-physical values (outside the method)")
+        # PPMP traces this Mach-3 rough state to negative pressures, outside the method's
+        # domain (the oracle's own step has p < 0); the same seeded state at Mach 2 stays
+        # physical and gives the pair (PPMP, Roe + H, outflow) its rough case
+        wl = WL.random_state(20, 17, 13, seed=72, bc=(1,) * 6, mach=2.0)
     cfg = oracle_config(wl, riemann=1, h_correction=1, recon=recon)
     u = oracle_state(wl, cfg)
     gpu, ref, counters, st = _step_both(ctu, wl, prec, cfg, u, recon)
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= (TOL64 if prec == 0 else TOL32), (name, err)
+    assert_parity(gpu, ref, wl.gamma, *parity_bounds(prec), what=(name, recon, prec))
     # (HLLE counts are not compared: the oracle's first stage also solves a ring of
     # transverse faces beyond what the second stage reads)
 
@@ -105,8 +109,7 @@ def test_one_step_hcorr_evolved_noh(ctu):
     cfg = oracle_config(wl, riemann=1, h_correction=1)
     cfg, u, t, n = run_oracle(wl, steps=25, cfg=cfg)
     gpu, ref, counters, st = _step_both(ctu, wl, 0, cfg, u, 0)
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= TOL64, err
+    assert_parity(gpu, ref, wl.gamma, TOL64, ELEM64, what="evolved noh")
 
 
 def test_noh_3d_analytic(ctu):
@@ -141,8 +144,8 @@ def test_duct_shock_300_steps_parity(ctu):
     assert status == ctu.OK, (flags, counters)
     info = g.info()
     assert info.steps == 300 and abs(info.t / t - 1.0) < 1e-12
-    err = rel_l1(g.get_state(), O.real(cfg, u), wl.gamma)
-    assert err.max() <= 1e-10, err
+    assert_parity(g.get_state(), O.real(cfg, u), wl.gamma, 1e-10, MULTI64,
+                  what="duct shock, 300 steps")
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])

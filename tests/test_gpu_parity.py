@@ -1,8 +1,10 @@
 """GPU parity: the HIP library (through its C ABI) against the CPU oracle.
 
 One step from the same seeded input and the same dt, compared field by field with the
-relative L1 metric of tests.common.rel_l1: FP64 <= 1e-12, FP32 <= 1e-5.  Per-pass checks
-compare the first-stage and CTU fluxes on every face the step computes.  Workloads span
+relative L1 metric of tests.common.rel_l1 (FP64 <= 1e-12, FP32 <= 1e-5) and cell by cell,
+each cell against its own scale (tests.common.elem_err: FP64 <= 1e-10, FP32 <= 1e-4).
+Per-pass checks compare the first-stage and CTU flux differences on every cell the step
+computes, also cell by cell.  Workloads span
 several tiles and ragged sizes, both boundary types, and the degenerate shapes (1-cell
 axes, tiny grids).
 """
@@ -16,10 +18,12 @@ pytestmark = pytest.mark.gpu
 
 import oracle as O
 from paper_1410_4194_amd import workloads as WL
-from tests.common import oracle_config, oracle_state, rel_l1, run_oracle
+from tests.common import (ELEM32, ELEM64, TOL32, TOL64, assert_parity, cell_scales,
+                          oracle_config, oracle_state, parity_bounds, rel_l1, run_oracle)
 
-TOL64 = 1e-12
-TOL32 = 1e-5
+# per-cell bound of multi-step FP64 runs, where rounding differences between the two
+# implementations grow at discontinuities over the steps
+MULTI64 = 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -79,8 +83,7 @@ GAMMA_CASES = [
 def test_one_step_general_gamma(ctu, name, make, prec):
     wl = make()
     g, gpu, ref, cfg, u0, dt = _one_step(ctu, wl, prec)
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= (TOL64 if prec == 0 else TOL32), (name, err)
+    assert_parity(gpu, ref, wl.gamma, *parity_bounds(prec), what=(name, prec))
     status, flags, counters = g.check()
     assert status == ctu.OK, (flags, counters)
 
@@ -89,8 +92,7 @@ def test_one_step_general_gamma(ctu, name, make, prec):
 def test_one_step_fp64(ctu, name, make):
     wl = make()
     g, gpu, ref, cfg, u0, dt = _one_step(ctu, wl, ctu.FP64)
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= TOL64, (name, err)
+    assert_parity(gpu, ref, wl.gamma, TOL64, ELEM64, what=(name, "fp64"))
     status, flags, counters = g.check()
     assert status == ctu.OK, (flags, counters)
 
@@ -100,18 +102,22 @@ def test_one_step_fp32(ctu, name, make):
     wl = make()
     g, gpu, ref, cfg, u0, dt = _one_step(ctu, wl, ctu.FP32)
     assert gpu.dtype == np.float32
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= TOL32, (name, err)
+    assert_parity(gpu, ref, wl.gamma, TOL32, ELEM32, what=(name, "fp32"))
 
 
-def _flux_err(gpu_f, ref_f):
+def _flux_err(gpu_f, ref_f, u, gamma):
+    """Relative L1 per field over the cells the oracle computed, and the largest per-cell
+    error against the cell's flux scale (its field scale times its signal speed |V| + a)."""
     mask = np.isfinite(ref_f[0])
-    errs = []
+    scales, speed = cell_scales(u, gamma)
+    errs, cells = [], []
     for f in range(5):
-        num = np.abs(gpu_f[f][mask] - ref_f[f][mask]).sum()
+        d = np.abs(gpu_f[f][mask] - ref_f[f][mask])
+        num = d.sum()
         den = np.abs(ref_f[f][mask]).sum()
         errs.append(0.0 if num == 0.0 else num / max(den, 1e-300))
-    return np.array(errs), int(mask.sum())
+        cells.append(float(np.max(d / (scales[f][mask] * speed[mask]))))
+    return np.array(errs), np.array(cells), int(mask.sum())
 
 
 def _cell_diff(F, d):
@@ -143,11 +149,13 @@ def test_per_pass_fluxes_fp64(ctu, name, make):
     g.debug_keep_fluxes(True)
     g.step(dt)
     for d in range(3):  # the step keeps per-cell differences of each pass's fluxes
-        e1, n1 = _flux_err(g.debug_fluxes(0, d), _cell_diff(fstar[d], d))
-        e2, n2 = _flux_err(g.debug_fluxes(1, d), _cell_diff(fhalf[d], d))
+        e1, c1, n1 = _flux_err(g.debug_fluxes(0, d), _cell_diff(fstar[d], d), u, wl.gamma)
+        e2, c2, n2 = _flux_err(g.debug_fluxes(1, d), _cell_diff(fhalf[d], d), u, wl.gamma)
+        print(f"[parity] {name} dir {d}: F* L1 {e1.max():.2e} cell {c1.max():.2e}; "
+              f"F^(n+1/2) L1 {e2.max():.2e} cell {c2.max():.2e}", flush=True)
         assert n1 > 0 and n2 > 0
-        assert e1.max() <= TOL64, ("F*", d, e1)
-        assert e2.max() <= TOL64, ("F^{n+1/2}", d, e2)
+        assert e1.max() <= TOL64 and c1.max() <= ELEM64, ("F*", d, e1, c1)
+        assert e2.max() <= TOL64 and c2.max() <= ELEM64, ("F^{n+1/2}", d, e2, c2)
     # keeping the fluxes changes nothing else
     g2 = ctu.Grid.from_workload(wl, prec=ctu.FP64)
     g2.step(dt)
@@ -221,7 +229,7 @@ def test_invalid_step_arguments_change_nothing(ctu):
     dt = O.compute_dt(cfg, u)
     g.step(dt)
     O.step(cfg, u, dt)
-    assert rel_l1(g.get_state(), O.real(cfg, u), wl.gamma).max() <= TOL64
+    assert_parity(g.get_state(), O.real(cfg, u), wl.gamma, TOL64, ELEM64, what="after refusals")
 
 
 def test_advance_equals_host_loop(ctu):
@@ -250,8 +258,8 @@ def test_sod_to_t02_matches_oracle_and_exact(ctu):
     cfg1, u1, t1, n1 = run_oracle(wl1, t_end=0.2)
     assert n1 == info.steps
     ref = O.real(cfg1, u1)[:, 0, 0, :]
-    err = rel_l1(st[:, 0, 0, :], ref, 1.4)
-    assert err.max() <= 1e-10, err
+    # ~100 steps: rounding differences grow at the shock and contact
+    assert_parity(st[:, 0, 0, :], ref, 1.4, 1e-10, MULTI64, what="sod to t=0.2")
     x = (np.arange(128) + 0.5) / 128
     ex = O.exact_solution((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4, (x - 0.5) / 0.2)
     assert np.mean(np.abs(st[0, 0, 0] - ex[0])) < 0.003
@@ -303,8 +311,7 @@ def test_march_segments_do_not_change_results(ctu, prec):
         if ref is None:
             ref = U
         else:
-            err = rel_l1(U, ref, wl.gamma)
-            assert err.max() <= (TOL64 if prec == 0 else TOL32), (seg, err)
+            assert_parity(U, ref, wl.gamma, *parity_bounds(prec), what=("segments", seg, prec))
 
 
 def test_newton_histogram_counts_every_solve(ctu):
@@ -326,8 +333,7 @@ def test_newton_histogram_counts_every_solve(ctu):
     hist = g.newton_histogram()
     assert sum(hist.values()) == 2 * solves, hist
     assert hist["0-1"] + hist["2"] + hist["3"] > 0 and hist["cap"] == 0
-    err = rel_l1(g.get_state(), ref, wl.gamma)
-    assert err.max() <= TOL64, err
+    assert_parity(g.get_state(), ref, wl.gamma, TOL64, ELEM64, what="instrumented sweeps")
     capped = ctu.Grid(ctu.make_config(nx, ny, nz, wl.dx, wl.dy, wl.dz, wl.gamma, wl.bc,
                                       newton_max_iter=1))
     capped.set_primitive(wl.W)
@@ -354,8 +360,7 @@ def test_near_vacuum_rarefaction(ctu):
     gpu = g.get_state()
     ref = O.real(cfg, u)
     assert np.isfinite(ref).all()
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= TOL64, err
+    assert_parity(gpu, ref, wl.gamma, TOL64, MULTI64, what="near vacuum, 8 steps")
 
 METHODS = [("ppmc_exact", {}), ("ppmc_roe", dict(riemann=1)),
            ("ppmc_roe_hcorr", dict(riemann=1, h_correction=1)), ("ppmp_exact", dict(recon=1)),

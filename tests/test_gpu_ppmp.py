@@ -16,10 +16,12 @@ pytestmark = pytest.mark.gpu
 
 import oracle as O
 from paper_1410_4194_amd import workloads as WL
-from tests.common import oracle_config, oracle_state, rel_l1, run_oracle
+from tests.common import (ELEM64, TOL64, assert_parity, oracle_config, oracle_state,
+                          parity_bounds, rel_l1, run_oracle)
 
-TOL64 = 1e-12
-TOL32 = 1e-5
+# per-cell bound of multi-step FP64 runs, where rounding differences between the two
+# implementations grow at discontinuities over the steps
+MULTI64 = 1e-8
 PPMP = 1
 
 
@@ -76,8 +78,8 @@ def test_one_step_ppmp(ctu, name, make, riemann, prec):
     cfg = oracle_config(wl, recon=O.RECON_PPMP, riemann=riemann)
     u = oracle_state(wl, cfg)
     gpu, ref, counters, st = _step_both(ctu, wl, prec, cfg, u, riemann)
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= (TOL64 if prec == 0 else TOL32), (name, err)
+    assert_parity(gpu, ref, wl.gamma, *parity_bounds(prec),
+                  what=(name, prec))
 
 
 @pytest.mark.parametrize("name,make,steps", [
@@ -91,8 +93,8 @@ def test_one_step_ppmp_evolved(ctu, name, make, steps, prec):
     cfg = oracle_config(wl, recon=O.RECON_PPMP)
     cfg, u, t, n = run_oracle(wl, steps=steps, cfg=cfg)
     gpu, ref, counters, st = _step_both(ctu, wl, prec, cfg, u, 0)
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= (TOL64 if prec == 0 else TOL32), err
+    assert_parity(gpu, ref, wl.gamma, *parity_bounds(prec),
+                  what=(wl.name, prec))
 
 
 def test_sod_ppmp_to_t02(ctu):
@@ -108,8 +110,8 @@ def test_sod_ppmp_to_t02(ctu):
     cfg1 = oracle_config(wl1, recon=O.RECON_PPMP)
     cfg1, u1, t1, n1 = run_oracle(wl1, t_end=0.2, cfg=cfg1)
     assert n1 == info.steps
-    err = rel_l1(st[:, 0, 0, :], O.real(cfg1, u1)[:, 0, 0, :], 1.4)
-    assert err.max() <= 1e-10, err
+    assert_parity(st[:, 0, 0, :], O.real(cfg1, u1)[:, 0, 0, :], 1.4, 1e-10, MULTI64,
+                  what=(wl.name, 'to t = 0.2'))
 
 
 @pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])

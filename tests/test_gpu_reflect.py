@@ -15,10 +15,12 @@ pytestmark = pytest.mark.gpu
 
 import oracle as O
 from paper_1410_4194_amd import workloads as WL
-from tests.common import oracle_config, oracle_state, rel_l1, run_oracle
+from tests.common import (ELEM64, TOL64, assert_parity, oracle_config, oracle_state,
+                          parity_bounds, rel_l1, run_oracle)
 
-TOL64 = 1e-12
-TOL32 = 1e-5
+# per-cell bound of multi-step FP64 runs, where rounding differences between the two
+# implementations grow at discontinuities over the steps
+MULTI64 = 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -68,8 +70,8 @@ def test_one_step_reflect(ctu, name, make, prec):
     cfg = oracle_config(wl)
     u = oracle_state(wl, cfg)
     gpu, ref = _step_both(ctu, wl, prec, cfg, u)
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= (TOL64 if prec == 0 else TOL32), (name, err)
+    assert_parity(gpu, ref, wl.gamma, *parity_bounds(prec),
+                  what=(name, prec))
 
 
 @pytest.mark.parametrize("name,make,steps", [
@@ -82,8 +84,8 @@ def test_one_step_reflect_evolved(ctu, name, make, steps, prec):
     wl = make()
     cfg, u, t, n = run_oracle(wl, steps=steps)
     gpu, ref = _step_both(ctu, wl, prec, cfg, u)
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= (TOL64 if prec == 0 else TOL32), (name, err)
+    assert_parity(gpu, ref, wl.gamma, *parity_bounds(prec),
+                  what=(name, prec))
 
 
 def test_mirror_box_identity_on_gpu(ctu):
@@ -105,8 +107,7 @@ def test_mirror_box_identity_on_gpu(ctu):
     g2.set_primitive(W2)
     g2.step(dt)
     b = g2.get_state()[..., :45]
-    err = rel_l1(a, b, wl.gamma)
-    assert err.max() <= TOL64, err
+    assert_parity(a, b, wl.gamma, TOL64, ELEM64, what='mirror box')
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
@@ -164,5 +165,4 @@ def test_blast_waves_to_t_end(ctu):
         assert abs(after[f] - before[f]) <= 1e-12 * abs(before[f])
     cfg, u, t, n = run_oracle(wl, t_end=wl.t_end)
     assert n == info.steps
-    err = rel_l1(st, O.real(cfg, u), wl.gamma)
-    assert err.max() <= 1e-9, err
+    assert_parity(st, O.real(cfg, u), wl.gamma, 1e-9, MULTI64, what="blast waves to t_end")

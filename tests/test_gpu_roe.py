@@ -15,10 +15,12 @@ pytestmark = pytest.mark.gpu
 
 import oracle as O
 from paper_1410_4194_amd import workloads as WL
-from tests.common import oracle_config, oracle_state, rel_l1, run_oracle
+from tests.common import (ELEM64, TOL64, assert_parity, oracle_config, oracle_state,
+                          parity_bounds, rel_l1, run_oracle)
 
-TOL64 = 1e-12
-TOL32 = 1e-5
+# per-cell bound of multi-step FP64 runs, where rounding differences between the two
+# implementations grow at discontinuities over the steps
+MULTI64 = 1e-8
 ROE = 1
 
 
@@ -70,8 +72,8 @@ def test_one_step_roe(ctu, name, make, prec):
     cfg = oracle_config(wl, riemann=ROE)
     u = oracle_state(wl, cfg)
     gpu, ref, counters, st = _step_both(ctu, wl, prec, cfg, u)
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= (TOL64 if prec == 0 else TOL32), (name, err)
+    assert_parity(gpu, ref, wl.gamma, *parity_bounds(prec),
+                  what=(name, prec))
     if prec == 0:
         # the same faces fall back to HLLE on both sides
         assert counters[3] == st.hlle, (counters, st)
@@ -84,8 +86,8 @@ def test_one_step_roe_evolved_blast_waves(ctu, prec):
     cfg = oracle_config(wl, riemann=ROE)
     cfg, u, t, n = run_oracle(wl, steps=60, cfg=cfg)
     gpu, ref, counters, st = _step_both(ctu, wl, prec, cfg, u)
-    err = rel_l1(gpu, ref, wl.gamma)
-    assert err.max() <= (TOL64 if prec == 0 else TOL32), err
+    assert_parity(gpu, ref, wl.gamma, *parity_bounds(prec),
+                  what=(wl.name, prec))
 
 
 def test_hlle_substitutions_are_counted(ctu):
@@ -113,8 +115,8 @@ def test_sod_roe_to_t02(ctu):
     cfg1 = oracle_config(WL.sod(128, 1, 1), riemann=ROE)
     cfg1, u1, t1, n1 = run_oracle(WL.sod(128, 1, 1), t_end=0.2, cfg=cfg1)
     assert n1 == info.steps
-    err = rel_l1(st[:, 0, 0, :], O.real(cfg1, u1)[:, 0, 0, :], 1.4)
-    assert err.max() <= 1e-10, err
+    assert_parity(st[:, 0, 0, :], O.real(cfg1, u1)[:, 0, 0, :], 1.4, 1e-10, MULTI64,
+                  what=(wl.name, 'to t = 0.2'))
     x = (np.arange(128) + 0.5) / 128
     ex = O.exact_solution((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4, (x - 0.5) / 0.2)
     assert np.mean(np.abs(st[0, 0, 0] - ex[0])) < 0.004
