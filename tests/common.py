@@ -61,17 +61,20 @@ def rel_l1(gpu: np.ndarray, ref: np.ndarray, gamma: float) -> np.ndarray:
     return np.array([np.abs(gpu[f] - ref[f]).sum() / scales[f].sum() for f in range(5)])
 
 
-def elem_err(gpu: np.ndarray, ref: np.ndarray, gamma: float):
+def elem_err(gpu: np.ndarray, ref: np.ndarray, gamma: float, allow=None):
     """Per-field largest cell error max_cells |q_gpu - q_ref| / s_f(cell), each cell measured
     against its own scale (cell_scales of the reference), and the index of the worst cell of
     each field.  Unlike the L1 norm this does not dilute an error confined to a few cells
-    (a seam between tiles, chunks or segments)."""
+    (a seam between tiles, chunks or segments).  With `allow` (an array of the cells' shape)
+    each cell's error is divided by its own allowance first."""
     ref = np.asarray(ref, dtype=np.float64)
     gpu = np.asarray(gpu, dtype=np.float64)
     scales, _ = cell_scales(ref, gamma)
     errs, where = [], []
     for f in range(5):
         e = np.abs(gpu[f] - ref[f]) / np.maximum(scales[f], 1e-300)
+        if allow is not None:
+            e = e / allow
         e = np.where(np.isnan(e), np.inf, e)  # a NaN on either side is the worst error
         k = int(np.argmax(e))
         errs.append(float(e.flat[k]))
@@ -79,9 +82,28 @@ def elem_err(gpu: np.ndarray, ref: np.ndarray, gamma: float):
     return np.array(errs), where
 
 
-# One-step parity bounds, FP64 and the FP32 form (relative L1 and per cell, as defined above).
+def cell_condition(ref: np.ndarray, gamma: float, reach: int = 3) -> np.ndarray:
+    """Condition number of each cell's pressure, p = (gamma-1)(E - rho V^2/2) (the primitive
+    variables of Sec. 2): a relative rounding error in E comes back amplified by
+    kappa = E / (E - rho V^2/2) = 1 + kinetic / internal energy, which is of order one in most
+    flows and about 3e5 in the cold hypersonic inflow of Noh's problem (p = 1e-6 at unit
+    speed).  Every quantity a step derives from a cell's state inherits it, so each cell takes
+    the largest kappa within `reach` cells along every axis (the stencil of one CTU step)."""
+    ref = np.asarray(ref, dtype=np.float64)
+    rho = ref[0]
+    ke = 0.5 * (ref[1] ** 2 + ref[2] ** 2 + ref[3] ** 2) / rho
+    eint = np.maximum(ref[4] - ke, 1e-300)
+    kappa = 1.0 + ke / eint
+    from scipy.ndimage import maximum_filter
+    return maximum_filter(kappa, size=2 * reach + 1, mode="nearest")
+
+
+# One-step parity bounds, FP64 and the FP32 form: relative L1 per field, and per cell
+# max(ELEM, COND x kappa) with kappa the pressure's condition number (cell_condition): about
+# 100 units of rounding of each precision per step, amplified as the pressure amplifies them.
 TOL64, TOL32 = 1e-12, 1e-5
 ELEM64, ELEM32 = 1e-10, 1e-4
+COND64, COND32 = 1e-14, 1e-5
 
 
 def _report(record):
@@ -91,18 +113,28 @@ def _report(record):
             fh.write(json.dumps(record) + "\n")
 
 
-def assert_parity(gpu, ref, gamma, tol_l1, tol_elem, what=""):
-    """Both bounds: relative L1 per field <= tol_l1 and every cell within tol_elem of its own
-    scale.  Prints the worst cell (field, (z, y, x) index within the compared arrays)."""
+def assert_parity(gpu, ref, gamma, tol_l1, tol_elem, what="", cond=None):
+    """Both bounds: relative L1 per field <= tol_l1, and every cell within
+    max(tol_elem, cond x kappa) of its own scale, with kappa its pressure's condition number
+    (cell_condition; cond defaults to COND64 for an FP64 bound, COND32 otherwise).  Prints the
+    worst cell (field, (z, y, x) index within the compared arrays)."""
+    if cond is None:
+        cond = COND64 if tol_elem < 1e-6 else COND32
     l1 = rel_l1(gpu, ref, gamma)
+    kappa = cell_condition(ref, gamma)
+    allow = np.maximum(tol_elem, cond * kappa)
     el, where = elem_err(gpu, ref, gamma)
-    f = int(np.argmax(el))
-    print(f"[parity] {what}: relative L1 {l1.max():.2e}, worst cell {el[f]:.2e} "
-          f"(field {f} at z,y,x = {where[f]})", flush=True)
-    _report(dict(what=str(what), l1=float(l1.max()), elem=float(el[f]), field=f,
-                 at=list(where[f]), tol_l1=tol_l1, tol_elem=tol_elem))
+    ratio, rwhere = elem_err(gpu, ref, gamma, allow=allow)
+    f = int(np.argmax(ratio))
+    at = rwhere[f]
+    print(f"[parity] {what}: relative L1 {l1.max():.2e}, worst cell {el.max():.2e}; "
+          f"largest error / allowance {ratio[f]:.2e} (field {f} at z,y,x = {at}, "
+          f"kappa {kappa[at]:.3g})", flush=True)
+    _report(dict(what=str(what), l1=float(l1.max()), elem=float(el.max()),
+                 ratio=float(ratio[f]), kappa=float(kappa[at]), field=f, at=list(at),
+                 tol_l1=tol_l1, tol_elem=tol_elem, cond=cond))
     assert l1.max() <= tol_l1, (what, "relative L1", l1)
-    assert el.max() <= tol_elem, (what, "worst cell", el, where)
+    assert ratio.max() <= 1.0, (what, "worst cell / allowance", ratio, rwhere, el)
     return l1, el
 
 
