@@ -19,8 +19,10 @@
  * Streams: every grid is bound to the HIP stream given at creation (NULL = the default
  *   stream).  Entry points marked "async" only enqueue work; entry points marked "syncs"
  *   wait for that stream.
- * State layout: structure of arrays.  Field q in {0: rho, 1: rho*u, 2: rho*v, 3: rho*w,
- *   4: E} (total energy per volume, E = p/(gamma-1) + rho V^2/2, Sec. 2) occupies a
+ * State layout (Sec. 3.2, memory structure: one contiguous array per conserved field,
+ *   fields one after another, ghost cells included): structure of arrays.  Field q in
+ *   {0: rho, 1: rho*u, 2: rho*v, 3: rho*w, 4: E} (total energy per volume,
+ *   E = p/(gamma-1) + rho V^2/2, Sec. 2) occupies a
  *   contiguous array of the allocated box (nx+2g)(ny+2g)(nz+2g), x fastest: real cell
  *   (i, j, k), 0 <= i < nx, is element (i+g) + NX*((j+g) + NY*(k+g)), NX = nx+2g,
  *   NY = ny+2g.  Consecutive fields start `field_stride` elements apart
@@ -132,6 +134,9 @@ ctu_status ctu_workspace_bytes(const ctu_config* cfg, size_t* state_bytes, size_
 
 /* Create a grid over caller-owned device buffers d_state (>= state_bytes) and d_work
  * (>= work_bytes, 256-byte aligned), bound to hip_stream (hipStream_t, NULL = default).
+ * This is the set-up half of Sec. 3.1 (simulation overview: the grid, its ghost cells and
+ * boundary types, the header values of domain size and time), with the device memory of
+ * Sec. 3.2 resident for the grid's lifetime instead of copied every step.
  * Validates cfg (CTU_EINVAL) and sizes (CTU_ENOMEM); launches nothing.  A grid of more
  * than 2^31 real cells, or one whose largest pass would exceed 2^32 - 1 work-items in one
  * dispatch, is refused with CTU_EINVAL (memory runs out first on one MI355X: 1024^3 takes
@@ -142,14 +147,16 @@ ctu_status ctu_grid_destroy(ctu_grid* g);
 ctu_status ctu_grid_info_get(ctu_grid* g, ctu_grid_info* info); /* syncs */
 
 /* Upload conserved real-cell values: h_fields[5] host arrays of nx*ny*nz elements of the
- * grid's element type.  Resets t and the step count.  Syncs. */
+ * grid's element type, scattered into the field arrays of the layout above (Sec. 3.2; the
+ * initial conditions of Sec. 3.1 are the caller's).  Resets t and the step count.  Syncs. */
 ctu_status ctu_set_state(ctu_grid* g, const void* const h_fields[5]);
 
 /* Upload primitive real-cell values (rho, u, v, w, p) as host double arrays and convert
  * them to conserved variables on the device with the ideal-gas EOS (Sec. 2).  Syncs. */
 ctu_status ctu_set_primitive(ctu_grid* g, const double* const h_fields[5]);
 
-/* Download conserved real-cell values into h_fields[5] (grid element type).  Syncs;
+/* Download conserved real-cell values into h_fields[5] (grid element type), gathered from
+ * the field arrays of the layout above (Sec. 3.2).  Syncs;
  * returns CTU_ENONPHYS if the device error word is set (the data is still copied). */
 ctu_status ctu_get_state(ctu_grid* g, void* const h_fields[5]);
 
@@ -157,16 +164,20 @@ ctu_status ctu_get_state(ctu_grid* g, void* const h_fields[5]);
  * cfl * min(dx/(|u|+a), dy/(|v|+a), dz/(|w|+a))).  Syncs. */
 ctu_status ctu_compute_dt(ctu_grid* g, double* dt);
 
-/* One CTU step with time step dt > 0: ghost fill, reconstruction + tracing and first
- * Riemann solve per direction, transverse correction and second Riemann solve per
- * direction, conservative update (eq. conserved_update), and the reduction that yields the
- * next CFL time step.  Async. */
+/* One CTU step with time step dt > 0 (Sec. 2.1, steps 1-5): ghost fill, reconstruction +
+ * tracing and first Riemann solve per direction, transverse correction and second Riemann
+ * solve per direction, conservative update (eq. conserved_update), and the reduction that
+ * yields the next CFL time step (Sec. 3.5).  The kernel sequence follows Sec. 3.4 (one
+ * kernel per stage and direction, intermediates in device memory), with reconstruction and
+ * Riemann solve fused per direction and the last second-stage sweep fused with the update.
+ * Async. */
 ctu_status ctu_step(ctu_grid* g, double dt);
 
 /* nsteps CTU steps with the time step computed on the device from the state each step
  * starts with, the last one clipped so that t does not pass t_end (steps after t_end, and
- * steps after an update was flagged non-physical, are no-ops).  No host synchronization.
- * Async. */
+ * steps after an update was flagged non-physical, are no-ops): the main loop of Sec. 3.1
+ * (boundaries, CTU step, time update), with the time step of Sec. 3.5 kept on the device
+ * so that no step waits for the host.  No host synchronization.  Async. */
 ctu_status ctu_advance(ctu_grid* g, int32_t nsteps, double t_end);
 
 /* Sums over the real cells of the five conserved fields, accumulated in double in a fixed
@@ -211,6 +222,23 @@ ctu_status ctu_profile_read(ctu_grid* g, int32_t max_classes, double* ms, int64_
                             int32_t* count);
 const char* ctu_profile_name(int32_t k);
 ctu_status ctu_newton_histogram(ctu_grid* g, uint64_t hist[8]);
+
+/* Plain streaming kernels, not part of the method: what this GPU's HBM delivers to accesses
+ * shaped like the sweeps' (one 8-byte element per lane, 64 consecutive elements per
+ * wavefront, four independent loads per lane): the achievable ceiling beside the published
+ * 8 TB/s peak when the cell-update rate of Sec. 3.7.3 is set against HBM bandwidth.  kind:
+ *   CTU_STREAM_READ      c[b] = sum of block b's elements of a (every element read once;
+ *                        c needs ctu_stream_probe_blocks(n) doubles);
+ *   CTU_STREAM_COPY      c[i] = a[i];
+ *   CTU_STREAM_ADD       c[i] = a[i] + b[i];
+ *   CTU_STREAM_COMBINE5  c[i] = a[i] + a[n+i] + a[2n+i] + a[3n+i] + a[4n+i] (a holds 5n).
+ * a, b, c: device arrays of doubles (b only for ADD); n >= 1 elements.  Async on hip_stream
+ * (NULL = default).  CTU_EINVAL for an unknown kind, a missing array or n = 0;
+ * CTU_EDEVICE if the launch fails. */
+enum { CTU_STREAM_READ = 0, CTU_STREAM_COPY = 1, CTU_STREAM_ADD = 2, CTU_STREAM_COMBINE5 = 3 };
+size_t ctu_stream_probe_blocks(size_t n);
+ctu_status ctu_stream_probe(int32_t kind, const double* a, const double* b, double* c, size_t n,
+                            void* hip_stream);
 
 /* ---- Batches: many independent grids advanced together ----------------------------------
  * Continuous batching of independent grids (each created as above, any sizes, boundary

@@ -11,7 +11,10 @@
  *     van Leer limiter of App. A.1.
  *   - Exact Riemann solver: App. B.1 (Toro's solver, sampled at x/t = 0).
  *   - Roe solver with the HLLE failsafe: Sec. 2.3.2-2.3.3, App. B.2.
- *   - H correction of the second-stage Roe fluxes: App. C.
+ *   - H correction of the second-stage Roe fluxes: App. C.  [Q36] eta is taken from the
+ *     second-stage (transverse-corrected) states; no printed value fixes that choice, so
+ *     parity of it is unpinned (taking eta from the first-stage states instead passes every
+ *     pin; the rest of the H correction is pinned).
  *   - Boundary conditions: Sec. 3.1 (periodic, transmissive and reflecting ghosts).
  * Readings of garbled or silent passages are marked [Qn] and listed in the design notes.
  *

@@ -15,7 +15,8 @@ ARCH = os.environ.get("CTU_OFFLOAD_ARCH", "gfx950")
 # (source, object, extra defines): the sweep kernels are compiled once per storage type,
 # solver class (exact solver per gas class 0, 3, 5; Roe solver 1; Roe with the H correction
 # 2) and reconstruction (PPMC 0, PPMP 1), in parallel
-UNITS = [("ctu_kernels.hip", "ctu_kernels.o", []), ("ctu_runtime.cpp", "ctu_runtime.o", [])] + [
+UNITS = [("ctu_kernels.hip", "ctu_kernels.o", []), ("ctu_runtime.cpp", "ctu_runtime.o", []),
+         ("ctu_stream.hip", "ctu_stream.o", [])] + [
     ("ctu_sweeps.hip", f"ctu_sweeps_{t[0]}{k}{'p' if r else ''}.o",
      [f"-DCTU_SWEEP_T={t}", f"-DCTU_SWEEP_K={k}", f"-DCTU_SWEEP_R={r}"])
     for t in ("double", "float") for k in (0, 1, 2, 3, 5) for r in (0, 1)]

@@ -181,6 +181,12 @@ hipError_t launch_set_end(DevScalars* s, double t_end, long long steps_left, hip
 hipError_t launch_gather_scalars(DevScalars* const* src, int n, DevScalars* out,
                                  hipStream_t stream);
 
+// Plain streaming kernels (ctu_stream.hip): kinds as in ctu_stream_probe of ctu.h.
+enum { STREAM_READ = 0, STREAM_COPY = 1, STREAM_ADD = 2, STREAM_COMBINE5 = 3 };
+size_t stream_probe_blocks(size_t n);
+hipError_t launch_stream_probe(int kind, const double* a, const double* b, double* c, size_t n,
+                               hipStream_t stream);
+
 template <typename T>
 hipError_t launch_totals(const T* u, const GridParams& P, double* part, int nblocks, double* out,
                          hipStream_t stream);

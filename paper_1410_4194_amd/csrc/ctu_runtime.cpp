@@ -389,6 +389,18 @@ ctu_status ctu_profile_read(ctu_grid* g, int32_t max_classes, double* ms, int64_
 
 const char* ctu_profile_name(int32_t k) { return ctu::kernel_class_name(k); }
 
+size_t ctu_stream_probe_blocks(size_t n) { return ctu::stream_probe_blocks(n); }
+
+ctu_status ctu_stream_probe(int32_t kind, const double* a, const double* b, double* c, size_t n,
+                            void* hip_stream) {
+  if (kind < CTU_STREAM_READ || kind > CTU_STREAM_COMBINE5)
+    return fail(CTU_EINVAL, "unknown stream kind");
+  if (!a || !c || (kind == CTU_STREAM_ADD && !b) || n == 0)
+    return fail(CTU_EINVAL, "null array or empty stream");
+  HIP_TRY(ctu::launch_stream_probe(kind, a, b, c, n, (hipStream_t)hip_stream), "stream probe");
+  return CTU_OK;
+}
+
 ctu_status ctu_newton_histogram(ctu_grid* g, uint64_t hist[8]) {
   if (!g || !hist) return fail(CTU_EINVAL, "null argument");
   if (!g->prof || !g->prof->hist) return fail(CTU_EINVAL, "Newton histogram not enabled");

@@ -40,7 +40,8 @@ EXPORTS = [
     "ctu_debug_fluxes", "ctu_debug_keep_fluxes", "ctu_batch_workspace_bytes", "ctu_batch_create", "ctu_batch_submit",
     "ctu_batch_run",
     "ctu_batch_poll", "ctu_batch_destroy", "ctu_last_error", "ctu_profile_enable",
-    "ctu_profile_read", "ctu_profile_name", "ctu_newton_histogram",
+    "ctu_profile_read", "ctu_profile_name", "ctu_newton_histogram", "ctu_stream_probe_blocks",
+    "ctu_stream_probe",
 ]
 
 
@@ -101,6 +102,8 @@ def _load() -> C.CDLL:
                               C.POINTER(C.c_int32)], st),
         "ctu_profile_name": ([C.c_int32], C.c_char_p),
         "ctu_newton_histogram": ([vp, C.POINTER(C.c_uint64)], st),
+        "ctu_stream_probe_blocks": ([sz], sz),
+        "ctu_stream_probe": ([C.c_int32, vp, vp, vp, sz, vp], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -159,6 +162,25 @@ def _torch():
     if not torch.cuda.is_available():
         raise RuntimeError("no GPU visible: the CTU library runs on an MI355X (gfx950) only")
     return torch
+
+
+STREAM_READ, STREAM_COPY, STREAM_ADD, STREAM_COMBINE5 = 0, 1, 2, 3
+
+
+def stream_probe_blocks(n: int) -> int:
+    """Doubles the output of a STREAM_READ probe over n elements needs."""
+    return int(lib.ctu_stream_probe_blocks(C.c_size_t(n)))
+
+
+def stream_probe(kind: int, a, b, c, n: int, stream=None) -> None:
+    """One launch of a plain streaming kernel (ctu_stream_probe) over torch float64 device
+    tensors a, b (or None) and c, n elements; on `stream` (default: torch's current)."""
+    torch = _torch()
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.ctu_stream_probe(int(kind), C.c_void_p(a.data_ptr()),
+                                C.c_void_p(b.data_ptr() if b is not None else 0),
+                                C.c_void_p(c.data_ptr()), C.c_size_t(n),
+                                C.c_void_p(stream.cuda_stream)))
 
 
 class Grid:

@@ -13,7 +13,7 @@ LIB = os.path.join(REPO, "paper_1410_4194_amd", "libctu.so")
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:ctu_status|const char\*)\s+(ctu_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:ctu_status|const char\*|size_t)\s+(ctu_\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -130,3 +130,16 @@ def test_batch_workspace_and_validation(ctu):
     assert st == ctu.EINVAL and h.value is None
     st = ctu.lib.ctu_batch_create(64, C.c_void_p(100), C.c_size_t(small), None, 0, C.byref(h))
     assert st == ctu.EINVAL and h.value is None
+
+
+def test_stream_probe_validates_on_the_host(ctu):
+    """The streaming probe refuses an unknown kind, a missing array and an empty range before
+    anything is launched (no GPU needed); its read variant needs one double per 1024 elements."""
+    lib = ctu.lib
+    assert ctu.stream_probe_blocks(1) == 1 and ctu.stream_probe_blocks(1024) == 1
+    assert ctu.stream_probe_blocks(1025) == 2
+    fake = C.c_void_p(4096)
+    for kind, a, b, c, n in ((7, fake, fake, fake, 16), (-1, fake, fake, fake, 16),
+                             (0, None, None, fake, 16), (1, fake, None, None, 16),
+                             (2, fake, None, fake, 16), (3, fake, None, fake, 0)):
+        assert lib.ctu_stream_probe(kind, a, b, c, n, None) == ctu.EINVAL

@@ -63,6 +63,8 @@ M=[
  ("ppmp chi^m_R sign", "WsR[1] = pR[1] - CR * chimR;", "WsR[1] = pR[1] + CR * chimR;"),
  ("hcorr own face only", "eta_h = fmax(eta_h, eta[t][box_index(&E[t], m[0], m[1], m[2])]);\n                eta_h = fmax(eta_h, eta[t][box_index(&E[t], cc[0], cc[1], cc[2])]);", "(void)m;"),
  ("hcorr eta without half", "eta[d][box_index(&E[d], i, j, k)] = 0.5 * fabs(sR - sL);", "eta[d][box_index(&E[d], i, j, k)] = fabs(sR - sL);"),
+ ("hcorr eta from first-stage states", "ctu_face_states(c, d, cl, dt, &X, Us, Fs, Uh);\n            for (int side = 0; side < 2; ++side) ref_cons_to_prim(Uh[side], g, c->p_floor, w[side]);", "ctu_face_states(c, d, cl, 0.0, &X, Us, Fs, Uh);\n            for (int side = 0; side < 2; ++side) ref_cons_to_prim(Uh[side], g, c->p_floor, w[side]);"),
+ ("clamp before the steep-gradient fix", "    if ((wr - wl) * (wl - (3.0 * c - 2.0 * wr)) < 0.0) wl = 3.0 * c - 2.0 * wr;\n    if ((wr - wl) * ((3.0 * c - 2.0 * wl) - wr) < 0.0) wr = 3.0 * c - 2.0 * wl;\n    /* Step 5: bound the face values by the neighbouring cell averages. */\n    double lo = fmin(c, wm[q]), hi = fmax(c, wm[q]);\n    wl = fmin(hi, fmax(lo, wl));\n    lo = fmin(c, wp[q]);\n    hi = fmax(c, wp[q]);\n    wr = fmin(hi, fmax(lo, wr));", "    double lo = fmin(c, wm[q]), hi = fmax(c, wm[q]);\n    wl = fmin(hi, fmax(lo, wl));\n    lo = fmin(c, wp[q]);\n    hi = fmax(c, wp[q]);\n    wr = fmin(hi, fmax(lo, wr));\n    if ((wr - wl) * (wl - (3.0 * c - 2.0 * wr)) < 0.0) wl = 3.0 * c - 2.0 * wr;\n    if ((wr - wl) * ((3.0 * c - 2.0 * wl) - wr) < 0.0) wr = 3.0 * c - 2.0 * wl;"),
  ("own rho for slopes", "  double rho = w0[0];\n  double a = sound_speed(w0, gamma);", "  double rho = wm[0];\n  double a = sound_speed(wm, gamma);"),
 ]
 
@@ -70,9 +72,29 @@ PINS = ["tests/test_oracle_riemann.py", "tests/test_oracle_roe.py", "tests/test_
         "tests/test_oracle_ppmp.py", "tests/test_oracle_hcorr.py", "tests/test_oracle_step.py"]
 
 
+# Readings that no printed value or closed form fixes: a mutation to the other reading is
+# expected to survive every pin (strict, so that a pin that starts catching it is noticed).
+# App. C takes eta from "the left and right input states" and corrects the second-stage
+# fluxes only; the oracle reads these as the second-stage (transverse-corrected) states, the
+# one reading that needs the extra ghost layer the paper adds.  Where the first- and
+# second-stage states differ, nothing printed gives a value to compare with: parity of the
+# stage choice is unpinned.
+UNPINNED_READINGS = {"hcorr eta from first-stage states"}
+
+
+def _params():
+    out = []
+    for m in M:
+        marks = ()
+        if m[0] in UNPINNED_READINGS:
+            marks = pytest.mark.xfail(strict=True, reason="a reading no printed value fixes")
+        out.append(pytest.param(*m, id=m[0], marks=marks))
+    return out
+
+
 @pytest.mark.slow
 @pytest.mark.skipif(not os.environ.get("CTU_MUTATIONS"), reason="opt-in: set CTU_MUTATIONS=1")
-@pytest.mark.parametrize("name,old,new", M, ids=[m[0] for m in M])
+@pytest.mark.parametrize("name,old,new", _params())
 def test_pins_catch_mutation(name, old, new, tmp_path):
     src = open(SRC).read()
     assert src.count(old) >= 1, name
