@@ -275,6 +275,25 @@ ctu_status ctu_batch_run(ctu_batch* b, int32_t steps); /* async */
 ctu_status ctu_batch_poll(ctu_batch* b, uint64_t ticket, int32_t* state, double* t_now); /* syncs */
 ctu_status ctu_batch_destroy(ctu_batch* b);
 
+/* ---- A step that allocates nothing -------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, serving
+ * loops that must not allocate, harnesses that forbid hipMalloc.  ctu_step_noalloc takes one
+ * CTU step exactly as ctu_step does (same kernels, same results; the state's ghost cells are
+ * filled by the step) of the state in d_state (the layout above, state_bytes of
+ * ctu_workspace_bytes, 256-byte aligned, caller-owned), with the step's workspace taken from a
+ * fixed array in the library's own device memory instead of a caller buffer:
+ * CTU_NOALLOC_SCRATCH_BYTES (128 MiB) per GPU, which every GPU the library runs on holds
+ * until the process ends.  A configuration whose work_bytes (ctu_workspace_bytes) exceeds it
+ * is refused with CTU_EINVAL before anything is launched (PPMC + exact: up to about 76^3 real
+ * cells in FP64, 97^3 in FP32).  cfg is validated as by ctu_workspace_bytes; dt must be finite
+ * and > 0.  Uses the current device (hip_stream, NULL = default, must belong to it); calls no
+ * hipMalloc, hipFree or other allocating routine, on the device or the host.  Async.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's contents (each
+ * call rewrites all it reads): calls whose work overlaps on one GPU race, so order them (one
+ * stream).  The step's device error word is not reported (there is no grid to query it). */
+#define CTU_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+ctu_status ctu_step_noalloc(const ctu_config* cfg, void* d_state, double dt, void* hip_stream);
+
 /* Message for the last failing call on this thread (valid until the next call). */
 const char* ctu_last_error(void);
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,15 +18,19 @@ using ctu::GridParams;
 
 namespace {
 
-thread_local std::string g_err;
+// Message of the last failing call on this thread, in fixed storage (setting it allocates
+// nothing).
+thread_local char g_err[512];
 
-ctu_status fail(ctu_status s, const std::string& msg) {
-  g_err = msg;
+ctu_status fail(ctu_status s, const char* msg) {
+  std::snprintf(g_err, sizeof(g_err), "%s", msg);
   return s;
 }
 
+ctu_status fail(ctu_status s, const std::string& msg) { return fail(s, msg.c_str()); }
+
 ctu_status hip_fail(hipError_t e, const char* where) {
-  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  std::snprintf(g_err, sizeof(g_err), "%s: %s", where, hipGetErrorString(e));
   return CTU_EDEVICE;
 }
 
@@ -187,6 +192,17 @@ bool build_starts(const std::vector<GridParams>& Ps, std::vector<int>& start) {
   return true;
 }
 
+// build_starts for one grid, into a caller array of 2 * P_NUM ints (allocates nothing).
+bool build_starts_one(const GridParams& P, int* start) {
+  for (int p = 0; p < ctu::P_NUM; ++p) {
+    const long long nb = (ctu::pass_blocks(P, p) + 7) / 8 * 8;
+    if (nb * ctu::kBlock > 0xffffffffLL) return false;
+    start[2 * p] = 0;
+    start[2 * p + 1] = (int)nb;
+  }
+  return true;
+}
+
 }  // namespace
 
 struct ctu_grid {
@@ -259,7 +275,7 @@ ctu_status read_scalars(ctu_grid* g, DevScalars* s) {
 
 extern "C" {
 
-const char* ctu_last_error(void) { return g_err.c_str(); }
+const char* ctu_last_error(void) { return g_err; }
 
 ctu_status ctu_config_default(ctu_config* c) {
   if (!c) return fail(CTU_EINVAL, "null config");
@@ -607,6 +623,108 @@ ctu_status ctu_debug_fluxes(ctu_grid* g, int32_t which, int32_t dir, double* con
       for (size_t i = 0; i < n; ++i) h_fields[f][i] = src[i];
     }
   }
+  return CTU_OK;
+}
+
+// ---- the step without device allocation ------------------------------------------------------
+
+}  // extern "C"
+
+// Workspace of ctu_step_noalloc: one fixed array per GPU in the library's own device memory,
+// allocated with the code object and held until the process ends.  Host code uses only the
+// address hipGetSymbolAddress returns for the current device (kept in g_scratch_ptr), never
+// the array's name, which on the host is a stand-in and not a device address.
+static __device__ __align__(256) char scratch[CTU_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per device.
+ctu_status scratch_for_current_device(char** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(CTU_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(CTU_EDEVICE, "hipGetSymbolAddress(scratch) returned no address");
+    g_scratch_ptr[dev] = reinterpret_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return CTU_OK;
+}
+
+// Header of one step in the scratch array, passed by value as a kernel argument.
+struct NoAllocHeader {
+  ctu::GridDesc desc;
+  int start[2 * ctu::P_NUM];
+  double dt;
+};
+
+// Writes the grid descriptor, the block table and fresh scalars (time step dt, no CFL
+// bound, cleared error word and counters) into the scratch header.
+__global__ void k_noalloc_header(NoAllocHeader h, char* base) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  DevScalars z;
+  std::memset(&z, 0, sizeof(z));
+  z.dt = h.dt;
+  z.dt_next_bits = 0x7ff0000000000000ull;
+  *reinterpret_cast<DevScalars*>(base + kScalarsOffset) = z;
+  *reinterpret_cast<ctu::GridDesc*>(base + kDescOffset) = h.desc;
+  int* st = reinterpret_cast<int*>(base + kStartOffset);
+  for (int i = 0; i < 2 * ctu::P_NUM; ++i) st[i] = h.start[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+ctu_status ctu_step_noalloc(const ctu_config* cfg, void* d_state, double dt, void* hip_stream) {
+  ctu_status s = validate(cfg);
+  if (s != CTU_OK) return s;
+  if (!d_state) return fail(CTU_EINVAL, "null device buffer");
+  if (reinterpret_cast<uintptr_t>(d_state) % 256 != 0)
+    return fail(CTU_EINVAL, "the state buffer must be 256-byte aligned");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CTU_EINVAL, "dt must be finite and > 0");
+  size_t need_state = 0, need_work = 0;
+  ctu_workspace_bytes(cfg, &need_state, &need_work);
+  if (need_work > CTU_NOALLOC_SCRATCH_BYTES) {
+    char msg[160];
+    std::snprintf(msg, sizeof(msg),
+                  "grid needs %zu bytes of workspace; the fixed scratch holds %zu",
+                  need_work, (size_t)CTU_NOALLOC_SCRATCH_BYTES);
+    return fail(CTU_EINVAL, msg);
+  }
+  char* base = nullptr;
+  s = scratch_for_current_device(&base);
+  if (s != CTU_OK) return s;
+  NoAllocHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.desc.P = make_params(*cfg);
+  const size_t fb = (size_t)h.desc.P.stride * elem_bytes(cfg->prec);
+  char* fields = base + kHeaderBytes;
+  h.desc.u = d_state;
+  h.desc.flux = fields;
+  h.desc.s = reinterpret_cast<DevScalars*>(base + kScalarsOffset);
+  h.desc.part = reinterpret_cast<double*>(fields + (size_t)fields_per_grid(*cfg) * fb);
+  h.desc.coef = cfg->recon == CTU_RECON_PPMP ? fields + 30 * fb : nullptr;
+  h.desc.eta = cfg->h_correction ? fields + (30 + coef_fields(*cfg)) * fb : nullptr;
+  for (int i = 0; i < 6; ++i) h.desc.bc[i] = cfg->bc[i];
+  h.desc.flags = 0;
+  if (!build_starts_one(h.desc.P, h.start))
+    return fail(CTU_EINVAL, "grid too large for one launch per pass");
+  h.dt = dt;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(k_noalloc_header, dim3(1), dim3(64), 0, stream, h, base);
+  HIP_TRY(hipGetLastError(), "scratch header");
+  const ctu::PlanView v{reinterpret_cast<ctu::GridDesc*>(base + kDescOffset),
+                        reinterpret_cast<int*>(base + kStartOffset), 1, h.start,
+                        cfg->prec == CTU_FP32 ? 1 : 0, ctu::gas_class(h.desc.P), h.desc.P.recon};
+  HIP_TRY(ctu::launch_step(v, false, stream, nullptr), "step launch");
   return CTU_OK;
 }
 

@@ -41,7 +41,7 @@ EXPORTS = [
     "ctu_batch_run",
     "ctu_batch_poll", "ctu_batch_destroy", "ctu_last_error", "ctu_profile_enable",
     "ctu_profile_read", "ctu_profile_name", "ctu_newton_histogram", "ctu_stream_probe_blocks",
-    "ctu_stream_probe",
+    "ctu_stream_probe", "ctu_step_noalloc",
 ]
 
 
@@ -104,6 +104,7 @@ def _load() -> C.CDLL:
         "ctu_newton_histogram": ([vp, C.POINTER(C.c_uint64)], st),
         "ctu_stream_probe_blocks": ([sz], sz),
         "ctu_stream_probe": ([C.c_int32, vp, vp, vp, sz, vp], st),
+        "ctu_step_noalloc": ([C.POINTER(Config), vp, C.c_double, vp], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -180,6 +181,19 @@ def stream_probe(kind: int, a, b, c, n: int, stream=None) -> None:
     _check(lib.ctu_stream_probe(int(kind), C.c_void_p(a.data_ptr()),
                                 C.c_void_p(b.data_ptr() if b is not None else 0),
                                 C.c_void_p(c.data_ptr()), C.c_size_t(n),
+                                C.c_void_p(stream.cuda_stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def step_noalloc(cfg: Config, d_state, dt: float, stream=None) -> None:
+    """One CTU step of the state held in the torch device tensor d_state (the library's layout,
+    workspace_bytes(cfg)[0] bytes) with the library's fixed scratch as workspace
+    (ctu_step_noalloc); on `stream` (default: torch's current)."""
+    torch = _torch()
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.ctu_step_noalloc(C.byref(cfg), C.c_void_p(d_state.data_ptr()), float(dt),
                                 C.c_void_p(stream.cuda_stream)))
 
 
