@@ -110,6 +110,14 @@ typedef struct {
                               face and of the transverse faces around its two cells, taken
                               from the second-stage states; needs CTU_RIEMANN_ROE and one
                               ghost layer more */
+  int32_t x_rows;          /* tile shape: x-rows of real cells per wavefront of the x sweep
+                              fused with the update, 1..8 (capped at ny); 0 = the library's
+                              choice (the fewest idle lanes, one row unless more cut idle lanes
+                              by 20%).  Changes the launch shape only: results are bitwise
+                              the same */
+  int32_t x_chunks;        /* tile shape: consecutive 58-cell chunks per wavefront of the
+                              first-stage x sweep, 1..16; 0 = the library default (4).
+                              Changes the launch shape only: results are bitwise the same */
 } ctu_config;
 
 typedef struct ctu_grid ctu_grid;

@@ -40,6 +40,7 @@ struct GridParams {
   double inv_gm1;       // 1 / (gamma - 1)
   int seg[3];           // faces per thread segment of the marching sweeps along y and z
   int xrows;            // x-rows of real cells per wavefront in the fused x update
+  int xchunks;          // chunks of the flattened line per wavefront of the first-stage x sweep
   int riemann;          // 0 exact, 1 Roe with the HLLE failsafe
   int recon;            // 0 PPMC, 1 PPMP
   int ext;              // 1 with the H correction: the first stage covers one more cell

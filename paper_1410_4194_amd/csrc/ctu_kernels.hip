@@ -471,7 +471,7 @@ long long pass_blocks(const GridParams& P, int pass) {
       const long long e = 2 + 2 * P.ext;
       return P.recon == 1 ? cdiv((n0 + e) * (n1 + e), kBlock) * cdiv(n2 + e, kCoefSeg) : 0;
     }
-    case P_S1_X: return cdiv(cdiv((n1 + 2) * N0, XW) * (n2 + 2), kXChunks * (kBlock / 64));
+    case P_S1_X: return cdiv(cdiv((n1 + 2) * N0, XW) * (n2 + 2), P.xchunks * (kBlock / 64));
     case P_S1_Y: return cdiv((n0 + 2) * (n2 + 2), kBlock) * cdiv(n1 + 2 * P.ext, P.seg[1]);
     case P_S1_Z: return cdiv((n0 + 2) * (n1 + 2), kBlock) * cdiv(n2 + 2 * P.ext, P.seg[2]);
     case P_ETA_X: return P.ext ? cdiv(cdiv((n1 + 2) * N0, XW) * (n2 + 2), kBlock / 64) : 0;

@@ -21,8 +21,9 @@ enum Pass {
 };
 
 constexpr int kBlock = 256;  // threads per block of every pass
-// Consecutive chunks of XW positions per wavefront of the first-stage x sweep: the
-// wavefront's set-up (grid lookup, parameters, task arithmetic) is paid once for all of them.
+// Consecutive chunks of XW positions per wavefront of the first-stage x sweep (default; a
+// grid may set its own): the wavefront's set-up (grid lookup, parameters, task arithmetic)
+// is paid once for all of them.
 constexpr int kXChunks = 4;
 constexpr int kSegDefault = 32;  // target cells per thread segment in the marching sweeps
 constexpr int XW = 58;       // x-cells per wavefront in the first-stage x sweep

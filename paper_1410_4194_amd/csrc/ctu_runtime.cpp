@@ -106,6 +106,8 @@ ctu_status validate(const ctu_config* c) {
   for (int a = 0; a < 2; ++a)
     if (c->march_seg[a] < 0 || c->march_seg[a] > 4096)
       return fail(CTU_EINVAL, "march_seg must lie in [0, 4096]");
+  if (c->x_rows < 0 || c->x_rows > 8) return fail(CTU_EINVAL, "x_rows must lie in [0, 8]");
+  if (c->x_chunks < 0 || c->x_chunks > 16) return fail(CTU_EINVAL, "x_chunks must lie in [0, 16]");
   for (int a = 0; a < 3; ++a) {
     int lo = c->bc[2 * a], hi = c->bc[2 * a + 1];
     for (int b : {lo, hi})
@@ -168,7 +170,8 @@ GridParams make_params(const ctu_config& c) {
     nseg = nseg < 1 ? 1 : (nseg > cells ? cells : nseg);
     P.seg[a] = (cells + nseg - 1) / nseg;
   }
-  P.xrows = ctu::choose_xrows(c.nx, c.ny);
+  P.xrows = c.x_rows > 0 ? (c.x_rows < c.ny ? c.x_rows : c.ny) : ctu::choose_xrows(c.nx, c.ny);
+  P.xchunks = c.x_chunks > 0 ? c.x_chunks : ctu::kXChunks;
   return P;
 }
 

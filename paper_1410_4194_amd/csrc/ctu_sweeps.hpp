@@ -420,7 +420,7 @@ __global__ __launch_bounds__(256) void k_eta_x(LaunchTab tab) {
 // 0 <= c <= n_x, and lanes 3..60 store the difference dF(c) = F(c-1/2) - F(c+1/2) of their
 // real cell (F(c+1/2) from the next lane).  Every stencil of such a face lies in its own
 // row, so short rows share a chunk instead of leaving most of its lanes idle.  A wavefront
-// takes kXChunks consecutive chunks, paying its set-up once for them.
+// takes P.xchunks consecutive chunks, paying its set-up once for them.
 template <typename T, int STAGE, bool HIST, int K, int R>
 __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   static_assert(STAGE == 1, "the second-stage x sweep is fused with the update");
@@ -432,7 +432,8 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
   GLOBAL T* __restrict__ out = (GLOBAL T*)r.G->flux;
   const int lane = threadIdx.x & 63;
-  const long long task0 = (r.lb * (kBlock / 64) + wave_in_block()) * kXChunks;
+  const int nchunks = P.xchunks;
+  const long long task0 = (r.lb * (kBlock / 64) + wave_in_block()) * nchunks;
   const long long plen = (long long)(P.n[1] + 2) * P.N[0];  // positions of one plane
   const long long nw = (plen + XW - 1) / XW;                   // chunks per plane
   const long long ntask = nw * (P.n[2] + 2);
@@ -442,7 +443,7 @@ __global__ __launch_bounds__(256) void k_sweep_x(LaunchTab tab) {
   const int lp1 = lane < 63 ? lane + 1 : 63;
   const int e = P.ext;  // one more cell on each side with the H correction
   NewtonHist hist{};
-  for (int qc = 0; qc < kXChunks; ++qc) {
+  for (int qc = 0; qc < nchunks; ++qc) {
     const long long task = task0 + qc;
     if (task >= ntask) break;  // wave-uniform
     const int k = (int)(task / nw) - 1;

@@ -52,7 +52,7 @@ class Config(C.Structure):
                 ("cfl", C.c_double), ("newton_tol", C.c_double),
                 ("newton_max_iter", C.c_int32), ("p_floor", C.c_double),
                 ("march_seg", C.c_int32 * 2), ("riemann", C.c_int32), ("recon", C.c_int32),
-                ("h_correction", C.c_int32)]
+                ("h_correction", C.c_int32), ("x_rows", C.c_int32), ("x_chunks", C.c_int32)]
 
 
 class GridInfo(C.Structure):
@@ -124,12 +124,14 @@ def _check(status: int, allow=()) -> int:
 
 def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64, cfl=0.3,
                 newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20, march_seg=None,
-                riemann=0, recon=0, h_correction=0) -> Config:
+                riemann=0, recon=0, h_correction=0, x_rows=None, x_chunks=None) -> Config:
     """Grid configuration.  riemann: RIEMANN_EXACT or RIEMANN_ROE (with the HLLE failsafe);
     recon: RECON_PPMC or RECON_PPMP; h_correction: 1 for the H correction of the
-    second-stage Roe fluxes.  march_seg: target cells per thread of the y and z sweeps; None
-    takes the autotuned table (tiles.json beside this module) when it exists, else the
-    library default."""
+    second-stage Roe fluxes.  Tile shapes (launch shapes only): march_seg, target cells per
+    thread of the y and z sweeps; x_rows, rows per wavefront of the x sweep fused with the
+    update; x_chunks, chunks per wavefront of the first-stage x sweep.  None takes the
+    autotuned table (tiles.json beside this module) when it has the entry, else the library
+    default."""
     c = Config()
     lib.ctu_config_default(C.byref(c))
     c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
@@ -142,10 +144,15 @@ def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64,
     c.newton_tol = float(newton_tol)
     c.newton_max_iter = int(newton_max_iter)
     c.p_floor = float(p_floor)
-    if march_seg is None:
-        from .autotune import lookup
-        march_seg = lookup(int(prec), int(ny), int(nz))
+    if march_seg is None or x_rows is None or x_chunks is None:
+        from .autotune import lookup, lookup_x
+        if march_seg is None:
+            march_seg = lookup(int(prec), int(ny), int(nz))
+        tx = lookup_x(int(prec), int(nx), int(ny))
+        x_rows = tx[0] if x_rows is None else x_rows
+        x_chunks = tx[1] if x_chunks is None else x_chunks
     c.march_seg[0], c.march_seg[1] = int(march_seg[0]), int(march_seg[1])
+    c.x_rows, c.x_chunks = int(x_rows), int(x_chunks)
     c.riemann = int(riemann)
     c.recon = int(recon)
     c.h_correction = int(h_correction)

@@ -314,6 +314,32 @@ def test_march_segments_do_not_change_results(ctu, prec):
             assert_parity(U, ref, wl.gamma, *parity_bounds(prec), what=("segments", seg, prec))
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_x_tile_shapes_are_bitwise_invariant(ctu, prec):
+    """The x sweeps' tile shapes (x-rows per wavefront of the fused update, 1..8, and chunks
+    per wavefront of the first-stage x sweep, 1..16) change only which wavefront computes a
+    cell, never its arithmetic: the state after three steps is bitwise the same, on short
+    rows (several per wavefront) and ragged sizes."""
+    _announce("x tile shapes", prec)
+    for wl in (WL.random_state(12, 37, 29, seed=78, bc=(0, 0, 1, 1, 0, 0)),
+               WL.random_state(70, 6, 5, seed=79, bc=(1, 1, 0, 0, 1, 1))):
+        ref = None
+        for rows, chunks in ((0, 0), (1, 1), (2, 3), (3, 16), (8, 2), (5, 7)):
+            cfg = ctu.make_config(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.gamma, wl.bc,
+                                  prec, wl.cfl, march_seg=(0, 0), x_rows=rows, x_chunks=chunks)
+            g = ctu.Grid(cfg)
+            g.set_primitive(wl.W)
+            g.advance(3)
+            U = g.get_state()
+            status, flags, counters = g.check()
+            g.close()
+            assert status == ctu.OK, (flags, counters)
+            if ref is None:
+                ref = U
+            else:
+                assert np.array_equal(U, ref), (wl.name, rows, chunks)
+
+
 def test_newton_histogram_counts_every_solve(ctu):
     """The instrumented sweeps count one Newton-iteration bin per exact Riemann solve: the
     bins add up to the number of solves a step makes (stage 1 on the extended transverse
