@@ -176,7 +176,7 @@ def run_batched(ctu, torch, WL, prec, steps, warmup, count=64, compare_solo_step
     `steps` timed steps of every grid; optionally the same grids advanced one at a time."""
     wls = WL.kh_batch(count=count, steps=steps)
     cells = sum(w.cells for w in wls)
-    grids = [ctu.Grid.from_workload(w, prec=prec) for w in wls]
+    grids = [ctu.Grid.from_workload(w, prec=prec, batch=True) for w in wls]
     b = ctu.Batch(count, graph=True)
     tickets = [b.submit(g, warmup + steps) for g in grids]
     b.run(warmup)

@@ -132,6 +132,62 @@ def lookup(prec: int, ny: int, nz: int, path: str = TABLE_PATH):
     return (int(rows[nearest(ny)]["y"]), int(rows[nearest(nz)]["z"]))
 
 
+def tune_batch(precs=None, steps=30, log=print, segs=(4, 8, 12, 16, 24),
+               chunks=(1, 2, 4, 8), rows=(0, 1, 2)):
+    """Tile shapes for grids advanced together in a batch, timed on the 64-grid
+    Kelvin-Helmholtz batch (edges from {32, ..., 128}) with one shape for every grid: the
+    segment length (y and z), then the x chunks, then the x rows (0: the library's choice per
+    grid), each with the best of the earlier ones.  A batch fills the GPU where one small grid
+    alone does not, so it prefers less parallelism per grid than the single-grid table."""
+    from . import ctu, workloads as WL
+    import torch
+    precs = precs if precs is not None else (ctu.FP64, ctu.FP32)
+    wls = WL.kh_batch(count=64, steps=steps)
+    cells = sum(w.cells for w in wls)
+    out = {}
+
+    def rate(prec, seg, ch, rw):
+        grids = [ctu.Grid.from_workload(w, prec=prec, march_seg=(seg, seg), x_rows=rw,
+                                        x_chunks=ch) for w in wls]
+        b = ctu.Batch(len(grids), graph=True)
+        tickets = [b.submit(g, 2 + steps) for g in grids]
+        b.run(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(steps)
+        for t in tickets:
+            b.poll(t)
+        torch.cuda.synchronize()
+        v = cells * steps / (time.perf_counter() - t0)
+        b.close()
+        for g in grids:
+            g.close()
+        return v
+    for prec in precs:
+        name = "fp64" if prec == ctu.FP64 else "fp32"
+        vs = {s: rate(prec, s, 4, 0) for s in segs}
+        seg = max(vs, key=vs.get)
+        vc = {c: rate(prec, seg, c, 0) for c in chunks}
+        ch = max(vc, key=vc.get)
+        vr = {r: rate(prec, seg, ch, r) for r in rows}
+        rw = max(vr, key=vr.get)
+        out[name] = {"march_seg": seg, "x_chunks": ch, "x_rows": rw,
+                     "rate_by_seg": {str(k): round(v) for k, v in vs.items()},
+                     "rate_by_x_chunks": {str(k): round(v) for k, v in vc.items()},
+                     "rate_by_x_rows": {str(k): round(v) for k, v in vr.items()}}
+        log(f"[autotune] batch {name}: seg {seg} ({vs}), x chunks {ch} ({vc}), x rows {rw} ({vr})")
+    return out
+
+
+def lookup_batch(prec: int, path: str = TABLE_PATH):
+    """Tuned (segment, x rows, x chunks) for grids advanced in a batch, or None."""
+    lookup(prec, 1, 1, path)  # loads the table
+    e = ((_cache.get(path) or {}).get("batch") or {}).get("fp64" if prec == 0 else "fp32")
+    if not e:
+        return None
+    return (int(e["march_seg"]), int(e["x_rows"]), int(e["x_chunks"]))
+
+
 def lookup_x(prec: int, nx: int, ny: int, path: str = TABLE_PATH):
     """Tuned (x rows, x chunks) for a grid, from the nearest tuned edge (by nx); (0, 0) (the
     library's choice) when the table has no such entry."""
@@ -151,10 +207,21 @@ def main():
     ap.add_argument("--sizes", type=int, nargs="*", default=list(DEFAULT_SIZES))
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--workload", choices=WORKLOADS, default="shock_cloud")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="tune only the batch shapes, into the existing table")
     args = ap.parse_args()
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.batch_only:
+        with open(TABLE_PATH) as fh:
+            table = json.load(fh)
+        table["batch"] = tune_batch(log=log)
+        with open(args.out, "w") as fh:
+            json.dump(table, fh, indent=1)
+        print(f"[autotune] wrote {args.out}", file=sys.stderr)
+        return
     t0 = time.perf_counter()
-    table = tune(args.sizes, steps=args.steps, workload=args.workload,
-                 log=lambda *a: print(*a, file=sys.stderr, flush=True))
+    table = tune(args.sizes, steps=args.steps, workload=args.workload, log=log)
+    table["batch"] = tune_batch(log=log)
     table["seconds"] = round(time.perf_counter() - t0, 1)
     with open(args.out, "w") as fh:
         json.dump(table, fh, indent=1)

@@ -124,14 +124,16 @@ def _check(status: int, allow=()) -> int:
 
 def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64, cfl=0.3,
                 newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20, march_seg=None,
-                riemann=0, recon=0, h_correction=0, x_rows=None, x_chunks=None) -> Config:
+                riemann=0, recon=0, h_correction=0, x_rows=None, x_chunks=None,
+                batch=False) -> Config:
     """Grid configuration.  riemann: RIEMANN_EXACT or RIEMANN_ROE (with the HLLE failsafe);
     recon: RECON_PPMC or RECON_PPMP; h_correction: 1 for the H correction of the
     second-stage Roe fluxes.  Tile shapes (launch shapes only): march_seg, target cells per
     thread of the y and z sweeps; x_rows, rows per wavefront of the x sweep fused with the
     update; x_chunks, chunks per wavefront of the first-stage x sweep.  None takes the
     autotuned table (tiles.json beside this module) when it has the entry, else the library
-    default."""
+    default; batch=True takes the shapes tuned for grids advanced in a batch (where the GPU
+    is full, unlike a small grid alone), when the table has them."""
     c = Config()
     lib.ctu_config_default(C.byref(c))
     c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
@@ -145,7 +147,12 @@ def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64,
     c.newton_max_iter = int(newton_max_iter)
     c.p_floor = float(p_floor)
     if march_seg is None or x_rows is None or x_chunks is None:
-        from .autotune import lookup, lookup_x
+        from .autotune import lookup, lookup_batch, lookup_x
+        tb = lookup_batch(int(prec)) if batch else None
+        if tb is not None:
+            march_seg = (tb[0], tb[0]) if march_seg is None else march_seg
+            x_rows = tb[1] if x_rows is None else x_rows
+            x_chunks = tb[2] if x_chunks is None else x_chunks
         if march_seg is None:
             march_seg = lookup(int(prec), int(ny), int(nz))
         tx = lookup_x(int(prec), int(nx), int(ny))

@@ -166,7 +166,8 @@ def serve(requests: List[Request], hbm_budget: int, max_slots: int = 64,
                     break
                 req = pending[i]
                 need = need_of[req.rid]
-                g = ctu.Grid.from_workload(req.workload, prec=req.prec, stream=io_stream)
+                g = ctu.Grid.from_workload(req.workload, prec=req.prec, stream=io_stream,
+                                           batch=True)
                 ticket = batch.submit(g, req.max_steps, req.t_end)
                 if ticket is None:
                     g.close()

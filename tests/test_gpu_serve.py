@@ -38,7 +38,8 @@ def test_served_answers_equal_solo(prec, policy):
     for req, res in zip(requests, stats.results):
         assert res.rid == req.rid and res.steps > 0
         assert abs(res.t - req.t_end) <= 1e-14 * req.t_end
-        g = ctu.Grid.from_workload(req.workload, prec=prec)
+        # the same request, with the same configuration (the batch tile shapes), alone
+        g = ctu.Grid.from_workload(req.workload, prec=prec, batch=True)
         g.advance(res.steps + 3, req.t_end)
         info = g.info()
         assert info.steps == res.steps and info.t == res.t
