@@ -118,6 +118,13 @@ typedef struct {
   int32_t x_chunks;        /* tile shape: consecutive 58-cell chunks per wavefront of the
                               first-stage x sweep, 1..16; 0 = the library default (4).
                               Changes the launch shape only: results are bitwise the same */
+  int32_t serial_passes;   /* 0: a grid stepped by ctu_step / ctu_advance runs its
+                              second-stage z sweep on a stream of its own (created with the
+                              grid, default priority), beside the first-stage z and
+                              second-stage y sweeps, ordered with events; the caller's stream
+                              still sees each step as one ordered unit.  1: every pass in
+                              order on the grid's stream.  Results are bitwise the same.
+                              Batches and ctu_step_noalloc always run in order. */
 } ctu_config;
 
 typedef struct ctu_grid ctu_grid;

@@ -122,6 +122,10 @@ struct PlanView {
   int gclass;          // solver class: exact with gas class 3 (gamma 5/3), 5 (gamma 7/5) or
                        // 0 (other), kRoe, or kRoeH
   int recon;           // 0 PPMC, 1 PPMP
+  // Optional second stream (default priority) and three events for the overlapped schedule
+  // of the sweeps (enqueue_sweeps); null side: every pass in order on the launch stream.
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr;
 };
 
 // Solver class of a grid: kRoe for the Roe solver; for the exact solver its gas class, K

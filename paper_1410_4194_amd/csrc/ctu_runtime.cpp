@@ -108,6 +108,8 @@ ctu_status validate(const ctu_config* c) {
       return fail(CTU_EINVAL, "march_seg must lie in [0, 4096]");
   if (c->x_rows < 0 || c->x_rows > 8) return fail(CTU_EINVAL, "x_rows must lie in [0, 8]");
   if (c->x_chunks < 0 || c->x_chunks > 16) return fail(CTU_EINVAL, "x_chunks must lie in [0, 16]");
+  if (c->serial_passes != 0 && c->serial_passes != 1)
+    return fail(CTU_EINVAL, "serial_passes must be 0 or 1");
   for (int a = 0; a < 3; ++a) {
     int lo = c->bc[2 * a], hi = c->bc[2 * a + 1];
     for (int b : {lo, hi})
@@ -220,6 +222,17 @@ struct ctu_grid {
   ctu::Profiler* prof = nullptr;  // per-kernel timing when enabled
   ctu::GridDesc desc;             // host copy of the descriptor at d_work + kDescOffset
   std::vector<int> h_start;       // host copy of the one-grid block table
+  // the side stream and events of the overlapped sweep schedule (null when serial)
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr;
+  ~ctu_grid() {
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
+    for (hipEvent_t ev : {fork, xdone, join})
+      if (ev) (void)hipEventDestroy(ev);
+  }
   DevScalars* scalars() const { return reinterpret_cast<DevScalars*>(d_work + kScalarsOffset); }
   double* partial() const { return reinterpret_cast<double*>(d_work + kPartialOffset); }
   double* totals_out() const { return reinterpret_cast<double*>(d_work + kTotalsOutOffset); }
@@ -232,7 +245,7 @@ struct ctu_grid {
   int* d_start() const { return reinterpret_cast<int*>(d_work + kStartOffset); }
   ctu::PlanView plan() const {
     return ctu::PlanView{d_desc(), d_start(), 1, h_start.data(), cfg.prec == CTU_FP32 ? 1 : 0,
-                         ctu::gas_class(P), P.recon};
+                         ctu::gas_class(P), P.recon, side, fork, xdone, join};
   }
 };
 
@@ -340,7 +353,18 @@ ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, s
     delete g;
     return fail(CTU_EINVAL, "grid too large for one launch per pass");
   }
-  hipError_t e = hipMemcpyAsync(g->d_desc(), &g->desc, sizeof(g->desc), hipMemcpyHostToDevice,
+  hipError_t e = hipSuccess;
+  if (!cfg->serial_passes && ctu::gas_class(g->P) != ctu::kRoeH) {
+    // default priority, like every stream of the library
+    e = hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking);
+    for (hipEvent_t* ev : {&g->fork, &g->xdone, &g->join})
+      if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      delete g;
+      return hip_fail(e, "side stream");
+    }
+  }
+  e = hipMemcpyAsync(g->d_desc(), &g->desc, sizeof(g->desc), hipMemcpyHostToDevice,
                                 g->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(g->d_start(), g->h_start.data(), sizeof(int) * g->h_start.size(),

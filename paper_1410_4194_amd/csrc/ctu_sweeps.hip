@@ -17,13 +17,10 @@ hipError_t launch_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, CTU_SWEEP_R>(const PlanView& 
                                                                 Profiler* prof) {
   // the Newton histogram exists for the exact solver only
   if constexpr (CTU_SWEEP_K != kRoe && CTU_SWEEP_K != kRoeH) {
-    if (prof && prof->hist) {
-      enqueue_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, true, CTU_SWEEP_R>(v, stage, stream, prof);
-      return hipGetLastError();
-    }
+    if (prof && prof->hist)
+      return enqueue_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, true, CTU_SWEEP_R>(v, stage, stream, prof);
   }
-  enqueue_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, false, CTU_SWEEP_R>(v, stage, stream, prof);
-  return hipGetLastError();
+  return enqueue_sweeps<CTU_SWEEP_T, CTU_SWEEP_K, false, CTU_SWEEP_R>(v, stage, stream, prof);
 }
 
 }  // namespace ctu

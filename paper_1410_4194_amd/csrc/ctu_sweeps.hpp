@@ -664,21 +664,52 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
   block_min_store(bound, (GLOBAL double*)r.G->part, r.lb);
 }
 
-// The six sweeps of one stage for every grid of a plan (one launch per direction).
+// The three sweeps of one stage for every grid of a plan (one launch per direction).
+// With a side stream in the plan the sweeps overlap where the data allow it.  The first-stage
+// y sweep needs only u^n, so it runs on the side stream beside the first-stage x sweep; the
+// second-stage z sweep needs only the first-stage x and y differences, so it follows there
+// as soon as both are done, beside the first-stage z sweep (bound by FP64 issue) and the
+// second-stage y sweep (bound by memory) on the launch stream; the update waits for it.
+// Kernels of one pass still see everything they read complete, so results are bitwise those
+// of the serial order.  Not with the H correction (the z sweep reads eta along y, which the
+// y sweep writes), and not while kernels are timed one by one.
 template <typename T, int K, bool HIST, int R>
-void enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
+hipError_t enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
   const int stride = v.ngrids + 1;
   auto tab = [&](int pass) { return LaunchTab{v.d_grids, v.d_start + pass * stride, v.ngrids}; };
   auto nblocks = [&](int pass) { return dim3((unsigned)v.h_start[pass * stride + v.ngrids]); };
   const dim3 B(kBlock);
+  const bool overlap = K != kRoeH && v.side && v.fork && v.xdone && v.join && !(prof && prof->timing);
+  hipError_t e = hipSuccess;
   if (stage == 1) {
     // a2-a5: F*, G*, H* on the extended transverse range
-    CTU_TIMED(K_SWEEP1_X, hipLaunchKernelGGL((k_sweep_x<T, 1, HIST, K, R>), nblocks(P_S1_X), B, 0,
-                                             stream, tab(P_S1_X)));
-    CTU_TIMED(K_SWEEP1_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 1, HIST, K, R>), nblocks(P_S1_Y),
-                                             B, 0, stream, tab(P_S1_Y)));
-    CTU_TIMED(K_SWEEP1_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 1, HIST, K, R>), nblocks(P_S1_Z),
-                                             B, 0, stream, tab(P_S1_Z)));
+    if (overlap) {
+      // side: the first-stage y sweep beside the x sweep, then (once the x differences are
+      // done) the second-stage z sweep
+      e = hipEventRecord(v.fork, stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(v.side, v.fork, 0);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_sweep_march<T, 1, 1, HIST, K, R>), nblocks(P_S1_Y), B, 0, v.side,
+                         tab(P_S1_Y));
+      hipLaunchKernelGGL((k_sweep_x<T, 1, HIST, K, R>), nblocks(P_S1_X), B, 0, stream,
+                         tab(P_S1_X));
+      e = hipEventRecord(v.xdone, stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(v.side, v.xdone, 0);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_sweep_march<T, 2, 2, HIST, K, R>), nblocks(P_S2_Z), B, 0, v.side,
+                         tab(P_S2_Z));
+      e = hipEventRecord(v.join, v.side);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_sweep_march<T, 2, 1, HIST, K, R>), nblocks(P_S1_Z), B, 0, stream,
+                         tab(P_S1_Z));
+    } else {
+      CTU_TIMED(K_SWEEP1_X, hipLaunchKernelGGL((k_sweep_x<T, 1, HIST, K, R>), nblocks(P_S1_X), B,
+                                               0, stream, tab(P_S1_X)));
+      CTU_TIMED(K_SWEEP1_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 1, HIST, K, R>),
+                                               nblocks(P_S1_Y), B, 0, stream, tab(P_S1_Y)));
+      CTU_TIMED(K_SWEEP1_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 1, HIST, K, R>),
+                                               nblocks(P_S1_Z), B, 0, stream, tab(P_S1_Z)));
+    }
   } else {
     if constexpr (K == kRoeH) {
       // eta of every face the H stencils of the second stage read
@@ -692,12 +723,18 @@ void enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* 
     // update (a8) and the CFL bound of the new state (a9)
     CTU_TIMED(K_SWEEP2_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 2, HIST, K, R>), nblocks(P_S2_Y),
                                              B, 0, stream, tab(P_S2_Y)));
-    CTU_TIMED(K_SWEEP2_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 2, HIST, K, R>), nblocks(P_S2_Z),
-                                             B, 0, stream, tab(P_S2_Z)));
+    if (overlap) {
+      e = hipStreamWaitEvent(stream, v.join, 0);
+      if (e != hipSuccess) return e;
+    } else {
+      CTU_TIMED(K_SWEEP2_Z, hipLaunchKernelGGL((k_sweep_march<T, 2, 2, HIST, K, R>),
+                                               nblocks(P_S2_Z), B, 0, stream, tab(P_S2_Z)));
+    }
     CTU_TIMED(K_SWEEP2_X_UPDATE,
               hipLaunchKernelGGL((k_sweep_x_update<T, HIST, K, R>), nblocks(P_S2_X), B, 0, stream,
                                  tab(P_S2_X)));
   }
+  return hipGetLastError();
 }
 
 }  // namespace ctu

@@ -52,7 +52,8 @@ class Config(C.Structure):
                 ("cfl", C.c_double), ("newton_tol", C.c_double),
                 ("newton_max_iter", C.c_int32), ("p_floor", C.c_double),
                 ("march_seg", C.c_int32 * 2), ("riemann", C.c_int32), ("recon", C.c_int32),
-                ("h_correction", C.c_int32), ("x_rows", C.c_int32), ("x_chunks", C.c_int32)]
+                ("h_correction", C.c_int32), ("x_rows", C.c_int32), ("x_chunks", C.c_int32),
+                ("serial_passes", C.c_int32)]
 
 
 class GridInfo(C.Structure):
@@ -125,7 +126,7 @@ def _check(status: int, allow=()) -> int:
 def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64, cfl=0.3,
                 newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20, march_seg=None,
                 riemann=0, recon=0, h_correction=0, x_rows=None, x_chunks=None,
-                batch=False) -> Config:
+                batch=False, serial_passes=0) -> Config:
     """Grid configuration.  riemann: RIEMANN_EXACT or RIEMANN_ROE (with the HLLE failsafe);
     recon: RECON_PPMC or RECON_PPMP; h_correction: 1 for the H correction of the
     second-stage Roe fluxes.  Tile shapes (launch shapes only): march_seg, target cells per
@@ -133,7 +134,9 @@ def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64,
     update; x_chunks, chunks per wavefront of the first-stage x sweep.  None takes the
     autotuned table (tiles.json beside this module) when it has the entry, else the library
     default; batch=True takes the shapes tuned for grids advanced in a batch (where the GPU
-    is full, unlike a small grid alone), when the table has them."""
+    is full, unlike a small grid alone), when the table has them.  serial_passes=1 runs
+    every pass of a step in order on the grid's stream instead of the second-stage z sweep
+    on a stream of the grid's own beside the others (same results, bitwise)."""
     c = Config()
     lib.ctu_config_default(C.byref(c))
     c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
@@ -163,6 +166,7 @@ def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64,
     c.riemann = int(riemann)
     c.recon = int(recon)
     c.h_correction = int(h_correction)
+    c.serial_passes = int(serial_passes)
     return c
 
 

@@ -340,6 +340,35 @@ def test_x_tile_shapes_are_bitwise_invariant(ctu, prec):
                 assert np.array_equal(U, ref), (wl.name, rows, chunks)
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_overlapped_passes_are_bitwise_serial(ctu, prec):
+    """The second-stage z sweep on the grid's side stream (the default) changes only when a
+    pass runs, never what it reads or writes: after three device-dt steps and two host-dt
+    steps the state is bitwise that of every pass in order on one stream, for the exact
+    solver (integer and general gamma), the Roe solver and PPMP, and with per-kernel timing
+    on (which runs the passes in order)."""
+    _announce("overlapped passes", prec)
+    cases = ((WL.random_state(23, 19, 17, seed=81, bc=(1, 1, 0, 0, 1, 1)), {}),
+             (WL.random_state(20, 14, 12, seed=82, gamma=1.3), {"recon": 1}),
+             (WL.random_state(18, 21, 13, seed=83), {"riemann": 1}),
+             (WL.shock_cloud(48), {}))
+    for wl, kw in cases:
+        out = []
+        for serial, timing in ((1, False), (0, False), (0, True)):
+            g = ctu.Grid.from_workload(wl, prec=prec, serial_passes=serial, **kw)
+            if timing:
+                g.profile_enable(True)
+            g.advance(3)
+            g.step(0.25 * g.compute_dt())
+            g.step(0.25 * g.compute_dt())
+            out.append(g.get_state())
+            status, flags, counters = g.check()
+            g.close()
+            assert status == ctu.OK, (wl.name, kw, flags, counters)
+        assert np.array_equal(out[1], out[0]), (wl.name, kw, "overlapped")
+        assert np.array_equal(out[2], out[0]), (wl.name, kw, "timed")
+
+
 def test_newton_histogram_counts_every_solve(ctu):
     """The instrumented sweeps count one Newton-iteration bin per exact Riemann solve: the
     bins add up to the number of solves a step makes (stage 1 on the extended transverse
