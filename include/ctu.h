@@ -124,7 +124,8 @@ typedef struct {
                               second-stage y sweeps, ordered with events; the caller's stream
                               still sees each step as one ordered unit.  1: every pass in
                               order on the grid's stream.  Results are bitwise the same.
-                              Batches and ctu_step_noalloc always run in order. */
+                              ctu_step_noalloc always runs in order; batches
+                              overlap on a stream of their own. */
 } ctu_config;
 
 typedef struct ctu_grid ctu_grid;
@@ -264,9 +265,12 @@ ctu_status ctu_stream_probe(int32_t kind, const double* a, const double* b, doub
  * ctu_batch_workspace_bytes: device bytes a batch of max_slots slots needs (1..65536).
  * ctu_batch_create: a batch over a caller-owned device buffer d_work (>= those bytes,
  *   256-byte aligned), ordered after and before the work of hip_stream (NULL = default
- *   stream); batch work itself runs on a stream of the batch's own, of default priority.
+ *   stream); batch work itself runs on a stream of the batch's own, of default priority,
+ *   with the overlapped sweep schedule of serial_passes = 0 on a second stream of the
+ *   batch's (whatever the grids' own serial_passes).
  *   flags: CTU_BATCH_GRAPH captures one step of the current set of grids in a HIP graph and
- *   replays it (recaptured whenever the set changes).  Creates a stream and two events.
+ *   replays it (recaptured whenever the set changes; the overlap becomes parallel branches
+ *   of the graph).  Creates two streams and five events.
  * ctu_batch_submit: places grid g in a free slot (CTU_EAGAIN when none is free) with a step
  *   budget nsteps >= 0 and an end time t_end; enqueues its CFL reduction on the grid's
  *   stream and orders the batch after it.  Until its ticket ends, every other call on g

@@ -777,8 +777,9 @@ struct ctu_batch {
     std::vector<int> start;
     ctu::GridDesc* d_desc = nullptr;
     int* d_start = nullptr;
-    ctu::PlanView view() const {
-      return ctu::PlanView{d_desc, d_start, (int)descs.size(), start.data(), prec, gclass, recon};
+    ctu::PlanView view(const ctu_batch* b) const {
+      return ctu::PlanView{d_desc, d_start, (int)descs.size(), start.data(), prec, gclass, recon,
+                           b->side, b->fork, b->xdone, b->join};
     }
   };
   // {FP64, FP32} x {PPMC, PPMP} x solver class {0, 3, 5, Roe, RoeH}
@@ -788,6 +789,9 @@ struct ctu_batch {
   hipStream_t caller = nullptr;  // the caller's stream: batch work is ordered after its work
   hipStream_t stream = nullptr;  // the batch's own stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // side stream and events of the overlapped sweep schedule, shared by the groups in turn
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr;
   Group groups[kGroups];
   DevScalars** d_sptr = nullptr;  // scalars of the used slots, gathered for poll
   DevScalars* d_sout = nullptr;
@@ -863,7 +867,7 @@ ctu_status rebuild(ctu_batch* b) {
 ctu_status enqueue_batch_step(ctu_batch* b) {
   for (int p = 0; p < ctu_batch::kGroups; ++p) {
     if (b->groups[p].descs.empty()) continue;
-    hipError_t e = ctu::launch_step(b->groups[p].view(), true, b->stream, nullptr);
+    hipError_t e = ctu::launch_step(b->groups[p].view(b), true, b->stream, nullptr);
     if (e != hipSuccess) return hip_fail(e, "batch step launch");
   }
   return CTU_OK;
@@ -940,8 +944,9 @@ ctu_status ctu_batch_create(int32_t max_slots, void* d_work, size_t work_bytes, 
   w += round256(sizeof(DevScalars*) * (size_t)max_slots);
   b->d_sout = reinterpret_cast<DevScalars*>(w);
   hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+  for (hipEvent_t* ev : {&b->ev_in, &b->ev_out, &b->fork, &b->xdone, &b->join})
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     ctu_batch_destroy(b);
     return hip_fail(e, "batch stream");
@@ -1045,11 +1050,13 @@ ctu_status ctu_batch_poll(ctu_batch* b, uint64_t ticket, int32_t* state, double*
 ctu_status ctu_batch_destroy(ctu_batch* b) {
   if (!b) return fail(CTU_EINVAL, "null batch");
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->side) (void)hipStreamSynchronize(b->side);
   for (auto& s : b->slots)
     if (s.used && s.grid) s.grid->in_batch = false;
   drop_graph(b);
-  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
-  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  for (hipEvent_t ev : {b->ev_in, b->ev_out, b->fork, b->xdone, b->join})
+    if (ev) (void)hipEventDestroy(ev);
+  if (b->side) (void)hipStreamDestroy(b->side);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return CTU_OK;
