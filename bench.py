@@ -5,10 +5,12 @@ uniform cloud of radius 0.1 at (0.3, 0.5, 0.5) with density contrast 10, Mach-10
 shock with the exact Rankine-Hugoniot post-shock state for x < 0.1, outflow boundaries,
 CFL 0.3), advanced with the device-side time step, state resident in HBM.  Each of
 `--repeats` runs starts from the initial state, takes `warmup` untimed steps and then times
-exactly `steps` steps between two device synchronizations, with no instrumentation;
-value = real cells x steps / time of the median run.  A further run of the same steps with
-per-kernel HIP events (recorded by the library on its own stream) gives the kernel times
-of the roofline.  The FP32 form (FP32 state, reconstruction and fluxes, FP64 Newton solve)
+exactly `steps` steps between two device synchronizations, with no instrumentation and the
+library's default schedule (the first-stage y and second-stage z sweeps on a second stream
+of the grid's, overlapping the other sweeps); value = real cells x steps / time of the
+median run.  A further run of the same steps with per-kernel HIP events (recorded by the
+library on its streams; timing runs every pass in order on one stream, so each kernel's
+time is its own) gives the kernel times of the roofline.  The FP32 form (FP32 state, reconstruction and fluxes, FP64 Newton solve)
 is timed the same way and reported beside it, with its relative L1 distance from FP64.
 
 The JSON line also carries
@@ -144,7 +146,8 @@ def run_gpu(wl, prec, steps, warmup, ctu, torch, repeats=5, keep_state=False,
     g.profile_enable(False)
     out = {"seconds": _median(secs), "runs_s": secs, "profile": prof,
            "profiled_seconds": prof_s, "status": status, "flags": flags,
-           "counters": counters, "t": info.t, "steps_done": info.steps}
+           "counters": counters, "t": info.t, "steps_done": info.steps,
+           "schedule": {1: "in order", 2: "overlapped"}.get(info.schedule, info.schedule)}
     if keep_state:
         out["state"] = g.get_state()
     if newton_hist:
@@ -654,7 +657,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"shock_cloud_{args.n}^3 Mach-10 chi-10 FP64 CFL 0.3",
                    "cells": cells, "grid": list(n), "parallelism": "single GPU",
-                   "repeats": args.repeats,
+                   "repeats": args.repeats, "schedule": r64["schedule"],
                    "runs_ms_per_step": [round(1e3 * s / args.steps, 4) for s in r64["runs_s"]],
                    "profiled_ms_per_step": round(1e3 * r64["profiled_seconds"] / args.steps, 4),
                    "newton_caps": r64["counters"][1], "status": r64["status"],

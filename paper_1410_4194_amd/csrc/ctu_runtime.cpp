@@ -108,8 +108,8 @@ ctu_status validate(const ctu_config* c) {
       return fail(CTU_EINVAL, "march_seg must lie in [0, 4096]");
   if (c->x_rows < 0 || c->x_rows > 8) return fail(CTU_EINVAL, "x_rows must lie in [0, 8]");
   if (c->x_chunks < 0 || c->x_chunks > 16) return fail(CTU_EINVAL, "x_chunks must lie in [0, 16]");
-  if (c->serial_passes != 0 && c->serial_passes != 1)
-    return fail(CTU_EINVAL, "serial_passes must be 0 or 1");
+  if (c->schedule < CTU_SCHEDULE_AUTO || c->schedule > CTU_SCHEDULE_OVERLAP)
+    return fail(CTU_EINVAL, "unknown schedule");
   for (int a = 0; a < 3; ++a) {
     int lo = c->bc[2 * a], hi = c->bc[2 * a + 1];
     for (int b : {lo, hi})
@@ -354,7 +354,10 @@ ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, s
     return fail(CTU_EINVAL, "grid too large for one launch per pass");
   }
   hipError_t e = hipSuccess;
-  if (!cfg->serial_passes && ctu::gas_class(g->P) != ctu::kRoeH) {
+  const bool overlap =
+      cfg->schedule == CTU_SCHEDULE_OVERLAP ||
+      (cfg->schedule == CTU_SCHEDULE_AUTO && g->fbytes() <= CTU_OVERLAP_MAX_FIELD_BYTES);
+  if (overlap && ctu::gas_class(g->P) != ctu::kRoeH) {
     // default priority, like every stream of the library
     e = hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking);
     for (hipEvent_t* ev : {&g->fork, &g->xdone, &g->join})
@@ -465,6 +468,7 @@ ctu_status ctu_grid_info_get(ctu_grid* g, ctu_grid_info* info) {
   info->t = s.t;
   info->steps = s.steps;
   info->ghost = g->P.ng;
+  info->schedule = g->side ? CTU_SCHEDULE_OVERLAP : CTU_SCHEDULE_IN_ORDER;
   return CTU_OK;
 }
 

@@ -26,6 +26,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, ENOCONV, EAGAIN = 0, -1, -2, -3, -4, -5, 
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
 RIEMANN_EXACT, RIEMANN_ROE = 0, 1
 RECON_PPMC, RECON_PPMP = 0, 1
+SCHEDULE_AUTO, SCHEDULE_IN_ORDER, SCHEDULE_OVERLAP = 0, 1, 2
 FP64, FP32 = 0, 1
 FLAG_NONFINITE, FLAG_DENSITY, FLAG_PFLOOR, FLAG_NEWTON_CAP = 1, 2, 4, 8
 TICKET_QUEUED, TICKET_RUNNING, TICKET_DONE, TICKET_FAILED, TICKET_UNKNOWN = 0, 1, 2, 3, -1
@@ -53,13 +54,13 @@ class Config(C.Structure):
                 ("newton_max_iter", C.c_int32), ("p_floor", C.c_double),
                 ("march_seg", C.c_int32 * 2), ("riemann", C.c_int32), ("recon", C.c_int32),
                 ("h_correction", C.c_int32), ("x_rows", C.c_int32), ("x_chunks", C.c_int32),
-                ("serial_passes", C.c_int32)]
+                ("schedule", C.c_int32)]
 
 
 class GridInfo(C.Structure):
     _fields_ = [("alloc_cells", C.c_int64), ("field_stride", C.c_int64),
                 ("elem_bytes", C.c_int32), ("t", C.c_double), ("steps", C.c_int64),
-                ("ghost", C.c_int32)]
+                ("ghost", C.c_int32), ("schedule", C.c_int32)]
 
 
 class CtuError(RuntimeError):
@@ -126,7 +127,7 @@ def _check(status: int, allow=()) -> int:
 def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64, cfl=0.3,
                 newton_tol=1e-6, newton_max_iter=50, p_floor=1e-20, march_seg=None,
                 riemann=0, recon=0, h_correction=0, x_rows=None, x_chunks=None,
-                batch=False, serial_passes=0) -> Config:
+                batch=False, schedule=0) -> Config:
     """Grid configuration.  riemann: RIEMANN_EXACT or RIEMANN_ROE (with the HLLE failsafe);
     recon: RECON_PPMC or RECON_PPMP; h_correction: 1 for the H correction of the
     second-stage Roe fluxes.  Tile shapes (launch shapes only): march_seg, target cells per
@@ -134,9 +135,10 @@ def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64,
     update; x_chunks, chunks per wavefront of the first-stage x sweep.  None takes the
     autotuned table (tiles.json beside this module) when it has the entry, else the library
     default; batch=True takes the shapes tuned for grids advanced in a batch (where the GPU
-    is full, unlike a small grid alone), when the table has them.  serial_passes=1 runs
-    every pass of a step in order on the grid's stream instead of the second-stage z sweep
-    on a stream of the grid's own beside the others (same results, bitwise)."""
+    is full, unlike a small grid alone), when the table has them.  schedule: SCHEDULE_AUTO
+    (the library's choice by size), SCHEDULE_IN_ORDER (every pass in order on the grid's
+    stream) or SCHEDULE_OVERLAP (the first-stage y and second-stage z sweeps on a stream of
+    the grid's own beside the others); results are bitwise the same."""
     c = Config()
     lib.ctu_config_default(C.byref(c))
     c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
@@ -166,7 +168,7 @@ def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64,
     c.riemann = int(riemann)
     c.recon = int(recon)
     c.h_correction = int(h_correction)
-    c.serial_passes = int(serial_passes)
+    c.schedule = int(schedule)
     return c
 
 

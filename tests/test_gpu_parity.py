@@ -342,20 +342,25 @@ def test_x_tile_shapes_are_bitwise_invariant(ctu, prec):
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
 def test_overlapped_passes_are_bitwise_serial(ctu, prec):
-    """The second-stage z sweep on the grid's side stream (the default) changes only when a
-    pass runs, never what it reads or writes: after three device-dt steps and two host-dt
-    steps the state is bitwise that of every pass in order on one stream, for the exact
-    solver (integer and general gamma), the Roe solver and PPMP, and with per-kernel timing
-    on (which runs the passes in order)."""
+    """The overlapped schedule (the first-stage y and second-stage z sweeps on the grid's
+    side stream) changes only when a pass runs, never what it reads or writes: after three
+    device-dt steps and two host-dt steps the state is bitwise that of every pass in order on
+    one stream, for the exact solver (integer and general gamma), the Roe solver and PPMP,
+    and with per-kernel timing on (which runs the passes in order).  The library's choice
+    overlaps these small grids."""
     _announce("overlapped passes", prec)
     cases = ((WL.random_state(23, 19, 17, seed=81, bc=(1, 1, 0, 0, 1, 1)), {}),
              (WL.random_state(20, 14, 12, seed=82, gamma=1.3), {"recon": 1}),
              (WL.random_state(18, 21, 13, seed=83), {"riemann": 1}),
              (WL.shock_cloud(48), {}))
+    runs = ((ctu.SCHEDULE_IN_ORDER, False), (ctu.SCHEDULE_OVERLAP, False),
+            (ctu.SCHEDULE_AUTO, False), (ctu.SCHEDULE_OVERLAP, True))
     for wl, kw in cases:
         out = []
-        for serial, timing in ((1, False), (0, False), (0, True)):
-            g = ctu.Grid.from_workload(wl, prec=prec, serial_passes=serial, **kw)
+        for schedule, timing in runs:
+            g = ctu.Grid.from_workload(wl, prec=prec, schedule=schedule, **kw)
+            want = ctu.SCHEDULE_IN_ORDER if schedule == ctu.SCHEDULE_IN_ORDER else ctu.SCHEDULE_OVERLAP
+            assert g.info().schedule == want, (schedule, g.info().schedule)
             if timing:
                 g.profile_enable(True)
             g.advance(3)
@@ -365,8 +370,28 @@ def test_overlapped_passes_are_bitwise_serial(ctu, prec):
             status, flags, counters = g.check()
             g.close()
             assert status == ctu.OK, (wl.name, kw, flags, counters)
-        assert np.array_equal(out[1], out[0]), (wl.name, kw, "overlapped")
-        assert np.array_equal(out[2], out[0]), (wl.name, kw, "timed")
+        for k in range(1, len(runs)):
+            assert np.array_equal(out[k], out[0]), (wl.name, kw, runs[k])
+
+
+def test_schedule_choice_by_field_size(ctu):
+    """The library's choice: overlapped while one field array takes at most
+    CTU_OVERLAP_MAX_FIELD_BYTES (192 MiB), in order above; never with the H correction
+    (its y sweep writes the eta that the z sweep reads)."""
+    limit = 192 << 20
+    for n, prec in ((256, ctu.FP64), (288, ctu.FP64), (352, ctu.FP32), (384, ctu.FP32)):
+        cfg = ctu.make_config(n, n, n, 1.0 / n, 1.0 / n, 1.0 / n, 5.0 / 3.0, prec=prec)
+        g = ctu.Grid(cfg)
+        info = g.info()
+        g.close()
+        small = info.field_stride * info.elem_bytes <= limit
+        assert info.schedule == (ctu.SCHEDULE_OVERLAP if small else ctu.SCHEDULE_IN_ORDER), n
+        assert small == (n in (256, 352)), (n, info.field_stride * info.elem_bytes)
+    cfg = ctu.make_config(16, 16, 16, 1, 1, 1, 1.4, riemann=ctu.RIEMANN_ROE, h_correction=1,
+                          schedule=ctu.SCHEDULE_OVERLAP)
+    g = ctu.Grid(cfg)
+    assert g.info().schedule == ctu.SCHEDULE_IN_ORDER
+    g.close()
 
 
 def test_newton_histogram_counts_every_solve(ctu):
