@@ -283,7 +283,7 @@ ctu_status ctu_stream_probe(int32_t kind, const double* a, const double* b, doub
  *   size).
  *   flags: CTU_BATCH_GRAPH captures one step of the current set of grids in a HIP graph and
  *   replays it (recaptured whenever the set changes; the overlap becomes parallel branches
- *   of the graph).  Creates two streams and five events.
+ *   of the graph).  Creates two streams and six events.
  * ctu_batch_submit: places grid g in a free slot (CTU_EAGAIN when none is free) with a step
  *   budget nsteps >= 0 and an end time t_end; enqueues its CFL reduction on the grid's
  *   stream and orders the batch after it.  Until its ticket ends, every other call on g

@@ -486,6 +486,24 @@ long long pass_blocks(const GridParams& P, int pass) {
   return 0;
 }
 
+template <typename T, int D>
+void launch_ppmp_coef(const PlanView& v, hipStream_t stream) {
+  const int stride = v.ngrids + 1;
+  const int pass = D == 0 ? P_COEF_X : (D == 1 ? P_COEF_Y : P_COEF_Z);
+  const LaunchTab tab{v.d_grids, v.d_start + pass * stride, v.ngrids};
+  const dim3 nb((unsigned)v.h_start[pass * stride + v.ngrids]);
+  if constexpr (D == 0)
+    hipLaunchKernelGGL((k_ppmp_coef_x<T>), nb, dim3(kBlock), 0, stream, tab);
+  else
+    hipLaunchKernelGGL((k_ppmp_coef_march<T, D>), nb, dim3(kBlock), 0, stream, tab);
+}
+template void launch_ppmp_coef<double, 0>(const PlanView&, hipStream_t);
+template void launch_ppmp_coef<double, 1>(const PlanView&, hipStream_t);
+template void launch_ppmp_coef<double, 2>(const PlanView&, hipStream_t);
+template void launch_ppmp_coef<float, 0>(const PlanView&, hipStream_t);
+template void launch_ppmp_coef<float, 1>(const PlanView&, hipStream_t);
+template void launch_ppmp_coef<float, 2>(const PlanView&, hipStream_t);
+
 template <typename T, int R>
 static hipError_t sweeps_r(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
   switch (v.gclass) {
@@ -519,13 +537,12 @@ static hipError_t enqueue_step(const PlanView& v, bool device_dt, hipStream_t st
             hipLaunchKernelGGL((k_bc_fill<T, 1>), nblocks(P_BC_Y), B, 0, stream, tab(P_BC_Y)));
   CTU_TIMED(K_BC_Z,
             hipLaunchKernelGGL((k_bc_fill<T, 2>), nblocks(P_BC_Z), B, 0, stream, tab(P_BC_Z)));
-  if (v.recon == 1) {
-    CTU_TIMED(K_PPMP_COEF, hipLaunchKernelGGL((k_ppmp_coef_x<T>), nblocks(P_COEF_X), B, 0, stream,
-                                              tab(P_COEF_X)));
-    CTU_TIMED(K_PPMP_COEF, hipLaunchKernelGGL((k_ppmp_coef_march<T, 1>), nblocks(P_COEF_Y), B, 0,
-                                              stream, tab(P_COEF_Y)));
-    CTU_TIMED(K_PPMP_COEF, hipLaunchKernelGGL((k_ppmp_coef_march<T, 2>), nblocks(P_COEF_Z), B, 0,
-                                              stream, tab(P_COEF_Z)));
+  // (in the overlapped schedule the first-stage sweeps launch the PPMP coefficient passes,
+  // each beside other work)
+  if (v.recon == 1 && !overlapped(v, prof)) {
+    CTU_TIMED(K_PPMP_COEF, (launch_ppmp_coef<T, 0>(v, stream)));
+    CTU_TIMED(K_PPMP_COEF, (launch_ppmp_coef<T, 1>(v, stream)));
+    CTU_TIMED(K_PPMP_COEF, (launch_ppmp_coef<T, 2>(v, stream)));
   }
   // stage 1 (a2-a5), then stage 2 (a2-a4 re-traced, a6-a7) with the update (a8) fused into
   // its last sweep

@@ -122,10 +122,10 @@ struct PlanView {
   int gclass;          // solver class: exact with gas class 3 (gamma 5/3), 5 (gamma 7/5) or
                        // 0 (other), kRoe, or kRoeH
   int recon;           // 0 PPMC, 1 PPMP
-  // Optional second stream (default priority) and three events for the overlapped schedule
+  // Optional second stream (default priority) and four events for the overlapped schedule
   // of the sweeps (enqueue_sweeps); null side: every pass in order on the launch stream.
   hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr, coefy = nullptr;
 };
 
 // Solver class of a grid: kRoe for the Roe solver; for the exact solver its gas class, K
@@ -136,6 +136,18 @@ inline int gas_class(const GridParams& P) {
              ? P.fan_int_exp
              : 0;
 }
+
+// Whether a step of the plan takes the overlapped schedule of enqueue_sweeps: a side stream
+// and its events are there, the solver is not Roe with the H correction (whose z sweep reads
+// the eta that the y sweep writes) and kernels are not being timed one by one.
+inline bool overlapped(const PlanView& v, const Profiler* prof) {
+  return v.gclass != kRoeH && v.side && v.fork && v.xdone && v.join && v.coefy &&
+         !(prof && prof->timing);
+}
+
+// PPMP coefficients along axis D for every grid of the plan (ctu_kernels.hip).
+template <typename T, int D>
+void launch_ppmp_coef(const PlanView& v, hipStream_t stream);
 
 // The three sweeps of stage 1 or 2 for every grid of a plan; one specialization per
 // (T, K, R) is compiled in its own translation unit (ctu_sweeps.hip).
