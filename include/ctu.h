@@ -124,11 +124,12 @@ typedef struct {
                               Changes the launch shape only: results are bitwise the same */
   int32_t schedule;        /* ctu_schedule: the order of the passes of a step taken by
                               ctu_step / ctu_advance.  CTU_SCHEDULE_OVERLAP runs the
-                              first-stage y sweep and then the second-stage z sweep on a
-                              stream of the grid's own (created with the grid, default
-                              priority), beside the first-stage x and z and second-stage y
-                              sweeps, ordered with events; the caller's stream still sees
-                              each step as one ordered unit.  CTU_SCHEDULE_IN_ORDER runs
+                              first-stage y sweep and then the second-stage z sweep (with
+                              the H correction: the eta pass along z) on a stream of the
+                              grid's own (created with the grid, default priority), beside
+                              the other sweeps, ordered with events, and the PPMP
+                              coefficient passes beside the first-stage sweeps; the
+                              caller's stream still sees each step as one ordered unit.  CTU_SCHEDULE_IN_ORDER runs
                               every pass in order on the grid's stream.  CTU_SCHEDULE_AUTO
                               (0) overlaps while one field array of the grid takes at most
                               CTU_OVERLAP_MAX_FIELD_BYTES, in order above (measured on

@@ -125,7 +125,7 @@ struct PlanView {
   // Optional second stream (default priority) and four events for the overlapped schedule
   // of the sweeps (enqueue_sweeps); null side: every pass in order on the launch stream.
   hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr, coefy = nullptr;
+  hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr, ydone = nullptr;
 };
 
 // Solver class of a grid: kRoe for the Roe solver; for the exact solver its gas class, K
@@ -138,11 +138,9 @@ inline int gas_class(const GridParams& P) {
 }
 
 // Whether a step of the plan takes the overlapped schedule of enqueue_sweeps: a side stream
-// and its events are there, the solver is not Roe with the H correction (whose z sweep reads
-// the eta that the y sweep writes) and kernels are not being timed one by one.
+// and its events are there and kernels are not being timed one by one.
 inline bool overlapped(const PlanView& v, const Profiler* prof) {
-  return v.gclass != kRoeH && v.side && v.fork && v.xdone && v.join && v.coefy &&
-         !(prof && prof->timing);
+  return v.side && v.fork && v.xdone && v.join && v.ydone && !(prof && prof->timing);
 }
 
 // PPMP coefficients along axis D for every grid of the plan (ctu_kernels.hip).

@@ -224,13 +224,13 @@ struct ctu_grid {
   std::vector<int> h_start;       // host copy of the one-grid block table
   // the side stream and events of the overlapped sweep schedule (null when serial)
   hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr, coefy = nullptr;
+  hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr, ydone = nullptr;
   ~ctu_grid() {
     if (side) {
       (void)hipStreamSynchronize(side);
       (void)hipStreamDestroy(side);
     }
-    for (hipEvent_t ev : {fork, xdone, join, coefy})
+    for (hipEvent_t ev : {fork, xdone, join, ydone})
       if (ev) (void)hipEventDestroy(ev);
   }
   DevScalars* scalars() const { return reinterpret_cast<DevScalars*>(d_work + kScalarsOffset); }
@@ -245,7 +245,7 @@ struct ctu_grid {
   int* d_start() const { return reinterpret_cast<int*>(d_work + kStartOffset); }
   ctu::PlanView plan() const {
     return ctu::PlanView{d_desc(), d_start(), 1, h_start.data(), cfg.prec == CTU_FP32 ? 1 : 0,
-                         ctu::gas_class(P), P.recon, side, fork, xdone, join, coefy};
+                         ctu::gas_class(P), P.recon, side, fork, xdone, join, ydone};
   }
 };
 
@@ -357,10 +357,10 @@ ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, s
   const bool overlap =
       cfg->schedule == CTU_SCHEDULE_OVERLAP ||
       (cfg->schedule == CTU_SCHEDULE_AUTO && g->fbytes() <= CTU_OVERLAP_MAX_FIELD_BYTES);
-  if (overlap && ctu::gas_class(g->P) != ctu::kRoeH) {
+  if (overlap) {
     // default priority, like every stream of the library
     e = hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking);
-    for (hipEvent_t* ev : {&g->fork, &g->xdone, &g->join, &g->coefy})
+    for (hipEvent_t* ev : {&g->fork, &g->xdone, &g->join, &g->ydone})
       if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
     if (e != hipSuccess) {
       delete g;
@@ -783,7 +783,7 @@ struct ctu_batch {
     int* d_start = nullptr;
     ctu::PlanView view(const ctu_batch* b) const {
       return ctu::PlanView{d_desc, d_start, (int)descs.size(), start.data(), prec, gclass, recon,
-                           b->side, b->fork, b->xdone, b->join, b->coefy};
+                           b->side, b->fork, b->xdone, b->join, b->ydone};
     }
   };
   // {FP64, FP32} x {PPMC, PPMP} x solver class {0, 3, 5, Roe, RoeH}
@@ -795,7 +795,7 @@ struct ctu_batch {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // side stream and events of the overlapped sweep schedule, shared by the groups in turn
   hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr, coefy = nullptr;
+  hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr, ydone = nullptr;
   Group groups[kGroups];
   DevScalars** d_sptr = nullptr;  // scalars of the used slots, gathered for poll
   DevScalars* d_sout = nullptr;
@@ -949,7 +949,7 @@ ctu_status ctu_batch_create(int32_t max_slots, void* d_work, size_t work_bytes, 
   b->d_sout = reinterpret_cast<DevScalars*>(w);
   hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
-  for (hipEvent_t* ev : {&b->ev_in, &b->ev_out, &b->fork, &b->xdone, &b->join, &b->coefy})
+  for (hipEvent_t* ev : {&b->ev_in, &b->ev_out, &b->fork, &b->xdone, &b->join, &b->ydone})
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     ctu_batch_destroy(b);
@@ -1058,7 +1058,7 @@ ctu_status ctu_batch_destroy(ctu_batch* b) {
   for (auto& s : b->slots)
     if (s.used && s.grid) s.grid->in_batch = false;
   drop_graph(b);
-  for (hipEvent_t ev : {b->ev_in, b->ev_out, b->fork, b->xdone, b->join, b->coefy})
+  for (hipEvent_t ev : {b->ev_in, b->ev_out, b->fork, b->xdone, b->join, b->ydone})
     if (ev) (void)hipEventDestroy(ev);
   if (b->side) (void)hipStreamDestroy(b->side);
   if (b->stream) (void)hipStreamDestroy(b->stream);

@@ -665,51 +665,54 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
 }
 
 // The three sweeps of one stage for every grid of a plan (one launch per direction).
-// With a side stream in the plan the sweeps overlap where the data allow it:
-//   launch stream: [fork] (coef x) x1 (coef z) [x done] z1 [coef y done] y2 [side done] update
-//   side stream:   [fork] (coef y) [coef y done] y1 [x done] z2 [side done]
-// (x1 = first-stage x sweep, y2 = second-stage y sweep; the PPMP coefficient passes in
-// parentheses).  The first-stage y sweep needs only u^n and its own coefficients, so it runs
-// beside the x sweep; the second-stage z sweep needs only the first-stage x and y differences
-// and the z coefficients, so it follows on the side as soon as those are done, beside the
-// first-stage z sweep (bound by FP64 issue) and the second-stage y sweep (bound by memory);
-// the memory-bound coefficient passes run beside the first-stage sweeps.  A pass still starts
-// only after everything it reads is complete, so results are bitwise those of the serial
-// order.  Not with the H correction (the z sweep reads eta along y, which the y sweep
-// writes), and not while kernels are timed one by one.
+// With a side stream in the plan the passes overlap where the data allow it (x1 = first-stage
+// x sweep, y2 = second-stage y sweep, ...; PPMP coefficient passes in parentheses):
+//   launch stream: [fork] (coef x) x1 (coef z) [x done] z1 [y done] y2 [side done] update
+//   side stream:   [fork] (coef y) y1 [y done] [x done] z2 [side done]
+// The first-stage y sweep needs only u^n and its own coefficients, so it runs beside the x
+// sweep; the second-stage z sweep needs only the first-stage x and y differences and the z
+// coefficients, so it follows on the side as soon as those are done, beside the first-stage
+// z sweep (bound by FP64 issue) and the second-stage y sweep (bound by memory); the
+// memory-bound coefficient passes run beside the first-stage sweeps.
+// With the H correction the second-stage z sweep reads the eta along y that the second-stage
+// y sweep writes, so those two stay in order; the eta pass along z (which needs the x and y
+// first-stage differences) moves to the side instead:
+//   launch stream: [fork] (coef x) x1 (coef z) [x done] z1 [y done] eta_x [side done] y2 z2 update
+//   side stream:   [fork] (coef y) y1 [y done] [x done] eta_z [side done]
+// A pass still starts only after everything it reads is complete, so results are bitwise those
+// of the serial order.  Not while kernels are timed one by one.
 template <typename T, int K, bool HIST, int R>
 hipError_t enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
   const int stride = v.ngrids + 1;
   auto tab = [&](int pass) { return LaunchTab{v.d_grids, v.d_start + pass * stride, v.ngrids}; };
   auto nblocks = [&](int pass) { return dim3((unsigned)v.h_start[pass * stride + v.ngrids]); };
   const dim3 B(kBlock);
-  const bool overlap = K != kRoeH && overlapped(v, prof);
+  const bool overlap = overlapped(v, prof);
   hipError_t e = hipSuccess;
   if (stage == 1) {
     // a2-a5: F*, G*, H* on the extended transverse range
     if (overlap) {
-      // side: the first-stage y sweep (after its PPMP coefficients) beside the x sweep, then
-      // (once the x differences are done) the second-stage z sweep
       e = hipEventRecord(v.fork, stream);
       if (e == hipSuccess) e = hipStreamWaitEvent(v.side, v.fork, 0);
       if (e != hipSuccess) return e;
-      if constexpr (R == 1) {
-        launch_ppmp_coef<T, 1>(v, v.side);
-        e = hipEventRecord(v.coefy, v.side);
-        if (e != hipSuccess) return e;
-      }
+      if constexpr (R == 1) launch_ppmp_coef<T, 1>(v, v.side);
       hipLaunchKernelGGL((k_sweep_march<T, 1, 1, HIST, K, R>), nblocks(P_S1_Y), B, 0, v.side,
                          tab(P_S1_Y));
+      e = hipEventRecord(v.ydone, v.side);
+      if (e != hipSuccess) return e;
       if constexpr (R == 1) launch_ppmp_coef<T, 0>(v, stream);
       hipLaunchKernelGGL((k_sweep_x<T, 1, HIST, K, R>), nblocks(P_S1_X), B, 0, stream,
                          tab(P_S1_X));
-      // the z coefficients run beside the side's y sweep; the second-stage z sweep needs them
       if constexpr (R == 1) launch_ppmp_coef<T, 2>(v, stream);
       e = hipEventRecord(v.xdone, stream);
       if (e == hipSuccess) e = hipStreamWaitEvent(v.side, v.xdone, 0);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((k_sweep_march<T, 2, 2, HIST, K, R>), nblocks(P_S2_Z), B, 0, v.side,
-                         tab(P_S2_Z));
+      if constexpr (K == kRoeH)  // eta along z
+        hipLaunchKernelGGL((k_sweep_march<T, 2, 3, false, K, R>), nblocks(P_ETA_Z), B, 0, v.side,
+                           tab(P_ETA_Z));
+      else
+        hipLaunchKernelGGL((k_sweep_march<T, 2, 2, HIST, K, R>), nblocks(P_S2_Z), B, 0, v.side,
+                           tab(P_S2_Z));
       e = hipEventRecord(v.join, v.side);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL((k_sweep_march<T, 2, 1, HIST, K, R>), nblocks(P_S1_Z), B, 0, stream,
@@ -723,23 +726,30 @@ hipError_t enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Prof
                                                nblocks(P_S1_Z), B, 0, stream, tab(P_S1_Z)));
     }
   } else {
+    // the side's PPMP y coefficients (read by the second-stage y sweep) and first-stage y
+    // differences (read by the eta pass along x)
+    if (overlap && (R == 1 || K == kRoeH)) {
+      e = hipStreamWaitEvent(stream, v.ydone, 0);
+      if (e != hipSuccess) return e;
+    }
     if constexpr (K == kRoeH) {
       // eta of every face the H stencils of the second stage read
       // (along y the second-stage y sweep computes them itself)
       CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_eta_x<T, R>), nblocks(P_ETA_X), B, 0, stream,
                                                 tab(P_ETA_X)));
-      CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_sweep_march<T, 2, 3, false, K, R>),
-                                                nblocks(P_ETA_Z), B, 0, stream, tab(P_ETA_Z)));
+      if (overlap) {  // eta along z came from the side stream
+        e = hipStreamWaitEvent(stream, v.join, 0);
+        if (e != hipSuccess) return e;
+      } else {
+        CTU_TIMED(K_HCORR_ETA, hipLaunchKernelGGL((k_sweep_march<T, 2, 3, false, K, R>),
+                                                  nblocks(P_ETA_Z), B, 0, stream, tab(P_ETA_Z)));
+      }
     }
     // a2-a4 re-traced, a6-a7: G^{n+1/2}, H^{n+1/2} on the real faces, then F^{n+1/2} with the
     // update (a8) and the CFL bound of the new state (a9)
-    if (overlap && R == 1) {  // the y coefficients came from the side stream
-      e = hipStreamWaitEvent(stream, v.coefy, 0);
-      if (e != hipSuccess) return e;
-    }
     CTU_TIMED(K_SWEEP2_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 2, HIST, K, R>), nblocks(P_S2_Y),
                                              B, 0, stream, tab(P_S2_Y)));
-    if (overlap) {
+    if (overlap && K != kRoeH) {  // the second-stage z sweep ran on the side stream
       e = hipStreamWaitEvent(stream, v.join, 0);
       if (e != hipSuccess) return e;
     } else {

@@ -345,13 +345,17 @@ def test_overlapped_passes_are_bitwise_serial(ctu, prec):
     """The overlapped schedule (the first-stage y and second-stage z sweeps on the grid's
     side stream) changes only when a pass runs, never what it reads or writes: after three
     device-dt steps and two host-dt steps the state is bitwise that of every pass in order on
-    one stream, for the exact solver (integer and general gamma), the Roe solver and PPMP,
-    and with per-kernel timing on (which runs the passes in order).  The library's choice
-    overlaps these small grids."""
+    one stream, for the exact solver (integer and general gamma), the Roe solver, PPMP and
+    the H correction (whose eta pass along z moves to the side stream), and with per-kernel
+    timing on (which runs the passes in order).  The library's choice overlaps these small
+    grids."""
     _announce("overlapped passes", prec)
     cases = ((WL.random_state(23, 19, 17, seed=81, bc=(1, 1, 0, 0, 1, 1)), {}),
              (WL.random_state(20, 14, 12, seed=82, gamma=1.3), {"recon": 1}),
              (WL.random_state(18, 21, 13, seed=83), {"riemann": 1}),
+             (WL.random_state(19, 16, 14, seed=84, bc=(1,) * 6), {"riemann": 1, "h_correction": 1}),
+             (WL.random_state(17, 15, 13, seed=85, rough=False, mach=2.0),
+              {"riemann": 1, "h_correction": 1, "recon": 1}),
              (WL.shock_cloud(48), {}))
     runs = ((ctu.SCHEDULE_IN_ORDER, False), (ctu.SCHEDULE_OVERLAP, False),
             (ctu.SCHEDULE_AUTO, False), (ctu.SCHEDULE_OVERLAP, True))
@@ -376,8 +380,8 @@ def test_overlapped_passes_are_bitwise_serial(ctu, prec):
 
 def test_schedule_choice_by_field_size(ctu):
     """The library's choice: overlapped while one field array takes at most
-    CTU_OVERLAP_MAX_FIELD_BYTES (192 MiB), in order above; never with the H correction
-    (its y sweep writes the eta that the z sweep reads)."""
+    CTU_OVERLAP_MAX_FIELD_BYTES (192 MiB), in order above; an explicit choice holds for every
+    method."""
     limit = 192 << 20
     for n, prec in ((256, ctu.FP64), (288, ctu.FP64), (352, ctu.FP32), (384, ctu.FP32)):
         cfg = ctu.make_config(n, n, n, 1.0 / n, 1.0 / n, 1.0 / n, 5.0 / 3.0, prec=prec)
@@ -387,11 +391,12 @@ def test_schedule_choice_by_field_size(ctu):
         small = info.field_stride * info.elem_bytes <= limit
         assert info.schedule == (ctu.SCHEDULE_OVERLAP if small else ctu.SCHEDULE_IN_ORDER), n
         assert small == (n in (256, 352)), (n, info.field_stride * info.elem_bytes)
-    cfg = ctu.make_config(16, 16, 16, 1, 1, 1, 1.4, riemann=ctu.RIEMANN_ROE, h_correction=1,
-                          schedule=ctu.SCHEDULE_OVERLAP)
-    g = ctu.Grid(cfg)
-    assert g.info().schedule == ctu.SCHEDULE_IN_ORDER
-    g.close()
+    for schedule in (ctu.SCHEDULE_IN_ORDER, ctu.SCHEDULE_OVERLAP):
+        cfg = ctu.make_config(16, 16, 16, 1, 1, 1, 1.4, riemann=ctu.RIEMANN_ROE, h_correction=1,
+                              recon=ctu.RECON_PPMP, schedule=schedule)
+        g = ctu.Grid(cfg)
+        assert g.info().schedule == schedule
+        g.close()
 
 
 def test_newton_histogram_counts_every_solve(ctu):
