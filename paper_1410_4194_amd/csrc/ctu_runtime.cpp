@@ -360,8 +360,11 @@ ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, s
   if (overlap) {
     // default priority, like every stream of the library
     e = hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking);
+    // the events only order the grid's two streams on one GPU: a device-scope release is
+    // enough (measured: 4% per step at 64^3 against the default system-scope fence)
     for (hipEvent_t* ev : {&g->fork, &g->xdone, &g->join, &g->ydone})
-      if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+      if (e == hipSuccess)
+        e = hipEventCreateWithFlags(ev, hipEventDisableTiming | hipEventDisableSystemFence);
     if (e != hipSuccess) {
       delete g;
       return hip_fail(e, "side stream");
@@ -949,8 +952,12 @@ ctu_status ctu_batch_create(int32_t max_slots, void* d_work, size_t work_bytes, 
   b->d_sout = reinterpret_cast<DevScalars*>(w);
   hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
-  for (hipEvent_t* ev : {&b->ev_in, &b->ev_out, &b->fork, &b->xdone, &b->join, &b->ydone})
+  for (hipEvent_t* ev : {&b->ev_in, &b->ev_out})
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  // the schedule's events only order the batch's two streams on one GPU
+  for (hipEvent_t* ev : {&b->fork, &b->xdone, &b->join, &b->ydone})
+    if (e == hipSuccess)
+      e = hipEventCreateWithFlags(ev, hipEventDisableTiming | hipEventDisableSystemFence);
   if (e != hipSuccess) {
     ctu_batch_destroy(b);
     return hip_fail(e, "batch stream");
