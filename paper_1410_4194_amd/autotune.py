@@ -11,8 +11,12 @@ Three tile shapes change how the sweeps are launched, not what they compute:
   * x chunks: the first-stage x sweep gives each wavefront that many consecutive chunks of
     its flattened plane line, paying the wavefront's set-up once for all of them.
 The best shapes depend on the axis lengths, the cross-section and the precision.  This module
-times candidates on the GPU with the library's own per-kernel event timing and stores the
-winners in a table that ``ctu.make_config`` consults when no shape is given.
+times candidates on the GPU and stores the winners in a table that ``ctu.make_config``
+consults when no shape is given.  The default objective is the whole step as the library
+runs it (the overlapped schedule on the grid sizes that use it, where the sweeps share the
+GPU and no kernel's time is its own), each candidate timed from the same initial state;
+``--objective kernels`` times the kernels a shape changes one by one instead (with per-kernel
+events, which run the passes in order).
 
     python -m paper_1410_4194_amd.autotune --out tiles.json [--sizes 32 48 64 ...]
 
@@ -53,6 +57,53 @@ def _time_shape(ctu, wl, prec, steps, classes, **shape):
     return [sum(prof[k][0] for k in cls) / steps for cls in classes]
 
 
+def _time_step(ctu, wl, prec, steps, reps=3, **shape):
+    """Median milliseconds per whole step with the given tile shape and the library's default
+    schedule, each of `reps` runs from the initial state (2 untimed steps, then `steps`)."""
+    import torch
+    cfg = ctu.make_config(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.gamma, wl.bc, prec,
+                          wl.cfl, **shape)
+    g = ctu.Grid(cfg)
+    out = []
+    for _ in range(reps):
+        g.set_primitive(wl.W)
+        g.advance(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.advance(steps)
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t0) * 1e3 / steps)
+    g.close()
+    return sorted(out)[len(out) // 2]
+
+
+def _tune_steps(ctu, wl, prec, steps, candidates, x_rows, x_chunks, log, name, n):
+    """Whole-step search: segments with y = z, then y and z each with the other fixed, then x
+    rows, then x chunks, each with the best of the earlier ones."""
+    t = lambda **sh: _time_step(ctu, wl, prec, steps, **sh)  # noqa: E731
+    segs = [s for s in candidates if s <= n + 1]
+    joint = {s: t(march_seg=(s, s), x_rows=0, x_chunks=0) for s in segs}
+    s0 = min(joint, key=joint.get)
+    ys = {s: (joint[s] if s == s0 else t(march_seg=(s, s0), x_rows=0, x_chunks=0)) for s in segs}
+    by = min(ys, key=ys.get)
+    zs = {s: (ys[by] if s == s0 else t(march_seg=(by, s), x_rows=0, x_chunks=0)) for s in segs}
+    bz = min(zs, key=zs.get)
+    seg = (by, bz)
+    rows = {r: t(march_seg=seg, x_rows=r, x_chunks=0) for r in x_rows if r <= n}
+    best_r = min(rows, key=rows.get)
+    chunks = {c: t(march_seg=seg, x_rows=best_r, x_chunks=c) for c in x_chunks}
+    best_c = min(chunks, key=chunks.get)
+    log(f"[autotune] {name} n={n}: segments y {by} z {bz} (y = z: "
+        + " ".join(f"{s}:{v:.4f}" for s, v in joint.items()) + f"), x rows {best_r}, x chunks "
+        f"{best_c}: {chunks[best_c]:.4f} ms per step")
+    return {"y": by, "z": bz, "x_rows": best_r, "x_chunks": best_c,
+            "ms_step_joint": {str(s): round(v, 4) for s, v in joint.items()},
+            "ms_step_y": {str(s): round(v, 4) for s, v in ys.items()},
+            "ms_step_z": {str(s): round(v, 4) for s, v in zs.items()},
+            "ms_step_x_rows": {str(r): round(v, 4) for r, v in rows.items()},
+            "ms_step_x_chunks": {str(c): round(v, 4) for c, v in chunks.items()}}
+
+
 def _time_candidate(ctu, wl, prec, seg, steps):
     return _time_shape(ctu, wl, prec, steps,
                        (("sweep1_y", "sweep2_y"), ("sweep1_z", "sweep2_z")),
@@ -63,18 +114,26 @@ WORKLOADS = ("shock_cloud", "kh")
 
 
 def tune(sizes=DEFAULT_SIZES, precs=None, candidates=CANDIDATES, steps=8, log=print,
-         workload="shock_cloud", x_rows=X_ROWS, x_chunks=X_CHUNKS):
+         workload="shock_cloud", x_rows=X_ROWS, x_chunks=X_CHUNKS, objective="step"):
     from . import ctu, workloads as WL
     if workload not in WORKLOADS:
         raise ValueError(f"unknown workload {workload!r}")
+    if objective not in ("step", "kernels"):
+        raise ValueError(f"unknown objective {objective!r}")
     precs = precs if precs is not None else (ctu.FP64, ctu.FP32)
     table = {"candidates": list(candidates), "x_rows_candidates": list(x_rows),
              "x_chunks_candidates": list(x_chunks), "steps": steps, "workload": workload,
-             "fp64": {}, "fp32": {}}
+             "objective": objective, "fp64": {}, "fp32": {}}
     for prec in precs:
         name = "fp64" if prec == ctu.FP64 else "fp32"
         for n in sizes:
             wl = WL.shock_cloud(n) if workload == "shock_cloud" else WL.kelvin_helmholtz(n, n, n)
+            if objective == "step":
+                # at least ~20 ms of steps per timing: small grids take many more steps
+                nsteps = max(steps, int(round(steps * (256 / n) ** 2)))
+                table[name][str(n)] = _tune_steps(ctu, wl, prec, nsteps, candidates, x_rows,
+                                                  x_chunks, log, name, n)
+                continue
             times = {}
             for seg in candidates:
                 if seg > n + 1:
@@ -207,6 +266,9 @@ def main():
     ap.add_argument("--sizes", type=int, nargs="*", default=list(DEFAULT_SIZES))
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--workload", choices=WORKLOADS, default="shock_cloud")
+    ap.add_argument("--objective", choices=("step", "kernels"), default="step",
+                    help="time whole steps as the library runs them (default) or the kernels "
+                         "a shape changes, one by one")
     ap.add_argument("--batch-only", action="store_true",
                     help="tune only the batch shapes, into the existing table")
     args = ap.parse_args()
@@ -220,7 +282,8 @@ def main():
         print(f"[autotune] wrote {args.out}", file=sys.stderr)
         return
     t0 = time.perf_counter()
-    table = tune(args.sizes, steps=args.steps, workload=args.workload, log=log)
+    table = tune(args.sizes, steps=args.steps, workload=args.workload, log=log,
+                 objective=args.objective)
     table["batch"] = tune_batch(log=log)
     table["seconds"] = round(time.perf_counter() - t0, 1)
     with open(args.out, "w") as fh:
