@@ -191,13 +191,15 @@ def lookup(prec: int, ny: int, nz: int, path: str = TABLE_PATH):
     return (int(rows[nearest(ny)]["y"]), int(rows[nearest(nz)]["z"]))
 
 
-def tune_batch(precs=None, steps=30, log=print, segs=(4, 8, 12, 16, 24),
+def tune_batch(precs=None, steps=200, log=print, segs=(4, 8, 12, 16, 24),
                chunks=(1, 2, 4, 8), rows=(0, 1, 2)):
     """Tile shapes for grids advanced together in a batch, timed on the 64-grid
     Kelvin-Helmholtz batch (edges from {32, ..., 128}) with one shape for every grid: the
     segment length (y and z), then the x chunks, then the x rows (0: the library's choice per
     grid), each with the best of the earlier ones.  A batch fills the GPU where one small grid
-    alone does not, so it prefers less parallelism per grid than the single-grid table."""
+    alone does not, so it prefers less parallelism per grid than the single-grid table.  The
+    shear layers evolve over a run, so the timing takes the bench's 200 steps (a 30-step
+    timing picked 8-cell segments, 1.7% slower than 12 over 200 steps)."""
     from . import ctu, workloads as WL
     import torch
     precs = precs if precs is not None else (ctu.FP64, ctu.FP32)
