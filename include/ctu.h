@@ -198,8 +198,10 @@ ctu_status ctu_compute_dt(ctu_grid* g, double* dt);
  * solve per direction, conservative update (eq. conserved_update), and the reduction that
  * yields the next CFL time step (Sec. 3.5).  The kernel sequence follows Sec. 3.4 (one
  * kernel per stage and direction, intermediates in device memory), with reconstruction and
- * Riemann solve fused per direction and the last second-stage sweep fused with the update.
- * Async. */
+ * Riemann solve fused per direction and the last second-stage sweep fused with the update;
+ * with the overlapped schedule (ctu_config.schedule) the kernels whose inputs allow it run on
+ * the grid's second stream beside the others.  Async on the grid's stream, which sees the
+ * whole step as one ordered unit. */
 ctu_status ctu_step(ctu_grid* g, double dt);
 
 /* nsteps CTU steps with the time step computed on the device from the state each step
