@@ -21,25 +21,15 @@ __global__ void k_set_end(DevScalars* s, double t_end, long long steps_left) {
 // Device-side time step of every grid: C0 * (min CFL bound), clipped to t_end - t; a grid
 // whose step budget is used up, or whose state was flagged non-physical, takes dt = 0 (its
 // passes become no-ops).
-__global__ void k_begin_step(const GridDesc* __restrict__ grids, int ngrids) {
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ngrids; g += gridDim.x * blockDim.x) {
-    DevScalars* s = grids[g].s;
-    const double bound = __longlong_as_double((long long)s->dt_next_bits);
-    double dt = fmin(grids[g].P.cfl * bound, s->t_end - s->t);
-    if (s->steps_left <= 0 || (s->flags & 3u)) dt = 0.0;  // budget used up, or non-physical
-    s->dt = dt;
-  }
-}
-
-__global__ void k_end_step(const GridDesc* __restrict__ grids, int ngrids) {
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ngrids; g += gridDim.x * blockDim.x) {
-    DevScalars* s = grids[g].s;
-    if (s->dt > 0.0) {
-      s->t += s->dt;
-      s->steps += 1;
-      s->steps_left -= 1;
-    }
-  }
+// Device-side time step of a grid (Sec. 3.5): dt = min(C0 x bound, t_end - t) from the CFL
+// bound of the current state, or 0 once the step budget is used or the state was flagged
+// non-physical (the grid then takes no-op steps).
+__device__ __forceinline__ double device_step_dt(const GridDesc& G) {
+  const DevScalars* s = G.s;
+  const double bound = __longlong_as_double((long long)s->dt_next_bits);
+  double dt = fmin(G.P.cfl * bound, s->t_end - s->t);
+  if (s->steps_left <= 0 || (s->flags & 3u)) dt = 0.0;
+  return dt;
 }
 
 // Copies of the scalars of n grids into one array (one read-back for a whole batch).
@@ -51,11 +41,21 @@ __global__ void k_gather_scalars(DevScalars* const* __restrict__ src, int n, Dev
 // ---- a1: ghost fill (Sec. 3.1) ------------------------------------------------------------
 // Axis AXIS ghosts over the full extent of the other two axes (ghosts included), so
 // running x, then y, then z fills edges and corners consistently.
+// The x pass is the first of a step: with begin != 0 it also takes the device-side time step.
+// Every block computes it from the grid's scalars and the grid's first block stores it for the
+// passes after this one (nothing in this launch reads it back).
 template <typename T, int AXIS>
-__global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab) {
+__global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab, int begin) {
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
-  if (!(r.G->s->dt > 0.0)) return;
+  double dt;
+  if (AXIS == 0 && begin) {
+    dt = device_step_dt(*r.G);
+    if (r.lb == 0 && threadIdx.x == 0) r.G->s->dt = dt;
+  } else {
+    dt = r.G->s->dt;
+  }
+  if (!(dt > 0.0)) return;
   GLOBAL T* __restrict__ u = (GLOBAL T*)r.G->u;
   const int n = P.n[AXIS];
   const int ng = P.ng;  // ghost layers of this grid
@@ -282,7 +282,10 @@ __global__ __launch_bounds__(256) void k_dt(LaunchTab tab) {
 }
 
 // Minimum of each grid's block partials into its dt_next_bits: block g reduces grid g.
-__global__ __launch_bounds__(1024) void k_dt_final(const GridDesc* __restrict__ grids) {
+// end_step != 0 (the last pass of a step): also account the step taken, t += dt, one step more
+// and one less in the budget, unless it was a no-op step.
+__global__ __launch_bounds__(1024) void k_dt_final(const GridDesc* __restrict__ grids,
+                                                   int end_step) {
   const GridDesc& G = grids[blockIdx.x];
   const long long nblocks = update_blocks(G.P);
   const GLOBAL double* __restrict__ part = (const GLOBAL double*)G.part;
@@ -296,8 +299,15 @@ __global__ __launch_bounds__(1024) void k_dt_final(const GridDesc* __restrict__ 
   if (wave == 0) {
     double v = lane < (int)(blockDim.x >> 6) ? smin[lane] : INFINITY;
     v = wave_min(v);
-    if (lane == 0)
-      G.s->dt_next_bits = (unsigned long long)__double_as_longlong(v);
+    if (lane == 0) {
+      DevScalars* s = G.s;
+      if (end_step && s->dt > 0.0) {
+        s->t += s->dt;
+        s->steps += 1;
+        s->steps_left -= 1;
+      }
+      s->dt_next_bits = (unsigned long long)__double_as_longlong(v);
+    }
   }
 }
 
@@ -528,15 +538,13 @@ static hipError_t enqueue_step(const PlanView& v, bool device_dt, hipStream_t st
   auto tab = [&](int pass) { return LaunchTab{v.d_grids, v.d_start + pass * stride, v.ngrids}; };
   auto nblocks = [&](int pass) { return dim3((unsigned)v.h_start[pass * stride + v.ngrids]); };
   const dim3 B(kBlock);
-  const dim3 gsmall((unsigned)cdiv(v.ngrids, kBlock));
-  if (device_dt) hipLaunchKernelGGL(k_begin_step, gsmall, B, 0, stream, v.d_grids, v.ngrids);
-  // a1: ghost fill x, then y, then z
-  CTU_TIMED(K_BC_X,
-            hipLaunchKernelGGL((k_bc_fill<T, 0>), nblocks(P_BC_X), B, 0, stream, tab(P_BC_X)));
-  CTU_TIMED(K_BC_Y,
-            hipLaunchKernelGGL((k_bc_fill<T, 1>), nblocks(P_BC_Y), B, 0, stream, tab(P_BC_Y)));
-  CTU_TIMED(K_BC_Z,
-            hipLaunchKernelGGL((k_bc_fill<T, 2>), nblocks(P_BC_Z), B, 0, stream, tab(P_BC_Z)));
+  // a1: ghost fill x (which takes the device-side time step when asked), then y, then z
+  CTU_TIMED(K_BC_X, hipLaunchKernelGGL((k_bc_fill<T, 0>), nblocks(P_BC_X), B, 0, stream,
+                                       tab(P_BC_X), device_dt ? 1 : 0));
+  CTU_TIMED(K_BC_Y, hipLaunchKernelGGL((k_bc_fill<T, 1>), nblocks(P_BC_Y), B, 0, stream,
+                                       tab(P_BC_Y), 0));
+  CTU_TIMED(K_BC_Z, hipLaunchKernelGGL((k_bc_fill<T, 2>), nblocks(P_BC_Z), B, 0, stream,
+                                       tab(P_BC_Z), 0));
   // (in the overlapped schedule the first-stage sweeps launch the PPMP coefficient passes,
   // each beside other work)
   if (v.recon == 1 && !overlapped(v, prof)) {
@@ -549,10 +557,9 @@ static hipError_t enqueue_step(const PlanView& v, bool device_dt, hipStream_t st
   hipError_t e = sweeps<T>(v, 1, stream, prof);
   if (e == hipSuccess) e = sweeps<T>(v, 2, stream, prof);
   if (e != hipSuccess) return e;
-  // a9: minimum of the CFL partials that the fused update wrote
+  // a9: minimum of the CFL partials that the fused update wrote, and the step's accounting
   CTU_TIMED(K_DT_FINAL,
-            hipLaunchKernelGGL(k_dt_final, dim3(v.ngrids), dim3(1024), 0, stream, v.d_grids));
-  hipLaunchKernelGGL(k_end_step, gsmall, B, 0, stream, v.d_grids, v.ngrids);
+            hipLaunchKernelGGL(k_dt_final, dim3(v.ngrids), dim3(1024), 0, stream, v.d_grids, 1));
   return hipGetLastError();
 }
 
@@ -567,7 +574,7 @@ static void enqueue_dt(const PlanView& v, hipStream_t stream) {
   const LaunchTab tab{v.d_grids, v.d_start + P_DT * stride, v.ngrids};
   hipLaunchKernelGGL(k_dt<T>, dim3((unsigned)v.h_start[P_DT * stride + v.ngrids]), dim3(kBlock), 0,
                      stream, tab);
-  hipLaunchKernelGGL(k_dt_final, dim3(v.ngrids), dim3(1024), 0, stream, v.d_grids);
+  hipLaunchKernelGGL(k_dt_final, dim3(v.ngrids), dim3(1024), 0, stream, v.d_grids, 0);
 }
 
 hipError_t launch_dt(const PlanView& v, hipStream_t stream) {

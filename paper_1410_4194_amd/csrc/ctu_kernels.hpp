@@ -185,7 +185,7 @@ CTU_DECLARE_SWEEPS(float, kRoeH, 1)
   } while (0)
 
 // One step for every grid of the plan.  device_dt: take dt from each grid's CFL bound and
-// end time (k_begin_step); otherwise each grid's dt was set beforehand.
+// end time (taken by the first ghost-fill pass); otherwise each grid's dt was set beforehand.
 hipError_t launch_step(const PlanView& v, bool device_dt, hipStream_t stream, Profiler* prof);
 // CFL bound of the current state of every grid of the plan (into dt_next_bits).
 hipError_t launch_dt(const PlanView& v, hipStream_t stream);
