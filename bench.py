@@ -104,10 +104,8 @@ def _design_values(cls, n, ng=3):
         e[d[cls[-1]]] += 1
         u = e[0] * e[1] * e[2]
         return u, DESIGN_VALUES_PER_UNIT["sweep2"] * u
-    if cls.startswith("bc_fill"):
-        N = [nx + 2 * ng, ny + 2 * ng, nz + 2 * ng]
-        N[d[cls[-1]]] = 2 * ng
-        u = N[0] * N[1] * N[2]
+    if cls == "bc_fill":  # every ghost cell of the allocated box
+        u = (nx + 2 * ng) * (ny + 2 * ng) * (nz + 2 * ng) - nx * ny * nz
         return u, DESIGN_VALUES_PER_UNIT["bc"] * u
     return None
 
@@ -457,8 +455,7 @@ def cpu_baseline(wl, seconds_target=12.0, serial_seconds=5.0, methods=(), method
 # rocprofv3 kernel names of the primary step's kernels -> the library's kernel classes
 # (PPMC + exact solver for gamma 5/3: solver class 3, reconstruction 0).
 _CLASS_PATTERNS = [
-    (r"k_bc_fill<(double|float), 0>", "bc_fill_x"), (r"k_bc_fill<(double|float), 1>", "bc_fill_y"),
-    (r"k_bc_fill<(double|float), 2>", "bc_fill_z"),
+    (r"k_bc_fill<(double|float)>", "bc_fill"),
     (r"k_sweep_x<(double|float), 1, false, 3, 0>", "sweep1_x"),
     (r"k_sweep_march<(double|float), 1, 1, false, 3, 0>", "sweep1_y"),
     (r"k_sweep_march<(double|float), 2, 1, false, 3, 0>", "sweep1_z"),

@@ -39,17 +39,35 @@ __global__ void k_gather_scalars(DevScalars* const* __restrict__ src, int n, Dev
 }
 
 // ---- a1: ghost fill (Sec. 3.1) ------------------------------------------------------------
-// Axis AXIS ghosts over the full extent of the other two axes (ghosts included), so
-// running x, then y, then z fills edges and corners consistently.
-// The x pass is the first of a step: with begin != 0 it also takes the device-side time step.
+// Source index along one axis of a cell index q of the allocated box (q itself for a real
+// cell): periodic one period away, outflow the edge cell, reflect the mirror image across the
+// wall (n >= ng is validated); *flip is set for a reflected ghost.
+__device__ __forceinline__ int ghost_source(int q, int n, int bc_lo, int bc_hi, bool* flip) {
+  if (q >= 0 && q < n) return q;
+  const int bc = q < 0 ? bc_lo : bc_hi;
+  if (bc == 0) {
+    int s = q % n;
+    return s < 0 ? s + n : s;
+  }
+  if (bc == 1) return q < 0 ? 0 : n - 1;
+  *flip = true;
+  return q < 0 ? -1 - q : 2 * n - 1 - q;
+}
+
+// Every ghost cell in one pass, copied from its source real cell with the momentum component
+// of every reflecting axis negated: the composition of the three one-axis fills (x over the
+// whole extent of y and z, then y, then z), which is what they leave in edges and corners, so
+// one pass gives the same values.  The ghost cells are taken as three disjoint slabs: x ghosts
+// over all (j, k); y ghosts over real i and all k; z ghosts over real i and j.
+// The pass is the first of a step: with begin != 0 it also takes the device-side time step.
 // Every block computes it from the grid's scalars and the grid's first block stores it for the
 // passes after this one (nothing in this launch reads it back).
-template <typename T, int AXIS>
+template <typename T>
 __global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab, int begin) {
   const BlockRef r = block_ref(tab);
   const GridParams P = r.G->P;
   double dt;
-  if (AXIS == 0 && begin) {
+  if (begin) {
     dt = device_step_dt(*r.G);
     if (r.lb == 0 && threadIdx.x == 0) r.G->s->dt = dt;
   } else {
@@ -57,53 +75,46 @@ __global__ __launch_bounds__(256) void k_bc_fill(LaunchTab tab, int begin) {
   }
   if (!(dt > 0.0)) return;
   GLOBAL T* __restrict__ u = (GLOBAL T*)r.G->u;
-  const int n = P.n[AXIS];
   const int ng = P.ng;  // ghost layers of this grid
   const long long tid = r.lb * blockDim.x + threadIdx.x;
-  int i, j, k, layer;
-  if (AXIS == 0) {
-    const long long total = 2LL * ng * P.N[1] * P.N[2];
-    if (tid >= total) return;
-    layer = (int)(tid % (2 * ng));
+  const long long sx = 2LL * ng * P.N[1] * P.N[2];
+  const long long sy = (long long)P.n[0] * 2 * ng * P.N[2];
+  const long long sz = (long long)P.n[0] * P.n[1] * 2 * ng;
+  int i, j, k;
+  if (tid < sx) {  // x ghosts, ghost layer fastest
+    const int layer = (int)(tid % (2 * ng));
     const long long q = tid / (2 * ng);
+    i = layer < ng ? layer - ng : P.n[0] + (layer - ng);
     j = (int)(q % P.N[1]) - ng;
     k = (int)(q / P.N[1]) - ng;
-    i = 0;
-  } else if (AXIS == 1) {
-    const long long total = 2LL * ng * P.N[0] * P.N[2];
-    if (tid >= total) return;
-    i = (int)(tid % P.N[0]) - ng;
-    const long long q = tid / P.N[0];
-    layer = (int)(q % (2 * ng));
+  } else if (tid < sx + sy) {  // y ghosts of real i, i fastest
+    const long long t = tid - sx;
+    i = (int)(t % P.n[0]);
+    const long long q = t / P.n[0];
+    const int layer = (int)(q % (2 * ng));
+    j = layer < ng ? layer - ng : P.n[1] + (layer - ng);
     k = (int)(q / (2 * ng)) - ng;
-    j = 0;
+  } else if (tid < sx + sy + sz) {  // z ghosts of real i and j, i fastest
+    const long long t = tid - sx - sy;
+    i = (int)(t % P.n[0]);
+    const long long q = t / P.n[0];
+    j = (int)(q % P.n[1]);
+    const int layer = (int)(q / P.n[1]);
+    k = layer < ng ? layer - ng : P.n[2] + (layer - ng);
   } else {
-    const long long total = 2LL * ng * P.N[0] * P.N[1];
-    if (tid >= total) return;
-    i = (int)(tid % P.N[0]) - ng;
-    const long long q = tid / P.N[0];
-    j = (int)(q % P.N[1]) - ng;
-    layer = (int)(q / P.N[1]);
-    k = 0;
+    return;
   }
-  const int q = layer < ng ? layer - ng : n + (layer - ng);
-  const int bc = layer < ng ? r.G->bc[2 * AXIS] : r.G->bc[2 * AXIS + 1];
-  int src;
-  if (bc == 0) {          // periodic: one period away
-    src = q % n;
-    if (src < 0) src += n;
-  } else if (bc == 1) {   // outflow: the edge cell
-    src = q < 0 ? 0 : n - 1;
-  } else {                // reflect: the mirror image across the wall (n >= ng is validated)
-    src = q < 0 ? -1 - q : 2 * n - 1 - q;
-  }
-  const long long d = cell_index(P, AXIS == 0 ? q : i, AXIS == 1 ? q : j, AXIS == 2 ? q : k);
-  const long long sidx =
-      cell_index(P, AXIS == 0 ? src : i, AXIS == 1 ? src : j, AXIS == 2 ? src : k);
+  bool fx = false, fy = false, fz = false;
+  const int si = ghost_source(i, P.n[0], r.G->bc[0], r.G->bc[1], &fx);
+  const int sj = ghost_source(j, P.n[1], r.G->bc[2], r.G->bc[3], &fy);
+  const int sk = ghost_source(k, P.n[2], r.G->bc[4], r.G->bc[5], &fz);
+  const long long d = cell_index(P, i, j, k);
+  const long long sidx = cell_index(P, si, sj, sk);
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
     const T v = u[f * P.stride + sidx];
-    u[f * P.stride + d] = (bc == 2 && f == 1 + AXIS) ? -v : v;
+    const bool neg = (f == 1 && fx) || (f == 2 && fy) || (f == 3 && fz);
+    u[f * P.stride + d] = neg ? -v : v;
   }
 }
 
@@ -398,7 +409,7 @@ __global__ void k_prim_to_cons(const double* __restrict__ packed, T* __restrict_
 // ---- per-kernel timing ----------------------------------------------------------------------
 const char* kernel_class_name(int k) {
   static const char* names[K_NUM_CLASSES] = {
-      "bc_fill_x", "bc_fill_y", "bc_fill_z", "ppmp_coef", "sweep1_x", "sweep1_y", "sweep1_z",
+      "bc_fill", "ppmp_coef", "sweep1_x", "sweep1_y", "sweep1_z",
       "hcorr_eta", "sweep2_y", "sweep2_z", "sweep2_x_update", "dt_final"};
   return (k >= 0 && k < K_NUM_CLASSES) ? names[k] : "";
 }
@@ -466,9 +477,7 @@ long long pass_blocks(const GridParams& P, int pass) {
   const long long n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const long long N0 = P.N[0], N1 = P.N[1], N2 = P.N[2];
   switch (pass) {
-    case P_BC_X: return cdiv(2LL * P.ng * N1 * N2, kBlock);
-    case P_BC_Y: return cdiv(2LL * P.ng * N0 * N2, kBlock);
-    case P_BC_Z: return cdiv(2LL * P.ng * N0 * N1, kBlock);
+    case P_BC: return cdiv(2LL * P.ng * (N1 * N2 + n0 * N2 + n0 * n1), kBlock);
     case P_COEF_X: {
       const long long e = 2 + 2 * P.ext;  // cells [-1 - ext, n + ext] per axis
       return P.recon == 1 ? cdiv(cdiv((n1 + e) * N0, XW) * (n2 + e), kBlock / 64) : 0;
@@ -538,13 +547,9 @@ static hipError_t enqueue_step(const PlanView& v, bool device_dt, hipStream_t st
   auto tab = [&](int pass) { return LaunchTab{v.d_grids, v.d_start + pass * stride, v.ngrids}; };
   auto nblocks = [&](int pass) { return dim3((unsigned)v.h_start[pass * stride + v.ngrids]); };
   const dim3 B(kBlock);
-  // a1: ghost fill x (which takes the device-side time step when asked), then y, then z
-  CTU_TIMED(K_BC_X, hipLaunchKernelGGL((k_bc_fill<T, 0>), nblocks(P_BC_X), B, 0, stream,
-                                       tab(P_BC_X), device_dt ? 1 : 0));
-  CTU_TIMED(K_BC_Y, hipLaunchKernelGGL((k_bc_fill<T, 1>), nblocks(P_BC_Y), B, 0, stream,
-                                       tab(P_BC_Y), 0));
-  CTU_TIMED(K_BC_Z, hipLaunchKernelGGL((k_bc_fill<T, 2>), nblocks(P_BC_Z), B, 0, stream,
-                                       tab(P_BC_Z), 0));
+  // a1: ghost fill (which takes the device-side time step when asked)
+  CTU_TIMED(K_BC, hipLaunchKernelGGL((k_bc_fill<T>), nblocks(P_BC), B, 0, stream, tab(P_BC),
+                                     device_dt ? 1 : 0));
   // (in the overlapped schedule the first-stage sweeps launch the PPMP coefficient passes,
   // each beside other work)
   if (v.recon == 1 && !overlapped(v, prof)) {

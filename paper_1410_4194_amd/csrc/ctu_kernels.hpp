@@ -16,7 +16,7 @@ namespace ctu {
 
 // Passes of one step, in launch order, plus the stand-alone CFL reduction.
 enum Pass {
-  P_BC_X, P_BC_Y, P_BC_Z, P_COEF_X, P_COEF_Y, P_COEF_Z, P_S1_X, P_S1_Y, P_S1_Z, P_ETA_X,
+  P_BC, P_COEF_X, P_COEF_Y, P_COEF_Z, P_S1_X, P_S1_Y, P_S1_Z, P_ETA_X,
   P_ETA_Z, P_S2_Y, P_S2_Z, P_S2_X, P_DT, P_NUM
 };
 
@@ -87,7 +87,7 @@ long long pass_blocks(const GridParams& P, int pass);
 
 // Per-kernel timing with HIP events recorded on the launch stream, accumulated per class.
 enum KernelClass {
-  K_BC_X, K_BC_Y, K_BC_Z, K_PPMP_COEF, K_SWEEP1_X, K_SWEEP1_Y, K_SWEEP1_Z, K_HCORR_ETA,
+  K_BC, K_PPMP_COEF, K_SWEEP1_X, K_SWEEP1_Y, K_SWEEP1_Z, K_HCORR_ETA,
   K_SWEEP2_Y, K_SWEEP2_Z, K_SWEEP2_X_UPDATE, K_DT_FINAL, K_NUM_CLASSES
 };
 const char* kernel_class_name(int k);
