@@ -145,7 +145,8 @@ def run_gpu(wl, prec, steps, warmup, ctu, torch, repeats=5, keep_state=False,
     out = {"seconds": _median(secs), "runs_s": secs, "profile": prof,
            "profiled_seconds": prof_s, "status": status, "flags": flags,
            "counters": counters, "t": info.t, "steps_done": info.steps,
-           "schedule": {1: "in order", 2: "overlapped"}.get(info.schedule, info.schedule)}
+           "schedule": {1: "in order", 2: "overlapped", 3: "fused z"}.get(info.schedule,
+                                                                          info.schedule)}
     if keep_state:
         out["state"] = g.get_state()
     if newton_hist:

@@ -74,9 +74,18 @@ typedef enum { CTU_RIEMANN_EXACT = 0, CTU_RIEMANN_ROE = 1 } ctu_riemann;
  * primitive variables with contact steepening, shock flattening and CW84 tracing
  * (App. A.4); its three-cell stencil needs four ghost layers. */
 typedef enum { CTU_RECON_PPMC = 0, CTU_RECON_PPMP = 1 } ctu_recon;
-typedef enum { CTU_SCHEDULE_AUTO = 0, CTU_SCHEDULE_IN_ORDER = 1, CTU_SCHEDULE_OVERLAP = 2 } ctu_schedule;
-/* CTU_SCHEDULE_AUTO overlaps the sweeps of grids whose field arrays take at most this many
- * bytes each (elem_bytes x field_stride of ctu_grid_info) */
+typedef enum {
+  CTU_SCHEDULE_AUTO = 0,
+  CTU_SCHEDULE_IN_ORDER = 1,
+  CTU_SCHEDULE_OVERLAP = 2,
+  CTU_SCHEDULE_FUSED_Z = 3
+} ctu_schedule;
+/* CTU_SCHEDULE_AUTO overlaps the sweeps of grids of at most this many real cells and fuses
+ * the z sweeps above (measured crossover on MI355X: between 256^3 and 288^3 in both
+ * precisions) */
+#define CTU_OVERLAP_MAX_CELLS ((int64_t)20 << 20)
+/* with the H correction (no fused z) CTU_SCHEDULE_AUTO overlaps while each field array takes
+ * at most this many bytes (elem_bytes x field_stride of ctu_grid_info), in order above */
 #define CTU_OVERLAP_MAX_FIELD_BYTES ((size_t)192 << 20)
 
 /* Device error-word bits reported by ctu_check. */
@@ -129,15 +138,22 @@ typedef struct {
                               grid's own (created with the grid, default priority), beside
                               the other sweeps, ordered with events, and the PPMP
                               coefficient passes beside the first-stage sweeps; the
-                              caller's stream still sees each step as one ordered unit.  CTU_SCHEDULE_IN_ORDER runs
-                              every pass in order on the grid's stream.  CTU_SCHEDULE_AUTO
-                              (0) overlaps while one field array of the grid takes at most
-                              CTU_OVERLAP_MAX_FIELD_BYTES, in order above (measured on
-                              MI355X: the overlap gains 3-4% at 256^3 and 10-20% on small
-                              grids, and loses up to 8% once the concurrent sweeps' streams
-                              no longer fit the GPU's last-level cache).  Results are
-                              bitwise the same.  ctu_step_noalloc always runs in order;
-                              batches overlap on a stream of their own. */
+                              caller's stream still sees each step as one ordered unit.
+                              CTU_SCHEDULE_FUSED_Z runs the first-stage y sweep on that
+                              stream beside the x sweep and then both z stages in one march
+                              (with the H correction: as OVERLAP).  CTU_SCHEDULE_IN_ORDER
+                              runs every pass in order on the grid's stream.
+                              CTU_SCHEDULE_AUTO (0) overlaps grids of at most
+                              CTU_OVERLAP_MAX_CELLS real cells and fuses the z sweeps above;
+                              with the H correction it overlaps while one field array takes
+                              at most CTU_OVERLAP_MAX_FIELD_BYTES and runs in order above
+                              (measured on MI355X: the overlap gains 3-4% at 256^3 and
+                              10-25% on small grids, fused z 1.4-4% on 288^3-512^3 grids
+                              where overlapped sweeps no longer fit the last-level cache).
+                              In order and overlapped give bitwise the same results; fused z
+                              agrees with them to rounding (a separately compiled copy of the
+                              same formulas).  ctu_step_noalloc always runs in order; batches
+                              overlap on a stream of their own. */
 } ctu_config;
 
 typedef struct ctu_grid ctu_grid;
@@ -150,7 +166,8 @@ typedef struct {
   double t;              /* simulation time accumulated by step/advance (syncs) */
   int64_t steps;         /* steps taken (syncs) */
   int32_t ghost;         /* g, ghost layers per side */
-  int32_t schedule;      /* the schedule steps use: CTU_SCHEDULE_IN_ORDER or _OVERLAP */
+  int32_t schedule;      /* the schedule steps use: CTU_SCHEDULE_IN_ORDER, _OVERLAP or
+                            _FUSED_Z */
 } ctu_grid_info;
 
 /* Fill *cfg with the defaults: cfl 0.3, newton_tol 1e-6, newton_max_iter 50,

@@ -126,6 +126,7 @@ struct PlanView {
   // of the sweeps (enqueue_sweeps); null side: every pass in order on the launch stream.
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr, ydone = nullptr;
+  bool fused_z = false;  // with the side stream: both z stages in one march (k_sweep_z_both)
 };
 
 // Solver class of a grid: kRoe for the Roe solver; for the exact solver its gas class, K
@@ -141,6 +142,11 @@ inline int gas_class(const GridParams& P) {
 // and its events are there and kernels are not being timed one by one.
 inline bool overlapped(const PlanView& v, const Profiler* prof) {
   return v.side && v.fork && v.xdone && v.join && v.ydone && !(prof && prof->timing);
+}
+
+// The fused-z variant of that schedule (never with the H correction).
+inline bool fused_z(const PlanView& v, const Profiler* prof) {
+  return v.fused_z && v.gclass != kRoeH && overlapped(v, prof);
 }
 
 // PPMP coefficients along axis D for every grid of the plan (ctu_kernels.hip).

@@ -108,7 +108,7 @@ ctu_status validate(const ctu_config* c) {
       return fail(CTU_EINVAL, "march_seg must lie in [0, 4096]");
   if (c->x_rows < 0 || c->x_rows > 8) return fail(CTU_EINVAL, "x_rows must lie in [0, 8]");
   if (c->x_chunks < 0 || c->x_chunks > 16) return fail(CTU_EINVAL, "x_chunks must lie in [0, 16]");
-  if (c->schedule < CTU_SCHEDULE_AUTO || c->schedule > CTU_SCHEDULE_OVERLAP)
+  if (c->schedule < CTU_SCHEDULE_AUTO || c->schedule > CTU_SCHEDULE_FUSED_Z)
     return fail(CTU_EINVAL, "unknown schedule");
   for (int a = 0; a < 3; ++a) {
     int lo = c->bc[2 * a], hi = c->bc[2 * a + 1];
@@ -225,6 +225,7 @@ struct ctu_grid {
   // the side stream and events of the overlapped sweep schedule (null when serial)
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, xdone = nullptr, join = nullptr, ydone = nullptr;
+  int schedule = CTU_SCHEDULE_IN_ORDER;  // the schedule steps use
   ~ctu_grid() {
     if (side) {
       (void)hipStreamSynchronize(side);
@@ -245,7 +246,8 @@ struct ctu_grid {
   int* d_start() const { return reinterpret_cast<int*>(d_work + kStartOffset); }
   ctu::PlanView plan() const {
     return ctu::PlanView{d_desc(), d_start(), 1, h_start.data(), cfg.prec == CTU_FP32 ? 1 : 0,
-                         ctu::gas_class(P), P.recon, side, fork, xdone, join, ydone};
+                         ctu::gas_class(P), P.recon, side, fork, xdone, join, ydone,
+                         schedule == CTU_SCHEDULE_FUSED_Z};
   }
 };
 
@@ -354,10 +356,24 @@ ctu_status ctu_grid_create(const ctu_config* cfg, void* d_state, void* d_work, s
     return fail(CTU_EINVAL, "grid too large for one launch per pass");
   }
   hipError_t e = hipSuccess;
-  const bool overlap =
-      cfg->schedule == CTU_SCHEDULE_OVERLAP ||
-      (cfg->schedule == CTU_SCHEDULE_AUTO && g->fbytes() <= CTU_OVERLAP_MAX_FIELD_BYTES);
-  if (overlap) {
+  // the schedule (fused z has no H correction variant: its eta pass along z needs the second-
+  // stage states of the ring columns, so such grids take the overlapped schedule)
+  const bool hcorr = ctu::gas_class(g->P) == ctu::kRoeH;
+  const long long cells = (long long)cfg->nx * cfg->ny * cfg->nz;
+  switch (cfg->schedule) {
+    case CTU_SCHEDULE_IN_ORDER: g->schedule = CTU_SCHEDULE_IN_ORDER; break;
+    case CTU_SCHEDULE_OVERLAP: g->schedule = CTU_SCHEDULE_OVERLAP; break;
+    case CTU_SCHEDULE_FUSED_Z:
+      g->schedule = hcorr ? CTU_SCHEDULE_OVERLAP : CTU_SCHEDULE_FUSED_Z;
+      break;
+    default:
+      if (hcorr)
+        g->schedule = g->fbytes() <= CTU_OVERLAP_MAX_FIELD_BYTES ? CTU_SCHEDULE_OVERLAP
+                                                                  : CTU_SCHEDULE_IN_ORDER;
+      else
+        g->schedule = cells <= CTU_OVERLAP_MAX_CELLS ? CTU_SCHEDULE_OVERLAP : CTU_SCHEDULE_FUSED_Z;
+  }
+  if (g->schedule != CTU_SCHEDULE_IN_ORDER) {
     // default priority, like every stream of the library
     e = hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking);
     // the events only order the grid's two streams on one GPU: a device-scope release is
@@ -471,7 +487,7 @@ ctu_status ctu_grid_info_get(ctu_grid* g, ctu_grid_info* info) {
   info->t = s.t;
   info->steps = s.steps;
   info->ghost = g->P.ng;
-  info->schedule = g->side ? CTU_SCHEDULE_OVERLAP : CTU_SCHEDULE_IN_ORDER;
+  info->schedule = g->schedule;
   return CTU_OK;
 }
 

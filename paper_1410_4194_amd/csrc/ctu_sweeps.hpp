@@ -664,9 +664,163 @@ __global__ __launch_bounds__(256) void k_sweep_x_update(LaunchTab tab) {
   block_min_store(bound, (GLOBAL double*)r.G->part, r.lb);
 }
 
+// First- and second-stage z sweeps in one march (the fused-z schedule; not with the H
+// correction, whose eta pass along z needs the second-stage states of the ring columns).  The
+// second-stage z sweep needs only the x and y first-stage differences, so once those are done
+// both z stages can share one march: the column's primitives, slopes and traces are computed
+// once per cell, and each face is solved twice, from the traced primitive states (stage 1,
+// H*) and from the same states in conserved form plus the transverse correction (stage 2,
+// H^{n+1/2}).  u^n is read once for both.  Stage 1 covers the extended transverse range
+// [-1, n] (its differences feed the y and x corrections there), stage 2 the real columns.
+// Same block layout and segments as the first-stage z sweep.
+template <typename T, bool HIST, int K, int R>
+__global__ __launch_bounds__(256, 2) void k_sweep_z_both(LaunchTab tab) {
+  constexpr int D = 2;
+  const BlockRef r = block_ref(tab);
+  const GridParams P = r.G->P;
+  DevScalars* __restrict__ s = r.G->s;
+  const double dt = s->dt;
+  if (!(dt > 0.0)) return;
+  const GLOBAL T* __restrict__ u = (const GLOBAL T*)r.G->u;
+  const GLOBAL T* __restrict__ dstar_all = (const GLOBAL T*)r.G->flux;
+  const long long fds = 5 * P.stride;
+  GLOBAL T* __restrict__ out1 = (GLOBAL T*)r.G->flux + D * fds;
+  GLOBAL T* __restrict__ out2 = (GLOBAL T*)r.G->flux + (3 + D) * fds;
+  const int ea = P.n[0] + 2;
+  const int eb = P.n[1] + 2;
+  const int nd = P.n[D];
+  const long long nbx = ((long long)ea * eb + kBlock - 1) / kBlock;
+  const int seg = P.seg[D];
+  const long long nseg = (nd + seg - 1) / seg;
+  if (r.lb >= nbx * nseg) return;
+  const long long tid = (r.lb % nbx) * kBlock + threadIdx.x;
+  if (tid >= (long long)ea * eb) return;
+  const int i = (int)(tid % ea) - 1;
+  const int o = (int)(tid / ea) - 1;
+  const int f0 = (int)(r.lb / nbx) * seg;
+  const int f1 = min(f0 + seg, nd);
+  const bool real = i >= 0 && i < P.n[0] && o >= 0 && o < P.n[1];
+  const long long sd = (long long)P.N[0] * P.N[1];
+  const long long c0 = cell_index(P, i, o, 0);
+  const T dtodx = T(dt / P.dx[D]);
+  const T igm1 = T(P.inv_gm1);
+  const T h1 = T(0.5 * dt / P.dx[0]);
+  const T h2 = T(0.5 * dt / P.dx[1]);
+
+  Prim<T> q0, q1, q2, q3;
+  T s0[5], s1[5], s2[5];
+  {
+    Prim<T> qm;
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 - 3) * sd, P, qm);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 - 2) * sd, P, q0);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 - 1) * sd, P, q1);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0)*sd, P, q2);
+    load_prim<T, D>(u, P.stride, c0 + (long long)(f0 + 1) * sd, P, q3);
+    slope_sel<R>(qm, q0, q1, s0);
+    slope_sel<R>(q0, q1, q2, s1);
+    slope_sel<R>(q1, q2, q3, s2);
+  }
+  T prevR1[5], prevR2[5];  // right-face state of the previous cell: primitive / conserved
+  {
+    T WL[5], WR[5];
+    trace_sel<R>(q0, q1, q2, s0, s1, s2,
+                 load_coef<R, D, T>(r.G, P.stride, c0 + (long long)(f0 - 1) * sd),
+                 T(P.gamma), dtodx, WL, WR);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) prevR1[q] = WR[q];
+    to_cons(WR, igm1, prevR2);
+    if (real) {
+      T dT[5];
+      transverse_delta<T, D>(dstar_all, fds, P.stride, c0 + (long long)(f0 - 1) * sd, h1, h2, dT);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) prevR2[q] += dT[q];
+    }
+  }
+  q0 = q1;
+  q1 = q2;
+  q2 = q3;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    s0[q] = s1[q];
+    s1[q] = s2[q];
+  }
+  T raw[5];
+#pragma unroll
+  for (int sl = 0; sl < 5; ++sl) raw[sl] = u[rot<D>(sl) * P.stride + c0 + (long long)(f0 + 2) * sd];
+  RiemannCounts cnt{0u, 0u, 0};
+  NewtonHist hist{};
+  __shared__ T prevF1[5][kBlock];
+  __shared__ T prevF2[5][kBlock];
+  for (int c = f0; c <= f1; ++c) {
+    make_prim(raw, T(P.gamma), T(P.gm1), T(P.p_floor), q3);
+    if (c + 1 <= f1) {
+      const long long nid = c0 + (long long)(c + 3) * sd;
+#pragma unroll
+      for (int sl = 0; sl < 5; ++sl) raw[sl] = u[rot<D>(sl) * P.stride + nid];
+    }
+    slope_sel<R>(q1, q2, q3, s2);
+    T WL[5], WR[5], F1[5], F2[5];
+    trace_sel<R>(q0, q1, q2, s0, s1, s2, load_coef<R, D, T>(r.G, P.stride, c0 + (long long)c * sd),
+                 T(P.gamma), dtodx, WL, WR);
+    const bool dupface = c == f1 && f1 < nd;
+    RiemannCounts dup{0u, 0u, 0};
+    face_flux_w<T, K>(prevR1, WL, P, F1, dupface ? dup : cnt);
+    if (HIST) hist.add(dupface ? dup.iters : cnt.iters, !dupface);
+    T UL[5], UR[5];
+    to_cons(WL, igm1, UL);
+    to_cons(WR, igm1, UR);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) F2[q] = T(0);
+    int it2 = -1;
+    if (real) {
+      T dT[5];
+      transverse_delta<T, D>(dstar_all, fds, P.stride, c0 + (long long)c * sd, h1, h2, dT);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        UL[q] += dT[q];
+        UR[q] += dT[q];
+      }
+      RiemannCounts dup2{0u, 0u, 0};
+      face_flux_u<T, K>(prevR2, UL, P, F2, dupface ? dup2 : cnt, T(0));
+      it2 = dupface ? dup2.iters : cnt.iters;
+    }
+    if (HIST) hist.add(it2 < 0 ? 0 : it2, real && !dupface);
+    asm volatile("" ::: "memory");
+    if (c > f0) {
+      const long long co = c0 + (long long)(c - 1) * sd;
+#pragma unroll
+      for (int sl = 0; sl < 5; ++sl) out1[rot<D>(sl) * P.stride + co] = prevF1[sl][threadIdx.x] - F1[sl];
+      if (real) {
+#pragma unroll
+        for (int sl = 0; sl < 5; ++sl)
+          out2[rot<D>(sl) * P.stride + co] = prevF2[sl][threadIdx.x] - F2[sl];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      prevF1[q][threadIdx.x] = F1[q];
+      prevF2[q][threadIdx.x] = F2[q];
+      prevR1[q] = WR[q];
+      prevR2[q] = UR[q];
+      s0[q] = s1[q];
+      s1[q] = s2[q];
+    }
+    q0 = q1;
+    q1 = q2;
+    q2 = q3;
+  }
+  flush_counts(cnt, s);
+  if (HIST) hist.flush(s);
+}
+
 // The three sweeps of one stage for every grid of a plan (one launch per direction).
 // With a side stream in the plan the passes overlap where the data allow it (x1 = first-stage
-// x sweep, y2 = second-stage y sweep, ...; PPMP coefficient passes in parentheses):
+// x sweep, y2 = second-stage y sweep, z12 = both z stages in one march, ...; PPMP coefficient
+// passes in parentheses).  Fused z (large grids, where two concurrent memory-bound sweeps no
+// longer fit the last-level cache):
+//   launch stream: [fork] (coef x) x1 (coef z) [y done] z12 y2 update
+//   side stream:   [fork] (coef y) y1 [y done]
+// Overlapped:
 //   launch stream: [fork] (coef x) x1 (coef z) [x done] z1 [y done] y2 [side done] update
 //   side stream:   [fork] (coef y) y1 [y done] [x done] z2 [side done]
 // The first-stage y sweep needs only u^n and its own coefficients, so it runs beside the x
@@ -688,6 +842,7 @@ hipError_t enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Prof
   auto nblocks = [&](int pass) { return dim3((unsigned)v.h_start[pass * stride + v.ngrids]); };
   const dim3 B(kBlock);
   const bool overlap = overlapped(v, prof);
+  const bool fz = fused_z(v, prof);
   hipError_t e = hipSuccess;
   if (stage == 1) {
     // a2-a5: F*, G*, H* on the extended transverse range
@@ -704,6 +859,15 @@ hipError_t enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Prof
       hipLaunchKernelGGL((k_sweep_x<T, 1, HIST, K, R>), nblocks(P_S1_X), B, 0, stream,
                          tab(P_S1_X));
       if constexpr (R == 1) launch_ppmp_coef<T, 2>(v, stream);
+      if constexpr (K != kRoeH) {
+        if (fz) {  // both z stages, once the side's y differences are done
+          e = hipStreamWaitEvent(stream, v.ydone, 0);
+          if (e != hipSuccess) return e;
+          hipLaunchKernelGGL((k_sweep_z_both<T, HIST, K, R>), nblocks(P_S1_Z), B, 0, stream,
+                             tab(P_S1_Z));
+          return hipGetLastError();
+        }
+      }
       e = hipEventRecord(v.xdone, stream);
       if (e == hipSuccess) e = hipStreamWaitEvent(v.side, v.xdone, 0);
       if (e != hipSuccess) return e;
@@ -749,7 +913,9 @@ hipError_t enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Prof
     // update (a8) and the CFL bound of the new state (a9)
     CTU_TIMED(K_SWEEP2_Y, hipLaunchKernelGGL((k_sweep_march<T, 1, 2, HIST, K, R>), nblocks(P_S2_Y),
                                              B, 0, stream, tab(P_S2_Y)));
-    if (overlap && K != kRoeH) {  // the second-stage z sweep ran on the side stream
+    if (fz) {
+      // the second-stage z differences came from the fused z march
+    } else if (overlap && K != kRoeH) {  // the second-stage z sweep ran on the side stream
       e = hipStreamWaitEvent(stream, v.join, 0);
       if (e != hipSuccess) return e;
     } else {

@@ -26,7 +26,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENONPHYS, ENOCONV, EAGAIN = 0, -1, -2, -3, -4, -5, 
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
 RIEMANN_EXACT, RIEMANN_ROE = 0, 1
 RECON_PPMC, RECON_PPMP = 0, 1
-SCHEDULE_AUTO, SCHEDULE_IN_ORDER, SCHEDULE_OVERLAP = 0, 1, 2
+SCHEDULE_AUTO, SCHEDULE_IN_ORDER, SCHEDULE_OVERLAP, SCHEDULE_FUSED_Z = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 FLAG_NONFINITE, FLAG_DENSITY, FLAG_PFLOOR, FLAG_NEWTON_CAP = 1, 2, 4, 8
 TICKET_QUEUED, TICKET_RUNNING, TICKET_DONE, TICKET_FAILED, TICKET_UNKNOWN = 0, 1, 2, 3, -1
@@ -137,8 +137,10 @@ def make_config(nx, ny, nz, dx, dy, dz, gamma, bc=(BC_PERIODIC,) * 6, prec=FP64,
     default; batch=True takes the shapes tuned for grids advanced in a batch (where the GPU
     is full, unlike a small grid alone), when the table has them.  schedule: SCHEDULE_AUTO
     (the library's choice by size), SCHEDULE_IN_ORDER (every pass in order on the grid's
-    stream) or SCHEDULE_OVERLAP (the first-stage y and second-stage z sweeps on a stream of
-    the grid's own beside the others); results are bitwise the same."""
+    stream), SCHEDULE_OVERLAP (the first-stage y and second-stage z sweeps on a stream of the
+    grid's own beside the others) or SCHEDULE_FUSED_Z (the first-stage y sweep beside the x
+    sweep, then both z stages in one march); the first three give bitwise the same results,
+    fused z the same up to rounding."""
     c = Config()
     lib.ctu_config_default(C.byref(c))
     c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)

@@ -57,7 +57,7 @@ def test_workspace_bytes_and_validation(ctu):
         dict(newton_max_iter=0), dict(newton_tol=0.0), dict(p_floor=0.0),
         dict(march_seg=(-1, 0)), dict(march_seg=(0, 5000)),
         dict(x_rows=-1), dict(x_rows=9), dict(x_chunks=-1), dict(x_chunks=17),
-        dict(schedule=-1), dict(schedule=3),
+        dict(schedule=-1), dict(schedule=4),
     ]
     for b in bad:
         args = dict(nx=8, ny=8, nz=8, dx=1.0, dy=1.0, dz=1.0, gamma=1.4)

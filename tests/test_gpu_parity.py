@@ -343,12 +343,14 @@ def test_x_tile_shapes_are_bitwise_invariant(ctu, prec):
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
 def test_overlapped_passes_are_bitwise_serial(ctu, prec):
     """The overlapped schedule (the first-stage y and second-stage z sweeps on the grid's
-    side stream) changes only when a pass runs, never what it reads or writes: after three
-    device-dt steps and two host-dt steps the state is bitwise that of every pass in order on
-    one stream, for the exact solver (integer and general gamma), the Roe solver, PPMP and
-    the H correction (whose eta pass along z moves to the side stream), and with per-kernel
-    timing on (which runs the passes in order).  The library's choice overlaps these small
-    grids."""
+    side stream) changes only when a pass runs, never its arithmetic: after three device-dt
+    steps and two host-dt steps the state is bitwise that of every pass in order on one
+    stream, for the exact solver (integer and general gamma), the Roe solver, PPMP and the H
+    correction, and with per-kernel timing on (which runs the passes in order).  The fused-z
+    schedule (the first-stage y sweep on the side, then both z stages in one march) solves
+    the same faces with a separately compiled copy of the same formulas, whose multiply-adds
+    the compiler may fuse differently: it agrees to rounding, inside the parity bound (the H
+    correction takes the overlapped schedule instead, bitwise)."""
     _announce("overlapped passes", prec)
     cases = ((WL.random_state(23, 19, 17, seed=81, bc=(1, 1, 0, 0, 1, 1)), {}),
              (WL.random_state(20, 14, 12, seed=82, gamma=1.3), {"recon": 1}),
@@ -356,14 +358,19 @@ def test_overlapped_passes_are_bitwise_serial(ctu, prec):
              (WL.random_state(19, 16, 14, seed=84, bc=(1,) * 6), {"riemann": 1, "h_correction": 1}),
              (WL.random_state(17, 15, 13, seed=85, rough=False, mach=2.0),
               {"riemann": 1, "h_correction": 1, "recon": 1}),
+             (WL.random_state(21, 18, 37, seed=86, bc=(2, 2, 1, 1, 0, 0)), {"recon": 1}),
              (WL.shock_cloud(48), {}))
     runs = ((ctu.SCHEDULE_IN_ORDER, False), (ctu.SCHEDULE_OVERLAP, False),
-            (ctu.SCHEDULE_AUTO, False), (ctu.SCHEDULE_OVERLAP, True))
+            (ctu.SCHEDULE_FUSED_Z, False), (ctu.SCHEDULE_AUTO, False),
+            (ctu.SCHEDULE_OVERLAP, True), (ctu.SCHEDULE_FUSED_Z, True))
     for wl, kw in cases:
+        hcorr = kw.get("h_correction", 0) == 1
         out = []
         for schedule, timing in runs:
             g = ctu.Grid.from_workload(wl, prec=prec, schedule=schedule, **kw)
-            want = ctu.SCHEDULE_IN_ORDER if schedule == ctu.SCHEDULE_IN_ORDER else ctu.SCHEDULE_OVERLAP
+            want = {ctu.SCHEDULE_AUTO: ctu.SCHEDULE_OVERLAP,
+                    ctu.SCHEDULE_FUSED_Z: ctu.SCHEDULE_OVERLAP if hcorr else ctu.SCHEDULE_FUSED_Z
+                    }.get(schedule, schedule)
             assert g.info().schedule == want, (schedule, g.info().schedule)
             if timing:
                 g.profile_enable(True)
@@ -375,25 +382,38 @@ def test_overlapped_passes_are_bitwise_serial(ctu, prec):
             g.close()
             assert status == ctu.OK, (wl.name, kw, flags, counters)
         for k in range(1, len(runs)):
-            assert np.array_equal(out[k], out[0]), (wl.name, kw, runs[k])
+            if runs[k][0] == ctu.SCHEDULE_FUSED_Z and not hcorr:
+                assert_parity(out[k], out[0], wl.gamma, *parity_bounds(prec),
+                              what=("fused z", wl.name, kw, prec))
+            else:
+                assert np.array_equal(out[k], out[0]), (wl.name, kw, runs[k])
 
 
-def test_schedule_choice_by_field_size(ctu):
-    """The library's choice: overlapped while one field array takes at most
-    CTU_OVERLAP_MAX_FIELD_BYTES (192 MiB), in order above; an explicit choice holds for every
-    method."""
-    limit = 192 << 20
-    for n, prec in ((256, ctu.FP64), (288, ctu.FP64), (352, ctu.FP32), (384, ctu.FP32)):
+def test_schedule_choice_by_size(ctu):
+    """The library's choice: overlapped for grids of at most CTU_OVERLAP_MAX_CELLS real cells,
+    fused z above; with the H correction overlapped while one field array takes at most
+    CTU_OVERLAP_MAX_FIELD_BYTES (192 MiB), in order above.  An explicit choice holds."""
+    cells_limit = 20 << 20
+    bytes_limit = 192 << 20
+    for n, prec in ((256, ctu.FP64), (288, ctu.FP64), (256, ctu.FP32), (352, ctu.FP32)):
         cfg = ctu.make_config(n, n, n, 1.0 / n, 1.0 / n, 1.0 / n, 5.0 / 3.0, prec=prec)
+        g = ctu.Grid(cfg)
+        sched = g.info().schedule
+        g.close()
+        want = ctu.SCHEDULE_OVERLAP if n ** 3 <= cells_limit else ctu.SCHEDULE_FUSED_Z
+        assert sched == want, (n, prec, sched)
+        assert (n == 256) == (want == ctu.SCHEDULE_OVERLAP)
+    for n in (256, 288):
+        cfg = ctu.make_config(n, n, n, 1.0 / n, 1.0 / n, 1.0 / n, 1.4, riemann=ctu.RIEMANN_ROE,
+                              h_correction=1)
         g = ctu.Grid(cfg)
         info = g.info()
         g.close()
-        small = info.field_stride * info.elem_bytes <= limit
+        small = info.field_stride * info.elem_bytes <= bytes_limit
+        assert small == (n == 256), (n, info.field_stride * info.elem_bytes)
         assert info.schedule == (ctu.SCHEDULE_OVERLAP if small else ctu.SCHEDULE_IN_ORDER), n
-        assert small == (n in (256, 352)), (n, info.field_stride * info.elem_bytes)
-    for schedule in (ctu.SCHEDULE_IN_ORDER, ctu.SCHEDULE_OVERLAP):
-        cfg = ctu.make_config(16, 16, 16, 1, 1, 1, 1.4, riemann=ctu.RIEMANN_ROE, h_correction=1,
-                              recon=ctu.RECON_PPMP, schedule=schedule)
+    for schedule in (ctu.SCHEDULE_IN_ORDER, ctu.SCHEDULE_OVERLAP, ctu.SCHEDULE_FUSED_Z):
+        cfg = ctu.make_config(24, 20, 16, 1, 1, 1, 1.4, recon=ctu.RECON_PPMP, schedule=schedule)
         g = ctu.Grid(cfg)
         assert g.info().schedule == schedule
         g.close()
