@@ -610,7 +610,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the CTU step shards by block decomposition, which this build does not run)",
+              "(the CTU step would shard by 3D block decomposition with halo exchange, which the library does not implement)",
               file=sys.stderr)
         sys.exit(2)
 
