@@ -833,8 +833,9 @@ __global__ __launch_bounds__(256, 2) void k_sweep_z_both(LaunchTab tab) {
 // first-stage differences) moves to the side instead:
 //   launch stream: [fork] (coef x) x1 (coef z) [x done] z1 [y done] eta_x [side done] y2 z2 update
 //   side stream:   [fork] (coef y) y1 [y done] [x done] eta_z [side done]
-// A pass still starts only after everything it reads is complete, so results are bitwise those
-// of the serial order.  Not while kernels are timed one by one.
+// A pass still starts only after everything it reads is complete, so the overlapped results
+// are bitwise those of the serial order; the fused z march agrees with them to rounding (a
+// separately compiled copy of the same formulas).  Not while kernels are timed one by one.
 template <typename T, int K, bool HIST, int R>
 hipError_t enqueue_sweeps(const PlanView& v, int stage, hipStream_t stream, Profiler* prof) {
   const int stride = v.ngrids + 1;
