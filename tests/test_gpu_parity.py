@@ -419,20 +419,23 @@ def test_schedule_choice_by_size(ctu):
         g.close()
 
 
-def test_newton_histogram_counts_every_solve(ctu):
+@pytest.mark.parametrize("schedule", [1, 2, 3], ids=["in_order", "overlap", "fused_z"])
+def test_newton_histogram_counts_every_solve(ctu, schedule):
     """The instrumented sweeps count one Newton-iteration bin per exact Riemann solve: the
     bins add up to the number of solves a step makes (stage 1 on the extended transverse
-    ranges, stage 2 on the real faces), and the instrumented step gives the same state."""
+    ranges, stage 2 on the real faces), in every schedule (the fused z march counts its
+    second-stage solves on the real columns only), and the instrumented step gives the same
+    state."""
     wl = WL.random_state(21, 14, 9, seed=5, bc=(1, 1, 0, 0, 1, 1))
     nx, ny, nz = wl.nx, wl.ny, wl.nz
     solves = ((nx + 1) * (ny + 2) * (nz + 2) + (nx + 2) * (ny + 1) * (nz + 2)
               + (nx + 2) * (ny + 2) * (nz + 1)
               + (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1))
-    _announce("newton histogram")
-    plain = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    _announce("newton histogram", schedule)
+    plain = ctu.Grid.from_workload(wl, prec=ctu.FP64, schedule=schedule)
     plain.advance(2)
     ref = plain.get_state()
-    g = ctu.Grid.from_workload(wl, prec=ctu.FP64)
+    g = ctu.Grid.from_workload(wl, prec=ctu.FP64, schedule=schedule)
     g.profile_enable(False, newton=True)
     g.advance(2)
     hist = g.newton_histogram()
@@ -440,7 +443,7 @@ def test_newton_histogram_counts_every_solve(ctu):
     assert hist["0-1"] + hist["2"] + hist["3"] > 0 and hist["cap"] == 0
     assert_parity(g.get_state(), ref, wl.gamma, TOL64, ELEM64, what="instrumented sweeps")
     capped = ctu.Grid(ctu.make_config(nx, ny, nz, wl.dx, wl.dy, wl.dz, wl.gamma, wl.bc,
-                                      newton_max_iter=1))
+                                      newton_max_iter=1, schedule=schedule))
     capped.set_primitive(wl.W)
     capped.profile_enable(False, newton=True)
     capped.step(capped.compute_dt())
