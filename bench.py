@@ -566,6 +566,10 @@ def main():
     ap.add_argument("--repeats", type=int, default=5,
                     help="timed runs of the primary and FP32 legs (the median is reported)")
     ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--schedule", choices=("auto", "in_order", "overlap", "fused_z"),
+                    default="auto",
+                    help="pass order of the primary FP64 and FP32 steps (the library's choice "
+                         "by default)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -638,8 +642,10 @@ def main():
 
     log(f"[bench] FP64: {args.repeats} runs of warmup {args.warmup} + timed {args.steps} steps, "
         "then one run with per-kernel events")
+    sched = {"auto": ctu.SCHEDULE_AUTO, "in_order": ctu.SCHEDULE_IN_ORDER,
+             "overlap": ctu.SCHEDULE_OVERLAP, "fused_z": ctu.SCHEDULE_FUSED_Z}[args.schedule]
     r64 = run_gpu(wl, ctu.FP64, args.steps, args.warmup, ctu, torch, repeats=args.repeats,
-                  keep_state=not args.no_fp32, newton_hist=True)
+                  keep_state=not args.no_fp32, newton_hist=True, schedule=sched)
     v64 = cells * args.steps / r64["seconds"]
     log(f"[bench] FP64 {v64:.4g} cell-updates/s (median), runs "
         f"{[round(1e3 * s / args.steps, 4) for s in r64['runs_s']]} ms/step; "
@@ -671,7 +677,7 @@ def main():
     if not args.no_fp32:
         log(f"[bench] FP32 form: {args.repeats} runs of warmup {args.warmup} + timed {args.steps} steps")
         r32 = run_gpu(wl, ctu.FP32, args.steps, args.warmup, ctu, torch, repeats=args.repeats,
-                      keep_state=True)
+                      keep_state=True, schedule=sched)
         v32 = cells * args.steps / r32["seconds"]
         log(f"[bench] FP32 {v32:.4g} cell-updates/s")
         l1 = rel_l1(r32.pop("state"), r64.pop("state"), wl.gamma)
