@@ -3,8 +3,11 @@
 * The whole 256^3 shock-cloud grid, every cell, one step from an evolved state (the shock
   started at x = 0.17 has run into the cloud after 90 GPU steps), in FP64 and in the FP32
   form; the oracle runs its OpenMP build for this.
+* The same in FP64 under the fused-z schedule (both z stages in one march), which grids above
+  20M cells take by default.
 * Sampled boxes of one step from the initial states of the 256^3 shock-cloud with every
-  method, of the 512^3 turbulent cloud (FP32), and of its FP64 steps 25 and 50.
+  method (and under the fused-z schedule for PPMC + Roe and PPMP + exact), of the 512^3
+  turbulent cloud (FP32, fused z by default), and of its FP64 steps 25 and 50.
 
 Both sides use the same dt, so the GPU runs the same kernels and launch shapes as the
 benchmark.  Every comparison checks the relative L1 norm and every cell against its own
@@ -34,13 +37,15 @@ def _boxes(n, special, rng, count=6, size=8):
     return boxes
 
 
-def _check(ctu, wl, prec, tol, special, seed, **method):
-    print(f"[gpu-test] full size {wl.name} prec {prec} {method}", flush=True)
+def _check(ctu, wl, prec, tol, special, seed, schedule=0, **method):
+    print(f"[gpu-test] full size {wl.name} prec {prec} {method} schedule {schedule}", flush=True)
     cfg = oracle_config(wl, **method)
     u = O.state_from_primitive(cfg, wl.W)
     O.bc_fill(cfg, u)
     dt = O.compute_dt(cfg, u)
-    g = ctu.Grid.from_workload(wl, prec=prec, **method)
+    g = ctu.Grid.from_workload(wl, prec=prec, schedule=schedule, **method)
+    if schedule:
+        assert g.info().schedule == schedule
     dt_gpu = g.compute_dt()
     assert dt_gpu == pytest.approx(dt, rel=1e-14 if prec == ctu.FP64 else 1e-6)
     g.step(dt)
@@ -75,19 +80,24 @@ def _oracle_threads():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
-def test_shock_cloud_256_full_grid_evolved(prec):
+@pytest.mark.parametrize("prec,schedule", [(0, 0), (1, 0), (0, 3)],
+                         ids=["fp64", "fp32", "fp64-fused_z"])
+def test_shock_cloud_256_full_grid_evolved(prec, schedule):
     """Every cell of the 256^3 shock-cloud after one step from an evolved state: the GPU runs
     90 steps (its own CFL time steps) with the shock started at x = 0.17, so that it has
     entered the cloud (edge at x = 0.2) and compressed it; its state is downloaded and one more GPU step is
     compared with the oracle's step of that same state (FP64 arithmetic on the float state
-    in the FP32 form), cell by cell over the whole grid."""
+    in the FP32 form), cell by cell over the whole grid.  The grid takes the library's
+    schedule for its size (overlapped), and once, in FP64, the fused-z schedule that larger
+    grids take (both z stages in one march)."""
     from paper_1410_4194_amd import ctu
     wl = WL.shock_cloud(256, x_shock=0.17)
     cfg = oracle_config(wl)
-    print(f"[gpu-test] full grid 256^3 shock-cloud (x_shock 0.17) prec {prec}: 90 GPU steps",
-          flush=True)
-    g = ctu.Grid.from_workload(wl, prec=prec)
+    print(f"[gpu-test] full grid 256^3 shock-cloud (x_shock 0.17) prec {prec} schedule "
+          f"{schedule}: 90 GPU steps", flush=True)
+    g = ctu.Grid.from_workload(wl, prec=prec, schedule=schedule)
+    if schedule:
+        assert g.info().schedule == schedule
     g.advance(90)
     U = g.get_state()
     dt = g.compute_dt()
@@ -132,6 +142,18 @@ def test_shock_cloud_256_methods(name, method, prec):
     from paper_1410_4194_amd import ctu
     _check(ctu, WL.shock_cloud(256), prec, 1e-12 if prec == 0 else 1e-5,
            _shock_cloud_special(256), seed=33, **method)
+
+
+# the fused-z schedule with the methods it has a variant for (not the H correction)
+FUSED_Z_METHODS = [("ppmc_roe", dict(riemann=1)), ("ppmp_exact", dict(recon=1))]
+
+
+@pytest.mark.parametrize("name,method", FUSED_Z_METHODS, ids=[m[0] for m in FUSED_Z_METHODS])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_shock_cloud_256_methods_fused_z(name, method, prec):
+    from paper_1410_4194_amd import ctu
+    _check(ctu, WL.shock_cloud(256), prec, 1e-12 if prec == 0 else 1e-5,
+           _shock_cloud_special(256), seed=34, schedule=ctu.SCHEDULE_FUSED_Z, **method)
 
 
 @pytest.mark.timeout(600)
