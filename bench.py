@@ -7,8 +7,8 @@ CFL 0.3), advanced with the device-side time step, state resident in HBM.  Each 
 `--repeats` runs starts from the initial state, takes `warmup` untimed steps and then times
 exactly `steps` steps between two device synchronizations, with no instrumentation and the
 library's default schedule (the first-stage y and second-stage z sweeps on a second stream
-of the grid's, overlapping the other sweeps); value = real cells x steps / time of the
-median run.  A further run of the same steps with per-kernel HIP events (recorded by the
+of the grid's, overlapping the other sweeps; `--schedule` forces in order, overlapped or
+fused z for the FP64 and FP32 legs); value = real cells x steps / time of the median run.  A further run of the same steps with per-kernel HIP events (recorded by the
 library on its streams; timing runs every pass in order on one stream, so each kernel's
 time is its own) gives the kernel times of the roofline.  The FP32 form (FP32 state, reconstruction and fluxes, FP64 Newton solve)
 is timed the same way and reported beside it, with its relative L1 distance from FP64.
