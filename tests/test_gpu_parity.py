@@ -389,6 +389,30 @@ def test_overlapped_passes_are_bitwise_serial(ctu, prec):
                 assert np.array_equal(out[k], out[0]), (wl.name, kw, runs[k])
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_overlapped_long_run_is_bitwise_serial(ctu, prec):
+    """A race between the two streams of the overlapped schedule (a pass reading data that the
+    other stream has not finished writing) would show as a difference from the in-order
+    schedule at some step.  At 128^3 the side stream's sweeps really run beside the launch
+    stream's, and 200 device-dt steps of the shock-cloud (the shock running into the cloud)
+    leave the state, the time and the step count bitwise those of every pass in order."""
+    _announce("overlapped long run 128^3", prec)
+    wl = WL.shock_cloud(128)
+    res = []
+    for schedule in (ctu.SCHEDULE_IN_ORDER, ctu.SCHEDULE_OVERLAP):
+        g = ctu.Grid.from_workload(wl, prec=prec, schedule=schedule)
+        assert g.info().schedule == schedule
+        g.advance(200)
+        info = g.info()
+        status, flags, counters = g.check()
+        assert status == ctu.OK, (schedule, flags, counters)
+        res.append((g.get_state(), info.t, info.steps))
+        g.close()
+    assert res[0][2] == res[1][2] == 200
+    assert res[0][1] == res[1][1]
+    assert np.array_equal(res[0][0], res[1][0])
+
+
 def test_schedule_choice_by_size(ctu):
     """The library's choice: overlapped for grids of at most CTU_OVERLAP_MAX_CELLS real cells,
     fused z above; with the H correction overlapped while one field array takes at most
