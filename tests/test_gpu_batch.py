@@ -93,6 +93,31 @@ def test_batch_matches_solo(ctu, graph):
         assert np.array_equal(U, solo[i][0]), wl.name
 
 
+def test_batch_long_run_matches_solo_in_order(ctu):
+    """A race between the batch's two streams (or between the branches of its captured graph)
+    would show as a difference from the same grid advanced alone with every pass in order:
+    six Kelvin-Helmholtz grids of edges 48-96 in both precisions, 150 graph-replayed steps
+    each, end bitwise equal to those solo runs."""
+    kh = WL.kh_batch(count=6, edges=(48, 64, 96), steps=150)
+    jobs = [(wl, i % 2, 150) for i, wl in enumerate(kh)]
+    _announce("batch long run vs solo in order", len(jobs), "jobs")
+    solo = []
+    for wl, prec, n in jobs:
+        g = ctu.Grid.from_workload(wl, prec=prec, schedule=ctu.SCHEDULE_IN_ORDER)
+        g.advance(n)
+        info = g.info()
+        solo.append((g.get_state(), info.t, info.steps))
+        g.close()
+    b = ctu.Batch(max_slots=len(jobs), graph=True)
+    res = _serve(ctu, b, jobs, run_steps=50)
+    b.close()
+    for i, (wl, prec, n) in enumerate(jobs):
+        U, t, steps = res[i]
+        assert steps == n == solo[i][2], (wl.name, steps, n)
+        assert t == solo[i][1], wl.name
+        assert np.array_equal(U, solo[i][0]), wl.name
+
+
 def test_graph_replays_match_eager(ctu):
     """The captured step is replayed many times, with eager work and host synchronization
     between replays and recaptures whenever the set of grids changes; every grid, finishing
